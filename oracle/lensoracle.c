@@ -1,0 +1,454 @@
+/*
+ * lensoracle.c -- plain, slow FP64 CPU oracle for inverse ray-shooting of a
+ * microlensing magnification map with the near/far (Taylor) deflection scheme.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+ * the CPU-baseline leg of the benchmark may load or call this library.  The
+ * product path (liblensmap) never links or calls it, and the two share no
+ * source, header, table or helper.
+ *
+ * What is computed (all lengths in Einstein radii, all arithmetic in FP64):
+ *
+ *  Lens equation with a constant macro Jacobian, point-mass microlenses and a
+ *  compensating negative mass sheet (Sec. 2, Eq. 1 and Eq. 6):
+ *      beta = diag(1-kappa-gamma, 1-kappa+gamma) theta + kappa_star theta
+ *             - sum_k m_k (theta - theta_k) / |theta - theta_k|^2
+ *  The sheet of density -kappa_star is read as infinite and uniform about the
+ *  coordinate origin, so its term is +kappa_star * theta.
+ *
+ *  Ray lattice (Sec. 3.2, level-3 grid, Eq. 11): ray (i,j) sits at the centre
+ *  of level-3 pixel (i,j): theta = (X0 + (i+1/2) L3x, Y0 + (j+1/2) L3y).
+ *
+ *  Direct scheme (Sec. 3.2, the direct deflection sum): every lens enters the
+ *  sum.  A term whose ray coincides exactly with its lens is skipped.
+ *
+ *  Interpolated scheme (Sec. 3.2, Eq. 9, levels 1-2):
+ *   - level-2 cell (ci,cj) = (floor(i/R), floor(j/R)): a block of R x R rays
+ *     with centre z_c = (X0 + (ci+1/2) R L3x, Y0 + (cj+1/2) R L3y);
+ *   - level-1 cell (I,J) = (floor(ci/Kx), floor(cj/Ky)); a lens belongs to
+ *     level-1 cell (floor((x-X0)/(Kx R L3x)), floor((y-Y0)/(Ky R L3y)));
+ *   - near lenses of a ray: those whose level-1 cell lies within H cells of the
+ *     ray's level-1 cell in both directions (the 3x3 block for H = 1);
+ *   - far lenses enter through P complex Taylor coefficients of the level-2
+ *     cell (P = 4 gives the eight real coefficients of Sec. 3.2.2):
+ *       conj(alpha_far)(z) = sum_{n<P} a_n (z - z_c)^n,
+ *       a_n = - sum_{k far} m_k / (z_k - z_c)^{n+1},
+ *     which is the power series of sum_k m_k / (z - z_k) about z_c;
+ *   - alpha = alpha_near (direct sum over near lenses) + alpha_far.
+ *
+ *  Binning and magnification (Sec. 3.2, Eq. 12): pixel (p,q) covers
+ *  [Bx0 + p dx, Bx0 + (p+1) dx) x [By0 + q dy, By0 + (q+1) dy); a ray outside
+ *  every pixel is counted in n_out; mu_pq = N_pq * (L3x L3y) / (dx dy).
+ *
+ * Sums of many terms use Neumaier's compensated summation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    /* source map */
+    double src_x0, src_y0, src_dx, src_dy;
+    int64_t src_nx, src_ny;
+    /* ray lattice */
+    double ray_x0, ray_y0, ray_dx, ray_dy;
+    int64_t ray_nx, ray_ny;
+    /* macro model */
+    double kappa, gamma, kappa_star;
+    /* scheme: 0 direct, 1 interpolated */
+    int64_t scheme, coarse, l1_kx, l1_ky, halo, terms;
+} lmo_params;
+
+typedef struct {
+    const double *x, *y, *m;
+    int64_t n;
+} lmo_lenses;
+
+/* ---- compensated summation (Neumaier) ---------------------------------- */
+typedef struct { double s, c; } nsum;
+
+static inline void nsum_add(nsum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+static inline double nsum_get(const nsum *a) { return a->s + a->c; }
+
+/* ---- lens equation pieces ---------------------------------------------- */
+
+/* Direct deflection of a lens subset: alpha = sum m_k (theta-theta_k)/|.|^2.
+ * idx (may be NULL for all lenses) lists the lenses that enter, in lens order. */
+static void direct_sum(const lmo_lenses *L, const int64_t *idx, int64_t nidx,
+                       double tx, double ty, double *ax, double *ay)
+{
+    nsum sx = {0, 0}, sy = {0, 0};
+    int64_t cnt = idx ? nidx : L->n;
+    for (int64_t t = 0; t < cnt; ++t) {
+        int64_t k = idx ? idx[t] : t;
+        double dx = tx - L->x[k], dy = ty - L->y[k];
+        double r2 = dx * dx + dy * dy;
+        if (r2 == 0.0) continue; /* ray on the lens: term skipped */
+        nsum_add(&sx, L->m[k] * dx / r2);
+        nsum_add(&sy, L->m[k] * dy / r2);
+    }
+    *ax = nsum_get(&sx);
+    *ay = nsum_get(&sy);
+}
+
+/* indices of the lenses flagged near, in lens order; returns their number */
+static int64_t near_list(const unsigned char *near, int64_t n, int64_t *idx)
+{
+    int64_t c = 0;
+    for (int64_t k = 0; k < n; ++k)
+        if (near[k]) idx[c++] = k;
+    return c;
+}
+
+static int64_t floor_div_i64(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+/* level-1 cell of a lens (Sec. 3.2.1) */
+static void lens_l1(const lmo_params *p, double x, double y, int64_t *I, int64_t *J)
+{
+    double wx = p->ray_dx * (double)(p->coarse * p->l1_kx);
+    double wy = p->ray_dy * (double)(p->coarse * p->l1_ky);
+    double fi = floor((x - p->ray_x0) / wx);
+    double fj = floor((y - p->ray_y0) / wy);
+    /* clamp far-away lenses: they stay far from every ray cell */
+    double lim = 4.0e15;
+    if (fi > lim) fi = lim;
+    if (fi < -lim) fi = -lim;
+    if (fj > lim) fj = lim;
+    if (fj < -lim) fj = -lim;
+    *I = (int64_t)fi;
+    *J = (int64_t)fj;
+}
+
+/* near mask of level-2 cell (ci,cj): 1 where the lens is near */
+static void near_mask(const lmo_params *p, const lmo_lenses *L, int64_t ci, int64_t cj,
+                      unsigned char *near)
+{
+    int64_t I = floor_div_i64(ci, p->l1_kx), J = floor_div_i64(cj, p->l1_ky);
+    for (int64_t k = 0; k < L->n; ++k) {
+        int64_t Ik, Jk;
+        lens_l1(p, L->x[k], L->y[k], &Ik, &Jk);
+        int64_t di = Ik - I, dj = Jk - J;
+        near[k] = (di >= -p->halo && di <= p->halo && dj >= -p->halo && dj <= p->halo);
+    }
+}
+
+static void cell_centre(const lmo_params *p, int64_t ci, int64_t cj, double *zx, double *zy)
+{
+    *zx = p->ray_x0 + ((double)ci + 0.5) * (double)p->coarse * p->ray_dx;
+    *zy = p->ray_y0 + ((double)cj + 0.5) * (double)p->coarse * p->ray_dy;
+}
+
+/* Taylor coefficients a_n, n < P, of the far lenses about z_c (Sec. 3.2.2).
+ * a[2n] = Re a_n, a[2n+1] = Im a_n. */
+static void far_coeffs(const lmo_params *p, const lmo_lenses *L, const unsigned char *near,
+                       double zx, double zy, double *a)
+{
+    int64_t P = p->terms;
+    nsum *re = (nsum *)calloc((size_t)P, sizeof(nsum));
+    nsum *im = (nsum *)calloc((size_t)P, sizeof(nsum));
+    for (int64_t k = 0; k < L->n; ++k) {
+        if (near[k]) continue;
+        /* u = 1 / (z_k - z_c) */
+        double wx = L->x[k] - zx, wy = L->y[k] - zy;
+        double w2 = wx * wx + wy * wy;
+        double ux = wx / w2, uy = -wy / w2;
+        /* t = m u^{n+1}, accumulated as -t */
+        double tx = L->m[k] * ux, ty = L->m[k] * uy;
+        for (int64_t n = 0; n < P; ++n) {
+            nsum_add(&re[n], -tx);
+            nsum_add(&im[n], -ty);
+            double nx = tx * ux - ty * uy;
+            double ny = tx * uy + ty * ux;
+            tx = nx;
+            ty = ny;
+        }
+    }
+    for (int64_t n = 0; n < P; ++n) {
+        a[2 * n] = nsum_get(&re[n]);
+        a[2 * n + 1] = nsum_get(&im[n]);
+    }
+    free(re);
+    free(im);
+}
+
+/* alpha_far = conj( sum_n a_n d^n ), d = z - z_c, evaluated by Horner */
+static void far_eval(int64_t P, const double *a, double dx, double dy, double *ax, double *ay)
+{
+    double fx = a[2 * (P - 1)], fy = a[2 * (P - 1) + 1];
+    for (int64_t n = P - 2; n >= 0; --n) {
+        double gx = fx * dx - fy * dy + a[2 * n];
+        double gy = fx * dy + fy * dx + a[2 * n + 1];
+        fx = gx;
+        fy = gy;
+    }
+    *ax = fx;
+    *ay = -fy;
+}
+
+/* source-plane position (Eq. 6 with the constant Jacobian of Eq. 1) */
+static void lens_map(const lmo_params *p, double tx, double ty, double ax, double ay,
+                     double *bx, double *by)
+{
+    double lt = 1.0 - p->kappa - p->gamma, lr = 1.0 - p->kappa + p->gamma;
+    *bx = (lt + p->kappa_star) * tx - ax;
+    *by = (lr + p->kappa_star) * ty - ay;
+}
+
+/* pixel index q*nx + p of a source position, or -1 outside the map */
+static int64_t bin_of(const lmo_params *p, double bx, double by)
+{
+    double u = floor((bx - p->src_x0) / p->src_dx);
+    double v = floor((by - p->src_y0) / p->src_dy);
+    if (!(u >= 0.0 && u < (double)p->src_nx && v >= 0.0 && v < (double)p->src_ny)) return -1;
+    return (int64_t)v * p->src_nx + (int64_t)u;
+}
+
+static int check_params(const lmo_params *p)
+{
+    if (!(p->src_dx > 0 && p->src_dy > 0 && p->ray_dx > 0 && p->ray_dy > 0)) return -1;
+    if (p->src_nx <= 0 || p->src_ny <= 0 || p->ray_nx < 0 || p->ray_ny < 0) return -1;
+    if (p->scheme == 1) {
+        if (p->coarse <= 0 || p->l1_kx <= 0 || p->l1_ky <= 0 || p->halo < 0) return -1;
+        if (p->terms <= 0 || p->terms > 16) return -1;
+    } else if (p->scheme != 0) {
+        return -1;
+    }
+    return 0;
+}
+
+/* ---- exported entry points ---------------------------------------------- */
+
+/* Direct deflection at arbitrary positions (Sec. 3.2, direct sum). */
+int lmo_deflect_direct(const double *lx, const double *ly, const double *lm, int64_t n,
+                       const double *theta, int64_t nth, double *alpha)
+{
+    lmo_lenses L = {lx, ly, lm, n};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < nth; ++t)
+        direct_sum(&L, NULL, 0, theta[2 * t], theta[2 * t + 1], &alpha[2 * t], &alpha[2 * t + 1]);
+    return 0;
+}
+
+/* Taylor coefficients of level-2 cell (ci,cj); a has 2*terms doubles. */
+int lmo_coeffs(const lmo_params *p, const double *lx, const double *ly, const double *lm,
+               int64_t n, int64_t ci, int64_t cj, double *a)
+{
+    if (check_params(p) || p->scheme != 1) return -1;
+    lmo_lenses L = {lx, ly, lm, n};
+    unsigned char *near = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
+    near_mask(p, &L, ci, cj, near);
+    double zx, zy;
+    cell_centre(p, ci, cj, &zx, &zy);
+    far_coeffs(p, &L, near, zx, zy, a);
+    free(near);
+    return 0;
+}
+
+/* Near mask of level-2 cell (ci,cj) as bytes (1 = near). */
+int lmo_near_mask(const lmo_params *p, const double *lx, const double *ly, int64_t n,
+                  int64_t ci, int64_t cj, unsigned char *near)
+{
+    if (check_params(p) || p->scheme != 1) return -1;
+    lmo_lenses L = {lx, ly, NULL, n};
+    near_mask(p, &L, ci, cj, near);
+    return 0;
+}
+
+/* Deflection of the configured scheme at arbitrary positions.  For the
+ * interpolated scheme the level-2 cell is the one containing theta. */
+int lmo_deflect(const lmo_params *p, const double *lx, const double *ly, const double *lm,
+                int64_t n, const double *theta, int64_t nth, double *alpha)
+{
+    if (check_params(p)) return -1;
+    if (p->scheme == 0) return lmo_deflect_direct(lx, ly, lm, n, theta, nth, alpha);
+    lmo_lenses L = {lx, ly, lm, n};
+    int64_t P = p->terms;
+    int err = 0;
+#pragma omp parallel
+    {
+        unsigned char *near = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
+        int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+        double *a = (double *)malloc(sizeof(double) * 2 * (size_t)P);
+        if (!near || !idx || !a) {
+#pragma omp atomic write
+            err = -2;
+        } else {
+#pragma omp for schedule(dynamic, 16)
+            for (int64_t t = 0; t < nth; ++t) {
+                double tx = theta[2 * t], ty = theta[2 * t + 1];
+                int64_t ci = (int64_t)floor((tx - p->ray_x0) / ((double)p->coarse * p->ray_dx));
+                int64_t cj = (int64_t)floor((ty - p->ray_y0) / ((double)p->coarse * p->ray_dy));
+                double zx, zy, nx, ny, fx, fy;
+                near_mask(p, &L, ci, cj, near);
+                cell_centre(p, ci, cj, &zx, &zy);
+                far_coeffs(p, &L, near, zx, zy, a);
+                int64_t nn = near_list(near, n, idx);
+                direct_sum(&L, idx, nn, tx, ty, &nx, &ny);
+                far_eval(P, a, tx - zx, ty - zy, &fx, &fy);
+                alpha[2 * t] = nx + fx;
+                alpha[2 * t + 1] = ny + fy;
+            }
+        }
+        free(near);
+        free(idx);
+        free(a);
+    }
+    return err;
+}
+
+/* Source positions and pixel indices of listed lattice rays (i[t], j[t]). */
+int lmo_trace(const lmo_params *p, const double *lx, const double *ly, const double *lm,
+              int64_t n, const int64_t *ii, const int64_t *jj, int64_t nr, double *beta,
+              int64_t *pix)
+{
+    if (check_params(p)) return -1;
+    double *th = (double *)calloc(2 * (size_t)(nr > 0 ? nr : 1), sizeof(double));
+    double *al = (double *)malloc(sizeof(double) * 2 * (size_t)(nr > 0 ? nr : 1));
+    if (!th || !al) {
+        free(th);
+        free(al);
+        return -2;
+    }
+    for (int64_t t = 0; t < nr; ++t) {
+        th[2 * t] = p->ray_x0 + ((double)ii[t] + 0.5) * p->ray_dx;
+        th[2 * t + 1] = p->ray_y0 + ((double)jj[t] + 0.5) * p->ray_dy;
+    }
+    int rc = lmo_deflect(p, lx, ly, lm, n, th, nr, al);
+    if (rc == 0) {
+        for (int64_t t = 0; t < nr; ++t) {
+            double bx, by;
+            lens_map(p, th[2 * t], th[2 * t + 1], al[2 * t], al[2 * t + 1], &bx, &by);
+            beta[2 * t] = bx;
+            beta[2 * t + 1] = by;
+            pix[t] = bin_of(p, bx, by);
+        }
+    }
+    free(th);
+    free(al);
+    return rc;
+}
+
+/* Shoot the rays of the lattice sub-rectangle [i0,i0+ni) x [j0,j0+nj) and add
+ * them to counts[src_ny*src_nx] (row-major, q*src_nx + p); rays outside the
+ * map are added to *n_out.  nthreads <= 0 uses the OpenMP default. */
+int lmo_shoot(const lmo_params *p, const double *lx, const double *ly, const double *lm,
+              int64_t n, int64_t i0, int64_t j0, int64_t ni, int64_t nj, uint64_t *counts,
+              uint64_t *n_out, int nthreads)
+{
+    if (check_params(p)) return -1;
+    if (ni < 0 || nj < 0 || i0 < 0 || j0 < 0 || i0 + ni > p->ray_nx || j0 + nj > p->ray_ny)
+        return -1;
+    if (ni == 0 || nj == 0) return 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    lmo_lenses L = {lx, ly, lm, n};
+    uint64_t outs = 0;
+    int err = 0;
+    if (p->scheme == 0) {
+        /* direct: one row of rays per task */
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : outs)
+        for (int64_t j = j0; j < j0 + nj; ++j) {
+            double ty = p->ray_y0 + ((double)j + 0.5) * p->ray_dy;
+            for (int64_t i = i0; i < i0 + ni; ++i) {
+                double tx = p->ray_x0 + ((double)i + 0.5) * p->ray_dx;
+                double ax, ay, bx, by;
+                direct_sum(&L, NULL, 0, tx, ty, &ax, &ay);
+                lens_map(p, tx, ty, ax, ay, &bx, &by);
+                int64_t b = bin_of(p, bx, by);
+                if (b < 0) {
+                    ++outs;
+                } else {
+#pragma omp atomic update
+                    counts[b] += 1;
+                }
+            }
+        }
+    } else {
+        /* interpolated: one level-2 cell per task; its coefficients and near
+         * set are found once and used for all of its rays */
+        int64_t R = p->coarse, P = p->terms;
+        int64_t ci0 = i0 / R, ci1 = (i0 + ni - 1) / R, cj0 = j0 / R, cj1 = (j0 + nj - 1) / R;
+        int64_t ncx = ci1 - ci0 + 1, ncells = ncx * (cj1 - cj0 + 1);
+#pragma omp parallel reduction(+ : outs)
+        {
+            unsigned char *near = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
+            int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+            double *a = (double *)malloc(sizeof(double) * 2 * (size_t)P);
+            if (!near || !idx || !a) {
+#pragma omp atomic write
+                err = -2;
+            } else {
+#pragma omp for schedule(dynamic, 1)
+                for (int64_t c = 0; c < ncells; ++c) {
+                    int64_t ci = ci0 + c % ncx, cj = cj0 + c / ncx;
+                    double zx, zy;
+                    near_mask(p, &L, ci, cj, near);
+                    cell_centre(p, ci, cj, &zx, &zy);
+                    far_coeffs(p, &L, near, zx, zy, a);
+                    int64_t nn = near_list(near, n, idx);
+                    int64_t ia = ci * R > i0 ? ci * R : i0;
+                    int64_t ib = (ci + 1) * R < i0 + ni ? (ci + 1) * R : i0 + ni;
+                    int64_t ja = cj * R > j0 ? cj * R : j0;
+                    int64_t jb = (cj + 1) * R < j0 + nj ? (cj + 1) * R : j0 + nj;
+                    for (int64_t j = ja; j < jb; ++j) {
+                        double ty = p->ray_y0 + ((double)j + 0.5) * p->ray_dy;
+                        for (int64_t i = ia; i < ib; ++i) {
+                            double tx = p->ray_x0 + ((double)i + 0.5) * p->ray_dx;
+                            double nx, ny, fx, fy, bx, by;
+                            direct_sum(&L, idx, nn, tx, ty, &nx, &ny);
+                            far_eval(P, a, tx - zx, ty - zy, &fx, &fy);
+                            lens_map(p, tx, ty, nx + fx, ny + fy, &bx, &by);
+                            int64_t b = bin_of(p, bx, by);
+                            if (b < 0) {
+                                ++outs;
+                            } else {
+#pragma omp atomic update
+                                counts[b] += 1;
+                            }
+                        }
+                    }
+                }
+            }
+            free(near);
+            free(idx);
+            free(a);
+        }
+    }
+    *n_out += outs;
+    return err;
+}
+
+/* Magnification of a pixel from its count (Eq. 12). */
+double lmo_mu_factor(const lmo_params *p)
+{
+    return (p->ray_dx * p->ray_dy) / (p->src_dx * p->src_dy);
+}
+
+int lmo_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

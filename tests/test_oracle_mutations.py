@@ -1,0 +1,47 @@
+"""The oracle's pins must catch plausible slips.  Each case plants one mistake in
+a copy of the oracle source (on the CPU, in a temporary directory), rebuilds it
+and checks that the pin suite then fails."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTATIONS = {
+    "sheet_sign": ("*bx = (lt + p->kappa_star) * tx - ax;", "*bx = (lt - p->kappa_star) * tx - ax;"),
+    "deflection_sign": ("*by = (lr + p->kappa_star) * ty - ay;", "*by = (lr + p->kappa_star) * ty + ay;"),
+    "missing_conjugate": ("    *ay = -fy;", "    *ay = fy;"),
+    "dropped_taylor_term": ("for (int64_t n = P - 2; n >= 0; --n) {", "for (int64_t n = P - 2; n >= 1; --n) {"),
+    "x_y_swap": ("double lt = 1.0 - p->kappa - p->gamma, lr = 1.0 - p->kappa + p->gamma;",
+                 "double lr = 1.0 - p->kappa - p->gamma, lt = 1.0 - p->kappa + p->gamma;"),
+    "bin_ceil": ("double u = floor((bx - p->src_x0) / p->src_dx);", "double u = ceil((bx - p->src_x0) / p->src_dx);"),
+    "near_halo_off_by_one": ("near[k] = (di >= -p->halo && di <= p->halo", "near[k] = (di >= -p->halo && di < p->halo"),
+    "coefficient_sign": ("nsum_add(&im[n], -ty);", "nsum_add(&im[n], ty);"),
+    "dropped_mass": ("nsum_add(&sx, L->m[k] * dx / r2);", "nsum_add(&sx, dx / r2);"),
+    "cell_centre_offset": ("*zx = p->ray_x0 + ((double)ci + 0.5)", "*zx = p->ray_x0 + ((double)ci + 0.0)"),
+    "power_transposed": ("double ny = tx * uy + ty * ux;", "double ny = tx * uy - ty * ux;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    before, after = MUTATIONS[name]
+    d = tmp_path / "copy"
+    shutil.copytree(os.path.join(ROOT, "oracle"), d / "oracle",
+                    ignore=shutil.ignore_patterns("*.so", "*.tmp*", "__pycache__"))
+    shutil.copytree(os.path.join(ROOT, "tests"), d / "tests",
+                    ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutations.py"))
+    pkg = d / "paper_2308_14278_amd"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text("")
+    shutil.copy(os.path.join(ROOT, "paper_2308_14278_amd", "inputs.py"), pkg / "inputs.py")
+    src = (d / "oracle" / "lensoracle.c").read_text()
+    assert before in src
+    (d / "oracle" / "lensoracle.c").write_text(src.replace(before, after))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "tests/test_oracle_pins.py"], cwd=d, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0, "planted mistake %r was not caught:\n%s" % (name, r.stdout[-2000:])

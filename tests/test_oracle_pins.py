@@ -1,0 +1,321 @@
+"""Pins of the FP64 oracle against results the paper and the mathematics fix.
+
+Each test names the passage it rests on.  Every plausible slip in the oracle
+(a dropped sheet term, a wrong deflection sign, a conjugation or index error in
+the Taylor series, an x/y swap, an off-by-one in binning) fails at least one of
+them:
+
+  zero lenses, aligned lattice  -> macro mapping, binning and Eq. 12 (exact)
+  zero lenses, kappa_star > 0   -> sign and size of the negative-sheet term
+  one point lens                -> deflection sign/size against A(u)
+  every ray counted             -> counting
+  mean magnification            -> lenses + sheet, protection zone (Sec. 3.1)
+  all lenses near               -> interpolated == direct (bitwise)
+  one far lens                  -> Taylor coefficients and their evaluation
+  tiny brute force              -> the whole interpolated scheme vs direct
+  additivity, mirror symmetry   -> sub-rectangles, signs
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle.geometry import OracleGeometry, derive_geometry
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _geom(**kw):
+    base = dict(src_x0=-5.0, src_y0=-5.0, src_dx=10 / 64, src_dy=10 / 64, src_nx=64, src_ny=64,
+                ray_x0=-100.0, ray_y0=-10 / 1.05 / 2, ray_dx=200 / 1024,
+                ray_dy=10 / 1.05 / 1024, ray_nx=1024, ray_ny=1024, scheme=0)
+    base.update(kw)
+    return OracleGeometry(**base)
+
+
+def point_lens_A(u):
+    """Point-lens total magnification A(u) = (u^2+2)/(u sqrt(u^2+4))."""
+    return (u * u + 2.0) / (u * np.sqrt(u * u + 4.0))
+
+
+# --------------------------------------------------------------------- macro
+
+
+def test_zero_lenses_aligned_lattice_exact(oracle_lib):
+    """Eq. 1 + Eq. 12: with no lenses and no sheet, beta = diag(lt, lr) theta.
+    With pixel sides of exactly 16 ray images each way, every pixel holds 256
+    rays and mu = 1/|(1-k)^2 - g^2| exactly."""
+    kappa, gamma = 0.45, 0.5
+    g = _geom()
+    o = oracle_lib.Oracle(g, kappa, gamma, 0.0, [], [], [])
+    counts, n_out = o.shoot()
+    assert counts.dtype == np.uint64
+    assert np.all(counts == 256)
+    assert n_out == 0
+    mu = counts * o.mu_factor()
+    macro = 1.0 / abs((1 - kappa) ** 2 - gamma ** 2)
+    assert abs(macro - 19.047619047619047) < 1e-12
+    np.testing.assert_allclose(mu, macro, rtol=1e-12)
+
+
+def test_zero_lenses_sheet_term(oracle_lib):
+    """Eq. 6 with no lenses: the -kappa_star sheet adds +kappa_star theta, so the
+    mean magnification becomes 1/((lt+ks)(lr+ks)); the wrong sign would give
+    1/((lt-ks)(lr-ks)), about 50% larger here."""
+    kappa, gamma, ks = 0.45, 0.5, 0.01
+    g = _geom()
+    o = oracle_lib.Oracle(g, kappa, gamma, ks, [], [], [])
+    counts, n_out = o.shoot()
+    lt, lr = 1 - kappa - gamma, 1 - kappa + gamma
+    mu_mean = counts.mean() * o.mu_factor()
+    expect = 1.0 / ((lt + ks) * (lr + ks))
+    assert abs(mu_mean / expect - 1) < 2e-3
+    assert int(counts.sum()) + n_out == g.ray_nx * g.ray_ny
+    # the map is separable: N_pq = c_x(p) c_y(q)
+    cx = counts.sum(axis=0).astype(np.float64)
+    cy = counts.sum(axis=1).astype(np.float64)
+    np.testing.assert_array_equal(counts.astype(np.float64) * counts.sum(),
+                                  np.outer(cy, cx))
+
+
+# ----------------------------------------------------------------- point lens
+
+
+def test_golden_point_lens_values():
+    """Fixture values of the point-lens magnification curve."""
+    with open(os.path.join(GOLDEN, "point_lens.json")) as f:
+        gold = json.load(f)
+    for u, a, _closed_form in gold["A_of_u"]:
+        assert abs(point_lens_A(np.float64(u)) - a) < 5e-5
+
+
+def test_single_point_lens_magnification(oracle_lib):
+    """One unit lens at the origin, kappa = gamma = kappa_star = 0: the pixel
+    magnification must follow the pixel average of A(u) (u >= 0.2)."""
+    n = 4096
+    g = OracleGeometry(src_x0=-2, src_y0=-2, src_dx=4 / 32, src_dy=4 / 32, src_nx=32,
+                       src_ny=32, ray_x0=-4, ray_y0=-4, ray_dx=8 / n, ray_dy=8 / n,
+                       ray_nx=n, ray_ny=n, scheme=0)
+    o = oracle_lib.Oracle(g, 0.0, 0.0, 0.0, [0.0], [0.0], [1.0])
+    counts, n_out = o.shoot()
+    assert int(counts.sum()) + n_out == n * n
+    mu = counts * o.mu_factor()
+    sub = (np.arange(24) + 0.5) / 24 * g.src_dx
+    aavg = np.empty((32, 32))
+    for q in range(32):
+        yy = g.src_y0 + q * g.src_dy + sub
+        for p in range(32):
+            xx = g.src_x0 + p * g.src_dx + sub
+            X, Y = np.meshgrid(xx, yy)
+            aavg[q, p] = point_lens_A(np.hypot(X, Y)).mean()
+    c = g.src_x0 + (np.arange(32) + 0.5) * g.src_dx
+    X, Y = np.meshgrid(c, c)
+    ok = np.hypot(X, Y) >= 0.2
+    rel = mu[ok] / aavg[ok] - 1.0
+    assert np.abs(rel).max() < 0.02
+    assert abs(rel.mean()) < 2e-3
+
+
+def test_single_lens_deflection_closed_form(oracle_lib):
+    """alpha = m (theta - theta_k)/|theta - theta_k|^2 for one lens (Sec. 2)."""
+    rng = np.random.default_rng(7)
+    th = rng.uniform(-3, 3, size=(100, 2))
+    o = oracle_lib.Oracle(_geom(), 0, 0, 0, [0.3], [-0.2], [0.7])
+    a = o.deflect_direct(th)
+    d = th - np.array([0.3, -0.2])
+    ref = 0.7 * d / (d ** 2).sum(axis=1, keepdims=True)
+    np.testing.assert_allclose(a, ref, rtol=1e-14, atol=1e-15)
+
+
+# ------------------------------------------------------------ counting, mean mu
+
+
+def _rect_lenses(seed, n, hx, hy):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (rng.random(n) * 2 - 1) * hx, (rng.random(n) * 2 - 1) * hy, np.ones(n)
+
+
+def test_mean_magnification_and_protection_zone(oracle_lib):
+    """Sec. 3.1: lenses plus the compensating sheet leave the mean macro
+    magnification 1/|lt lr|; a protection zone of 10 sqrt(kappa_star) brings the
+    map to ~98% of it.  Without the zone the loss at the edges is larger."""
+    lt, lr, ks, side = 0.3, 0.5, 0.05, 40.0
+    kappa, gamma = 1 - 0.5 * (lt + lr), 0.5 * (lr - lt)
+    wbig = 60 * math.sqrt(ks)
+    hx, hy = (side + 2 * wbig) / lt / 2, (side + 2 * wbig) / lr / 2
+    n = int(round(ks * 4 * hx * hy / math.pi))
+    rel = {0.0: [], 10.0: []}
+    for seed in range(4):
+        x, y, m = _rect_lenses(seed, n, hx, hy)
+        ks_eff = math.pi * m.sum() / (4 * hx * hy)
+        for wm in rel:
+            g = derive_geometry(side, side, 100, 100, kappa, gamma, ks, n_rays=1e7, scheme=1,
+                                coarse=64, protect=wm * math.sqrt(ks))
+            o = oracle_lib.Oracle(g, kappa, gamma, ks_eff, x, y, m)
+            counts, n_out = o.shoot()
+            assert int(counts.sum()) + n_out == g.ray_nx * g.ray_ny
+            rel[wm].append(counts.mean() * o.mu_factor() * lt * lr - 1.0)
+    with_zone, without = np.mean(rel[10.0]), np.mean(rel[0.0])
+    assert -0.04 < with_zone < 0.0
+    assert without < with_zone - 0.01
+
+
+# ----------------------------------------------------------- interpolated scheme
+
+
+def test_interp_equals_direct_when_all_lenses_near(oracle_lib):
+    """Eq. 9 with every lens near: alpha_far = 0 and the interpolated map is the
+    direct map, bit for bit."""
+    rng = np.random.default_rng(3)
+    n = 40
+    x, y, m = rng.uniform(-60, 60, n), rng.uniform(-4, 4, n), rng.uniform(0.1, 1.0, n)
+    gd = _geom(ray_nx=256, ray_ny=256, ray_dx=200 / 256, ray_dy=10 / 1.05 / 256)
+    gi = _geom(ray_nx=256, ray_ny=256, ray_dx=200 / 256, ray_dy=10 / 1.05 / 256, scheme=1,
+               coarse=64, l1_kx=1, l1_ky=1, halo=1000, terms=4)
+    cd, od = oracle_lib.Oracle(gd, 0.45, 0.5, 0.01, x, y, m).shoot()
+    ci, oi = oracle_lib.Oracle(gi, 0.45, 0.5, 0.01, x, y, m).shoot()
+    np.testing.assert_array_equal(cd, ci)
+    assert od == oi
+
+
+def _interp_geom(P=4, R=64, K=1, n=256, side=4.0):
+    return OracleGeometry(src_x0=-5, src_y0=-5, src_dx=10 / 64, src_dy=10 / 64, src_nx=64,
+                          src_ny=64, ray_x0=-side / 2, ray_y0=-side / 2, ray_dx=side / n,
+                          ray_dy=side / n, ray_nx=n, ray_ny=n, scheme=1, coarse=R, l1_kx=K,
+                          l1_ky=K, halo=1, terms=P)
+
+
+def test_single_far_lens_coefficients(oracle_lib):
+    """Sec. 3.2.2: for one far lens, a_n = -m / (z_k - z_c)^(n+1)."""
+    g = _interp_geom()
+    zk = complex(7.3, -5.1)
+    o = oracle_lib.Oracle(g, 0, 0, 0, [zk.real], [zk.imag], [0.6])
+    for ci, cj in [(0, 0), (2, 1), (3, 3)]:
+        zc = complex(g.ray_x0 + (ci + 0.5) * g.coarse * g.ray_dx,
+                     g.ray_y0 + (cj + 0.5) * g.coarse * g.ray_dy)
+        a = o.coeffs(ci, cj)
+        ref = np.array([-0.6 / (zk - zc) ** (k + 1) for k in range(g.terms)])
+        np.testing.assert_allclose(a, ref, rtol=1e-13)
+
+
+def test_single_far_lens_remainder(oracle_lib):
+    """The truncated series leaves the geometric remainder
+    conj(alpha_far) - sum_{n<P} a_n d^n = -(m/w)(d/w)^P / (1 - d/w), w = z_k - z_c,
+    and the error falls by the factor rho = |d/w| per extra term."""
+    zk, m = complex(6.1, 4.7), 0.8
+    rng = np.random.default_rng(11)
+    errs = {}
+    for P in (2, 3, 4, 5):
+        g = _interp_geom(P=P)
+        o = oracle_lib.Oracle(g, 0, 0, 0, [zk.real], [zk.imag], [m])
+        th = rng.uniform(-2, 2, size=(200, 2))
+        ai = o.deflect(th)
+        ad = o.deflect_direct(th)
+        ci = np.floor((th[:, 0] - g.ray_x0) / (g.coarse * g.ray_dx))
+        cj = np.floor((th[:, 1] - g.ray_y0) / (g.coarse * g.ray_dy))
+        zc = (g.ray_x0 + (ci + 0.5) * g.coarse * g.ray_dx) + 1j * (
+            g.ray_y0 + (cj + 0.5) * g.coarse * g.ray_dy)
+        z = th[:, 0] + 1j * th[:, 1]
+        w, d = zk - zc, z - zc
+        rem = -(m / w) * (d / w) ** P / (1 - d / w)
+        got = (ai[:, 0] - ad[:, 0]) - 1j * (ai[:, 1] - ad[:, 1])  # conj(alpha_i - alpha_d)
+        np.testing.assert_allclose(got, -rem, rtol=1e-6, atol=1e-15)
+        errs[P] = np.abs(rem).max()
+    for P in (2, 3, 4):
+        assert errs[P + 1] < errs[P] * 0.6
+
+
+def test_tiny_brute_force_interp_vs_direct(oracle_lib):
+    """Brute force on a tiny field: per ray, |alpha_interp - alpha_direct| is
+    bounded by the far-lens remainder sum and stays below 1e-4 theta_E when the
+    level-2 cell is 1/8 of the level-1 cell."""
+    g = _interp_geom(P=4, R=8, K=8, n=512, side=16.0)
+    rng = np.random.default_rng(5)
+    n = 10
+    x = np.concatenate([rng.uniform(-8, 8, 4), rng.uniform(-30, 30, 6)])
+    y = np.concatenate([rng.uniform(-8, 8, 4), rng.uniform(-30, 30, 6)])
+    m = rng.uniform(0.1, 1.0, n)
+    o = oracle_lib.Oracle(g, 0.45, 0.5, 0.01, x, y, m)
+    ii, jj = np.meshgrid(np.arange(0, 512, 7), np.arange(0, 512, 9))
+    ii, jj = ii.ravel(), jj.ravel()
+    th = np.stack([g.ray_x0 + (ii + 0.5) * g.ray_dx, g.ray_y0 + (jj + 0.5) * g.ray_dy], axis=1)
+    err = np.hypot(*(o.deflect(th) - o.deflect_direct(th)).T)
+    bound = np.zeros(len(ii))
+    for t in range(len(ii)):
+        ci, cj = ii[t] // g.coarse, jj[t] // g.coarse
+        far = ~o.near_mask(ci, cj)
+        zc = complex(g.ray_x0 + (ci + 0.5) * g.coarse * g.ray_dx,
+                     g.ray_y0 + (cj + 0.5) * g.coarse * g.ray_dy)
+        d = complex(*th[t]) - zc
+        wk = (x[far] + 1j * y[far]) - zc
+        rho = abs(d) / np.abs(wk)
+        assert rho.max() < 1
+        bound[t] = (m[far] * rho ** g.terms / (np.abs(wk) * (1 - rho))).sum()
+    assert np.all(err <= bound * (1 + 1e-9) + 1e-13)
+    assert err.max() < 1e-4
+
+
+def test_near_set_is_3x3_block(oracle_lib):
+    """Sec. 3.2.1 (our reading, H = 1): near lenses are those in the 3x3 block of
+    level-1 cells around the ray's level-1 cell."""
+    g = _interp_geom(P=4, R=64, K=2, n=512)   # level-1 cell = 128 rays = 1 theta_E
+    L1 = g.coarse * g.l1_kx * g.ray_dx
+    xs, ys = np.meshgrid(np.arange(-4, 8) + 0.5, np.arange(-4, 8) + 0.5)
+    x = g.ray_x0 + xs.ravel() * L1
+    y = g.ray_y0 + ys.ravel() * L1
+    o = oracle_lib.Oracle(g, 0, 0, 0, x, y, np.ones(x.size))
+    for ci, cj in [(0, 0), (3, 5), (7, 7)]:
+        near = o.near_mask(ci, cj)
+        I, J = ci // g.l1_kx, cj // g.l1_ky
+        expect = (np.abs(np.floor(xs.ravel()) - I) <= 1) & (np.abs(np.floor(ys.ravel()) - J) <= 1)
+        np.testing.assert_array_equal(near, expect)
+        assert near.sum() == 9
+
+
+# ------------------------------------------------------ additivity and symmetry
+
+
+def test_additivity_over_sub_rectangles(oracle_lib):
+    """Counts are additive over disjoint ray sets (exact, integer)."""
+    rng = np.random.default_rng(2)
+    x, y, m = rng.uniform(-3, 3, 30), rng.uniform(-3, 3, 30), rng.uniform(0.1, 1, 30)
+    g = _interp_geom(P=4, R=64, K=1, n=320)
+    o = oracle_lib.Oracle(g, 0.45, 0.5, 0.01, x, y, m)
+    full, nf = o.shoot()
+    a, na = o.shoot(0, 0, 320, 130)
+    b, nb = o.shoot(0, 130, 200, 190)
+    c, nc = o.shoot(200, 130, 120, 190)
+    np.testing.assert_array_equal(full, a + b + c)
+    assert nf == na + nb + nc
+
+
+def test_mirror_symmetry(oracle_lib):
+    """Reflecting the lens field x -> -x reflects the map p -> Nx-1-p
+    (direct scheme, lattice and map symmetric about x = 0)."""
+    rng = np.random.default_rng(9)
+    n = 60
+    x, y, m = rng.uniform(-80, 80, n), rng.uniform(-6, 6, n), rng.uniform(0.1, 1, n)
+    g = _geom(ray_nx=1024, ray_ny=512, ray_dy=10 / 1.05 / 512)
+    c1, n1 = oracle_lib.Oracle(g, 0.45, 0.5, 0.01, x, y, m).shoot()
+    c2, n2 = oracle_lib.Oracle(g, 0.45, 0.5, 0.01, -x, y, m).shoot()
+    diff = np.abs(c1.astype(np.int64) - c2[:, ::-1].astype(np.int64)).sum()
+    assert diff <= 1e-6 * g.ray_nx * g.ray_ny
+    assert abs(n1 - n2) <= 1e-6 * g.ray_nx * g.ray_ny
+    # and it is not trivially symmetric
+    assert np.abs(c1.astype(np.int64) - c1[:, ::-1].astype(np.int64)).sum() > 1000
+
+
+def test_trace_agrees_with_shoot(oracle_lib):
+    """Per-ray pixels from lmo_trace rebuild the shot map."""
+    rng = np.random.default_rng(4)
+    x, y, m = rng.uniform(-3, 3, 20), rng.uniform(-3, 3, 20), rng.uniform(0.1, 1, 20)
+    g = _interp_geom(P=4, R=64, K=1, n=128)
+    o = oracle_lib.Oracle(g, 0.45, 0.5, 0.01, x, y, m)
+    counts, n_out = o.shoot()
+    ii, jj = np.meshgrid(np.arange(128), np.arange(128))
+    _, pix = o.trace(ii.ravel(), jj.ravel())
+    rebuilt = np.bincount(pix[pix >= 0], minlength=64 * 64).reshape(64, 64)
+    np.testing.assert_array_equal(rebuilt, counts)
+    assert (pix < 0).sum() == n_out
