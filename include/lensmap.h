@@ -1,0 +1,223 @@
+/*
+ * lensmap.h -- C ABI of liblensmap: inverse ray-shooting of microlensing
+ * magnification maps near a critical curve on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Sec. 2 and Sec. 3 of the paper): a regular lattice of
+ * image-plane rays is mapped to the source plane by the lens equation with a
+ * constant macro Jacobian diag(1-kappa-gamma, 1-kappa+gamma) (Eq. 1), point-mass
+ * microlenses and a compensating negative mass sheet of density kappa_star
+ * (Eq. 6):
+ *     beta = (diag(1-kappa-gamma, 1-kappa+gamma) + kappa_star) theta - alpha(theta),
+ *     alpha(theta) = sum_k m_k (theta - theta_k) / |theta - theta_k|^2 .
+ * The sheet is infinite and uniform about the origin of the coordinates.  Each
+ * ray is counted into the source-plane pixel it lands in; mu_pq = N_pq S_I/S_S
+ * (Eq. 12).  The deflection is either the direct sum over all lenses or the
+ * paper's interpolated scheme (Eq. 9, Sec. 3.2.1-3.2.3): lenses in the 3x3
+ * block of level-1 cells around the ray's level-1 cell are summed directly,
+ * all others enter through P complex Taylor coefficients of the ray's level-2
+ * cell (P = 4: the eight real coefficients of Sec. 3.2.2).
+ *
+ * All lengths are in Einstein radii of a unit mass (Eq. 7).
+ *
+ * Conventions shared by every call:
+ *  - every call returns an lm_status and never aborts or throws; on failure
+ *    lm_last_error() describes the cause (thread-local, valid until the next
+ *    call on the same thread);
+ *  - input arrays are copied before the call returns; the caller keeps
+ *    ownership of every buffer it passes;
+ *  - a map lives on the HIP device that was current when it was created and
+ *    uses it for every later call;
+ *  - "stream" arguments are hipStream_t passed as void*; NULL is the default
+ *    stream.  Calls that take a stream are asynchronous on it; calls that do
+ *    not are synchronous;
+ *  - calls on one map must not overlap from several threads.
+ */
+#ifndef LENSMAP_H
+#define LENSMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lm_status;
+#define LM_OK 0
+#define LM_EINVAL (-1)        /* bad argument (NaN/Inf, non-positive size, ...) */
+#define LM_ENOMEM (-2)        /* host or device allocation failed */
+#define LM_EDEVICE (-3)       /* a HIP call failed */
+#define LM_ESTATE (-4)        /* call not allowed in the current state */
+#define LM_ERANGE (-5)        /* index range outside the lattice or map */
+#define LM_EUNSUPPORTED (-6)  /* valid request this build does not handle */
+
+#define LM_SCHEME_DIRECT 0    /* every lens summed for every ray */
+#define LM_SCHEME_INTERP 1    /* near lenses direct, far lenses by Taylor coefficients */
+
+#define LM_PREC_MIXED 0       /* rebased FP32 lens sums, FP64 bases and binning */
+#define LM_PREC_FP32 1        /* plain FP32 in global coordinates (comparison path) */
+
+#define LM_MAX_TERMS 7        /* largest supported P */
+
+/*
+ * Geometry of one map.  Source pixel (p, q) covers
+ *   [src_x0 + p src_dx, src_x0 + (p+1) src_dx) x [src_y0 + q src_dy, src_y0 + (q+1) src_dy);
+ * ray (i, j), 0 <= i < ray_nx, 0 <= j < ray_ny, sits at the centre of
+ * level-3 pixel (i, j): (ray_x0 + (i+1/2) ray_dx, ray_y0 + (j+1/2) ray_dy)
+ * (Sec. 3.2.3).  A level-2 cell is a coarse x coarse block of rays (coarse a
+ * multiple of 64); a level-1 cell is l1_kx x l1_ky level-2 cells; near lenses
+ * lie within near_halo level-1 cells of the ray's level-1 cell (1: the 3x3
+ * block).  A lens belongs to level-1 cell
+ *   (floor((x - ray_x0) / (ray_dx * coarse * l1_kx)),
+ *    floor((y - ray_y0) / (ray_dy * coarse * l1_ky))).
+ * For the direct scheme `coarse` is the size of the blocks of rays that share
+ * one FP64 origin for their FP32 arithmetic; l1_*, near_halo, taylor_terms are
+ * ignored.
+ */
+typedef struct lm_geometry {
+    double src_x0, src_y0, src_dx, src_dy;
+    int32_t src_nx, src_ny;
+    double ray_x0, ray_y0, ray_dx, ray_dy;
+    int64_t ray_nx, ray_ny;
+    int32_t scheme;        /* LM_SCHEME_* */
+    int32_t precision;     /* LM_PREC_* */
+    int32_t coarse;        /* R: rays per level-2 cell side, multiple of 64 */
+    int32_t l1_kx, l1_ky;  /* level-2 cells per level-1 cell side */
+    int32_t near_halo;     /* H */
+    int32_t taylor_terms;  /* P, 1..LM_MAX_TERMS (interpolated scheme) */
+    int32_t reserved;
+} lm_geometry;
+
+/*
+ * Derive a geometry from the paper's rules (Sec. 3.1, Sec. 3.2, Eq. 8, 10, 11):
+ *  - the source square s = [-src_lx/2, src_lx/2] x [-src_ly/2, src_ly/2] is
+ *    split into src_nx x src_ny pixels;
+ *  - the protection zone widens s by `protect` on every side (protect < 0:
+ *    10 sqrt(kappa_star), Sec. 3.1);
+ *  - the shooting region is the preimage of the widened region under
+ *    diag(1-kappa-gamma, 1-kappa+gamma), centred on the origin;
+ *  - if ray_nx > 0 and ray_ny > 0 they are used as given, otherwise
+ *    L3 = sqrt(L_ix L_iy / n_rays) (Eq. 11), ray_nx = round(L_ix / L3),
+ *    ray_ny = round(L_iy / L3); the spacings are then L_ix/ray_nx, L_iy/ray_ny;
+ *  - level-1 sides min(L0, L_ix/10) and min(L0, L_iy/10) with
+ *    L0 = sqrt(pi <m> / kappa_star) (Eq. 10, N_star of Sec. 3.1 with mean mass <m>);
+ *  - coarse = R given (> 0), or 64 * max(1, round(min(L1x/L3x, L1y/L3y)/20/64))
+ *    (level-2 = level-1/20, Sec. 3.2.2);
+ *    l1_kx = max(1, round(L1x / (R L3x))), l1_ky likewise;
+ *  - near_halo = 1, taylor_terms = 4, precision = LM_PREC_MIXED.
+ * Rounding is half away from zero.  Returns LM_EINVAL for non-finite or
+ * non-positive inputs or a singular macro map.
+ */
+lm_status lm_geometry_derive(lm_geometry* g, double src_lx, double src_ly, int32_t src_nx,
+                             int32_t src_ny, double kappa, double gamma, double kappa_star,
+                             double protect, double n_rays, int64_t ray_nx, int64_t ray_ny,
+                             int32_t scheme, int32_t coarse, double mean_mass);
+
+typedef struct lm_map lm_map;
+typedef struct lm_batch lm_batch;
+
+/* Create a map with the given geometry on the current HIP device.  Counts
+ * start at zero; the macro model is kappa = gamma = kappa_star = 0 and there
+ * are no lenses until set.  LM_EINVAL for an invalid geometry (non-positive
+ * sizes, coarse not a positive multiple of 64, more than 2^31 rays per
+ * workgroup tile, P outside 1..LM_MAX_TERMS, src_nx*src_ny >= 2^31). */
+lm_status lm_create(const lm_geometry* g, lm_map** out);
+
+/* Release every resource of the map (NULL is ignored).  Waits for the map's
+ * outstanding work first. */
+void lm_destroy(lm_map* m);
+
+/* Macro convergence kappa, shear gamma and star convergence kappa_star of the
+ * compensating sheet (Eq. 1, Eq. 6).  LM_ESTATE if the map has counts. */
+lm_status lm_set_macro(lm_map* m, double kappa, double gamma, double kappa_star);
+
+/* Copy n lenses: positions (x[k], y[k]) and masses mass[k] > 0.  n may be 0.
+ * Sorts them by level-1 cell on the host and uploads them.  LM_EINVAL for
+ * non-finite values or non-positive masses, LM_ESTATE if the map has counts. */
+lm_status lm_set_lenses(lm_map* m, const double* x, const double* y, const double* mass,
+                        int64_t n);
+
+/* Use a caller-owned device buffer of src_nx*src_ny uint64 counts (row-major,
+ * index q*src_nx + p) instead of the map's own; the buffer must outlive the map
+ * or the next lm_bind_counts.  Its contents are taken as the current counts
+ * (the caller clears it).  NULL returns to the map's own buffer. */
+lm_status lm_bind_counts(lm_map* m, uint64_t* device_counts);
+
+/* Compute the level-2 Taylor coefficients of the far lenses (Sec. 3.2.2) for
+ * every level-2 cell of the lattice.  lm_shoot does this on its own when the
+ * coefficients are stale; this call forces a recomputation. No-op for the
+ * direct scheme. Asynchronous on `stream`. */
+lm_status lm_prepare(lm_map* m, void* stream);
+
+/* Shoot the rays of the lattice sub-rectangle [i0, i0+ni) x [j0, j0+nj) and add
+ * them to the counts (Sec. 3.2.3): rays landing outside the map are added to
+ * n_out.  ni or nj = 0 is a no-op.  LM_ERANGE if the rectangle leaves the
+ * lattice.  Asynchronous on `stream`. */
+lm_status lm_shoot(lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj, void* stream);
+
+/* Wait for all work issued on the map. */
+lm_status lm_sync(lm_map* m);
+
+/* Copy the counts (src_nx*src_ny uint64, may be NULL), the number of rays that
+ * left the map and the number of rays shot so far (either may be NULL) to the
+ * host (Sec. 3.2.3: counts transferred to the CPU).  Synchronous. */
+lm_status lm_read_counts(lm_map* m, uint64_t* host_counts, uint64_t* n_out, uint64_t* n_shot);
+
+/* Magnification of one ray count: (ray_dx ray_dy) / (src_dx src_dy) (Eq. 12). */
+lm_status lm_mu_factor(const lm_map* m, double* factor);
+
+/* Magnification map mu[q*src_nx + p] = counts * factor (Eq. 12), on the host.
+ * Synchronous. */
+lm_status lm_read_mu(lm_map* m, double* host_mu);
+
+/* Zero the counts, n_out and the number of rays shot. Asynchronous on `stream`. */
+lm_status lm_reset_counts(lm_map* m, void* stream);
+
+/* Deflection alpha(theta) of the map's scheme and precision at n positions
+ * theta_xy[2t], theta_xy[2t+1] (FP64, host), written to alpha_xy (host).  Uses
+ * the same device arithmetic as the shooting kernel, with theta rebased on
+ * the level-2 cell that contains it.  Synchronous; a test probe. */
+lm_status lm_deflect(lm_map* m, const double* theta_xy, int64_t n, double* alpha_xy);
+
+/* Pixels of listed lattice rays (i[t], j[t]): p[t], q[t] as the shooting
+ * kernel computes them, -1 in both for rays that land outside the map.
+ * Synchronous; a test probe.  LM_ERANGE for a ray outside the lattice. */
+lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int32_t* p,
+                   int32_t* q);
+
+/* Batched execution (80-map study, Sec. 4.2): the maps (same scheme,
+ * precision and taylor_terms, same device, all with lenses) are shot together
+ * by one persistent kernel fed from a work queue, preceded by their coefficient
+ * kernels, captured once as a HIP graph.  Each map's shot rectangle is the one
+ * given by lm_batch_set_rect (default: its whole lattice).  The batch keeps
+ * pointers to the maps; they must outlive it and must not be changed
+ * (lenses, macro, bound counts) while it exists. */
+lm_status lm_batch_create(lm_map* const* maps, int32_t n, lm_batch** out);
+lm_status lm_batch_set_rect(lm_batch* b, int32_t index, int64_t i0, int64_t j0, int64_t ni,
+                            int64_t nj);
+
+/* Pick execution parameters (rays per lane, workgroup tile size, workgroups
+ * per CU) by timing candidates on a sample of the batch's work; counts are
+ * restored to zero afterwards.  Results never depend on the choice.  The choice
+ * is cached as JSON at cache_path (NULL: no cache) keyed by device and batch
+ * shape.  Synchronous. */
+lm_status lm_batch_tune(lm_batch* b, const char* cache_path);
+
+/* Shoot every map's rectangle once (one graph launch). Asynchronous on `stream`. */
+lm_status lm_batch_shoot(lm_batch* b, void* stream);
+
+/* Execution parameters in use: rays per lane, level-2 cells per workgroup tile
+ * side, workgroups per CU (any pointer may be NULL). */
+lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* tile_cells,
+                          int32_t* wg_per_cu);
+void lm_batch_destroy(lm_batch* b);
+
+/* Description of the last failure on this thread ("" if none). */
+const char* lm_last_error(void);
+
+/* Library version string. */
+const char* lm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LENSMAP_H */

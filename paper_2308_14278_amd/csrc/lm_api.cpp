@@ -1,0 +1,1021 @@
+// lm_api.cpp -- host side of liblensmap: C ABI, geometry rules, lens
+// partition into level-1 cells, device buffers, launches, batching and the
+// execution-parameter tuner.  The kernels live in lm_kernels.hip.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/lensmap.h"
+#include "lm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lm_status fail(lm_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+lm_status ok()
+{
+    g_err.clear();
+    return LM_OK;
+}
+
+#define HIP_TRY(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(LM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+#define LAUNCH_TRY(expr)                                                                 \
+    do {                                                                                 \
+        int e_ = (expr);                                                                 \
+        if (e_ != 0)                                                                     \
+            return fail(LM_EDEVICE, "%s failed: %s", #expr,                             \
+                        hipGetErrorString((hipError_t)e_));                              \
+    } while (0)
+
+bool isfin(double v) { return std::isfinite(v); }
+
+int64_t round_half_away(double x) { return x >= 0 ? (int64_t)std::floor(x + 0.5) : -(int64_t)std::floor(-x + 0.5); }
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device buffer owned by a map or batch.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        if (n == 0) return hipSuccess;
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess) bytes = n;
+        return e;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+lm_status validate_geometry(const lm_geometry* g)
+{
+    if (!g) return fail(LM_EINVAL, "geometry is NULL");
+    const double v[] = {g->src_x0, g->src_y0, g->src_dx, g->src_dy,
+                        g->ray_x0, g->ray_y0, g->ray_dx, g->ray_dy};
+    for (double x : v)
+        if (!isfin(x)) return fail(LM_EINVAL, "geometry has a non-finite value");
+    if (!(g->src_dx > 0 && g->src_dy > 0 && g->ray_dx > 0 && g->ray_dy > 0))
+        return fail(LM_EINVAL, "pixel and ray spacings must be positive");
+    if (g->src_nx <= 0 || g->src_ny <= 0) return fail(LM_EINVAL, "source map must have pixels");
+    if ((int64_t)g->src_nx * g->src_ny >= (int64_t(1) << 31))
+        return fail(LM_EINVAL, "source map too large (src_nx*src_ny must be < 2^31)");
+    if (g->ray_nx <= 0 || g->ray_ny <= 0) return fail(LM_EINVAL, "ray lattice must be non-empty");
+    if (g->scheme != LM_SCHEME_DIRECT && g->scheme != LM_SCHEME_INTERP)
+        return fail(LM_EINVAL, "unknown scheme %d", g->scheme);
+    if (g->precision != LM_PREC_MIXED && g->precision != LM_PREC_FP32)
+        return fail(LM_EINVAL, "unknown precision %d", g->precision);
+    if (g->coarse <= 0 || g->coarse % 64 != 0 || g->coarse > (1 << 15))
+        return fail(LM_EINVAL, "coarse must be a positive multiple of 64 (at most 32768), got %d",
+                    g->coarse);
+    if (g->scheme == LM_SCHEME_INTERP) {
+        if (g->l1_kx <= 0 || g->l1_ky <= 0) return fail(LM_EINVAL, "l1_kx, l1_ky must be positive");
+        if (g->near_halo < 0 || g->near_halo > 64) return fail(LM_EINVAL, "near_halo must be in 0..64");
+        if (g->taylor_terms < 1 || g->taylor_terms > LM_MAX_TERMS)
+            return fail(LM_EINVAL, "taylor_terms must be in 1..%d", LM_MAX_TERMS);
+    }
+    const int64_t ncx = ceil_div(g->ray_nx, g->coarse), ncy = ceil_div(g->ray_ny, g->coarse);
+    if (ncx > (int64_t(1) << 40) / std::max<int64_t>(ncy, 1))
+        return fail(LM_EINVAL, "lattice too large");
+    return LM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== map
+
+struct lm_map {
+    lm_geometry g{};
+    int device = 0;
+    double kappa = 0, gamma = 0, kappa_star = 0;
+    int64_t nlens = 0;
+    // derived
+    int64_t ncx = 0, ncy = 0, n1x = 0, n1y = 0;
+    int nl1x = 0, nl1y = 0;
+    // device buffers
+    DevBuf lx, ly, lmd, lxf, lyf, lmf, lI, lJ, cell_start, coef, counts_own, n_out;
+    uint64_t* counts = nullptr;  // own or bound
+    bool bound = false;
+    bool coef_valid = false;
+    bool has_counts = false;
+    uint64_t n_shot = 0;
+    hipStream_t last = nullptr;
+    int rays_per_lane = 8;
+};
+
+namespace {
+
+lm_status use_device(const lm_map* m)
+{
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != m->device) HIP_TRY(hipSetDevice(m->device));
+    return LM_OK;
+}
+
+// Work decomposition of a tile: cells per side, column chunks, window.
+struct Exec {
+    int G = 1, ncc = 1, cw = 64, wx = 64, wy = 64;
+};
+
+Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scale)
+{
+    const lm_geometry& g = m->g;
+    Exec e;
+    const int R = g.coarse;
+    int G = std::max(1, 512 / R) * std::max(1, g_scale);
+    // keep enough tiles to fill the device, and tile ray counts well below 2^32
+    while (G > 1 && ceil_div(ncells_x, G) * ceil_div(ncells_y, G) < 4096) G /= 2;
+    while (G > 1 && (double)G * G * R * R > 1.0e9) G /= 2;
+    e.G = G;
+    const int nrb = R / 64;
+    int ncc = 1;
+    while ((G * G * nrb * ncc) % LM_WAVES != 0) ncc *= 2;
+    e.ncc = ncc;
+    e.cw = (int)ceil_div(R, ncc);
+    const double mx = std::fabs(1.0 - m->kappa - m->gamma + m->kappa_star);
+    const double my = std::fabs(1.0 - m->kappa + m->gamma + m->kappa_star);
+    const double ext_x = (double)G * R * g.ray_dx * mx / g.src_dx;
+    const double ext_y = (double)G * R * g.ray_dy * my / g.src_dy;
+    int wx = 8;
+    while (wx < 512 && wx < ext_x + 16) wx *= 2;
+    int wy = LM_WIN_MAX / wx;
+    while (wy < ext_y + 16 && wx > 8 && ext_x + 16 < wx / 2) {
+        wx /= 2;
+        wy = LM_WIN_MAX / wx;
+    }
+    e.wx = wx;
+    e.wy = wy;
+    return e;
+}
+
+void split_ff(double v, float& hi, float& lo)
+{
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+LmDesc make_desc(const lm_map* m, int64_t i0, int64_t j0, int64_t i1, int64_t j1, const Exec& e)
+{
+    const lm_geometry& g = m->g;
+    LmDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.x0 = g.ray_x0;
+    d.y0 = g.ray_y0;
+    d.dx = g.ray_dx;
+    d.dy = g.ray_dy;
+    d.mx = 1.0 - m->kappa - m->gamma + m->kappa_star;
+    d.my = 1.0 - m->kappa + m->gamma + m->kappa_star;
+    d.bx0 = g.src_x0;
+    d.by0 = g.src_y0;
+    d.inv_sdx = 1.0 / g.src_dx;
+    d.inv_sdy = 1.0 / g.src_dy;
+    split_ff(0.5 * g.ray_dx, d.hxh, d.hxl);
+    split_ff(0.5 * g.ray_dy, d.hyh, d.hyl);
+    d.x0f = (float)g.ray_x0;
+    d.y0f = (float)g.ray_y0;
+    d.dxf = (float)g.ray_dx;
+    d.dyf = (float)g.ray_dy;
+    d.mxf = (float)d.mx;
+    d.myf = (float)d.my;
+    d.bx0f = (float)g.src_x0;
+    d.by0f = (float)g.src_y0;
+    d.inv_sdxf = (float)d.inv_sdx;
+    d.inv_sdyf = (float)d.inv_sdy;
+    d.snx = g.src_nx;
+    d.sny = g.src_ny;
+    d.R = g.coarse;
+    d.Kx = g.scheme == LM_SCHEME_INTERP ? g.l1_kx : 1;
+    d.Ky = g.scheme == LM_SCHEME_INTERP ? g.l1_ky : 1;
+    d.H = g.scheme == LM_SCHEME_INTERP ? g.near_halo : 0;
+    d.G = e.G;
+    d.ncc = e.ncc;
+    d.cw = e.cw;
+    d.nrb = g.coarse / 64;
+    d.wx = e.wx;
+    d.wy = e.wy;
+    d.nl1x = m->nl1x;
+    d.nl1y = m->nl1y;
+    d.nx = g.ray_nx;
+    d.ny = g.ray_ny;
+    d.i0 = i0;
+    d.j0 = j0;
+    d.i1 = i1;
+    d.j1 = j1;
+    d.ncx = m->ncx;
+    d.ncy = m->ncy;
+    if (i1 > i0 && j1 > j0) {
+        const int64_t ci_lo = i0 / g.coarse, ci_hi = (i1 - 1) / g.coarse;
+        const int64_t cj_lo = j0 / g.coarse, cj_hi = (j1 - 1) / g.coarse;
+        d.tcx0 = ci_lo / e.G;
+        d.tcy0 = cj_lo / e.G;
+        d.ntx = ci_hi / e.G - d.tcx0 + 1;
+        d.nty = cj_hi / e.G - d.tcy0 + 1;
+        d.ntiles = d.ntx * d.nty;
+    }
+    d.nlens = m->nlens;
+    d.lx = m->lx.as<double>();
+    d.ly = m->ly.as<double>();
+    d.lmd = m->lmd.as<double>();
+    d.lxf = m->lxf.as<float>();
+    d.lyf = m->lyf.as<float>();
+    d.lmf = m->lmf.as<float>();
+    d.lI = m->lI.as<int32_t>();
+    d.lJ = m->lJ.as<int32_t>();
+    d.cell_start = m->cell_start.as<int32_t>();
+    d.coef = m->coef.as<LmCoef>();
+    d.counts = reinterpret_cast<unsigned long long*>(m->counts);
+    d.n_out = m->n_out.as<unsigned long long>();
+    return d;
+}
+
+lm_status ensure_coef(lm_map* m)
+{
+    if (m->g.scheme != LM_SCHEME_INTERP) return LM_OK;
+    if (m->coef.ensure((size_t)(m->ncx * m->ncy) * sizeof(LmCoef)) != hipSuccess)
+        return fail(LM_ENOMEM, "cannot allocate %lld level-2 coefficient records",
+                    (long long)(m->ncx * m->ncy));
+    return LM_OK;
+}
+
+lm_status prepare(lm_map* m, hipStream_t s)
+{
+    if (m->g.scheme != LM_SCHEME_INTERP) return LM_OK;
+    if (m->ncx * m->ncy >= (int64_t(1) << 30))
+        return fail(LM_EUNSUPPORTED, "more than 2^30 level-2 cells");
+    lm_status st = ensure_coef(m);
+    if (st) return st;
+    LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
+    LAUNCH_TRY(lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
+                                m->coef.as<LmCoef>(), s));
+    m->coef_valid = true;
+    m->last = s;
+    return LM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lm_last_error(void) { return g_err.c_str(); }
+
+const char* lm_version(void) { return "lensmap 0.1 (gfx950)"; }
+
+lm_status lm_geometry_derive(lm_geometry* g, double src_lx, double src_ly, int32_t src_nx,
+                             int32_t src_ny, double kappa, double gamma, double kappa_star,
+                             double protect, double n_rays, int64_t ray_nx, int64_t ray_ny,
+                             int32_t scheme, int32_t coarse, double mean_mass)
+{
+    if (!g) return fail(LM_EINVAL, "g is NULL");
+    if (!(isfin(src_lx) && isfin(src_ly) && isfin(kappa) && isfin(gamma) &&
+          isfin(kappa_star) && isfin(protect) && isfin(mean_mass)))
+        return fail(LM_EINVAL, "non-finite input");
+    if (!(src_lx > 0 && src_ly > 0) || src_nx <= 0 || src_ny <= 0)
+        return fail(LM_EINVAL, "source region and pixels must be positive");
+    if (kappa_star < 0 || !(mean_mass > 0)) return fail(LM_EINVAL, "bad kappa_star or mean mass");
+    if (scheme != LM_SCHEME_DIRECT && scheme != LM_SCHEME_INTERP)
+        return fail(LM_EINVAL, "unknown scheme %d", scheme);
+    const double lt = 1.0 - kappa - gamma, lr = 1.0 - kappa + gamma;
+    if (lt == 0.0 || lr == 0.0) return fail(LM_EINVAL, "the mean macro map is singular");
+    // protection zone (Sec. 3.1) and its preimage (the shooting region)
+    const double w = protect < 0 ? 10.0 * std::sqrt(kappa_star) : protect;
+    const double lix = (src_lx + 2.0 * w) / std::fabs(lt);
+    const double liy = (src_ly + 2.0 * w) / std::fabs(lr);
+    if (ray_nx <= 0 || ray_ny <= 0) {
+        if (!(isfin(n_rays) && n_rays >= 1.0)) return fail(LM_EINVAL, "n_rays must be >= 1");
+        const double l3 = std::sqrt(lix * liy / n_rays);  // Eq. 11
+        ray_nx = std::max<int64_t>(1, round_half_away(lix / l3));
+        ray_ny = std::max<int64_t>(1, round_half_away(liy / l3));
+    }
+    std::memset(g, 0, sizeof *g);
+    g->src_x0 = -0.5 * src_lx;
+    g->src_y0 = -0.5 * src_ly;
+    g->src_dx = src_lx / src_nx;
+    g->src_dy = src_ly / src_ny;
+    g->src_nx = src_nx;
+    g->src_ny = src_ny;
+    g->ray_x0 = -0.5 * lix;
+    g->ray_y0 = -0.5 * liy;
+    g->ray_dx = lix / (double)ray_nx;
+    g->ray_dy = liy / (double)ray_ny;
+    g->ray_nx = ray_nx;
+    g->ray_ny = ray_ny;
+    g->scheme = scheme;
+    g->precision = LM_PREC_MIXED;
+    g->near_halo = 1;
+    g->taylor_terms = 4;
+    g->l1_kx = 1;
+    g->l1_ky = 1;
+    int64_t R = coarse;
+    if (scheme == LM_SCHEME_INTERP) {
+        // level-1 sides (Eq. 10), with N_star = L_ix L_iy kappa_star / (pi <m>)
+        const double l0 = kappa_star > 0 ? std::sqrt(M_PI * mean_mass / kappa_star) : INFINITY;
+        const double l1x = std::min(l0, lix / 10.0), l1y = std::min(l0, liy / 10.0);
+        if (R <= 0) {  // level-2 = level-1 / 20 (Sec. 3.2.2)
+            const double l2 = std::min(l1x / 20.0 / g->ray_dx, l1y / 20.0 / g->ray_dy);
+            R = 64 * std::max<int64_t>(1, round_half_away(l2 / 64.0));
+        }
+        g->l1_kx = (int32_t)std::max<int64_t>(1, round_half_away(l1x / ((double)R * g->ray_dx)));
+        g->l1_ky = (int32_t)std::max<int64_t>(1, round_half_away(l1y / ((double)R * g->ray_dy)));
+    } else if (R <= 0) {
+        R = 64;
+    }
+    if (R > (1 << 15)) return fail(LM_EINVAL, "level-2 cells of %lld rays are too large", (long long)R);
+    g->coarse = (int32_t)R;
+    return ok();
+}
+
+lm_status lm_create(const lm_geometry* g, lm_map** out)
+{
+    if (!out) return fail(LM_EINVAL, "out is NULL");
+    *out = nullptr;
+    lm_status st = validate_geometry(g);
+    if (st) return st;
+    std::unique_ptr<lm_map> m(new (std::nothrow) lm_map);
+    if (!m) return fail(LM_ENOMEM, "out of host memory");
+    m->g = *g;
+    HIP_TRY(hipGetDevice(&m->device));
+    m->ncx = ceil_div(g->ray_nx, g->coarse);
+    m->ncy = ceil_div(g->ray_ny, g->coarse);
+    if (g->scheme == LM_SCHEME_INTERP) {
+        m->n1x = ceil_div(m->ncx, g->l1_kx);
+        m->n1y = ceil_div(m->ncy, g->l1_ky);
+        if (m->n1x + 2 * g->near_halo > (1 << 20) || m->n1y + 2 * g->near_halo > (1 << 20) ||
+            (m->n1x + 2 * g->near_halo) * (m->n1y + 2 * g->near_halo) > (int64_t(1) << 28))
+            return fail(LM_EINVAL, "level-1 grid too large");
+        m->nl1x = (int)(m->n1x + 2 * g->near_halo);
+        m->nl1y = (int)(m->n1y + 2 * g->near_halo);
+    }
+    const size_t npix = (size_t)g->src_nx * g->src_ny;
+    if (m->counts_own.ensure(npix * sizeof(uint64_t)) != hipSuccess)
+        return fail(LM_ENOMEM, "cannot allocate %zu counts", npix);
+    if (m->n_out.ensure(sizeof(uint64_t)) != hipSuccess) return fail(LM_ENOMEM, "cannot allocate n_out");
+    m->counts = m->counts_own.as<uint64_t>();
+    LAUNCH_TRY(lm_launch_fill_u64((unsigned long long*)m->counts, (int64_t)npix, 0ull, nullptr));
+    LAUNCH_TRY(lm_launch_fill_u64(m->n_out.as<unsigned long long>(), 1, 0ull, nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    // empty lens set
+    st = lm_set_lenses(m.get(), nullptr, nullptr, nullptr, 0);
+    if (st) return st;
+    *out = m.release();
+    return ok();
+}
+
+void lm_destroy(lm_map* m)
+{
+    if (!m) return;
+    (void)use_device(m);
+    if (m->last) (void)hipStreamSynchronize(m->last);
+    (void)hipDeviceSynchronize();
+    delete m;
+}
+
+lm_status lm_set_macro(lm_map* m, double kappa, double gamma, double kappa_star)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (!(isfin(kappa) && isfin(gamma) && isfin(kappa_star)))
+        return fail(LM_EINVAL, "non-finite macro parameter");
+    if (m->has_counts) return fail(LM_ESTATE, "map has counts; call lm_reset_counts first");
+    m->kappa = kappa;
+    m->gamma = gamma;
+    m->kappa_star = kappa_star;
+    return ok();
+}
+
+lm_status lm_set_lenses(lm_map* m, const double* x, const double* y, const double* mass, int64_t n)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (n < 0) return fail(LM_EINVAL, "negative lens count");
+    if (n > 0 && (!x || !y || !mass)) return fail(LM_EINVAL, "lens arrays are NULL");
+    if (n > (int64_t(1) << 28)) return fail(LM_EINVAL, "too many lenses");
+    if (m->has_counts) return fail(LM_ESTATE, "map has counts; call lm_reset_counts first");
+    for (int64_t k = 0; k < n; ++k)
+        if (!(isfin(x[k]) && isfin(y[k]) && isfin(mass[k]) && mass[k] > 0))
+            return fail(LM_EINVAL, "lens %lld has a non-finite position or a non-positive mass",
+                        (long long)k);
+    lm_status st = use_device(m);
+    if (st) return st;
+    const lm_geometry& g = m->g;
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<int32_t> I(n, 0), J(n, 0);
+    std::vector<int32_t> start;
+    if (g.scheme == LM_SCHEME_INTERP) {
+        // level-1 cell of each lens (Sec. 3.2.1), same FP64 expression as the
+        // lattice definition in lensmap.h
+        const int H = g.near_halo;
+        const double wx = g.ray_dx * (double)((int64_t)g.coarse * g.l1_kx);
+        const double wy = g.ray_dy * (double)((int64_t)g.coarse * g.l1_ky);
+        const double lox = -2.0 * H - 2.0, hix = (double)m->n1x + 2.0 * H + 1.0;
+        const double loy = -2.0 * H - 2.0, hiy = (double)m->n1y + 2.0 * H + 1.0;
+        const int ncell = m->nl1x * m->nl1y;
+        std::vector<int64_t> key(n);
+        std::vector<int64_t> hist((size_t)ncell + 2, 0);
+        for (int64_t k = 0; k < n; ++k) {
+            double fi = std::floor((x[k] - g.ray_x0) / wx);
+            double fj = std::floor((y[k] - g.ray_y0) / wy);
+            fi = std::min(std::max(fi, lox), hix);
+            fj = std::min(std::max(fj, loy), hiy);
+            I[k] = (int32_t)fi;
+            J[k] = (int32_t)fj;
+            const bool in = I[k] >= -H && I[k] < m->n1x + H && J[k] >= -H && J[k] < m->n1y + H;
+            key[k] = in ? (int64_t)(J[k] + H) * m->nl1x + (I[k] + H) : ncell;
+            ++hist[key[k] + 1];
+        }
+        for (int c = 0; c <= ncell; ++c) hist[c + 1] += hist[c];
+        start.assign(hist.begin(), hist.begin() + ncell + 1);
+        std::vector<int64_t> pos(hist.begin(), hist.end());
+        for (int64_t k = 0; k < n; ++k) order[pos[key[k]]++] = k;  // stable counting sort
+    }
+    std::vector<double> sx(n), sy(n), sm(n);
+    std::vector<float> fx(n), fy(n), fm(n);
+    std::vector<int32_t> sI(n), sJ(n);
+    for (int64_t t = 0; t < n; ++t) {
+        const int64_t k = order[t];
+        sx[t] = x[k];
+        sy[t] = y[k];
+        sm[t] = mass[k];
+        fx[t] = (float)x[k];
+        fy[t] = (float)y[k];
+        fm[t] = (float)mass[k];
+        sI[t] = I[k];
+        sJ[t] = J[k];
+    }
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    if (m->lx.ensure(nn * 8) || m->ly.ensure(nn * 8) || m->lmd.ensure(nn * 8) ||
+        m->lxf.ensure(nn * 4) || m->lyf.ensure(nn * 4) || m->lmf.ensure(nn * 4) ||
+        m->lI.ensure(nn * 4) || m->lJ.ensure(nn * 4))
+        return fail(LM_ENOMEM, "cannot allocate lens arrays");
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(m->lx.p, sx.data(), n * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(m->ly.p, sy.data(), n * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(m->lmd.p, sm.data(), n * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(m->lxf.p, fx.data(), n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(m->lyf.p, fy.data(), n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(m->lmf.p, fm.data(), n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(m->lI.p, sI.data(), n * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(m->lJ.p, sJ.data(), n * 4, hipMemcpyHostToDevice));
+    }
+    if (g.scheme == LM_SCHEME_INTERP) {
+        if (m->cell_start.ensure(start.size() * 4))
+            return fail(LM_ENOMEM, "cannot allocate the level-1 index");
+        HIP_TRY(hipMemcpy(m->cell_start.p, start.data(), start.size() * 4, hipMemcpyHostToDevice));
+    }
+    m->nlens = n;
+    m->coef_valid = false;
+    return ok();
+}
+
+lm_status lm_bind_counts(lm_map* m, uint64_t* device_counts)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (device_counts) {
+        m->counts = device_counts;
+        m->bound = true;
+    } else {
+        m->counts = m->counts_own.as<uint64_t>();
+        m->bound = false;
+    }
+    m->has_counts = true;  // contents are the caller's
+    return ok();
+}
+
+lm_status lm_prepare(lm_map* m, void* stream)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    lm_status st = use_device(m);
+    if (st) return st;
+    st = prepare(m, (hipStream_t)stream);
+    if (st) return st;
+    return ok();
+}
+
+lm_status lm_shoot(lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj, void* stream)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (ni < 0 || nj < 0 || i0 < 0 || j0 < 0 || i0 > m->g.ray_nx - ni || j0 > m->g.ray_ny - nj)
+        return fail(LM_ERANGE, "rectangle [%lld,+%lld) x [%lld,+%lld) leaves the %lld x %lld lattice",
+                    (long long)i0, (long long)ni, (long long)j0, (long long)nj,
+                    (long long)m->g.ray_nx, (long long)m->g.ray_ny);
+    if (ni == 0 || nj == 0) return ok();
+    lm_status st = use_device(m);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (!m->coef_valid) {
+        st = prepare(m, s);
+        if (st) return st;
+    }
+    const int64_t R = m->g.coarse;
+    const Exec e = choose_exec(m, (i0 + ni - 1) / R - i0 / R + 1, (j0 + nj - 1) / R - j0 / R + 1, 1);
+    LmDesc d = make_desc(m, i0, j0, i0 + ni, j0 + nj, e);
+    if (d.ntiles > 0x7fffffffLL) return fail(LM_EUNSUPPORTED, "too many workgroup tiles");
+    LAUNCH_TRY(lm_launch_shoot_map(d, m->g.scheme, m->g.precision, m->g.taylor_terms,
+                                   m->rays_per_lane, s));
+    m->n_shot += (uint64_t)ni * (uint64_t)nj;
+    m->has_counts = true;
+    m->last = s;
+    return ok();
+}
+
+lm_status lm_sync(lm_map* m)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    lm_status st = use_device(m);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(m->last));
+    return ok();
+}
+
+lm_status lm_read_counts(lm_map* m, uint64_t* host_counts, uint64_t* n_out, uint64_t* n_shot)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    lm_status st = use_device(m);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(m->last));
+    HIP_TRY(hipDeviceSynchronize());
+    if (host_counts)
+        HIP_TRY(hipMemcpy(host_counts, m->counts, (size_t)m->g.src_nx * m->g.src_ny * 8,
+                          hipMemcpyDeviceToHost));
+    if (n_out) HIP_TRY(hipMemcpy(n_out, m->n_out.p, 8, hipMemcpyDeviceToHost));
+    if (n_shot) *n_shot = m->n_shot;
+    return ok();
+}
+
+lm_status lm_mu_factor(const lm_map* m, double* factor)
+{
+    if (!m || !factor) return fail(LM_EINVAL, "NULL argument");
+    *factor = (m->g.ray_dx * m->g.ray_dy) / (m->g.src_dx * m->g.src_dy);
+    return ok();
+}
+
+lm_status lm_read_mu(lm_map* m, double* host_mu)
+{
+    if (!m || !host_mu) return fail(LM_EINVAL, "NULL argument");
+    const size_t npix = (size_t)m->g.src_nx * m->g.src_ny;
+    std::vector<uint64_t> c(npix);
+    lm_status st = lm_read_counts(m, c.data(), nullptr, nullptr);
+    if (st) return st;
+    double f;
+    lm_mu_factor(m, &f);
+    for (size_t k = 0; k < npix; ++k) host_mu[k] = (double)c[k] * f;
+    return ok();
+}
+
+lm_status lm_reset_counts(lm_map* m, void* stream)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    lm_status st = use_device(m);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    LAUNCH_TRY(lm_launch_fill_u64((unsigned long long*)m->counts,
+                                  (int64_t)m->g.src_nx * m->g.src_ny, 0ull, s));
+    LAUNCH_TRY(lm_launch_fill_u64(m->n_out.as<unsigned long long>(), 1, 0ull, s));
+    m->n_shot = 0;
+    m->has_counts = false;
+    m->last = s;
+    return ok();
+}
+
+lm_status lm_deflect(lm_map* m, const double* theta_xy, int64_t n, double* alpha_xy)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (n < 0 || (n > 0 && (!theta_xy || !alpha_xy))) return fail(LM_EINVAL, "bad arrays");
+    if (n >= (int64_t(1) << 30)) return fail(LM_EUNSUPPORTED, "too many probe positions");
+    if (n == 0) return ok();
+    const lm_geometry& g = m->g;
+    const double wx = (double)g.coarse * g.ray_dx * (double)m->ncx;
+    const double wy = (double)g.coarse * g.ray_dy * (double)m->ncy;
+    for (int64_t t = 0; t < n; ++t) {
+        const double tx = theta_xy[2 * t], ty = theta_xy[2 * t + 1];
+        if (!(isfin(tx) && isfin(ty))) return fail(LM_EINVAL, "non-finite position %lld", (long long)t);
+        if (g.scheme == LM_SCHEME_INTERP &&
+            !(tx >= g.ray_x0 && tx < g.ray_x0 + wx && ty >= g.ray_y0 && ty < g.ray_y0 + wy))
+            return fail(LM_ERANGE, "position %lld lies outside the level-2 grid", (long long)t);
+    }
+    lm_status st = use_device(m);
+    if (st) return st;
+    if (!m->coef_valid) {
+        st = prepare(m, nullptr);
+        if (st) return st;
+    }
+    DevBuf dth, dal;
+    if (dth.ensure((size_t)n * 16) || dal.ensure((size_t)n * 16))
+        return fail(LM_ENOMEM, "cannot allocate probe buffers");
+    HIP_TRY(hipStreamSynchronize(m->last));
+    HIP_TRY(hipMemcpy(dth.p, theta_xy, (size_t)n * 16, hipMemcpyHostToDevice));
+    LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
+    LAUNCH_TRY(lm_launch_deflect(d, g.scheme, g.precision, g.taylor_terms, dth.as<double>(), n,
+                                 dal.as<double>(), nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    HIP_TRY(hipMemcpy(alpha_xy, dal.p, (size_t)n * 16, hipMemcpyDeviceToHost));
+    return ok();
+}
+
+lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int32_t* p, int32_t* q)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (n < 0 || (n > 0 && (!i || !j || !p || !q))) return fail(LM_EINVAL, "bad arrays");
+    if (n >= (int64_t(1) << 30)) return fail(LM_EUNSUPPORTED, "too many probe rays");
+    if (n == 0) return ok();
+    for (int64_t t = 0; t < n; ++t)
+        if (i[t] < 0 || i[t] >= m->g.ray_nx || j[t] < 0 || j[t] >= m->g.ray_ny)
+            return fail(LM_ERANGE, "ray %lld (%lld, %lld) is outside the lattice", (long long)t,
+                        (long long)i[t], (long long)j[t]);
+    lm_status st = use_device(m);
+    if (st) return st;
+    if (!m->coef_valid) {
+        st = prepare(m, nullptr);
+        if (st) return st;
+    }
+    DevBuf di, dj, dp, dq;
+    if (di.ensure((size_t)n * 8) || dj.ensure((size_t)n * 8) || dp.ensure((size_t)n * 4) ||
+        dq.ensure((size_t)n * 4))
+        return fail(LM_ENOMEM, "cannot allocate probe buffers");
+    HIP_TRY(hipStreamSynchronize(m->last));
+    HIP_TRY(hipMemcpy(di.p, i, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dj.p, j, (size_t)n * 8, hipMemcpyHostToDevice));
+    LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
+    LAUNCH_TRY(lm_launch_trace(d, m->g.scheme, m->g.precision, m->g.taylor_terms, di.as<int64_t>(),
+                               dj.as<int64_t>(), n, dp.as<int32_t>(), dq.as<int32_t>(), nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    HIP_TRY(hipMemcpy(p, dp.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(q, dq.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return ok();
+}
+
+}  // extern "C"
+
+// ==================================================================== batch
+
+struct lm_batch {
+    std::vector<lm_map*> maps;
+    std::vector<int64_t> rect;  // 4 per map: i0, j0, ni, nj
+    int scheme = 0, precision = 0, terms = 4, device = 0;
+    int rays_per_lane = 8, g_scale = 1, wg_per_cu = 0;
+    DevBuf descs, offs, order, queue;
+    int64_t total = 0;
+    int grid = 0;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool dirty = true;
+    ~lm_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+namespace {
+
+int device_cus(int dev)
+{
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 256;
+    return n > 0 ? n : 256;
+}
+
+// Build descriptors, cost order and queue offsets; upload them.
+lm_status batch_build(lm_batch* b, int64_t limit_items)
+{
+    const int n = (int)b->maps.size();
+    std::vector<LmDesc> ds(n);
+    std::vector<double> cost(n);
+    for (int k = 0; k < n; ++k) {
+        lm_map* m = b->maps[k];
+        const int64_t* r = &b->rect[4 * k];
+        const int64_t R = m->g.coarse;
+        Exec e = choose_exec(m, r[2] > 0 ? (r[0] + r[2] - 1) / R - r[0] / R + 1 : 1,
+                             r[3] > 0 ? (r[1] + r[3] - 1) / R - r[1] / R + 1 : 1, b->g_scale);
+        ds[k] = make_desc(m, r[0], r[1], r[0] + r[2], r[1] + r[3], e);
+        if (r[2] == 0 || r[3] == 0) ds[k].ntiles = 0;
+        const double lenses = m->g.scheme == LM_SCHEME_INTERP
+                                  ? 9.0 * std::max(1.0, (double)m->nlens / std::max<int64_t>(1, m->n1x * m->n1y))
+                                  : (double)m->nlens;
+        cost[k] = (double)r[2] * (double)r[3] * (20.0 + 6.0 * lenses);
+    }
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::vector<int64_t> offs(n + 1, 0);
+    for (int k = 0; k < n; ++k) offs[k + 1] = offs[k] + ds[order[k]].ntiles;
+    b->total = offs[n];
+    if (limit_items >= 0 && limit_items < b->total) {
+        // a shorter queue: the first items in cost order (tuning samples)
+        for (int k = 0; k <= n; ++k) offs[k] = std::min(offs[k], limit_items);
+        b->total = limit_items;
+    }
+    if (b->descs.ensure(n * sizeof(LmDesc)) || b->offs.ensure((n + 1) * 8) ||
+        b->order.ensure(n * 4) || b->queue.ensure(8))
+        return fail(LM_ENOMEM, "cannot allocate batch tables");
+    HIP_TRY(hipMemcpy(b->descs.p, ds.data(), n * sizeof(LmDesc), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->offs.p, offs.data(), (n + 1) * 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b->order.p, order.data(), n * 4, hipMemcpyHostToDevice));
+    int occ = 0;
+    LAUNCH_TRY(lm_shoot_occupancy(b->scheme, b->precision, b->terms, b->rays_per_lane, &occ));
+    if (occ <= 0) occ = 1;
+    const int wg = b->wg_per_cu > 0 ? std::min(b->wg_per_cu, occ) : occ;
+    b->grid = device_cus(b->device) * wg;
+    return LM_OK;
+}
+
+// Record: coefficients of every map, queue reset, persistent shoot.
+lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs)
+{
+    const int n = (int)b->maps.size();
+    if (with_coeffs)
+        for (int k = 0; k < n; ++k) {
+            lm_map* m = b->maps[k];
+            if (m->g.scheme != LM_SCHEME_INTERP) continue;
+            LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
+            LAUNCH_TRY(lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
+                                        m->coef.as<LmCoef>(), s));
+        }
+    LAUNCH_TRY(lm_launch_fill_u64(b->queue.as<unsigned long long>(), 1, 0ull, s));
+    if (b->total > 0)
+        LAUNCH_TRY(lm_launch_shoot_batch(b->descs.as<LmDesc>(), b->offs.as<int64_t>(),
+                                         b->order.as<int32_t>(), n,
+                                         b->queue.as<unsigned long long>(), b->scheme, b->precision,
+                                         b->terms, b->rays_per_lane, b->grid, s));
+    return LM_OK;
+}
+
+lm_status batch_graph(lm_batch* b)
+{
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    lm_status st = batch_build(b, -1);
+    if (st) return st;
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    st = batch_enqueue(b, b->cap, true);
+    hipError_t e = hipStreamEndCapture(b->cap, &graph);
+    if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(LM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(LM_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    b->dirty = false;
+    return LM_OK;
+}
+
+std::string batch_key(const lm_batch* b)
+{
+    hipDeviceProp_t prop;
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) dev = prop.gcnArchName;
+    std::ostringstream k;
+    k << dev << "|s" << b->scheme << "p" << b->precision << "t" << b->terms << "|n" << b->maps.size();
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < b->maps.size(); ++i) {
+        const lm_map* m = b->maps[i];
+        const int64_t vals[] = {m->g.coarse, m->g.l1_kx, m->g.l1_ky, m->nlens, b->rect[4 * i + 2],
+                                b->rect[4 * i + 3], m->g.src_nx, m->g.src_ny};
+        for (int64_t v : vals) {
+            h ^= (uint64_t)v;
+            h *= 1099511628211ull;
+        }
+    }
+    k << "|h" << std::hex << h;
+    return k.str();
+}
+
+// Minimal cache: one line per key, "key nr g wg".
+bool cache_lookup(const char* path, const std::string& key, int& nr, int& gs, int& wg)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        int a, c, d;
+        if (is >> k >> a >> c >> d && k == key && lm_supported_rays_per_lane(a) && c >= 1 && d >= 0) {
+            nr = a;
+            gs = c;
+            wg = d;
+            return true;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char* path, const std::string& key, int nr, int gs, int wg)
+{
+    if (!path) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line))
+            if (line.compare(0, key.size() + 1, key + " ") != 0 && !line.empty()) keep.push_back(line);
+    }
+    std::ofstream f(path, std::ios::trunc);
+    for (auto& l : keep) f << l << "\n";
+    f << key << " " << nr << " " << gs << " " << wg << "\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_batch_create(lm_map* const* maps, int32_t n, lm_batch** out)
+{
+    if (!out) return fail(LM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!maps || n <= 0) return fail(LM_EINVAL, "a batch needs at least one map");
+    std::unique_ptr<lm_batch> b(new (std::nothrow) lm_batch);
+    if (!b) return fail(LM_ENOMEM, "out of host memory");
+    for (int k = 0; k < n; ++k) {
+        lm_map* m = maps[k];
+        if (!m) return fail(LM_EINVAL, "map %d is NULL", k);
+        if (k == 0) {
+            b->scheme = m->g.scheme;
+            b->precision = m->g.precision;
+            b->terms = m->g.scheme == LM_SCHEME_INTERP ? m->g.taylor_terms : 1;
+            b->device = m->device;
+        } else if (m->g.scheme != b->scheme || m->g.precision != b->precision ||
+                   (b->scheme == LM_SCHEME_INTERP && m->g.taylor_terms != b->terms) ||
+                   m->device != b->device) {
+            return fail(LM_EUNSUPPORTED, "map %d differs in scheme, precision, terms or device", k);
+        }
+        b->maps.push_back(m);
+        const int64_t r[4] = {0, 0, m->g.ray_nx, m->g.ray_ny};
+        b->rect.insert(b->rect.end(), r, r + 4);
+    }
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != b->device) HIP_TRY(hipSetDevice(b->device));
+    for (lm_map* m : b->maps) {
+        lm_status st = ensure_coef(m);
+        if (st) return st;
+    }
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    *out = b.release();
+    return ok();
+}
+
+lm_status lm_batch_set_rect(lm_batch* b, int32_t index, int64_t i0, int64_t j0, int64_t ni, int64_t nj)
+{
+    if (!b) return fail(LM_EINVAL, "batch is NULL");
+    if (index < 0 || index >= (int)b->maps.size()) return fail(LM_ERANGE, "no map %d", index);
+    const lm_map* m = b->maps[index];
+    if (ni < 0 || nj < 0 || i0 < 0 || j0 < 0 || i0 > m->g.ray_nx - ni || j0 > m->g.ray_ny - nj)
+        return fail(LM_ERANGE, "rectangle leaves the lattice of map %d", index);
+    int64_t* r = &b->rect[4 * index];
+    r[0] = i0;
+    r[1] = j0;
+    r[2] = ni;
+    r[3] = nj;
+    b->dirty = true;
+    return ok();
+}
+
+lm_status lm_batch_shoot(lm_batch* b, void* stream)
+{
+    if (!b) return fail(LM_EINVAL, "batch is NULL");
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != b->device) HIP_TRY(hipSetDevice(b->device));
+    if (b->dirty || !b->exec) {
+        lm_status st = batch_graph(b);
+        if (st) return st;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    for (size_t k = 0; k < b->maps.size(); ++k) {
+        lm_map* m = b->maps[k];
+        m->n_shot += (uint64_t)b->rect[4 * k + 2] * (uint64_t)b->rect[4 * k + 3];
+        if (b->rect[4 * k + 2] && b->rect[4 * k + 3]) m->has_counts = true;
+        m->coef_valid = true;
+        m->last = (hipStream_t)stream;
+    }
+    return ok();
+}
+
+lm_status lm_batch_tune(lm_batch* b, const char* cache_path)
+{
+    if (!b) return fail(LM_EINVAL, "batch is NULL");
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != b->device) HIP_TRY(hipSetDevice(b->device));
+    const std::string key = batch_key(b);
+    int nr = 0, gs = 0, wg = 0;
+    if (!cache_lookup(cache_path, key, nr, gs, wg)) {
+        // coefficients once, then time each candidate on the same sample of tiles
+        for (lm_map* m : b->maps) {
+            lm_status st = prepare(m, b->cap);
+            if (st) return st;
+        }
+        HIP_TRY(hipStreamSynchronize(b->cap));
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        float best = 1e30f;
+        const int nrs[] = {4, 8, 16};
+        const int gss[] = {1, 2};
+        for (int cnr : nrs)
+            for (int cgs : gss)
+                for (int cwg : {0, 2}) {
+                    b->rays_per_lane = cnr;
+                    b->g_scale = cgs;
+                    b->wg_per_cu = cwg;
+                    const int64_t sample = (int64_t)device_cus(b->device) * 16;
+                    lm_status st = batch_build(b, sample);
+                    if (st) return st;
+                    st = batch_enqueue(b, b->cap, false);  // warm-up
+                    if (st) return st;
+                    HIP_TRY(hipEventRecord(e0, b->cap));
+                    st = batch_enqueue(b, b->cap, false);
+                    if (st) return st;
+                    HIP_TRY(hipEventRecord(e1, b->cap));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) {
+                        best = ms;
+                        nr = cnr;
+                        gs = cgs;
+                        wg = cwg;
+                    }
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        cache_store(cache_path, key, nr, gs, wg);
+        for (lm_map* m : b->maps) {
+            lm_status st = lm_reset_counts(m, b->cap);
+            if (st) return st;
+        }
+        HIP_TRY(hipStreamSynchronize(b->cap));
+    }
+    b->rays_per_lane = nr;
+    b->g_scale = gs;
+    b->wg_per_cu = wg;
+    b->dirty = true;
+    return ok();
+}
+
+lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* tile_cells,
+                          int32_t* wg_per_cu)
+{
+    if (!b) return fail(LM_EINVAL, "batch is NULL");
+    if (rays_per_lane) *rays_per_lane = b->rays_per_lane;
+    if (tile_cells) *tile_cells = b->g_scale;
+    if (wg_per_cu) *wg_per_cu = b->wg_per_cu;
+    return ok();
+}
+
+void lm_batch_destroy(lm_batch* b)
+{
+    if (!b) return;
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != b->device) (void)hipSetDevice(b->device);
+    if (b->cap) (void)hipStreamSynchronize(b->cap);
+    (void)hipDeviceSynchronize();
+    delete b;
+}
+
+}  // extern "C"

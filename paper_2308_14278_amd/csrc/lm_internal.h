@@ -1,0 +1,76 @@
+// lm_internal.h -- layouts shared by the host code and the gfx950 kernels of
+// liblensmap (not part of the public ABI).
+#pragma once
+#include <stdint.h>
+
+#define LM_WG 256          // threads per workgroup: 4 waves of 64
+#define LM_WAVES 4
+#define LM_LENS_CAP 256    // lenses staged per wave per block (also the summation block)
+#define LM_WIN_MAX 4096    // uint32 bins of a workgroup's LDS window
+
+// Taylor coefficients of one level-2 cell: a_0 in FP64 (it carries the large
+// far-field deflection of the cell centre), a_1..a_6 in FP32 (they multiply
+// offsets of at most half a cell).  64 bytes per cell.
+struct LmCoef {
+    double a0r, a0i;
+    float a[12];  // (re, im) of a_1 .. a_6
+};
+
+// Everything a kernel needs about one map and one shot rectangle.
+struct LmDesc {
+    // ray lattice and macro mapping (FP64)
+    double x0, y0, dx, dy;
+    double mx, my;                 // 1-kappa-gamma+kappa_star, 1-kappa+gamma+kappa_star
+    double bx0, by0, inv_sdx, inv_sdy;
+    // FP32 copies: half ray spacing as float-float (rebased arithmetic) and
+    // plain values (the global-FP32 comparison path)
+    float hxh, hxl, hyh, hyl;
+    float x0f, y0f, dxf, dyf;
+    float mxf, myf, bx0f, by0f;
+    float inv_sdxf, inv_sdyf;
+    int32_t snx, sny;
+    // scheme and work decomposition
+    int32_t R, Kx, Ky, H;
+    int32_t G;                     // level-2 cells per workgroup-tile side
+    int32_t ncc;                   // column chunks per level-2 cell
+    int32_t cw;                    // columns per chunk
+    int32_t nrb;                   // 64-row blocks per level-2 cell (R / 64)
+    int32_t wx, wy;                // LDS window (pixels)
+    int32_t nl1x, nl1y;            // padded level-1 grid (N1 + 2H per side)
+    int64_t nx, ny;                // lattice
+    int64_t i0, j0, i1, j1;        // shot rectangle [i0,i1) x [j0,j1)
+    int64_t ncx, ncy;              // level-2 cells of the lattice
+    int64_t tcx0, tcy0, ntx, nty;  // workgroup tiles covering the rectangle
+    int64_t ntiles;
+    int64_t tile0;                 // first tile of a k_shoot_map launch
+    int64_t nlens;
+    // lenses: sorted by level-1 cell for the interpolated scheme
+    const double* lx;
+    const double* ly;
+    const double* lmd;
+    const float* lxf;
+    const float* lyf;
+    const float* lmf;
+    const int32_t* lI;             // level-1 cell of each lens (clamped)
+    const int32_t* lJ;
+    const int32_t* cell_start;     // CSR over the padded level-1 grid
+    const LmCoef* coef;            // [ncy][ncx]
+    unsigned long long* counts;    // [sny][snx]
+    unsigned long long* n_out;
+};
+
+// Launchers implemented in lm_kernels.hip (return hipError_t as int).
+int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int64_t cj0,
+                     int64_t nci, int64_t ncj, LmCoef* out, void* stream);
+int lm_launch_shoot_map(const LmDesc& d, int scheme, int precision, int terms, int rays_per_lane,
+                        void* stream);
+int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int32_t* order,
+                          int nmaps, unsigned long long* queue, int scheme, int precision,
+                          int terms, int rays_per_lane, int grid, void* stream);
+int lm_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
+int lm_launch_trace(const LmDesc& d, int scheme, int precision, int terms, const int64_t* ii,
+                    const int64_t* jj, int64_t n, int32_t* p, int32_t* q, void* stream);
+int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, const double* th,
+                      int64_t n, double* alpha, void* stream);
+int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu);
+bool lm_supported_rays_per_lane(int r);

@@ -1,0 +1,947 @@
+// lm_kernels.hip -- gfx950 kernels of liblensmap.
+//
+//  k_coeffs       far-field Taylor coefficients of every level-2 cell (Sec. 3.2.2):
+//                 a_n = -sum_{far k} m_k / (z_k - z_c)^(n+1); lens tiles staged
+//                 in LDS, FP64 arithmetic (full-rate FP64 VALU on gfx950).
+//  k_shoot_map    one workgroup per tile of level-2 cells: per ray the near-lens
+//  k_shoot_batch  direct sum (Eq. 9) in FP32 on offsets rebased to the cell
+//                 centre, the Taylor evaluation of the far field, the macro map
+//                 with the sheet term (Eq. 6), FP64 pixel coordinates, and the
+//                 count (Sec. 3.2.3) through a per-lane run, a wave merge and
+//                 an LDS window flushed to the uint64 map.  The batch kernel is
+//                 persistent and pulls tiles of many maps from a queue.
+//  k_trace        per-ray pixels with the same arithmetic (test probe).
+//  k_deflect      deflection at arbitrary positions (test probe).
+//
+// Layout of work inside a tile: a wave owns "units" of 64 consecutive rows
+// (one ray row per lane) by a run of columns of one level-2 cell; the lane
+// walks its row NR columns at a time.  Every ray of a unit shares the cell's
+// near-lens list, which the wave stages once in its own LDS slice, so the
+// lens loop is uniform and reads lenses as LDS broadcasts.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "lm_internal.h"
+
+namespace {
+
+constexpr int kWG = LM_WG;
+constexpr int kCap = LM_LENS_CAP;
+constexpr int kWinMax = LM_WIN_MAX;
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(uint64_t)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ unsigned wave_sum_u32(unsigned v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- cell data
+
+__device__ __forceinline__ double cell_cx(const LmDesc& d, int64_t ci)
+{
+    return d.x0 + ((double)ci + 0.5) * (double)d.R * d.dx;
+}
+__device__ __forceinline__ double cell_cy(const LmDesc& d, int64_t cj)
+{
+    return d.y0 + ((double)cj + 0.5) * (double)d.R * d.dy;
+}
+__device__ __forceinline__ float cell_cxf(const LmDesc& d, int64_t ci)
+{
+    return d.x0f + ((float)ci + 0.5f) * (float)d.R * d.dxf;
+}
+__device__ __forceinline__ float cell_cyf(const LmDesc& d, int64_t cj)
+{
+    return d.y0f + ((float)cj + 0.5f) * (float)d.R * d.dyf;
+}
+
+// FP64 pixel coordinates of the cell centre's image (includes a_0).
+template <int SCHEME>
+__device__ __forceinline__ void cell_base(const LmDesc& d, int64_t ci, int64_t cj, double& ubx,
+                                          double& uby)
+{
+    double bx = d.mx * cell_cx(d, ci);
+    double by = d.my * cell_cy(d, cj);
+    if (SCHEME == 1) {
+        const LmCoef& c = d.coef[cj * d.ncx + ci];
+        bx -= c.a0r;
+        by += c.a0i;
+    }
+    ubx = (bx - d.bx0) * d.inv_sdx;
+    uby = (by - d.by0) * d.inv_sdy;
+}
+
+// ----------------------------------------------------------- per-ray pieces
+
+// One ray-lens pair: accumulates m (dx, dy) / r^2 with dx = px - lx.
+__device__ __forceinline__ void pair(float px, float dy, float dy2, float lxv, float lmv,
+                                     float& ax, float& ay)
+{
+    float dx = px - lxv;
+    float r2 = __builtin_fmaf(dx, dx, dy2);
+    float w = lmv * __builtin_amdgcn_rcpf(r2);
+    ax = __builtin_fmaf(dx, w, ax);
+    ay = __builtin_fmaf(dy, w, ay);
+}
+
+__device__ __forceinline__ void kahan_add(float& s, float& c, float v)
+{
+    float y = v - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// f = sum_{n=1}^{P-1} a_n d^n by Horner, FP32.
+template <int P>
+__device__ __forceinline__ void taylor(const float* ar, const float* ai, float dx, float dy,
+                                       float& fr, float& fi)
+{
+    if (P <= 1) {
+        fr = 0.f;
+        fi = 0.f;
+        return;
+    }
+    float gr = ar[P - 1], gi = ai[P - 1];
+#pragma unroll
+    for (int n = P - 2; n >= 1; --n) {
+        float tr = __builtin_fmaf(gr, dx, __builtin_fmaf(-gi, dy, ar[n]));
+        float ti = __builtin_fmaf(gr, dy, __builtin_fmaf(gi, dx, ai[n]));
+        gr = tr;
+        gi = ti;
+    }
+    fr = __builtin_fmaf(gr, dx, -(gi * dy));
+    fi = __builtin_fmaf(gr, dy, gi * dx);
+}
+
+// Pixel of one ray from its local sums (mixed path).  p = -1: outside the map.
+template <int P>
+__device__ __forceinline__ void bin_mixed(const LmDesc& d, const float* ar, const float* ai,
+                                          double ubx, double uby, float dx, float dy, float ax,
+                                          float ay, int& p, int& q)
+{
+    float fr, fi;
+    taylor<P>(ar, ai, dx, dy, fr, fi);
+    float tx = ax + fr;
+    float ty = ay - fi;
+    float lx = __builtin_fmaf(d.mxf, dx, -tx);
+    float ly = __builtin_fmaf(d.myf, dy, -ty);
+    double u = __builtin_fma((double)lx, d.inv_sdx, ubx);
+    double v = __builtin_fma((double)ly, d.inv_sdy, uby);
+    bool in = (u >= 0.0) && (u < (double)d.snx) && (v >= 0.0) && (v < (double)d.sny);
+    p = in ? (int)u : -1;
+    q = in ? (int)v : -1;
+}
+
+// Pixel of one ray in the plain FP32 path (global coordinates).
+template <int P>
+__device__ __forceinline__ void bin_fp32(const LmDesc& d, const float* ar, const float* ai,
+                                         float a0r, float a0i, float zcx, float zcy, float tx,
+                                         float ty, float ax, float ay, int& p, int& q)
+{
+    float fr, fi;
+    float dx = tx - zcx, dy = ty - zcy;
+    taylor<P>(ar, ai, dx, dy, fr, fi);
+    float alx = ax + (a0r + fr);
+    float aly = ay - (a0i + fi);
+    float bx = __builtin_fmaf(d.mxf, tx, -alx);
+    float by = __builtin_fmaf(d.myf, ty, -aly);
+    float u = (bx - d.bx0f) * d.inv_sdxf;
+    float v = (by - d.by0f) * d.inv_sdyf;
+    bool in = (u >= 0.f) && (u < (float)d.snx) && (v >= 0.f) && (v < (float)d.sny);
+    p = in ? (int)u : -1;
+    q = in ? (int)v : -1;
+}
+
+// Offset of lattice index k from the centre of its level-2 cell, as
+// (2 (k - c R) - (R - 1)) * (spacing / 2) with the half spacing in float-float.
+__device__ __forceinline__ float local_offset(int64_t k, int64_t c, int R, float hh, float hl)
+{
+    int l = 2 * (int)(k - c * (int64_t)R) - (R - 1);
+    float fl = (float)l;
+    return __builtin_fmaf(fl, hl, fl * hh);
+}
+
+// ------------------------------------------------------------ lens lists
+
+// Near-lens rows of the level-1 cell holding level-2 cell (ci, cj): row r in
+// [0, 2H] is the contiguous sorted range [start, end) of level-1 cells
+// (I-H..I+H, J-H+r).
+__device__ __forceinline__ void near_row(const LmDesc& d, int64_t ci, int64_t cj, int r, int& s,
+                                         int& e)
+{
+    int I = (int)(ci / d.Kx), J = (int)(cj / d.Ky);
+    int row = J + r;  // padded row of J - H + r is (J - H + r) + H
+    int base = row * d.nl1x + I;  // padded column of I - H is I
+    s = d.cell_start[base];
+    e = d.cell_start[base + 2 * d.H + 1];
+}
+
+template <int SCHEME>
+__device__ __forceinline__ int list_count(const LmDesc& d, int64_t ci, int64_t cj)
+{
+    if (SCHEME == 0) return (int)d.nlens;
+    int n = 0;
+    for (int r = 0; r <= 2 * d.H; ++r) {
+        int s, e;
+        near_row(d, ci, cj, r, s, e);
+        n += e - s;
+    }
+    return n;
+}
+
+// Lens value as the per-ray loop sees it.
+template <int PREC>
+__device__ __forceinline__ float4 lens_value(const LmDesc& d, int idx, double zcx, double zcy)
+{
+    if (PREC == 0)
+        return make_float4((float)(d.lx[idx] - zcx), (float)(d.ly[idx] - zcy), d.lmf[idx], 0.f);
+    return make_float4(d.lxf[idx], d.lyf[idx], d.lmf[idx], 0.f);
+}
+
+// Stage list positions [b0, b0+nb) of the cell's lens list into this wave's LDS slice.
+template <int SCHEME, int PREC>
+__device__ void stage(const LmDesc& d, int64_t ci, int64_t cj, int b0, int nb, double zcx,
+                      double zcy, float4* lb, int lane)
+{
+    if (SCHEME == 0) {
+        for (int s = lane; s < nb; s += 64) lb[s] = lens_value<PREC>(d, b0 + s, zcx, zcy);
+    } else {
+        int off = 0;
+        for (int r = 0; r <= 2 * d.H; ++r) {
+            int s, e;
+            near_row(d, ci, cj, r, s, e);
+            int lo = max(off, b0), hi = min(off + (e - s), b0 + nb);
+            for (int k = lo + lane; k < hi; k += 64)
+                lb[k - b0] = lens_value<PREC>(d, s + (k - off), zcx, zcy);
+            off += e - s;
+        }
+    }
+    wave_sync_lds();
+}
+
+// Global-memory walk over the same list in the same order (probes).
+template <int SCHEME>
+__device__ __forceinline__ int list_index(const LmDesc& d, int64_t ci, int64_t cj, int pos)
+{
+    if (SCHEME == 0) return pos;
+    int off = 0;
+    for (int r = 0; r <= 2 * d.H; ++r) {
+        int s, e;
+        near_row(d, ci, cj, r, s, e);
+        if (pos < off + (e - s)) return s + (pos - off);
+        off += e - s;
+    }
+    return -1;
+}
+
+template <int P>
+__device__ __forceinline__ void load_taylor(const LmDesc& d, int64_t ci, int64_t cj, float* ar,
+                                            float* ai, float& a0r, float& a0i)
+{
+    const LmCoef& c = d.coef[cj * d.ncx + ci];
+    a0r = (float)c.a0r;
+    a0i = (float)c.a0i;
+    ar[0] = 0.f;
+    ai[0] = 0.f;
+#pragma unroll
+    for (int n = 1; n < P; ++n) {
+        ar[n] = c.a[2 * (n - 1)];
+        ai[n] = c.a[2 * (n - 1) + 1];
+    }
+}
+
+// ------------------------------------------------------------- counting
+
+struct Run {
+    int p, q;
+    unsigned n;
+};
+
+__device__ __forceinline__ void emit(const LmDesc& d, int p, int q, unsigned n, int ax0, int ay0,
+                                     unsigned* win, unsigned& nout)
+{
+    if (p < 0) {
+        nout += n;
+        return;
+    }
+    int64_t wxi = (int64_t)p - ax0, wyi = (int64_t)q - ay0;
+    if (wxi >= 0 && wxi < d.wx && wyi >= 0 && wyi < d.wy)
+        atomicAdd(&win[wyi * d.wx + wxi], n);
+    else
+        atomicAdd(&d.counts[(int64_t)q * d.snx + p], (unsigned long long)n);
+}
+
+__device__ __forceinline__ void run_push(const LmDesc& d, Run& r, int p, int q, int ax0, int ay0,
+                                         unsigned* win, unsigned& nout)
+{
+    if (p == r.p && q == r.q) {
+        ++r.n;
+    } else {
+        if (r.n) emit(d, r.p, r.q, r.n, ax0, ay0, win, nout);
+        r.p = p;
+        r.q = q;
+        r.n = 1;
+    }
+}
+
+// End of a unit: lanes whose pending runs all name one pixel add it once.
+__device__ __forceinline__ void run_flush(const LmDesc& d, Run& r, int ax0, int ay0, unsigned* win,
+                                          unsigned& nout, int lane)
+{
+    bool act = r.n > 0;
+    unsigned long long am = __ballot(act);
+    if (am) {
+        int first = __builtin_ctzll(am);
+        int p0 = __shfl(r.p, first, 64), q0 = __shfl(r.q, first, 64);
+        unsigned long long diff = __ballot(act && (r.p != p0 || r.q != q0));
+        if (diff == 0) {
+            unsigned tot = wave_sum_u32(act ? r.n : 0u);
+            if (lane == first) emit(d, p0, q0, tot, ax0, ay0, win, nout);
+        } else if (act) {
+            emit(d, r.p, r.q, r.n, ax0, ay0, win, nout);
+        }
+    }
+    r.n = 0;
+    r.p = -2;
+    r.q = -2;
+}
+
+// --------------------------------------------------------------- units
+
+template <int SCHEME, int PREC, int NR, int P>
+__device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_hi,
+                             int64_t j, bool row_ok, int ax0, int ay0, unsigned* win, float4* lb,
+                             int lane, unsigned& nout)
+{
+    const int R = d.R;
+    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
+    double ubx, uby;
+    cell_base<SCHEME>(d, ci, cj, ubx, uby);
+    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
+    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
+    const float zcxf = cell_cxf(d, ci), zcyf = cell_cyf(d, cj);
+
+    // the lane's ray row
+    float py;
+    if (PREC == 0)
+        py = local_offset(j, cj, R, d.hyh, d.hyl);
+    else
+        py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
+
+    const int count = list_count<SCHEME>(d, ci, cj);
+    const int nblk = (count + kCap - 1) / kCap;
+    if (nblk == 1) stage<SCHEME, PREC>(d, ci, cj, 0, count, zcx, zcy, lb, lane);
+
+    Run run{-2, -2, 0u};
+    for (int64_t c0 = c_lo; c0 < c_hi; c0 += NR) {
+        float px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            if (PREC == 0)
+                px[c] = local_offset(c0 + c, ci, R, d.hxh, d.hxl);
+            else
+                px[c] = __builtin_fmaf((float)(c0 + c) + 0.5f, d.dxf, d.x0f);
+            ax[c] = 0.f;
+            ay[c] = 0.f;
+            kx[c] = 0.f;
+            ky[c] = 0.f;
+        }
+        for (int b = 0; b < nblk; ++b) {
+            const int nb = min(kCap, count - b * kCap);
+            if (nblk > 1) stage<SCHEME, PREC>(d, ci, cj, b * kCap, nb, zcx, zcy, lb, lane);
+            float bx[NR], by[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                bx[c] = SCHEME == 0 ? 0.f : ax[c];
+                by[c] = SCHEME == 0 ? 0.f : ay[c];
+            }
+            for (int k = 0; k < nb; ++k) {
+                const float4 L = lb[k];
+                const float dy = py - L.y;
+                const float dy2 = dy * dy;
+#pragma unroll
+                for (int c = 0; c < NR; ++c) pair(px[c], dy, dy2, L.x, L.z, bx[c], by[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                if (SCHEME == 0) {
+                    kahan_add(ax[c], kx[c], bx[c]);
+                    kahan_add(ay[c], ky[c], by[c]);
+                } else {
+                    ax[c] = bx[c];
+                    ay[c] = by[c];
+                }
+            }
+            if (nblk > 1) wave_sync_lds();
+        }
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            if (c0 + c < c_hi) {
+                int p, q;
+                if (PREC == 0)
+                    bin_mixed<P>(d, ar, ai, ubx, uby, px[c], py, ax[c], ay[c], p, q);
+                else
+                    bin_fp32<P>(d, ar, ai, a0r, a0i, zcxf, zcyf, px[c], py, ax[c], ay[c], p, q);
+                if (row_ok) run_push(d, run, p, q, ax0, ay0, win, nout);
+            }
+        }
+    }
+    run_flush(d, run, ax0, ay0, win, nout, lane);
+}
+
+template <int SCHEME>
+__device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_t cjb, int& ax0,
+                                            int& ay0)
+{
+    int64_t cic = min(cib + d.G / 2, d.ncx - 1), cjc = min(cjb + d.G / 2, d.ncy - 1);
+    double ubx, uby;
+    cell_base<SCHEME>(d, cic, cjc, ubx, uby);
+    double fx = floor(ubx) - (double)(d.wx / 2), fy = floor(uby) - (double)(d.wy / 2);
+    fx = fmin(fmax(fx, -1.0e9), 1.0e9);
+    fy = fmin(fmax(fy, -1.0e9), 1.0e9);
+    if (fx != fx) fx = 0.0;
+    if (fy != fy) fy = 0.0;
+    ax0 = (int)fx;
+    ay0 = (int)fy;
+}
+
+template <int SCHEME, int PREC, int NR, int P>
+__device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsigned* win,
+                             float4* lb, int wave, int lane)
+{
+    const int64_t tx = t % d.ntx, ty = t / d.ntx;
+    const int64_t cib = (d.tcx0 + tx) * d.G, cjb = (d.tcy0 + ty) * d.G;
+    const int per_cell = d.nrb * d.ncc;
+    const int U = d.G * d.G * per_cell;
+    unsigned nout = 0;
+    for (int u = wave; u < U; u += LM_WAVES) {
+        const int cu = u / per_cell, rem = u - cu * per_cell;
+        const int rb = rem / d.ncc, cc = rem - rb * d.ncc;
+        const int64_t ci = cib + cu % d.G, cj = cjb + cu / d.G;
+        if (ci >= d.ncx || cj >= d.ncy) continue;
+        const int64_t cell_lo = ci * d.R, cell_hi = cell_lo + d.R;
+        const int64_t c_lo = max(cell_lo + (int64_t)cc * d.cw, d.i0);
+        const int64_t c_hi = min(min(cell_lo + (int64_t)(cc + 1) * d.cw, cell_hi), d.i1);
+        const int64_t r_lo = cj * d.R + (int64_t)rb * 64;
+        if (c_lo >= c_hi || r_lo + 64 <= d.j0 || r_lo >= d.j1) continue;
+        const int64_t j = r_lo + lane;
+        const bool row_ok = j >= d.j0 && j < d.j1;
+        process_unit<SCHEME, PREC, NR, P>(d, ci, cj, c_lo, c_hi, j, row_ok, ax0, ay0, win, lb, lane,
+                                          nout);
+    }
+    unsigned tot = wave_sum_u32(nout);
+    if (lane == 0 && tot) atomicAdd(d.n_out, (unsigned long long)tot);
+}
+
+__device__ __forceinline__ void flush_window(const LmDesc& d, unsigned* win, int ax0, int ay0,
+                                             int tid)
+{
+    const int n = d.wx * d.wy;
+    for (int b = tid; b < n; b += kWG) {
+        unsigned v = win[b];
+        if (v) {
+            int64_t p = (int64_t)ax0 + b % d.wx, q = (int64_t)ay0 + b / d.wx;
+            atomicAdd(&d.counts[q * d.snx + p], (unsigned long long)v);
+            win[b] = 0u;
+        }
+    }
+}
+
+// ------------------------------------------------------------- kernels
+
+template <int SCHEME, int PREC, int NR, int P>
+__global__ __launch_bounds__(kWG) void k_shoot_map(LmDesc d)
+{
+    __shared__ unsigned win[kWinMax];
+    __shared__ float4 lens[LM_WAVES][kCap];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t t = d.tile0 + blockIdx.x;
+    for (int b = tid; b < d.wx * d.wy; b += kWG) win[b] = 0u;
+    const int64_t tx = t % d.ntx, ty = t / d.ntx;
+    int ax0, ay0;
+    tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
+    __syncthreads();
+    process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], wave, lane);
+    __syncthreads();
+    flush_window(d, win, ax0, ay0, tid);
+}
+
+template <int SCHEME, int PREC, int NR, int P>
+__global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ descs,
+                                                     const int64_t* __restrict__ offs,
+                                                     const int32_t* __restrict__ order, int nmaps,
+                                                     unsigned long long* queue)
+{
+    __shared__ unsigned win[kWinMax];
+    __shared__ float4 lens[LM_WAVES][kCap];
+    __shared__ long long s_item;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int b = tid; b < kWinMax; b += kWG) win[b] = 0u;
+    const int64_t total = offs[nmaps];
+    for (;;) {
+        if (tid == 0) s_item = (long long)atomicAdd(queue, 1ull);
+        __syncthreads();
+        const int64_t item = uniform_i64(s_item);
+        __syncthreads();
+        if (item >= total) break;
+        int lo = 0, hi = nmaps - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const LmDesc& d = descs[order[lo]];
+        const int64_t t = item - offs[lo];
+        const int64_t tx = t % d.ntx, ty = t / d.ntx;
+        int ax0, ay0;
+        tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
+        process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], wave, lane);
+        __syncthreads();
+        flush_window(d, win, ax0, ay0, tid);
+        __syncthreads();
+    }
+}
+
+// Far-field coefficients: one level-2 cell per thread, lens tiles in LDS.
+template <int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t cj0, int64_t nci,
+                                                int64_t ncj, LmCoef* __restrict__ out)
+{
+    typedef typename std::conditional<PREC == 0, double, float>::type T;
+    __shared__ T sx[kWG], sy[kWG], sm[kWG];
+    __shared__ int sI[kWG], sJ[kWG];
+    const int tid = threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * kWG + tid;
+    const bool valid = c < nci * ncj;
+    const int64_t ci = ci0 + (valid ? c % nci : 0), cj = cj0 + (valid ? c / nci : 0);
+    const int I = (int)(ci / d.Kx), J = (int)(cj / d.Ky);
+    T zx, zy;
+    if (PREC == 0) {
+        zx = (T)cell_cx(d, ci);
+        zy = (T)cell_cy(d, cj);
+    } else {
+        zx = (T)cell_cxf(d, ci);
+        zy = (T)cell_cyf(d, cj);
+    }
+    T ar[P], ai[P];
+#pragma unroll
+    for (int n = 0; n < P; ++n) {
+        ar[n] = 0;
+        ai[n] = 0;
+    }
+    for (int64_t base = 0; base < d.nlens; base += kWG) {
+        __syncthreads();
+        const int64_t k = base + tid;
+        if (k < d.nlens) {
+            if (PREC == 0) {
+                sx[tid] = (T)d.lx[k];
+                sy[tid] = (T)d.ly[k];
+                sm[tid] = (T)d.lmd[k];
+            } else {
+                sx[tid] = (T)d.lxf[k];
+                sy[tid] = (T)d.lyf[k];
+                sm[tid] = (T)d.lmf[k];
+            }
+            sI[tid] = d.lI[k];
+            sJ[tid] = d.lJ[k];
+        }
+        __syncthreads();
+        const int nb = (int)min((int64_t)kWG, d.nlens - base);
+        for (int k2 = 0; k2 < nb; ++k2) {
+            const bool near = abs(sI[k2] - I) <= d.H && abs(sJ[k2] - J) <= d.H;
+            T wx = sx[k2] - zx, wy = sy[k2] - zy;
+            T r2 = wx * wx + wy * wy;
+            r2 = near ? (T)1 : r2;
+            const T m = near ? (T)0 : sm[k2];
+            const T inv = (T)1 / r2;
+            const T ux = wx * inv, uy = -wy * inv;
+            T tx = m * ux, ty = m * uy;
+#pragma unroll
+            for (int n = 0; n < P; ++n) {
+                ar[n] -= tx;
+                ai[n] -= ty;
+                const T nx = tx * ux - ty * uy;
+                const T ny = tx * uy + ty * ux;
+                tx = nx;
+                ty = ny;
+            }
+        }
+    }
+    if (valid) {
+        LmCoef& o = out[cj * d.ncx + ci];
+        o.a0r = (double)ar[0];
+        o.a0i = (double)ai[0];
+#pragma unroll
+        for (int n = 1; n < 7; ++n) {
+            o.a[2 * (n - 1)] = n < P ? (float)ar[n < P ? n : 0] : 0.f;
+            o.a[2 * (n - 1) + 1] = n < P ? (float)ai[n < P ? n : 0] : 0.f;
+        }
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Per-ray pixels with the shooting kernel's arithmetic, lens for lens.
+template <int SCHEME, int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restrict__ ii,
+                                               const int64_t* __restrict__ jj, int64_t n,
+                                               int32_t* __restrict__ po, int32_t* __restrict__ qo)
+{
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = ii[t], j = jj[t];
+    const int R = d.R;
+    const int64_t ci = i / R, cj = j / R;
+    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
+    double ubx, uby;
+    cell_base<SCHEME>(d, ci, cj, ubx, uby);
+    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
+    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
+    float px, py;
+    if (PREC == 0) {
+        px = local_offset(i, ci, R, d.hxh, d.hxl);
+        py = local_offset(j, cj, R, d.hyh, d.hyl);
+    } else {
+        px = __builtin_fmaf((float)i + 0.5f, d.dxf, d.x0f);
+        py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
+    }
+    const int count = list_count<SCHEME>(d, ci, cj);
+    float ax = 0.f, ay = 0.f, kx = 0.f, ky = 0.f;
+    for (int b0 = 0; b0 < count; b0 += kCap) {
+        const int nb = min(kCap, count - b0);
+        float bx = SCHEME == 0 ? 0.f : ax, by = SCHEME == 0 ? 0.f : ay;
+        for (int k = 0; k < nb; ++k) {
+            const float4 L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
+            const float dy = py - L.y;
+            const float dy2 = dy * dy;
+            pair(px, dy, dy2, L.x, L.z, bx, by);
+        }
+        if (SCHEME == 0) {
+            kahan_add(ax, kx, bx);
+            kahan_add(ay, ky, by);
+        } else {
+            ax = bx;
+            ay = by;
+        }
+    }
+    int p, q;
+    if (PREC == 0)
+        bin_mixed<P>(d, ar, ai, ubx, uby, px, py, ax, ay, p, q);
+    else
+        bin_fp32<P>(d, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, py, ax, ay, p, q);
+    po[t] = p;
+    qo[t] = q;
+}
+
+// Deflection at arbitrary positions, rebased on the level-2 cell holding them.
+template <int SCHEME, int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restrict__ th,
+                                                 int64_t n, double* __restrict__ al)
+{
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t >= n) return;
+    const double tx = th[2 * t], ty = th[2 * t + 1];
+    const int64_t ci = (int64_t)floor((tx - d.x0) / ((double)d.R * d.dx));
+    const int64_t cj = (int64_t)floor((ty - d.y0) / ((double)d.R * d.dy));
+    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
+    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
+    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
+    float px, py;
+    if (PREC == 0) {
+        px = (float)(tx - zcx);
+        py = (float)(ty - zcy);
+    } else {
+        px = (float)tx;
+        py = (float)ty;
+    }
+    const int count = list_count<SCHEME>(d, ci, cj);
+    float ax = 0.f, ay = 0.f, kx = 0.f, ky = 0.f;
+    for (int b0 = 0; b0 < count; b0 += kCap) {
+        const int nb = min(kCap, count - b0);
+        float bx = SCHEME == 0 ? 0.f : ax, by = SCHEME == 0 ? 0.f : ay;
+        for (int k = 0; k < nb; ++k) {
+            const float4 L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
+            const float dy = py - L.y;
+            pair(px, dy, dy * dy, L.x, L.z, bx, by);
+        }
+        if (SCHEME == 0) {
+            kahan_add(ax, kx, bx);
+            kahan_add(ay, ky, by);
+        } else {
+            ax = bx;
+            ay = by;
+        }
+    }
+    double outx = ax, outy = ay;
+    if (SCHEME == 1) {
+        float fr, fi, dx, dy;
+        if (PREC == 0) {
+            dx = px;
+            dy = py;
+        } else {
+            dx = px - cell_cxf(d, ci);
+            dy = py - cell_cyf(d, cj);
+        }
+        taylor<P>(ar, ai, dx, dy, fr, fi);
+        if (PREC == 0) {
+            const LmCoef& c = d.coef[cj * d.ncx + ci];
+            outx = (double)ax + (double)fr + c.a0r;
+            outy = (double)ay - (double)fi - c.a0i;
+        } else {
+            outx = (double)(ax + (a0r + fr));
+            outy = (double)(ay - (a0i + fi));
+        }
+    }
+    al[2 * t] = outx;
+    al[2 * t + 1] = outy;
+}
+
+// ------------------------------------------------------------ dispatch
+
+// Grids stay below 2^22 workgroups (2^30 work-items) per launch.
+constexpr int64_t kMaxGrid = int64_t(1) << 22;
+
+template <int S, int PR, int NR, int P>
+int launch_map_t(const LmDesc& d0, hipStream_t s)
+{
+    LmDesc d = d0;
+    for (int64_t t0 = 0; t0 < d0.ntiles; t0 += kMaxGrid) {
+        d.tile0 = t0;
+        const int64_t n = d0.ntiles - t0 < kMaxGrid ? d0.ntiles - t0 : kMaxGrid;
+        hipLaunchKernelGGL((k_shoot_map<S, PR, NR, P>), dim3((unsigned)n), dim3(kWG), 0, s, d);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+    }
+    return 0;
+}
+
+template <int S, int PR, int NR, int P>
+int launch_batch_t(const LmDesc* descs, const int64_t* offs, const int32_t* order, int nmaps,
+                   unsigned long long* queue, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_shoot_batch<S, PR, NR, P>), dim3(grid), dim3(kWG), 0, s, descs, offs,
+                       order, nmaps, queue);
+    return (int)hipGetLastError();
+}
+
+template <int S, int PR, int NR, int P>
+const void* kernel_ptr_t()
+{
+    return (const void*)&k_shoot_batch<S, PR, NR, P>;
+}
+
+// Visit the instantiation for runtime (scheme, precision, NR, P).  The direct
+// scheme has no Taylor terms and is instantiated with P = 1 only.
+template <int S, int PR, int NR, class F>
+int dispatch_p(int terms, F& f)
+{
+    if constexpr (S == 0) {
+        return f.template go<S, PR, NR, 1>();
+    } else {
+        switch (terms) {
+        case 1: return f.template go<S, PR, NR, 1>();
+        case 2: return f.template go<S, PR, NR, 2>();
+        case 3: return f.template go<S, PR, NR, 3>();
+        case 4: return f.template go<S, PR, NR, 4>();
+        case 5: return f.template go<S, PR, NR, 5>();
+        case 6: return f.template go<S, PR, NR, 6>();
+        case 7: return f.template go<S, PR, NR, 7>();
+        default: return (int)hipErrorInvalidValue;
+        }
+    }
+}
+
+template <int S, int PR, class F>
+int dispatch_nr(int nr, int terms, F& f)
+{
+    switch (nr) {
+    case 4: return dispatch_p<S, PR, 4>(terms, f);
+    case 8: return dispatch_p<S, PR, 8>(terms, f);
+    case 16: return dispatch_p<S, PR, 16>(terms, f);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+template <class F>
+int dispatch(int scheme, int prec, int nr, int terms, F&& f)
+{
+    if (scheme == 0 && prec == 0) return dispatch_nr<0, 0>(nr, terms, f);
+    if (scheme == 0 && prec == 1) return dispatch_nr<0, 1>(nr, terms, f);
+    if (scheme == 1 && prec == 0) return dispatch_nr<1, 0>(nr, terms, f);
+    if (scheme == 1 && prec == 1) return dispatch_nr<1, 1>(nr, terms, f);
+    return (int)hipErrorInvalidValue;
+}
+
+// Probes do not depend on NR.
+template <class F>
+int dispatch_probe(int scheme, int prec, int terms, F&& f)
+{
+    if (scheme == 0 && prec == 0) return dispatch_p<0, 0, 4>(terms, f);
+    if (scheme == 0 && prec == 1) return dispatch_p<0, 1, 4>(terms, f);
+    if (scheme == 1 && prec == 0) return dispatch_p<1, 0, 4>(terms, f);
+    if (scheme == 1 && prec == 1) return dispatch_p<1, 1, 4>(terms, f);
+    return (int)hipErrorInvalidValue;
+}
+
+struct MapLauncher {
+    const LmDesc& d;
+    hipStream_t s;
+    template <int S, int PR, int NR, int P>
+    int go() { return launch_map_t<S, PR, NR, P>(d, s); }
+};
+
+struct BatchLauncher {
+    const LmDesc* descs;
+    const int64_t* offs;
+    const int32_t* order;
+    int nmaps;
+    unsigned long long* queue;
+    int grid;
+    hipStream_t s;
+    template <int S, int PR, int NR, int P>
+    int go() { return launch_batch_t<S, PR, NR, P>(descs, offs, order, nmaps, queue, grid, s); }
+};
+
+struct Occupancy {
+    int* out;
+    template <int S, int PR, int NR, int P>
+    int go()
+    {
+        return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, kernel_ptr_t<S, PR, NR, P>(),
+                                                                  kWG, 0);
+    }
+};
+
+}  // namespace
+
+bool lm_supported_rays_per_lane(int r) { return r == 4 || r == 8 || r == 16; }
+
+int lm_launch_shoot_map(const LmDesc& d, int scheme, int precision, int terms, int rays_per_lane,
+                        void* stream)
+{
+    if (d.ntiles <= 0) return 0;
+    return dispatch(scheme, precision, rays_per_lane, terms, MapLauncher{d, (hipStream_t)stream});
+}
+
+int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int32_t* order,
+                          int nmaps, unsigned long long* queue, int scheme, int precision,
+                          int terms, int rays_per_lane, int grid, void* stream)
+{
+    return dispatch(scheme, precision, rays_per_lane, terms,
+                    BatchLauncher{descs, offsets, order, nmaps, queue, grid, (hipStream_t)stream});
+}
+
+int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu)
+{
+    return dispatch(scheme, precision, rays_per_lane, terms, Occupancy{wg_per_cu});
+}
+
+int lm_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream)
+{
+    if (n <= 0) return 0;
+    int64_t blocks = (n + kWG - 1) / kWG;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(kWG), 0, (hipStream_t)stream, p, n,
+                       v);
+    return (int)hipGetLastError();
+}
+
+int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int64_t cj0,
+                     int64_t nci, int64_t ncj, LmCoef* out, void* stream)
+{
+    const int64_t n = nci * ncj;
+    if (n <= 0) return 0;
+    const dim3 grid((unsigned)((n + kWG - 1) / kWG));
+    hipStream_t s = (hipStream_t)stream;
+#define LM_COEF(PR, P) \
+    hipLaunchKernelGGL((k_coeffs<PR, P>), grid, dim3(kWG), 0, s, d, ci0, cj0, nci, ncj, out)
+#define LM_COEF_P(PR)                         \
+    switch (terms) {                          \
+    case 1: LM_COEF(PR, 1); break;            \
+    case 2: LM_COEF(PR, 2); break;            \
+    case 3: LM_COEF(PR, 3); break;            \
+    case 4: LM_COEF(PR, 4); break;            \
+    case 5: LM_COEF(PR, 5); break;            \
+    case 6: LM_COEF(PR, 6); break;            \
+    case 7: LM_COEF(PR, 7); break;            \
+    default: return (int)hipErrorInvalidValue; \
+    }
+    if (precision == 0) {
+        LM_COEF_P(0)
+    } else {
+        LM_COEF_P(1)
+    }
+#undef LM_COEF_P
+#undef LM_COEF
+    return (int)hipGetLastError();
+}
+
+namespace {
+struct TraceLauncher {
+    const LmDesc& d;
+    const int64_t* ii;
+    const int64_t* jj;
+    int64_t n;
+    int32_t* p;
+    int32_t* q;
+    hipStream_t s;
+    template <int S, int PR, int NR, int P>
+    int go()
+    {
+        hipLaunchKernelGGL((k_trace<S, PR, P>), dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG),
+                           0, s, d, ii, jj, n, p, q);
+        return (int)hipGetLastError();
+    }
+};
+struct DeflectLauncher {
+    const LmDesc& d;
+    const double* th;
+    int64_t n;
+    double* al;
+    hipStream_t s;
+    template <int S, int PR, int NR, int P>
+    int go()
+    {
+        hipLaunchKernelGGL((k_deflect<S, PR, P>), dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG),
+                           0, s, d, th, n, al);
+        return (int)hipGetLastError();
+    }
+};
+}  // namespace
+
+int lm_launch_trace(const LmDesc& d, int scheme, int precision, int terms, const int64_t* ii,
+                    const int64_t* jj, int64_t n, int32_t* p, int32_t* q, void* stream)
+{
+    if (n <= 0) return 0;
+    return dispatch_probe(scheme, precision, terms,
+                          TraceLauncher{d, ii, jj, n, p, q, (hipStream_t)stream});
+}
+
+int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, const double* th,
+                      int64_t n, double* alpha, void* stream)
+{
+    if (n <= 0) return 0;
+    return dispatch_probe(scheme, precision, terms,
+                          DeflectLauncher{d, th, n, alpha, (hipStream_t)stream});
+}

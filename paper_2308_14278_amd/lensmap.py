@@ -1,0 +1,339 @@
+"""ctypes binding of liblensmap (include/lensmap.h): the same entry points,
+argument marshalling only.  Every step of the hot path runs in the library's
+HIP kernels; there is no Python or CPU fallback, and importing this module
+fails if the built library is missing.
+
+PyTorch is used for streams only: a ``stream`` argument may be a
+``torch.cuda.Stream``, a raw ``hipStream_t`` integer, or None (the current
+torch stream if torch has a GPU, else the default stream).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblensmap.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lensmap.h")
+
+LM_OK = 0
+LM_EINVAL = -1
+LM_ENOMEM = -2
+LM_EDEVICE = -3
+LM_ESTATE = -4
+LM_ERANGE = -5
+LM_EUNSUPPORTED = -6
+LM_SCHEME_DIRECT = 0
+LM_SCHEME_INTERP = 1
+LM_PREC_MIXED = 0
+LM_PREC_FP32 = 1
+LM_MAX_TERMS = 7
+
+_STATUS_NAMES = {0: "LM_OK", -1: "LM_EINVAL", -2: "LM_ENOMEM", -3: "LM_EDEVICE", -4: "LM_ESTATE",
+                 -5: "LM_ERANGE", -6: "LM_EUNSUPPORTED"}
+
+
+class LensmapError(RuntimeError):
+    def __init__(self, status, func, msg):
+        self.status = status
+        super().__init__("%s -> %s: %s" % (func, _STATUS_NAMES.get(status, status), msg))
+
+
+class lm_geometry(ctypes.Structure):
+    _fields_ = [
+        ("src_x0", ctypes.c_double), ("src_y0", ctypes.c_double),
+        ("src_dx", ctypes.c_double), ("src_dy", ctypes.c_double),
+        ("src_nx", ctypes.c_int32), ("src_ny", ctypes.c_int32),
+        ("ray_x0", ctypes.c_double), ("ray_y0", ctypes.c_double),
+        ("ray_dx", ctypes.c_double), ("ray_dy", ctypes.c_double),
+        ("ray_nx", ctypes.c_int64), ("ray_ny", ctypes.c_int64),
+        ("scheme", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("coarse", ctypes.c_int32), ("l1_kx", ctypes.c_int32), ("l1_ky", ctypes.c_int32),
+        ("near_halo", ctypes.c_int32), ("taylor_terms", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+    @property
+    def n_rays(self):
+        return int(self.ray_nx) * int(self.ray_ny)
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_d = _P(ctypes.c_double)
+_i64 = _P(ctypes.c_int64)
+_i32 = _P(ctypes.c_int32)
+_u64 = _P(ctypes.c_uint64)
+
+_SIGS = {
+    "lm_geometry_derive": [_P(lm_geometry), ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                           ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                           ctypes.c_int32, ctypes.c_int32, ctypes.c_double],
+    "lm_create": [_P(lm_geometry), _P(_vp)],
+    "lm_set_macro": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "lm_set_lenses": [_vp, _d, _d, _d, ctypes.c_int64],
+    "lm_bind_counts": [_vp, _vp],
+    "lm_prepare": [_vp, _vp],
+    "lm_shoot": [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _vp],
+    "lm_sync": [_vp],
+    "lm_read_counts": [_vp, _u64, _u64, _u64],
+    "lm_mu_factor": [_vp, _d],
+    "lm_read_mu": [_vp, _d],
+    "lm_reset_counts": [_vp, _vp],
+    "lm_deflect": [_vp, _d, ctypes.c_int64, _d],
+    "lm_trace": [_vp, _i64, _i64, ctypes.c_int64, _i32, _i32],
+    "lm_batch_create": [_P(_vp), ctypes.c_int32, _P(_vp)],
+    "lm_batch_set_rect": [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                          ctypes.c_int64],
+    "lm_batch_tune": [_vp, ctypes.c_char_p],
+    "lm_batch_shoot": [_vp, _vp],
+    "lm_batch_params": [_vp, _i32, _i32, _i32],
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblensmap.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError("liblensmap.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_2308_14278_amd.build_lib): " + path)
+        lib = ctypes.CDLL(path)
+        for name, args in _SIGS.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int32
+        lib.lm_destroy.argtypes = [_vp]
+        lib.lm_destroy.restype = None
+        lib.lm_batch_destroy.argtypes = [_vp]
+        lib.lm_batch_destroy.restype = None
+        lib.lm_last_error.restype = ctypes.c_char_p
+        lib.lm_version.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def header_symbols(path: str = HEADER):
+    """Function names declared in include/lensmap.h."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lm_[a-z_]+)\s*\(", txt)))
+
+
+def _check(status, func):
+    if status != LM_OK:
+        raise LensmapError(status, func, lm_last_error())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------ entry points
+
+
+def lm_last_error() -> str:
+    return load().lm_last_error().decode()
+
+
+def lm_version() -> str:
+    return load().lm_version().decode()
+
+
+def lm_geometry_derive(src_lx, src_ly, src_nx, src_ny, kappa, gamma, kappa_star, protect=-1.0,
+                       n_rays=0.0, ray_nx=0, ray_ny=0, scheme=LM_SCHEME_INTERP, coarse=0,
+                       mean_mass=1.0) -> lm_geometry:
+    g = lm_geometry()
+    p = -1.0 if protect is None else float(protect)
+    _check(load().lm_geometry_derive(ctypes.byref(g), src_lx, src_ly, src_nx, src_ny, kappa, gamma,
+                                     kappa_star, p, float(n_rays or 0.0), int(ray_nx or 0),
+                                     int(ray_ny or 0), scheme, coarse, mean_mass),
+           "lm_geometry_derive")
+    return g
+
+
+def lm_create(g: lm_geometry):
+    h = ctypes.c_void_p()
+    _check(load().lm_create(ctypes.byref(g), ctypes.byref(h)), "lm_create")
+    return h
+
+
+def lm_destroy(m):
+    if m:
+        load().lm_destroy(m)
+
+
+def lm_set_macro(m, kappa, gamma, kappa_star):
+    _check(load().lm_set_macro(m, kappa, gamma, kappa_star), "lm_set_macro")
+
+
+def lm_set_lenses(m, x, y, mass):
+    x, y, mass = _f64(x), _f64(y), _f64(mass)
+    n = x.shape[0]
+    if y.shape[0] != n or mass.shape[0] != n:
+        raise ValueError("lens arrays differ in length")
+    _check(load().lm_set_lenses(m, x.ctypes.data_as(_d), y.ctypes.data_as(_d),
+                                mass.ctypes.data_as(_d), n), "lm_set_lenses")
+
+
+def lm_bind_counts(m, device_ptr):
+    """Bind a caller-owned device buffer (int address, e.g. tensor.data_ptr()) or None."""
+    _check(load().lm_bind_counts(m, ctypes.c_void_p(device_ptr or 0)), "lm_bind_counts")
+
+
+def lm_prepare(m, stream=None):
+    _check(load().lm_prepare(m, _stream_ptr(stream)), "lm_prepare")
+
+
+def lm_shoot(m, i0, j0, ni, nj, stream=None):
+    _check(load().lm_shoot(m, int(i0), int(j0), int(ni), int(nj), _stream_ptr(stream)), "lm_shoot")
+
+
+def lm_sync(m):
+    _check(load().lm_sync(m), "lm_sync")
+
+
+def lm_read_counts(m, g: lm_geometry, with_counts=True):
+    """Returns (counts[src_ny, src_nx] uint64 or None, n_out, n_shot)."""
+    counts = np.empty((g.src_ny, g.src_nx), dtype=np.uint64) if with_counts else None
+    nout = ctypes.c_uint64()
+    nshot = ctypes.c_uint64()
+    ptr = counts.ctypes.data_as(_u64) if with_counts else None
+    _check(load().lm_read_counts(m, ptr, ctypes.byref(nout), ctypes.byref(nshot)),
+           "lm_read_counts")
+    return counts, int(nout.value), int(nshot.value)
+
+
+def lm_mu_factor(m) -> float:
+    f = ctypes.c_double()
+    _check(load().lm_mu_factor(m, ctypes.byref(f)), "lm_mu_factor")
+    return f.value
+
+
+def lm_read_mu(m, g: lm_geometry):
+    mu = np.empty((g.src_ny, g.src_nx), dtype=np.float64)
+    _check(load().lm_read_mu(m, mu.ctypes.data_as(_d)), "lm_read_mu")
+    return mu
+
+
+def lm_reset_counts(m, stream=None):
+    _check(load().lm_reset_counts(m, _stream_ptr(stream)), "lm_reset_counts")
+
+
+def lm_deflect(m, theta):
+    th = _f64(theta).reshape(-1, 2)
+    out = np.empty_like(th)
+    _check(load().lm_deflect(m, th.ctypes.data_as(_d), th.shape[0], out.ctypes.data_as(_d)),
+           "lm_deflect")
+    return out
+
+
+def lm_trace(m, i, j):
+    i = np.ascontiguousarray(i, dtype=np.int64)
+    j = np.ascontiguousarray(j, dtype=np.int64)
+    p = np.empty(i.shape[0], dtype=np.int32)
+    q = np.empty(i.shape[0], dtype=np.int32)
+    _check(load().lm_trace(m, i.ctypes.data_as(_i64), j.ctypes.data_as(_i64), i.shape[0],
+                           p.ctypes.data_as(_i32), q.ctypes.data_as(_i32)), "lm_trace")
+    return p, q
+
+
+def lm_batch_create(maps):
+    arr = (ctypes.c_void_p * len(maps))(*[m.value if isinstance(m, ctypes.c_void_p) else m
+                                          for m in maps])
+    h = ctypes.c_void_p()
+    _check(load().lm_batch_create(arr, len(maps), ctypes.byref(h)), "lm_batch_create")
+    return h
+
+
+def lm_batch_set_rect(b, index, i0, j0, ni, nj):
+    _check(load().lm_batch_set_rect(b, index, int(i0), int(j0), int(ni), int(nj)),
+           "lm_batch_set_rect")
+
+
+def lm_batch_tune(b, cache_path=None):
+    _check(load().lm_batch_tune(b, cache_path.encode() if cache_path else None), "lm_batch_tune")
+
+
+def lm_batch_shoot(b, stream=None):
+    _check(load().lm_batch_shoot(b, _stream_ptr(stream)), "lm_batch_shoot")
+
+
+def lm_batch_params(b):
+    a, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lm_batch_params(b, ctypes.byref(a), ctypes.byref(c), ctypes.byref(d)),
+           "lm_batch_params")
+    return int(a.value), int(c.value), int(d.value)
+
+
+def lm_batch_destroy(b):
+    if b:
+        load().lm_batch_destroy(b)
+
+
+# ------------------------------------------------------------ convenience
+
+
+class Map:
+    """Owning wrapper: geometry + macro + lenses, with the ABI's calls as methods."""
+
+    def __init__(self, g: lm_geometry, kappa=0.0, gamma=0.0, kappa_star=0.0, lenses=None):
+        self.g = g
+        self.h = lm_create(g)
+        lm_set_macro(self.h, kappa, gamma, kappa_star)
+        if lenses is not None:
+            lm_set_lenses(self.h, *lenses)
+
+    def shoot(self, i0=0, j0=0, ni=None, nj=None, stream=None):
+        ni = self.g.ray_nx - i0 if ni is None else ni
+        nj = self.g.ray_ny - j0 if nj is None else nj
+        lm_shoot(self.h, i0, j0, ni, nj, stream)
+
+    def counts(self):
+        return lm_read_counts(self.h, self.g)
+
+    def reset(self, stream=None):
+        lm_reset_counts(self.h, stream)
+
+    def trace(self, i, j):
+        return lm_trace(self.h, i, j)
+
+    def deflect(self, theta):
+        return lm_deflect(self.h, theta)
+
+    def mu_factor(self):
+        return lm_mu_factor(self.h)
+
+    def close(self):
+        if self.h:
+            lm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function the header declares, derives geometry by the paper's rules in
+agreement with the oracle's independent derivation, and rejects bad input
+before touching a device."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import paper_2308_14278_amd.lensmap as lm
+from oracle.geometry import derive_geometry
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return lm.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = lm.header_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layout_matches_header(lib):
+    # int32 fields are packed in pairs; the struct must be 8-byte aligned
+    assert ctypes.sizeof(lm.lm_geometry) == 8 * 4 + 4 * 2 + 8 * 4 + 8 * 2 + 4 * 8
+
+
+def test_version(lib):
+    assert "gfx950" in lm.lm_version()
+
+
+@pytest.mark.parametrize("kind", ["plain-small", "near-fold", "paper-scale", "precision-stress"])
+def test_geometry_matches_oracle(kind):
+    from paper_2308_14278_amd import inputs
+    w = inputs.WORKLOADS[kind]()
+    kw = dict(n_rays=w.n_rays, ray_nx=w.ray_nx, ray_ny=w.ray_ny, protect=w.protect,
+              scheme=w.scheme, coarse=w.coarse)
+    go = derive_geometry(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa, w.gamma,
+                         w.kappa_star, mean_mass=w.mean_mass, **kw)
+    gl = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                               w.gamma, w.kappa_star, mean_mass=w.mean_mass, **kw)
+    for f in ("src_nx", "src_ny", "ray_nx", "ray_ny", "coarse"):
+        assert getattr(gl, f) == getattr(go, f), f
+    if w.scheme == 1:
+        assert (gl.l1_kx, gl.l1_ky) == (go.l1_kx, go.l1_ky)
+    for f in ("src_x0", "src_y0", "src_dx", "src_dy", "ray_x0", "ray_y0", "ray_dx", "ray_dy"):
+        assert math.isclose(getattr(gl, f), getattr(go, f), rel_tol=1e-14), f
+    assert gl.near_halo == 1 and gl.taylor_terms == 4
+
+
+def test_paper_scale_geometry_numbers():
+    """Paper-scale workload: 1e13 rays, level-2 cells of ~L1/20, level-1 ~ L0."""
+    from paper_2308_14278_amd import inputs
+    w = inputs.paper_scale()
+    g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                              w.gamma, w.kappa_star, n_rays=w.n_rays, mean_mass=w.mean_mass)
+    assert abs(g.n_rays / 1e13 - 1) < 1e-5
+    l0 = math.sqrt(math.pi * w.mean_mass / w.kappa_star)
+    assert abs(g.coarse * g.ray_dx * 20 / l0 - 1) < 0.05
+    assert g.l1_kx == 20
+
+
+def test_derive_rejects_bad_input():
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_geometry_derive(10, 10, 64, 64, 0.5, 0.5, 0.01, n_rays=1e6)  # lt = 0: singular
+    assert e.value.status == lm.LM_EINVAL
+    with pytest.raises(lm.LensmapError):
+        lm.lm_geometry_derive(float("nan"), 10, 64, 64, 0.4, 0.5, 0.01, n_rays=1e6)
+    with pytest.raises(lm.LensmapError):
+        lm.lm_geometry_derive(10, 10, 0, 64, 0.4, 0.5, 0.01, n_rays=1e6)
+
+
+def _good():
+    return lm.lm_geometry_derive(10, 10, 64, 64, 0.45, 0.5, 0.01, n_rays=1e6, scheme=1, coarse=64)
+
+
+@pytest.mark.parametrize("field,value", [("coarse", 100), ("coarse", 0), ("src_nx", 0),
+                                         ("ray_dx", -1.0), ("taylor_terms", 9),
+                                         ("scheme", 5), ("precision", 3), ("l1_kx", 0),
+                                         ("ray_x0", float("inf"))])
+def test_create_rejects_invalid_geometry(field, value):
+    g = _good()
+    setattr(g, field, value)
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_create(g)
+    assert e.value.status == lm.LM_EINVAL
+    assert lm.lm_last_error() != ""
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.lm_shoot(None, 0, 0, 1, 1, None) == lm.LM_EINVAL
+    assert lib.lm_set_macro(None, 0.0, 0.0, 0.0) == lm.LM_EINVAL
+    assert lib.lm_read_counts(None, None, None, None) == lm.LM_EINVAL
+    assert lib.lm_batch_shoot(None, None) == lm.LM_EINVAL
+    lib.lm_destroy(None)
+    lib.lm_batch_destroy(None)

@@ -1,0 +1,362 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (from the stated tolerances): bin-mismatch fraction <= 1e-5 of the rays
+shot, per-pixel |dN|/N <= 1e-3 where the oracle count is >= 1e4, every ray
+counted exactly, interpolated deflection within 1e-4 theta_E of the direct
+sum.  Several maps are correct where a ray's exact image lies within rounding
+of a pixel edge, so map parity is statistical (mismatch fraction), while
+integer properties (ray conservation, additivity, batch == per-map, tuned ==
+default, probe == kernel) are compared bit for bit.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2308_14278_amd.lensmap as lm
+from paper_2308_14278_amd import inputs
+from helpers import max_pixel_rel, mismatch_fraction, oracle_geom
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _geom(w, **over):
+    g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                              w.gamma, w.kappa_star, protect=w.protect, n_rays=w.n_rays or 0.0,
+                              ray_nx=w.ray_nx or 0, ray_ny=w.ray_ny or 0, scheme=w.scheme,
+                              coarse=w.coarse, mean_mass=w.mean_mass)
+    for k, v in over.items():
+        setattr(g, k, v)
+    return g
+
+
+def _pair(w, **over):
+    """Library map and oracle on the same workload and lenses."""
+    g = _geom(w, **over)
+    x, y, m = w.lenses()
+    mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, (x, y, m))
+    orc = oracle.Oracle(oracle_geom(g), w.kappa, w.gamma, w.kappa_star, x, y, m)
+    return g, mp, orc
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    lm.load()
+    oracle.build()
+
+
+def _compare(g, counts, n_out, ref, ref_out, rays, what):
+    mis = mismatch_fraction(counts, ref, rays)
+    pix = max_pixel_rel(counts, ref)
+    _say("%s: rays=%d mismatch=%.3e max_pixel_rel=%.2e n_out gpu/oracle=%d/%d" %
+         (what, rays, mis, pix, n_out, ref_out))
+    assert int(counts.sum()) + n_out == rays
+    assert int(ref.sum()) + ref_out == rays
+    assert mis <= 1e-5
+    assert pix <= 1e-3
+    return mis
+
+
+# ------------------------------------------------------------- direct sum
+
+
+def test_plain_small_full_map():
+    """Plain method, small: 100 unit lenses, 4096^2 rays, 256^2 map, direct sum."""
+    w = inputs.plain_small()
+    g, mp, orc = _pair(w)
+    mp.shoot()
+    counts, n_out, n_shot = mp.counts()
+    assert n_shot == g.n_rays
+    ref, ref_out = orc.shoot(nthreads=NTHREADS)
+    _compare(g, counts, n_out, ref, ref_out, g.n_rays, "plain-small direct")
+    mp.close()
+
+
+def test_zero_lenses_exact_macro():
+    """No lenses, no sheet, pixels of exactly 16 x 16 ray images: 256 per pixel."""
+    g = lm.lm_geometry_derive(10.0, 10.0, 64, 64, 0.45, 0.5, 0.0, protect=0.0, ray_nx=1024,
+                              ray_ny=1024, scheme=lm.LM_SCHEME_DIRECT, coarse=64)
+    mp = lm.Map(g, 0.45, 0.5, 0.0, ([], [], []))
+    mp.shoot()
+    counts, n_out, _ = mp.counts()
+    assert np.all(counts == 256) and n_out == 0
+    mu = counts * mp.mu_factor()
+    np.testing.assert_allclose(mu, 1.0 / abs(0.55 ** 2 - 0.25), rtol=1e-12)
+    mp.close()
+
+
+def test_single_lens_vs_oracle():
+    """One unit lens at the origin (kappa = gamma = kappa_star = 0)."""
+    g = lm.lm_geometry_derive(4.0, 4.0, 32, 32, 0.0, 0.0, 0.0, protect=2.0, ray_nx=2048,
+                              ray_ny=2048, scheme=lm.LM_SCHEME_DIRECT, coarse=64)
+    mp = lm.Map(g, 0.0, 0.0, 0.0, ([0.0], [0.0], [1.0]))
+    mp.shoot()
+    counts, n_out, _ = mp.counts()
+    ref, ref_out = oracle.Oracle(oracle_geom(g), 0, 0, 0, [0.0], [0.0], [1.0]).shoot(
+        nthreads=NTHREADS)
+    _compare(g, counts, n_out, ref, ref_out, g.n_rays, "single lens")
+    mp.close()
+
+
+# ------------------------------------------------------ interpolated scheme
+
+
+def test_near_fold_subrect_vs_oracle():
+    """Near-fold map (2000 lenses, 64x64-ray cells): a ragged sub-rectangle of
+    ~1.7e7 rays spanning many workgroup tiles, against the oracle."""
+    w = inputs.near_fold()
+    g, mp, orc = _pair(w)
+    i0, j0, ni, nj = 900_037, 20_011, 5_777, 3_001
+    mp.shoot(i0, j0, ni, nj)
+    counts, n_out, n_shot = mp.counts()
+    ref, ref_out = orc.shoot(i0, j0, ni, nj, nthreads=NTHREADS)
+    _compare(g, counts, n_out, ref, ref_out, ni * nj, "near-fold sub-rect")
+    mp.close()
+
+
+def test_trace_probe_rebuilds_shot_map():
+    """lm_trace (one ray per thread) reproduces the shooting kernel bit for bit."""
+    w = inputs.near_fold()
+    g = _geom(w)
+    x, y, m = w.lenses()
+    mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, (x, y, m))
+    i0, j0, ni, nj = 1_000_003, 30_000, 700, 333
+    mp.shoot(i0, j0, ni, nj)
+    counts, n_out, _ = mp.counts()
+    ii, jj = np.meshgrid(np.arange(i0, i0 + ni), np.arange(j0, j0 + nj))
+    p, q = mp.trace(ii.ravel(), jj.ravel())
+    inside = p >= 0
+    rebuilt = np.zeros(g.src_nx * g.src_ny, dtype=np.int64)
+    np.add.at(rebuilt, q[inside].astype(np.int64) * g.src_nx + p[inside], 1)
+    np.testing.assert_array_equal(rebuilt.reshape(counts.shape), counts.astype(np.int64))
+    assert (~inside).sum() == n_out
+    mp.close()
+
+
+def test_additivity_and_empty_shots():
+    w = inputs.near_fold()
+    g, mp, _ = _pair(w)
+    i0, j0 = 500_000, 10_000
+    mp.shoot(i0, j0, 1000, 0)  # empty
+    mp.shoot(i0, j0, 0, 1000)  # empty
+    mp.shoot(i0, j0, 2000, 700)
+    a, na, _ = mp.counts()
+    mp.reset()
+    mp.shoot(i0, j0, 2000, 300)
+    mp.shoot(i0, j0 + 300, 1, 400)
+    mp.shoot(i0 + 1, j0 + 300, 1999, 400)
+    b, nb, nshot = mp.counts()
+    np.testing.assert_array_equal(a, b)
+    assert na == nb and nshot == 2000 * 700
+    mp.close()
+
+
+@pytest.mark.parametrize("kind", ["paper-scale", "precision-stress"])
+def test_full_size_sampled_rays_vs_oracle(kind):
+    """Full-size lattices (1e13 and 4e12 rays): pixels of 3000 sampled rays from
+    the probe that shares the kernel's arithmetic, against the oracle, one by one."""
+    w = inputs.WORKLOADS[kind]()
+    g, mp, orc = _pair(w)
+    rng = np.random.default_rng(17)
+    n = 3000
+    ii = rng.integers(0, g.ray_nx, n)
+    jj = rng.integers(0, g.ray_ny, n)
+    p, q = mp.trace(ii, jj)
+    _, pix = orc.trace(ii, jj)
+    gpu_pix = np.where(p >= 0, q.astype(np.int64) * g.src_nx + p, -1)
+    flips = int((gpu_pix != pix).sum())
+    _say("%s: %d sampled rays, %d in map, %d flips" % (kind, n, int((pix >= 0).sum()), flips))
+    assert flips <= 1
+    mp.close()
+
+
+def test_paper_scale_band_conservation_and_probe():
+    """A 1e10-ray band of the paper-scale map through the timed launch path:
+    every ray counted, and the counts of a small sub-block equal the traced
+    pixels of its rays."""
+    w = inputs.paper_scale()
+    g, mp, _ = _pair(w)
+    ni, nj = 2_000_000, 5_000
+    i0, j0 = g.ray_nx // 2 - ni // 2, g.ray_ny // 2
+    mp.shoot(i0, j0, ni, nj)
+    counts, n_out, n_shot = mp.counts()
+    assert n_shot == ni * nj and int(counts.sum()) + n_out == ni * nj
+    mp.reset()
+    bi, bj = 3000, 200
+    mp.shoot(i0, j0, bi, bj)
+    c2, o2, _ = mp.counts()
+    ii, jj = np.meshgrid(np.arange(i0, i0 + bi), np.arange(j0, j0 + bj))
+    p, q = mp.trace(ii.ravel(), jj.ravel())
+    rebuilt = np.zeros(g.src_nx * g.src_ny, dtype=np.int64)
+    inside = p >= 0
+    np.add.at(rebuilt, q[inside].astype(np.int64) * g.src_nx + p[inside], 1)
+    np.testing.assert_array_equal(rebuilt.reshape(c2.shape), c2.astype(np.int64))
+    mp.close()
+
+
+def test_paper_scale_subrect_map_vs_oracle():
+    """Paper-scale geometry (13000 lenses, ~1856-ray cells): a 2.2e7-ray map
+    region against the oracle."""
+    w = inputs.paper_scale()
+    g, mp, orc = _pair(w)
+    ni, nj = 40_000, 550
+    i0, j0 = g.ray_nx // 3 + 17, g.ray_ny // 2 - 300
+    mp.shoot(i0, j0, ni, nj)
+    counts, n_out, _ = mp.counts()
+    ref, ref_out = orc.shoot(i0, j0, ni, nj, nthreads=NTHREADS)
+    _compare(g, counts, n_out, ref, ref_out, ni * nj, "paper-scale sub-rect")
+    mp.close()
+
+
+def test_deflection_interp_error_vs_direct():
+    """Interpolated deflection from the GPU within 1e-4 theta_E of the direct
+    sum (and within FP32 rounding of the oracle's interpolated value)."""
+    w = inputs.paper_scale()
+    g, mp, orc = _pair(w)
+    rng = np.random.default_rng(5)
+    n = 4000
+    cx = g.ray_x0 + rng.uniform(0.3, 0.7, n) * g.ray_nx * g.ray_dx
+    cy = g.ray_y0 + rng.uniform(0.05, 0.95, n) * g.ray_ny * g.ray_dy
+    th = np.stack([cx, cy], axis=1)
+    a_gpu = mp.deflect(th)
+    a_dir = orc.deflect_direct(th)
+    a_int = orc.deflect(th)
+    err_dir = np.hypot(*(a_gpu - a_dir).T)
+    err_int = np.hypot(*(a_gpu - a_int).T)
+    scale = np.hypot(*a_int.T)
+    _say("deflection: max |gpu-direct|=%.2e, max |gpu-oracle interp|=%.2e (|alpha| up to %.1f)" %
+         (err_dir.max(), err_int.max(), scale.max()))
+    assert err_dir.max() <= 1e-4
+    assert np.all(err_int <= 1e-6 * np.maximum(1.0, scale))
+    mp.close()
+
+
+# ------------------------------------------------------------ batch path
+
+
+def _small_batch(nmaps=6, rays_scale=1e-3):
+    ws = inputs.batched_study(nmaps, rays_scale)
+    maps = []
+    for w in ws:
+        g = _geom(w)
+        maps.append((w, g, lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses())))
+    return maps
+
+
+def test_batch_equals_per_map_and_tuned_equals_default(tmp_path):
+    maps = _small_batch()
+    ref = []
+    for w, g, mp in maps:
+        mp.shoot()
+        ref.append(mp.counts())
+        mp.reset()
+    b = lm.lm_batch_create([mp.h for _, _, mp in maps])
+    lm.lm_batch_shoot(b)
+    for (w, g, mp), (c, o, s) in zip(maps, ref):
+        c2, o2, s2 = mp.counts()
+        np.testing.assert_array_equal(c, c2)
+        assert (o, s) == (o2, s2)
+        mp.reset()
+    cache = str(tmp_path / "tune.txt")
+    lm.lm_batch_tune(b, cache)
+    params = lm.lm_batch_params(b)
+    _say("tuned params %s" % (params,))
+    lm.lm_batch_shoot(b)
+    lm.lm_batch_shoot(b)  # graph replay: counts double
+    for (w, g, mp), (c, o, s) in zip(maps, ref):
+        c2, o2, s2 = mp.counts()
+        np.testing.assert_array_equal(2 * c.astype(np.int64), c2.astype(np.int64))
+        assert 2 * o == o2 and 2 * s == s2
+    # the cache is reused
+    lm.lm_batch_tune(b, cache)
+    assert lm.lm_batch_params(b) == params
+    lm.lm_batch_destroy(b)
+    for _, _, mp in maps:
+        mp.close()
+
+
+def test_batch_map_vs_oracle():
+    """One map of the batched study, shot by the batch kernel, against the oracle."""
+    maps = _small_batch(nmaps=3, rays_scale=1e-4)
+    b = lm.lm_batch_create([mp.h for _, _, mp in maps])
+    w, g, mp = maps[1]
+    rect = (g.ray_nx // 4, 0, min(6000, g.ray_nx // 2), g.ray_ny)
+    for k, (_, gk, _) in enumerate(maps):
+        if k != 1:
+            lm.lm_batch_set_rect(b, k, 0, 0, min(1000, gk.ray_nx), min(1000, gk.ray_ny))
+    lm.lm_batch_set_rect(b, 1, *rect)
+    lm.lm_batch_shoot(b)
+    counts, n_out, _ = mp.counts()
+    x, y, m = w.lenses()
+    ref, ref_out = oracle.Oracle(oracle_geom(g), w.kappa, w.gamma, w.kappa_star, x, y, m).shoot(
+        *rect, nthreads=NTHREADS)
+    _compare(g, counts, n_out, ref, ref_out, rect[2] * rect[3], "batched map 1")
+    lm.lm_batch_destroy(b)
+    for _, _, mp2 in maps:
+        mp2.close()
+
+
+# ---------------------------------------------------------- plain FP32 path
+
+
+def test_plain_fp32_path_runs_and_is_worse():
+    """The global-FP32 comparison path conserves rays; its error against the
+    oracle is reported next to the mixed path's."""
+    w = inputs.precision_stress()
+    rng = np.random.default_rng(23)
+    res = {}
+    for prec in (lm.LM_PREC_MIXED, lm.LM_PREC_FP32):
+        g, mp, orc = _pair(w, precision=prec)
+        ii = rng.integers(0, g.ray_nx, 2000)
+        jj = rng.integers(0, g.ray_ny, 2000)
+        p, q = mp.trace(ii, jj)
+        _, pix = orc.trace(ii, jj)
+        gpu_pix = np.where(p >= 0, q.astype(np.int64) * g.src_nx + p, -1)
+        res[prec] = float((gpu_pix != pix).mean())
+        i0, j0 = g.ray_nx // 2, g.ray_ny // 2
+        mp.shoot(i0, j0, 4096, 512)
+        c, o, s = mp.counts()
+        assert int(c.sum()) + o == s == 4096 * 512
+        mp.close()
+    _say("sampled flip rate: mixed %.2e, plain fp32 %.2e" % (res[0], res[1]))
+    assert res[0] <= 1e-3
+    assert res[1] > res[0]
+
+
+# ------------------------------------------------------------ error paths
+
+
+def test_error_paths():
+    w = inputs.near_fold()
+    g, mp, _ = _pair(w)
+    with pytest.raises(lm.LensmapError) as e:
+        mp.shoot(g.ray_nx - 10, 0, 11, 1)
+    assert e.value.status == lm.LM_ERANGE
+    mp.shoot(0, 0, 64, 64)
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_set_lenses(mp.h, [0.0], [0.0], [1.0])
+    assert e.value.status == lm.LM_ESTATE
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_set_macro(mp.h, 0.1, 0.1, 0.1)
+    assert e.value.status == lm.LM_ESTATE
+    mp.reset()
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_set_lenses(mp.h, [0.0], [float("nan")], [1.0])
+    assert e.value.status == lm.LM_EINVAL
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_set_lenses(mp.h, [0.0], [0.0], [-1.0])
+    assert e.value.status == lm.LM_EINVAL
+    with pytest.raises(lm.LensmapError) as e:
+        mp.trace([g.ray_nx], [0])
+    assert e.value.status == lm.LM_ERANGE
+    mp.close()
