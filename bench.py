@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput of inverse ray-shooting on one MI355X, paper-scale workload.
+
+One step = the whole hot path for one magnification map of the paper-scale
+workload (13000 Salpeter microlenses, lambda_t = 0.005, lambda_r = 0.3,
+kappa_star = 0.01, 1e13 rays, 5000 x 5000 uint64 map): counts reset, far-field
+Taylor coefficients of every level-2 cell, the persistent shooting kernel
+(one HIP-graph launch of the batched executor, autotuned), read-back of the
+counts and the magnification map.  Inputs (lenses, partition) are resident on
+the device before the timed region.
+
+Printed: one JSON line with the whole-job rays/s, the shooting kernel's
+roofline figures (algorithmic FP32 FLOPs from the exact near-lens pair count,
+over its event-timed duration, against the 157.3 TFLOP/s FP32 vector peak),
+the plain per-map FP32 comparison path, and the FP64 CPU oracle timed on a
+bounded sample of the same workload with the map errors of both GPU paths.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/s at 13k lenses; batched mixed vs plain per-map at stated map error vs FP64"
+PEAK_FP32_TFLOPS = 157.3
+KERNEL_SRC = os.path.join(ROOT, "paper_2308_14278_amd", "csrc", "lm_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_shoot_batch_paper_scale.json")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_flops(stats, terms):
+    """FP32 FLOPs the method needs per shot: 11 per near ray-lens pair (2 sub,
+    r^2 3, rcp 1, m*w 1, 2 FMA 4), 8 per Taylor term after a_0, 8 for the
+    map and pixel (rcp = 1, FMA = 2)."""
+    return 11.0 * stats.near_pairs + (8.0 * (terms - 1) + 8.0) * stats.rays
+
+
+def load_traffic(launch_rays):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    return t["bytes_per_ray"] * launch_rays
+
+
+def make_map(lm, w, g, lenses, precision):
+    g2 = type(g)()
+    for k, _ in g._fields_:
+        setattr(g2, k, getattr(g, k))
+    g2.precision = precision
+    return lm.Map(g2, w.kappa, w.gamma, w.kappa_star, lenses), g2
+
+
+def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
+    """The FP64 oracle on a bounded sample of the workload, and the errors of
+    the mixed and plain-FP32 GPU maps against it."""
+    import numpy as np
+
+    import oracle
+    from oracle.geometry import OracleGeometry
+    oracle.build()
+    og = OracleGeometry(**{k: getattr(g, k) for k in
+                           ("src_x0", "src_y0", "src_dx", "src_dy", "src_nx", "src_ny", "ray_x0",
+                            "ray_y0", "ray_dx", "ray_dy", "ray_nx", "ray_ny", "scheme", "coarse",
+                            "l1_kx", "l1_ky")}, halo=g.near_halo, terms=g.taylor_terms)
+    orc = oracle.Oracle(og, w.kappa, w.gamma, w.kappa_star, *lenses)
+    cores = oracle.num_threads()
+    # calibrate on a small block, then size the sample to the time budget
+    nj = 1856
+    i0, j0 = g.ray_nx // 2, g.ray_ny // 2 - nj // 2
+    t0 = time.perf_counter()
+    orc.shoot(i0, j0, 2048, nj)
+    rate0 = 2048 * nj / (time.perf_counter() - t0)
+    ni = int(max(4096, min(g.ray_nx // 2, rate0 * budget_s / nj)))
+    ni -= ni % 64
+    t0 = time.perf_counter()
+    ref, ref_out = orc.shoot(i0, j0, ni, nj)
+    dt = time.perf_counter() - t0
+    rays = ni * nj
+    log("oracle: %d rays in %.1f s on %d threads" % (rays, dt, cores))
+    errors = {}
+    rng = np.random.default_rng(2308)
+    ii = rng.integers(0, g.ray_nx, 4000)
+    jj = rng.integers(0, g.ray_ny, 4000)
+    _, pix = orc.trace(ii, jj)
+    for name, mp in (("batched_mixed", mp_mixed), ("plain_fp32", mp_fp32)):
+        mp.reset()
+        mp.shoot(i0, j0, ni, nj)
+        c, o, _ = mp.counts()
+        d = np.abs(c.astype(np.int64) - ref.astype(np.int64))
+        big = ref >= 10000
+        per_pix = float((d[big] / ref[big]).max()) if big.any() else 0.0
+        p, q = mp.trace(ii, jj)
+        gp = np.where(p >= 0, q.astype(np.int64) * g.src_nx + p, -1)
+        errors[name] = {"bin_mismatch": 0.5 * float(d.sum()) / rays,
+                        "max_pixel_rel_err_counts_ge_1e4": per_pix,
+                        "n_out_diff": int(o) - int(ref_out),
+                        "sampled_full_lattice_rays": int(ii.shape[0]),
+                        "sampled_pixel_flips": int((gp != pix).sum())}
+        mp.reset()
+    return {"value": rays / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
+            "sample": "FP64 oracle, interpolated scheme, %d x %d-ray sub-rectangle (%.3g rays) "
+                      "of the paper-scale lattice at i0=%d, j0=%d" % (ni, nj, rays, i0, j0),
+            "seconds": dt}, errors
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="time budget of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-rays", type=float, default=5e11,
+                    help="rays of the per-map comparison runs")
+    ap.add_argument("--rays", type=float, default=1e13,
+                    help="rays per map (1e13 is the workload; smaller values are for profiling)")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(how the work would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2308_14278_amd.lensmap as lm
+    from paper_2308_14278_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    lm.load()
+    w = inputs.paper_scale()
+    g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                              w.gamma, w.kappa_star, protect=w.protect, n_rays=args.rays,
+                              scheme=w.scheme, coarse=w.coarse, mean_mass=w.mean_mass)
+    lenses = w.lenses()
+    log("geometry: %d x %d rays (%.4g), R=%d, K=%dx%d, %d lenses" %
+        (g.ray_nx, g.ray_ny, g.n_rays, g.coarse, g.l1_kx, g.l1_ky, w.n_lenses))
+    mp, _ = make_map(lm, w, g, lenses, lm.LM_PREC_MIXED)
+    stats = lm.lm_shot_stats(mp.h, 0, 0, g.ray_nx, g.ray_ny)
+    flops = algorithmic_flops(stats, g.taylor_terms)
+    log("near pairs per ray %.3f, FLOP per ray %.1f" % (stats.near_pairs / stats.rays,
+                                                         flops / stats.rays))
+    b = lm.lm_batch_create([mp.h])
+    stream = torch.cuda.current_stream()
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        lm.lm_batch_tune(b, os.environ.get("LENSMAP_TUNE_CACHE"))
+        log("tuned %s in %.1f s" % (lm.lm_batch_params(b), time.perf_counter() - t0))
+
+    def step():
+        lm.lm_reset_counts(mp.h, stream)
+        lm.lm_batch_shoot(b, stream)
+        mu = lm.lm_read_mu(mp.h, g)
+        return mu
+
+    for k in range(args.warmup):
+        t0 = time.perf_counter()
+        step()
+        log("warmup %d: %.2f s" % (k, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    shoot_ms, coeff_ms = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        mu = step()
+        c_ms, s_ms = lm.lm_batch_timing(b)
+        coeff_ms.append(c_ms)
+        shoot_ms.append(s_ms)
+        log("step %d: shoot kernel %.1f ms, coefficients %.1f ms" % (k, s_ms, c_ms))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    counts, n_out, n_shot = lm.lm_read_counts(mp.h, g)
+    assert int(counts.sum()) + n_out == g.n_rays, "ray count not conserved"
+    assert abs(float(mu.mean()) - float(counts.mean()) * mp.mu_factor()) <= 1e-9 * float(mu.mean())
+    value = g.n_rays * args.steps / elapsed
+    avg_shoot_s = float(np.mean(shoot_ms)) / 1e3
+    achieved = flops / avg_shoot_s / 1e12
+    traffic = load_traffic(g.n_rays)
+    log("value %.4g rays/s; shoot kernel %.2f s -> %.1f TFLOP/s" % (value, avg_shoot_s, achieved))
+
+    # plain per-map FP32 path and the mixed per-map path on the same band
+    nj = min(g.ray_ny, 4 * g.coarse)
+    ni = min(g.ray_nx, int(args.plain_rays / nj) // 64 * 64)
+    i0 = (g.ray_nx - ni) // 2
+    j0 = (g.ray_ny - nj) // 2
+    mp32, _ = make_map(lm, w, g, lenses, lm.LM_PREC_FP32)
+    per_map = {}
+    for name, m in (("plain_fp32_per_map", mp32), ("mixed_per_map", mp)):
+        m.reset(stream)
+        m.shoot(i0, j0, ni, nj, stream)  # coefficients + warm-up
+        torch.cuda.synchronize()
+        m.reset(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m.shoot(i0, j0, ni, nj, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        per_map[name] = {"value": ni * nj / dt, "unit": "rays/s",
+                         "sample": "%d x %d-ray band of the paper-scale lattice" % (ni, nj)}
+        log("%s: %.4g rays/s" % (name, ni * nj / dt))
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale: 13000 Salpeter lenses (0.08-1.5), lambda_t=0.005, "
+                               "lambda_r=0.3, kappa_star=0.01, %.4g rays, 5000x5000 uint64 map "
+                               "over 24x24 theta_E, interpolated scheme (P=4, R=%d, K=%dx%d), "
+                               "batched mixed-precision path" %
+                               (g.n_rays, g.coarse, g.l1_kx, g.l1_ky),
+                   "rays": g.n_rays, "lenses": w.n_lenses, "map_pixels": [g.src_nx, g.src_ny],
+                   "precision": "FP32 lens sums on rebased offsets, FP64 cell bases and pixel "
+                                "coordinates, FP64 Taylor coefficients",
+                   "exec_params": list(lm.lm_batch_params(b))},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": traffic, "kernel": "k_shoot_batch",
+                     "flops_per_launch": flops, "avg_launch_s": avg_shoot_s,
+                     "flop_per_ray": flops / stats.rays,
+                     "near_pairs_per_ray": stats.near_pairs / stats.rays},
+        "coefficients_ms": float(np.mean(coeff_ms)),
+        "comparison": per_map,
+    }
+    if not args.no_cpu_baseline:
+        cb, errors = cpu_baseline_leg(lm, w, g, lenses, mp, mp32, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+        line["map_error_vs_fp64"] = errors
+    lm.lm_batch_destroy(b)
+    mp.close()
+    mp32.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

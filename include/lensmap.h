@@ -184,10 +184,23 @@ lm_status lm_deflect(lm_map* m, const double* theta_xy, int64_t n, double* alpha
 lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int32_t* p,
                    int32_t* q);
 
+/* Work of one shot, for throughput accounting: rays, ray-lens pairs of the
+ * directly summed (near) lenses, and for the interpolated scheme the level-2
+ * cells of the lattice and the (cell, far lens) pairs their Taylor
+ * coefficients need (Sec. 3.2.2).  Host-only, from the lens partition. */
+typedef struct lm_stats {
+    int64_t rays;
+    double near_pairs;
+    int64_t cells;
+    double far_pairs;
+} lm_stats;
+lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj,
+                        lm_stats* out);
+
 /* Batched execution (80-map study, Sec. 4.2): the maps (same scheme,
  * precision and taylor_terms, same device, all with lenses) are shot together
  * by one persistent kernel fed from a work queue, preceded by their coefficient
- * kernels, captured once as a HIP graph.  Each map's shot rectangle is the one
+ * kernels; both phases are captured once as HIP graphs and replayed.  Each map's shot rectangle is the one
  * given by lm_batch_set_rect (default: its whole lattice).  The batch keeps
  * pointers to the maps; they must outlive it and must not be changed
  * (lenses, macro, bound counts) while it exists. */
@@ -205,8 +218,15 @@ lm_status lm_batch_tune(lm_batch* b, const char* cache_path);
 /* Shoot every map's rectangle once (one graph launch). Asynchronous on `stream`. */
 lm_status lm_batch_shoot(lm_batch* b, void* stream);
 
-/* Execution parameters in use: rays per lane, level-2 cells per workgroup tile
- * side, workgroups per CU (any pointer may be NULL). */
+/* Device time of the last lm_batch_shoot, from events recorded on its stream
+ * around its two graph launches: all coefficient kernels (with the queue
+ * reset), and the shooting kernel alone (ms, either pointer may be NULL).
+ * Waits for that launch to finish. */
+lm_status lm_batch_timing(lm_batch* b, float* coeff_ms, float* shoot_ms);
+
+/* Execution parameters in use: rays per lane, tile scale (multiplier of the
+ * default level-2 cells per workgroup tile side), workgroups per CU (0: as many
+ * as fit).  Any pointer may be NULL. */
 lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* tile_cells,
                           int32_t* wg_per_cu);
 void lm_batch_destroy(lm_batch* b);

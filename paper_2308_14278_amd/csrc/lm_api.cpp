@@ -134,6 +134,7 @@ struct lm_map {
     int nl1x = 0, nl1y = 0;
     // device buffers
     DevBuf lx, ly, lmd, lxf, lyf, lmf, lI, lJ, cell_start, coef, counts_own, n_out;
+    std::vector<int32_t> h_start;  // host copy of the level-1 CSR
     uint64_t* counts = nullptr;  // own or bound
     bool bound = false;
     bool coef_valid = false;
@@ -501,6 +502,7 @@ lm_status lm_set_lenses(lm_map* m, const double* x, const double* y, const doubl
             return fail(LM_ENOMEM, "cannot allocate the level-1 index");
         HIP_TRY(hipMemcpy(m->cell_start.p, start.data(), start.size() * 4, hipMemcpyHostToDevice));
     }
+    m->h_start.swap(start);
     m->nlens = n;
     m->coef_valid = false;
     return ok();
@@ -683,6 +685,52 @@ lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int
     return ok();
 }
 
+lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj,
+                        lm_stats* out)
+{
+    if (!m || !out) return fail(LM_EINVAL, "NULL argument");
+    if (ni < 0 || nj < 0 || i0 < 0 || j0 < 0 || i0 > m->g.ray_nx - ni || j0 > m->g.ray_ny - nj)
+        return fail(LM_ERANGE, "rectangle leaves the lattice");
+    std::memset(out, 0, sizeof *out);
+    out->rays = ni * nj;
+    if (m->g.scheme != LM_SCHEME_INTERP) {
+        out->near_pairs = (double)out->rays * (double)m->nlens;
+        return ok();
+    }
+    const lm_geometry& g = m->g;
+    const int H = g.near_halo;
+    const int64_t sx = (int64_t)g.coarse * g.l1_kx, sy = (int64_t)g.coarse * g.l1_ky;
+    auto near_count = [&](int64_t I, int64_t J) {
+        int64_t n = 0;
+        for (int r = 0; r <= 2 * H; ++r) {
+            const int64_t base = (J + r) * m->nl1x + I;
+            n += m->h_start[base + 2 * H + 1] - m->h_start[base];
+        }
+        return n;
+    };
+    double pairs = 0;
+    if (ni > 0 && nj > 0)
+        for (int64_t J = j0 / sy; J <= (j0 + nj - 1) / sy; ++J) {
+            const int64_t ry = std::min(j0 + nj, (J + 1) * sy) - std::max(j0, J * sy);
+            for (int64_t I = i0 / sx; I <= (i0 + ni - 1) / sx; ++I) {
+                const int64_t rx = std::min(i0 + ni, (I + 1) * sx) - std::max(i0, I * sx);
+                pairs += (double)rx * (double)ry * (double)near_count(I, J);
+            }
+        }
+    out->near_pairs = pairs;
+    out->cells = m->ncx * m->ncy;
+    double far = 0;
+    for (int64_t J = 0; J < m->n1y; ++J) {
+        const int64_t cy = std::min(m->ncy, (J + 1) * (int64_t)g.l1_ky) - J * g.l1_ky;
+        for (int64_t I = 0; I < m->n1x; ++I) {
+            const int64_t cx = std::min(m->ncx, (I + 1) * (int64_t)g.l1_kx) - I * g.l1_kx;
+            far += (double)cx * (double)cy * (double)(m->nlens - near_count(I, J));
+        }
+    }
+    out->far_pairs = far;
+    return ok();
+}
+
 }  // extern "C"
 
 // ==================================================================== batch
@@ -696,11 +744,18 @@ struct lm_batch {
     int64_t total = 0;
     int grid = 0;
     hipStream_t cap = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // two graphs: every map's coefficients + queue reset, then the persistent
+    // shooting kernel; events on the caller's stream bracket both
+    hipGraphExec_t exec = nullptr, exec_pre = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // start, coefficients done, shoot done
+    bool launched = false;
     bool dirty = true;
     ~lm_batch()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
+        if (exec_pre) (void)hipGraphExecDestroy(exec_pre);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -758,11 +813,13 @@ lm_status batch_build(lm_batch* b, int64_t limit_items)
     return LM_OK;
 }
 
-// Record: coefficients of every map, queue reset, persistent shoot.
-lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs)
+// Enqueue phase 1 (coefficients of every map when asked, queue reset) and/or
+// phase 2 (persistent shoot).
+lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs, bool pre = true,
+                        bool shoot = true)
 {
     const int n = (int)b->maps.size();
-    if (with_coeffs)
+    if (pre && with_coeffs)
         for (int k = 0; k < n; ++k) {
             lm_map* m = b->maps[k];
             if (m->g.scheme != LM_SCHEME_INTERP) continue;
@@ -770,8 +827,8 @@ lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs)
             LAUNCH_TRY(lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
                                         m->coef.as<LmCoef>(), s));
         }
-    LAUNCH_TRY(lm_launch_fill_u64(b->queue.as<unsigned long long>(), 1, 0ull, s));
-    if (b->total > 0)
+    if (pre) LAUNCH_TRY(lm_launch_fill_u64(b->queue.as<unsigned long long>(), 1, 0ull, s));
+    if (shoot && b->total > 0)
         LAUNCH_TRY(lm_launch_shoot_batch(b->descs.as<LmDesc>(), b->offs.as<int64_t>(),
                                          b->order.as<int32_t>(), n,
                                          b->queue.as<unsigned long long>(), b->scheme, b->precision,
@@ -779,26 +836,38 @@ lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs)
     return LM_OK;
 }
 
-lm_status batch_graph(lm_batch* b)
+lm_status capture(lm_batch* b, bool pre, bool shoot, hipGraphExec_t* out)
 {
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-    }
-    lm_status st = batch_build(b, -1);
-    if (st) return st;
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    st = batch_enqueue(b, b->cap, true);
+    lm_status st = batch_enqueue(b, b->cap, true, pre, shoot);
     hipError_t e = hipStreamEndCapture(b->cap, &graph);
     if (st) {
         if (graph) (void)hipGraphDestroy(graph);
         return st;
     }
     if (e != hipSuccess) return fail(LM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(LM_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    return LM_OK;
+}
+
+lm_status batch_graph(lm_batch* b)
+{
+    for (hipGraphExec_t* e : {&b->exec, &b->exec_pre})
+        if (*e) {
+            (void)hipGraphExecDestroy(*e);
+            *e = nullptr;
+        }
+    lm_status st = batch_build(b, -1);
+    if (st) return st;
+    for (hipEvent_t& e : b->ev)
+        if (!e) HIP_TRY(hipEventCreate(&e));
+    st = capture(b, true, false, &b->exec_pre);
+    if (st) return st;
+    st = capture(b, false, true, &b->exec);
+    if (st) return st;
     b->dirty = false;
     return LM_OK;
 }
@@ -925,7 +994,13 @@ lm_status lm_batch_shoot(lm_batch* b, void* stream)
         lm_status st = batch_graph(b);
         if (st) return st;
     }
-    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(b->ev[0], s));
+    HIP_TRY(hipGraphLaunch(b->exec_pre, s));
+    HIP_TRY(hipEventRecord(b->ev[1], s));
+    HIP_TRY(hipGraphLaunch(b->exec, s));
+    HIP_TRY(hipEventRecord(b->ev[2], s));
+    b->launched = true;
     for (size_t k = 0; k < b->maps.size(); ++k) {
         lm_map* m = b->maps[k];
         m->n_shot += (uint64_t)b->rect[4 * k + 2] * (uint64_t)b->rect[4 * k + 3];
@@ -995,6 +1070,19 @@ lm_status lm_batch_tune(lm_batch* b, const char* cache_path)
     b->g_scale = gs;
     b->wg_per_cu = wg;
     b->dirty = true;
+    return ok();
+}
+
+lm_status lm_batch_timing(lm_batch* b, float* coeff_ms, float* shoot_ms)
+{
+    if (!b) return fail(LM_EINVAL, "batch is NULL");
+    if (!b->launched) return fail(LM_ESTATE, "the batch has not been shot");
+    HIP_TRY(hipEventSynchronize(b->ev[2]));
+    float a = 0, c = 0;
+    HIP_TRY(hipEventElapsedTime(&a, b->ev[0], b->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&c, b->ev[1], b->ev[2]));
+    if (coeff_ms) *coeff_ms = a;
+    if (shoot_ms) *shoot_ms = c;
     return ok();
 }
 

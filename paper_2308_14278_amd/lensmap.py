@@ -64,6 +64,11 @@ class lm_geometry(ctypes.Structure):
         return int(self.ray_nx) * int(self.ray_ny)
 
 
+class lm_stats(ctypes.Structure):
+    _fields_ = [("rays", ctypes.c_int64), ("near_pairs", ctypes.c_double),
+                ("cells", ctypes.c_int64), ("far_pairs", ctypes.c_double)]
+
+
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
 _d = _P(ctypes.c_double)
@@ -95,6 +100,9 @@ _SIGS = {
     "lm_batch_tune": [_vp, ctypes.c_char_p],
     "lm_batch_shoot": [_vp, _vp],
     "lm_batch_params": [_vp, _i32, _i32, _i32],
+    "lm_shot_stats": [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                      _P(lm_stats)],
+    "lm_batch_timing": [_vp, _P(ctypes.c_float), _P(ctypes.c_float)],
 }
 
 _lib = None
@@ -287,6 +295,20 @@ def lm_batch_params(b):
     _check(load().lm_batch_params(b, ctypes.byref(a), ctypes.byref(c), ctypes.byref(d)),
            "lm_batch_params")
     return int(a.value), int(c.value), int(d.value)
+
+
+def lm_shot_stats(m, i0, j0, ni, nj) -> lm_stats:
+    st = lm_stats()
+    _check(load().lm_shot_stats(m, int(i0), int(j0), int(ni), int(nj), ctypes.byref(st)),
+           "lm_shot_stats")
+    return st
+
+
+def lm_batch_timing(b):
+    """(coefficient ms, shooting-kernel ms) of the last lm_batch_shoot."""
+    a, c = ctypes.c_float(), ctypes.c_float()
+    _check(load().lm_batch_timing(b, ctypes.byref(a), ctypes.byref(c)), "lm_batch_timing")
+    return float(a.value), float(c.value)
 
 
 def lm_batch_destroy(b):
