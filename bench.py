@@ -82,14 +82,21 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
                             "l1_kx", "l1_ky")}, halo=g.near_halo, terms=g.taylor_terms)
     orc = oracle.Oracle(og, w.kappa, w.gamma, w.kappa_star, *lenses)
     cores = oracle.num_threads()
-    # calibrate on a small block, then size the sample to the time budget
-    nj = 1856
+    # calibrate on growing blocks until one takes a second, then size the
+    # sample to the time budget
+    nj = g.coarse
     i0, j0 = g.ray_nx // 2, g.ray_ny // 2 - nj // 2
-    t0 = time.perf_counter()
-    orc.shoot(i0, j0, 2048, nj)
-    rate0 = 2048 * nj / (time.perf_counter() - t0)
-    ni = int(max(4096, min(g.ray_nx // 2, rate0 * budget_s / nj)))
-    ni -= ni % 64
+    ni = g.coarse
+    while True:
+        t0 = time.perf_counter()
+        orc.shoot(i0, j0, ni, nj)
+        dt0 = time.perf_counter() - t0
+        if dt0 > 1.0 or ni >= g.ray_nx // 4:
+            break
+        ni *= 4
+    rate0 = ni * nj / dt0
+    ni = int(max(g.coarse, min(g.ray_nx // 2, rate0 * budget_s / nj)))
+    ni -= ni % g.coarse
     t0 = time.perf_counter()
     ref, ref_out = orc.shoot(i0, j0, ni, nj)
     dt = time.perf_counter() - t0
@@ -121,6 +128,19 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
             "seconds": dt}, errors
 
 
+def copy_calibration():
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
+    scale from counter units to bytes."""
+    import torch
+    n = 1 << 28  # float32 elements = 1 GiB
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,8 +153,18 @@ def main():
                     help="rays of the per-map comparison runs")
     ap.add_argument("--rays", type=float, default=1e13,
                     help="rays per map (1e13 is the workload; smaller values are for profiling)")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default execution parameters (8 rays per lane, tile scale 1, "
+                         "all workgroups that fit), which the tuner picks on MI355X")
+    ap.add_argument("--no-comparison", action="store_true",
+                    help="skip the per-map comparison runs (profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for the HBM "
+                         "byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(how the work would shard is described in DESIGN.md)", file=sys.stderr)
@@ -205,7 +235,8 @@ def main():
     j0 = (g.ray_ny - nj) // 2
     mp32, _ = make_map(lm, w, g, lenses, lm.LM_PREC_FP32)
     per_map = {}
-    for name, m in (("plain_fp32_per_map", mp32), ("mixed_per_map", mp)):
+    for name, m in (() if args.no_comparison else
+                    (("plain_fp32_per_map", mp32), ("mixed_per_map", mp))):
         m.reset(stream)
         m.shoot(i0, j0, ni, nj, stream)  # coefficients + warm-up
         torch.cuda.synchronize()

@@ -231,6 +231,12 @@ lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* ti
                           int32_t* wg_per_cu);
 void lm_batch_destroy(lm_batch* b);
 
+/* Device micro-benchmarks on the current device (diagnostics for the
+ * roofline): the issue rate of independent unpacked FP32 FMAs in TFLOP/s, and
+ * the rate of the near-lens pair instruction mix in 1e9 ray-lens pairs/s.
+ * Either pointer may be NULL.  Synchronous; takes well under a second. */
+lm_status lm_measure_valu_peak(double* fma_tflops, double* pair_gpairs);
+
 /* Description of the last failure on this thread ("" if none). */
 const char* lm_last_error(void);
 

@@ -176,14 +176,19 @@ Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scal
     e.cw = (int)ceil_div(R, ncc);
     const double mx = std::fabs(1.0 - m->kappa - m->gamma + m->kappa_star);
     const double my = std::fabs(1.0 - m->kappa + m->gamma + m->kappa_star);
-    const double ext_x = (double)G * R * g.ray_dx * mx / g.src_dx;
-    const double ext_y = (double)G * R * g.ray_dy * my / g.src_dy;
-    int wx = 8;
-    while (wx < 512 && wx < ext_x + 16) wx *= 2;
-    int wy = LM_WIN_MAX / wx;
-    while (wy < ext_y + 16 && wx > 8 && ext_x + 16 < wx / 2) {
-        wx /= 2;
-        wy = LM_WIN_MAX / wx;
+    // pixels spanned by the tile's smooth image, plus a margin of 0.1 theta_E
+    // (at least 8 pixels) on each side for the variation of the near-lens
+    // deflection across the tile
+    const double ext_x = (double)G * R * g.ray_dx * mx / g.src_dx + 2.0 * std::max(8.0, 0.1 / g.src_dx);
+    const double ext_y = (double)G * R * g.ray_dy * my / g.src_dy + 2.0 * std::max(8.0, 0.1 / g.src_dy);
+    int wx = 8, wy = 8;
+    while (wx < ext_x && wx < LM_WIN_MAX / 8) wx *= 2;
+    while (wy < ext_y && wy < LM_WIN_MAX / 8) wy *= 2;
+    while (wx * wy > LM_WIN_MAX) {
+        if (wx / ext_x > wy / ext_y)
+            wx /= 2;
+        else
+            wy /= 2;
     }
     e.wx = wx;
     e.wy = wy;

@@ -5,8 +5,9 @@
 
 #define LM_WG 256          // threads per workgroup: 4 waves of 64
 #define LM_WAVES 4
-#define LM_LENS_CAP 256    // lenses staged per wave per block (also the summation block)
-#define LM_WIN_MAX 4096    // uint32 bins of a workgroup's LDS window
+#define LM_LENS_CAP 256    // direct sum: lenses staged per wave per block (the summation block)
+#define LM_NEAR_CAP 64     // interpolated scheme: near lenses staged per wave per block
+#define LM_WIN_MAX 8192    // uint32 bins of a workgroup's LDS window
 
 // Taylor coefficients of one level-2 cell: a_0 in FP64 (it carries the large
 // far-field deflection of the cell centre), a_1..a_6 in FP32 (they multiply

@@ -27,8 +27,14 @@
 namespace {
 
 constexpr int kWG = LM_WG;
-constexpr int kCap = LM_LENS_CAP;
 constexpr int kWinMax = LM_WIN_MAX;
+
+// Lenses staged per wave per block: the direct sum sums 256-lens blocks (the
+// compensated blocks); a near list rarely exceeds a few tens of lenses.
+template <int SCHEME>
+struct Cap {
+    static constexpr int value = SCHEME == 0 ? LM_LENS_CAP : LM_NEAR_CAP;
+};
 
 __device__ __forceinline__ void wave_sync_lds()
 {
@@ -47,6 +53,37 @@ __device__ __forceinline__ unsigned wave_sum_u32(unsigned v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Map constants the per-ray code reads, copied into registers once per unit so
+// that the global atomics of the counting step do not force reloads.
+struct Hot {
+    double inv_sdx, inv_sdy, snxd, snyd;
+    float mxf, myf, bx0f, by0f, inv_sdxf, inv_sdyf, snxf, snyf;
+    int snx, wx, wy;
+    unsigned long long* counts;
+};
+
+__device__ __forceinline__ Hot make_hot(const LmDesc& d)
+{
+    Hot h;
+    h.inv_sdx = d.inv_sdx;
+    h.inv_sdy = d.inv_sdy;
+    h.snxd = (double)d.snx;
+    h.snyd = (double)d.sny;
+    h.mxf = d.mxf;
+    h.myf = d.myf;
+    h.bx0f = d.bx0f;
+    h.by0f = d.by0f;
+    h.inv_sdxf = d.inv_sdxf;
+    h.inv_sdyf = d.inv_sdyf;
+    h.snxf = (float)d.snx;
+    h.snyf = (float)d.sny;
+    h.snx = d.snx;
+    h.wx = d.wx;
+    h.wy = d.wy;
+    h.counts = d.counts;
+    return h;
 }
 
 // ---------------------------------------------------------------- cell data
@@ -127,9 +164,10 @@ __device__ __forceinline__ void taylor(const float* ar, const float* ai, float d
     fi = __builtin_fmaf(gr, dy, gi * dx);
 }
 
-// Pixel of one ray from its local sums (mixed path).  p = -1: outside the map.
+// Pixel of one ray from its local sums (mixed path).  p = -1: outside the map
+// (NaN coordinates included).
 template <int P>
-__device__ __forceinline__ void bin_mixed(const LmDesc& d, const float* ar, const float* ai,
+__device__ __forceinline__ void bin_mixed(const Hot& h, const float* ar, const float* ai,
                                           double ubx, double uby, float dx, float dy, float ax,
                                           float ay, int& p, int& q)
 {
@@ -137,18 +175,18 @@ __device__ __forceinline__ void bin_mixed(const LmDesc& d, const float* ar, cons
     taylor<P>(ar, ai, dx, dy, fr, fi);
     float tx = ax + fr;
     float ty = ay - fi;
-    float lx = __builtin_fmaf(d.mxf, dx, -tx);
-    float ly = __builtin_fmaf(d.myf, dy, -ty);
-    double u = __builtin_fma((double)lx, d.inv_sdx, ubx);
-    double v = __builtin_fma((double)ly, d.inv_sdy, uby);
-    bool in = (u >= 0.0) && (u < (double)d.snx) && (v >= 0.0) && (v < (double)d.sny);
+    float lx = __builtin_fmaf(h.mxf, dx, -tx);
+    float ly = __builtin_fmaf(h.myf, dy, -ty);
+    double u = __builtin_fma((double)lx, h.inv_sdx, ubx);
+    double v = __builtin_fma((double)ly, h.inv_sdy, uby);
+    bool in = (u >= 0.0) & (u < h.snxd) & (v >= 0.0) & (v < h.snyd);
     p = in ? (int)u : -1;
     q = in ? (int)v : -1;
 }
 
 // Pixel of one ray in the plain FP32 path (global coordinates).
 template <int P>
-__device__ __forceinline__ void bin_fp32(const LmDesc& d, const float* ar, const float* ai,
+__device__ __forceinline__ void bin_fp32(const Hot& h, const float* ar, const float* ai,
                                          float a0r, float a0i, float zcx, float zcy, float tx,
                                          float ty, float ax, float ay, int& p, int& q)
 {
@@ -157,11 +195,11 @@ __device__ __forceinline__ void bin_fp32(const LmDesc& d, const float* ar, const
     taylor<P>(ar, ai, dx, dy, fr, fi);
     float alx = ax + (a0r + fr);
     float aly = ay - (a0i + fi);
-    float bx = __builtin_fmaf(d.mxf, tx, -alx);
-    float by = __builtin_fmaf(d.myf, ty, -aly);
-    float u = (bx - d.bx0f) * d.inv_sdxf;
-    float v = (by - d.by0f) * d.inv_sdyf;
-    bool in = (u >= 0.f) && (u < (float)d.snx) && (v >= 0.f) && (v < (float)d.sny);
+    float bx = __builtin_fmaf(h.mxf, tx, -alx);
+    float by = __builtin_fmaf(h.myf, ty, -aly);
+    float u = (bx - h.bx0f) * h.inv_sdxf;
+    float v = (by - h.by0f) * h.inv_sdyf;
+    bool in = (u >= 0.f) & (u < h.snxf) & (v >= 0.f) & (v < h.snyf);
     p = in ? (int)u : -1;
     q = in ? (int)v : -1;
 }
@@ -271,35 +309,35 @@ struct Run {
     unsigned n;
 };
 
-__device__ __forceinline__ void emit(const LmDesc& d, int p, int q, unsigned n, int ax0, int ay0,
+__device__ __forceinline__ void emit(const Hot& h, int p, int q, unsigned n, int ax0, int ay0,
                                      unsigned* win, unsigned& nout)
 {
     if (p < 0) {
         nout += n;
         return;
     }
-    int64_t wxi = (int64_t)p - ax0, wyi = (int64_t)q - ay0;
-    if (wxi >= 0 && wxi < d.wx && wyi >= 0 && wyi < d.wy)
-        atomicAdd(&win[wyi * d.wx + wxi], n);
+    const unsigned wxi = (unsigned)p - (unsigned)ax0, wyi = (unsigned)q - (unsigned)ay0;
+    if ((wxi < (unsigned)h.wx) & (wyi < (unsigned)h.wy))
+        atomicAdd(&win[wyi * (unsigned)h.wx + wxi], n);
     else
-        atomicAdd(&d.counts[(int64_t)q * d.snx + p], (unsigned long long)n);
+        atomicAdd(&h.counts[(int64_t)q * h.snx + p], (unsigned long long)n);
 }
 
-__device__ __forceinline__ void run_push(const LmDesc& d, Run& r, int p, int q, int ax0, int ay0,
+__device__ __forceinline__ void run_push(const Hot& h, Run& r, int p, int q, int ax0, int ay0,
                                          unsigned* win, unsigned& nout)
 {
-    if (p == r.p && q == r.q) {
-        ++r.n;
-    } else {
-        if (r.n) emit(d, r.p, r.q, r.n, ax0, ay0, win, nout);
+    const bool same = (p == r.p) & (q == r.q);
+    if (!same) {
+        if (r.n) emit(h, r.p, r.q, r.n, ax0, ay0, win, nout);
         r.p = p;
         r.q = q;
-        r.n = 1;
+        r.n = 0;
     }
+    ++r.n;
 }
 
 // End of a unit: lanes whose pending runs all name one pixel add it once.
-__device__ __forceinline__ void run_flush(const LmDesc& d, Run& r, int ax0, int ay0, unsigned* win,
+__device__ __forceinline__ void run_flush(const Hot& h, Run& r, int ax0, int ay0, unsigned* win,
                                           unsigned& nout, int lane)
 {
     bool act = r.n > 0;
@@ -310,9 +348,9 @@ __device__ __forceinline__ void run_flush(const LmDesc& d, Run& r, int ax0, int 
         unsigned long long diff = __ballot(act && (r.p != p0 || r.q != q0));
         if (diff == 0) {
             unsigned tot = wave_sum_u32(act ? r.n : 0u);
-            if (lane == first) emit(d, p0, q0, tot, ax0, ay0, win, nout);
+            if (lane == first) emit(h, p0, q0, tot, ax0, ay0, win, nout);
         } else if (act) {
-            emit(d, r.p, r.q, r.n, ax0, ay0, win, nout);
+            emit(h, r.p, r.q, r.n, ax0, ay0, win, nout);
         }
     }
     r.n = 0;
@@ -328,6 +366,9 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                              int lane, unsigned& nout)
 {
     const int R = d.R;
+    const Hot h = make_hot(d);
+    const float hxh = d.hxh, hxl = d.hxl;
+    const float dxf = d.dxf, x0f = d.x0f;
     const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
     double ubx, uby;
     cell_base<SCHEME>(d, ci, cj, ubx, uby);
@@ -342,7 +383,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
     else
         py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
 
-    const int count = list_count<SCHEME>(d, ci, cj);
+    constexpr int kCap = Cap<SCHEME>::value;
+    const int count = __builtin_amdgcn_readfirstlane(list_count<SCHEME>(d, ci, cj));
     const int nblk = (count + kCap - 1) / kCap;
     if (nblk == 1) stage<SCHEME, PREC>(d, ci, cj, 0, count, zcx, zcy, lb, lane);
 
@@ -352,16 +394,16 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
             if (PREC == 0)
-                px[c] = local_offset(c0 + c, ci, R, d.hxh, d.hxl);
+                px[c] = local_offset(c0 + c, ci, R, hxh, hxl);
             else
-                px[c] = __builtin_fmaf((float)(c0 + c) + 0.5f, d.dxf, d.x0f);
+                px[c] = __builtin_fmaf((float)(c0 + c) + 0.5f, dxf, x0f);
             ax[c] = 0.f;
             ay[c] = 0.f;
             kx[c] = 0.f;
             ky[c] = 0.f;
         }
         for (int b = 0; b < nblk; ++b) {
-            const int nb = min(kCap, count - b * kCap);
+            const int nb = __builtin_amdgcn_readfirstlane(min(kCap, count - b * kCap));
             if (nblk > 1) stage<SCHEME, PREC>(d, ci, cj, b * kCap, nb, zcx, zcy, lb, lane);
             float bx[NR], by[NR];
 #pragma unroll
@@ -369,6 +411,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 bx[c] = SCHEME == 0 ? 0.f : ax[c];
                 by[c] = SCHEME == 0 ? 0.f : ay[c];
             }
+#pragma unroll 2
             for (int k = 0; k < nb; ++k) {
                 const float4 L = lb[k];
                 const float dy = py - L.y;
@@ -393,16 +436,18 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
             if (c0 + c < c_hi) {
                 int p, q;
                 if (PREC == 0)
-                    bin_mixed<P>(d, ar, ai, ubx, uby, px[c], py, ax[c], ay[c], p, q);
+                    bin_mixed<P>(h, ar, ai, ubx, uby, px[c], py, ax[c], ay[c], p, q);
                 else
-                    bin_fp32<P>(d, ar, ai, a0r, a0i, zcxf, zcyf, px[c], py, ax[c], ay[c], p, q);
-                if (row_ok) run_push(d, run, p, q, ax0, ay0, win, nout);
+                    bin_fp32<P>(h, ar, ai, a0r, a0i, zcxf, zcyf, px[c], py, ax[c], ay[c], p, q);
+                if (row_ok) run_push(h, run, p, q, ax0, ay0, win, nout);
             }
         }
     }
-    run_flush(d, run, ax0, ay0, win, nout, lane);
+    run_flush(h, run, ax0, ay0, win, nout, lane);
 }
 
+// Window origin of a tile: the pixel of the image of its centre cell's centre
+// (macro map, far field and near lenses, FP64), less half the window.
 template <int SCHEME>
 __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_t cjb, int& ax0,
                                             int& ay0)
@@ -410,6 +455,21 @@ __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_
     int64_t cic = min(cib + d.G / 2, d.ncx - 1), cjc = min(cjb + d.G / 2, d.ncy - 1);
     double ubx, uby;
     cell_base<SCHEME>(d, cic, cjc, ubx, uby);
+    const double zcx = cell_cx(d, cic), zcy = cell_cy(d, cjc);
+    const int count = list_count<SCHEME>(d, cic, cjc);
+    double sx = 0.0, sy = 0.0;
+    for (int k = 0; k < count; ++k) {
+        const int idx = list_index<SCHEME>(d, cic, cjc, k);
+        const double dx = zcx - d.lx[idx], dy = zcy - d.ly[idx];
+        const double r2 = dx * dx + dy * dy;
+        if (r2 > 0.0) {
+            const double w = d.lmd[idx] / r2;
+            sx += dx * w;
+            sy += dy * w;
+        }
+    }
+    ubx -= sx * d.inv_sdx;
+    uby -= sy * d.inv_sdy;
     double fx = floor(ubx) - (double)(d.wx / 2), fy = floor(uby) - (double)(d.wy / 2);
     fx = fmin(fmax(fx, -1.0e9), 1.0e9);
     fy = fmin(fmax(fy, -1.0e9), 1.0e9);
@@ -467,8 +527,10 @@ template <int SCHEME, int PREC, int NR, int P>
 __global__ __launch_bounds__(kWG) void k_shoot_map(LmDesc d)
 {
     __shared__ unsigned win[kWinMax];
-    __shared__ float4 lens[LM_WAVES][kCap];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    __shared__ float4 lens[LM_WAVES][Cap<SCHEME>::value];
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wave index as a scalar: everything derived from it stays uniform
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t t = d.tile0 + blockIdx.x;
     for (int b = tid; b < d.wx * d.wy; b += kWG) win[b] = 0u;
     const int64_t tx = t % d.ntx, ty = t / d.ntx;
@@ -487,9 +549,11 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
                                                      unsigned long long* queue)
 {
     __shared__ unsigned win[kWinMax];
-    __shared__ float4 lens[LM_WAVES][kCap];
+    __shared__ float4 lens[LM_WAVES][Cap<SCHEME>::value];
     __shared__ long long s_item;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wave index as a scalar: everything derived from it stays uniform
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int b = tid; b < kWinMax; b += kWG) win[b] = 0u;
     const int64_t total = offs[nmaps];
     for (;;) {
@@ -626,6 +690,7 @@ __global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restri
         px = __builtin_fmaf((float)i + 0.5f, d.dxf, d.x0f);
         py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
     }
+    constexpr int kCap = Cap<SCHEME>::value;
     const int count = list_count<SCHEME>(d, ci, cj);
     float ax = 0.f, ay = 0.f, kx = 0.f, ky = 0.f;
     for (int b0 = 0; b0 < count; b0 += kCap) {
@@ -646,10 +711,11 @@ __global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restri
         }
     }
     int p, q;
+    const Hot h = make_hot(d);
     if (PREC == 0)
-        bin_mixed<P>(d, ar, ai, ubx, uby, px, py, ax, ay, p, q);
+        bin_mixed<P>(h, ar, ai, ubx, uby, px, py, ax, ay, p, q);
     else
-        bin_fp32<P>(d, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, py, ax, ay, p, q);
+        bin_fp32<P>(h, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, py, ax, ay, p, q);
     po[t] = p;
     qo[t] = q;
 }
@@ -675,6 +741,7 @@ __global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restr
         px = (float)tx;
         py = (float)ty;
     }
+    constexpr int kCap = Cap<SCHEME>::value;
     const int count = list_count<SCHEME>(d, ci, cj);
     float ax = 0.f, ay = 0.f, kx = 0.f, ky = 0.f;
     for (int b0 = 0; b0 < count; b0 += kCap) {

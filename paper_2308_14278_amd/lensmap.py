@@ -103,6 +103,7 @@ _SIGS = {
     "lm_shot_stats": [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                       _P(lm_stats)],
     "lm_batch_timing": [_vp, _P(ctypes.c_float), _P(ctypes.c_float)],
+    "lm_measure_valu_peak": [_d, _d],
 }
 
 _lib = None
@@ -308,6 +309,13 @@ def lm_batch_timing(b):
     """(coefficient ms, shooting-kernel ms) of the last lm_batch_shoot."""
     a, c = ctypes.c_float(), ctypes.c_float()
     _check(load().lm_batch_timing(b, ctypes.byref(a), ctypes.byref(c)), "lm_batch_timing")
+    return float(a.value), float(c.value)
+
+
+def lm_measure_valu_peak():
+    """(unpacked FP32 FMA TFLOP/s, 1e9 ray-lens pairs/s) measured on the current device."""
+    a, c = ctypes.c_double(), ctypes.c_double()
+    _check(load().lm_measure_valu_peak(ctypes.byref(a), ctypes.byref(c)), "lm_measure_valu_peak")
     return float(a.value), float(c.value)
 
 
