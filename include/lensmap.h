@@ -184,6 +184,20 @@ lm_status lm_deflect(lm_map* m, const double* theta_xy, int64_t n, double* alpha
 lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int32_t* p,
                    int32_t* q);
 
+/* Light-curve peak identification (Sec. 4.2) on the map's current counts.
+ * A light curve is row i of the map (counts[i*src_nx + j], i along the
+ * caustic direction of the map's y axis, j across it).  For each listed row
+ * tracks[t] (0 <= tracks[t] < src_ny) and each j, flags[t*src_nx + j] gets
+ * bit 0 if (i, j) is a candidate peak (N_ij greater than both neighbours in j
+ * and N_ij - <N> > k sqrt(<N>), <N> the mean of the three counts; decided
+ * exactly in integers) and bit 1 if it is a true peak (also a candidate among
+ * (i-1, j-1..j+1) and among (i+1, j-1..j+1)).  End pixels of a row are never
+ * candidates; the first and last rows keep no true peaks.  k = 5 in the
+ * paper; 1 <= k <= 1000.  flags is host memory of n_tracks*src_nx bytes.
+ * Synchronous. */
+lm_status lm_find_peaks(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                        uint8_t* flags);
+
 /* Work of one shot, for throughput accounting: rays, ray-lens pairs of the
  * directly summed (near) lenses, and for the interpolated scheme the level-2
  * cells of the lattice and the (cell, far lens) pairs their Taylor

@@ -48,12 +48,15 @@ def build(verbose: bool = False) -> str:
               os.path.join(CSRC, "lm_kernels.hip"), "-o", ko])
         _run([cc, "--offload-arch=" + ARCH, *COMMON, "-c",
               os.path.join(CSRC, "lm_peak.hip"), "-o", po])
+        yo = os.path.join(tmp, "lm_analysis.o")
+        _run([cc, "--offload-arch=" + ARCH, *COMMON, "-c",
+              os.path.join(CSRC, "lm_analysis.hip"), "-o", yo])
         # host-only C++: plain g++ against the HIP runtime headers
         _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
               "-I" + os.path.join(ROCM, "include"), "-c", os.path.join(CSRC, "lm_api.cpp"),
               "-o", ao])
         out = LIB + ".tmp%d" % os.getpid()
-        _run([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out, ko, po, ao])
+        _run([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out, ko, po, yo, ao])
         os.replace(out, LIB)
     if verbose:
         print("built", LIB)

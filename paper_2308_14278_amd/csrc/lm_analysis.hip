@@ -1,0 +1,68 @@
+// lm_analysis.hip -- light-curve peak identification on a count map (Sec. 4.2).
+//
+// A light curve is row i of the row-major map counts[i][j] (fixed source index
+// along the caustic, j across it).  Candidate peak: N_ij > max(N_i,j-1, N_i,j+1)
+// and h_ij > k sigma_ij with h_ij = N_ij - <N>, <N> the mean of the three
+// counts and sigma_ij = sqrt(<N>); with S the sum of the three counts this is
+// (3 N_ij - S)^2 > 3 k^2 S, decided exactly in integers.  True peak: a
+// candidate with a candidate among (i-1, j-1..j+1) and among (i+1, j-1..j+1).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace {
+
+__device__ __forceinline__ bool candidate(const unsigned long long* __restrict__ c, int64_t nx,
+                                          int64_t i, int64_t j, unsigned k2x3)
+{
+    if (j <= 0 || j >= nx - 1) return false;
+    const unsigned long long* row = c + i * nx;
+    const unsigned long long a = row[j - 1], n = row[j], b = row[j + 1];
+    if (!(n > a && n > b)) return false;
+    const unsigned __int128 s = (unsigned __int128)a + n + b;
+    const unsigned __int128 n3 = (unsigned __int128)n * 3u;
+    if (n3 <= s) return false;
+    const unsigned __int128 t = n3 - s;
+    // 3 k^2 S < 2^90 for k <= 1000, so any t >= 2^64 passes
+    if ((unsigned long long)(t >> 64) != 0ull) return true;
+    const unsigned long long tl = (unsigned long long)t;
+    return (unsigned __int128)tl * tl > (unsigned __int128)k2x3 * s;
+}
+
+__global__ __launch_bounds__(256) void k_peaks(const unsigned long long* __restrict__ counts,
+                                               int64_t nx, int64_t ny,
+                                               const int32_t* __restrict__ tracks, int64_t nt,
+                                               unsigned k2x3, uint8_t* __restrict__ flags)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nt * nx) return;
+    const int64_t t = idx / nx, j = idx - t * nx;
+    const int64_t i = tracks[t];
+    uint8_t f = 0;
+    if (candidate(counts, nx, i, j, k2x3)) {
+        f = 1;
+        if (i > 0 && i < ny - 1) {
+            const bool left = candidate(counts, nx, i - 1, j - 1, k2x3) ||
+                              candidate(counts, nx, i - 1, j, k2x3) ||
+                              candidate(counts, nx, i - 1, j + 1, k2x3);
+            const bool right = candidate(counts, nx, i + 1, j - 1, k2x3) ||
+                               candidate(counts, nx, i + 1, j, k2x3) ||
+                               candidate(counts, nx, i + 1, j + 1, k2x3);
+            if (left && right) f |= 2;
+        }
+    }
+    flags[idx] = f;
+}
+
+}  // namespace
+
+int lm_launch_peaks(const unsigned long long* counts, int64_t nx, int64_t ny,
+                    const int32_t* tracks, int64_t nt, int k, uint8_t* flags, void* stream)
+{
+    const int64_t n = nt * nx;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_peaks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, counts, nx, ny, tracks, nt, (unsigned)(3 * k * k),
+                       flags);
+    return (int)hipGetLastError();
+}

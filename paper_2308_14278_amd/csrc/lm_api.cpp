@@ -690,6 +690,34 @@ lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int
     return ok();
 }
 
+lm_status lm_find_peaks(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                        uint8_t* flags)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (n_tracks < 0 || (n_tracks > 0 && (!tracks || !flags))) return fail(LM_EINVAL, "bad arrays");
+    if (k < 1 || k > 1000) return fail(LM_EINVAL, "k must be in 1..1000");
+    if (n_tracks == 0) return ok();
+    for (int32_t t = 0; t < n_tracks; ++t)
+        if (tracks[t] < 0 || tracks[t] >= m->g.src_ny)
+            return fail(LM_ERANGE, "track %d (row %d) is outside the map", t, tracks[t]);
+    if ((int64_t)n_tracks * m->g.src_nx >= (int64_t(1) << 31))
+        return fail(LM_EUNSUPPORTED, "too many track pixels");
+    lm_status st = use_device(m);
+    if (st) return st;
+    DevBuf dt, df;
+    const size_t nf = (size_t)n_tracks * m->g.src_nx;
+    if (dt.ensure((size_t)n_tracks * 4) || df.ensure(nf)) return fail(LM_ENOMEM, "cannot allocate");
+    HIP_TRY(hipStreamSynchronize(m->last));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(dt.p, tracks, (size_t)n_tracks * 4, hipMemcpyHostToDevice));
+    LAUNCH_TRY(lm_launch_peaks(reinterpret_cast<const unsigned long long*>(m->counts), m->g.src_nx,
+                               m->g.src_ny, dt.as<int32_t>(), n_tracks, k, df.as<uint8_t>(),
+                               nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    HIP_TRY(hipMemcpy(flags, df.p, nf, hipMemcpyDeviceToHost));
+    return ok();
+}
+
 lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj,
                         lm_stats* out)
 {

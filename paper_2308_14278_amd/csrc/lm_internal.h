@@ -73,5 +73,7 @@ int lm_launch_trace(const LmDesc& d, int scheme, int precision, int terms, const
                     const int64_t* jj, int64_t n, int32_t* p, int32_t* q, void* stream);
 int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, const double* th,
                       int64_t n, double* alpha, void* stream);
+int lm_launch_peaks(const unsigned long long* counts, int64_t nx, int64_t ny,
+                    const int32_t* tracks, int64_t nt, int k, uint8_t* flags, void* stream);
 int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu);
 bool lm_supported_rays_per_lane(int r);

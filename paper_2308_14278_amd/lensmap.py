@@ -104,6 +104,7 @@ _SIGS = {
                       _P(lm_stats)],
     "lm_batch_timing": [_vp, _P(ctypes.c_float), _P(ctypes.c_float)],
     "lm_measure_valu_peak": [_d, _d],
+    "lm_find_peaks": [_vp, _i32, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_uint8)],
 }
 
 _lib = None
@@ -296,6 +297,20 @@ def lm_batch_params(b):
     _check(load().lm_batch_params(b, ctypes.byref(a), ctypes.byref(c), ctypes.byref(d)),
            "lm_batch_params")
     return int(a.value), int(c.value), int(d.value)
+
+
+PEAK_CANDIDATE = 1
+PEAK_TRUE = 2
+
+
+def lm_find_peaks(m, g: lm_geometry, tracks, k=5):
+    """Peak flags (bit 0 candidate, bit 1 true peak) of the listed map rows:
+    uint8 array [len(tracks), src_nx]."""
+    tr = np.ascontiguousarray(tracks, dtype=np.int32)
+    flags = np.empty((tr.shape[0], g.src_nx), dtype=np.uint8)
+    _check(load().lm_find_peaks(m, tr.ctypes.data_as(_i32), tr.shape[0], int(k),
+                                flags.ctypes.data_as(_P(ctypes.c_uint8))), "lm_find_peaks")
+    return flags
 
 
 def lm_shot_stats(m, i0, j0, ni, nj) -> lm_stats:

@@ -1,0 +1,84 @@
+"""GPU parity of the light-curve peak finder (Sec. 4.2) against the oracle's
+plain implementation: flags are compared bit for bit."""
+import numpy as np
+import pytest
+
+import paper_2308_14278_amd.lensmap as lm
+from oracle.peaks import find_peaks
+from paper_2308_14278_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    lm.load()
+
+
+def _map_with_counts(counts):
+    """A map whose bound count buffer holds `counts` (int64 [ny, nx])."""
+    import torch
+    ny, nx = counts.shape
+    g = lm.lm_geometry_derive(1.0, 1.0, nx, ny, 0.4, 0.1, 0.0, protect=0.0, ray_nx=64,
+                              ray_ny=64, scheme=lm.LM_SCHEME_DIRECT, coarse=64)
+    mp = lm.Map(g, 0.4, 0.1, 0.0, ([], [], []))
+    buf = torch.from_numpy(np.ascontiguousarray(counts, dtype=np.int64)).cuda()
+    lm.lm_bind_counts(mp.h, buf.data_ptr())
+    return mp, g, buf
+
+
+def _oracle_flags(counts, tracks, k=5):
+    return np.array(find_peaks(counts.tolist(), list(tracks), k), dtype=np.uint8)
+
+
+def test_peaks_synthetic_maps_bitwise():
+    rng = np.random.default_rng(4)
+    c = rng.poisson(300, size=(24, 700)).astype(np.int64)
+    # planted micro-caustic-like ridges crossing neighbouring light curves
+    for r in range(2, 22, 3):
+        j = int(rng.integers(3, 690))
+        for d in range(-1, 2):
+            c[r + d, j + int(rng.integers(-1, 2))] += int(rng.integers(80, 400))
+    # threshold cases: h exactly around 5 sigma
+    c[5, 100:103] = [100, 185, 100]
+    c[6, 100:103] = [100, 184, 100]
+    c[7, 100:103] = [100, 185, 100]
+    # huge counts (beyond 2^40) and plateaus
+    c[10, 200:203] = [1 << 41, (1 << 41) + 10_000_000, 1 << 41]
+    c[11, 300:303] = [500, 500, 500]
+    mp, g, buf = _map_with_counts(c)
+    tracks = list(range(24))
+    got = lm.lm_find_peaks(mp.h, g, tracks)
+    ref = _oracle_flags(c, tracks)
+    np.testing.assert_array_equal(got, ref)
+    assert (ref & 1).sum() > 10 and (ref & 2).sum() > 0
+    # k other than 5, and a subset of tracks in any order
+    got3 = lm.lm_find_peaks(mp.h, g, [13, 2, 0, 23], k=3)
+    np.testing.assert_array_equal(got3, _oracle_flags(c, [13, 2, 0, 23], k=3))
+    lm.lm_bind_counts(mp.h, None)
+    mp.close()
+
+
+def test_peaks_on_a_shot_map():
+    """Ten light curves of a near-fold map region shot on the GPU."""
+    w = inputs.near_fold()
+    g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                              w.gamma, w.kappa_star, n_rays=w.n_rays, scheme=w.scheme,
+                              coarse=w.coarse, mean_mass=w.mean_mass)
+    mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses())
+    # a band of rows whose images fill map rows around the centre
+    mp.shoot(0, g.ray_ny // 2 - 2000, g.ray_nx, 4000)
+    counts, _, _ = mp.counts()
+    rows = np.nonzero(counts.sum(axis=1))[0]
+    tracks = np.linspace(rows.min() + 1, rows.max() - 1, 10).astype(int)
+    got = lm.lm_find_peaks(mp.h, g, tracks)
+    ref = _oracle_flags(counts.astype(np.int64), tracks)
+    np.testing.assert_array_equal(got, ref)
+    print("near-fold tracks: %d candidates, %d true peaks" % ((got & 1).sum(), (got >> 1).sum()))
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_find_peaks(mp.h, g, [g.src_ny])
+    assert e.value.status == lm.LM_ERANGE
+    mp.close()
