@@ -128,6 +128,55 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
             "seconds": dt}, errors
 
 
+def batched_study(lm, inputs, torch, scale):
+    """The 80-map study at a fraction of its rays: one batch (coefficients of
+    every map, one persistent shooting kernel over all maps' tiles), then ten
+    light curves per map through the peak finder."""
+    import numpy as np
+    ws = inputs.batched_study(80, scale)
+    maps, geoms = [], []
+    for w in ws:
+        g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                                  w.gamma, w.kappa_star, n_rays=w.n_rays, scheme=w.scheme,
+                                  coarse=w.coarse, mean_mass=w.mean_mass)
+        maps.append(lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses()))
+        geoms.append(g)
+    rays = sum(g.n_rays for g in geoms)
+    b = lm.lm_batch_create([m.h for m in maps])
+    lm.lm_batch_tune(b, None)
+    stream = torch.cuda.current_stream()
+    lm.lm_batch_shoot(b, stream)  # warm-up (graph build)
+    torch.cuda.synchronize()
+    for m in maps:
+        m.reset(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lm.lm_batch_shoot(b, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    c_ms, s_ms = lm.lm_batch_timing(b)
+    t1 = time.perf_counter()
+    n_cand = n_true = 0
+    for m, g in zip(maps, geoms):
+        tracks = np.linspace(g.src_ny // 10, g.src_ny - g.src_ny // 10, 10).astype(np.int32)
+        f = lm.lm_find_peaks(m.h, g, tracks)
+        n_cand += int((f & 1).sum())
+        n_true += int((f >> 1).sum())
+    dt_peaks = time.perf_counter() - t1
+    for m in maps:
+        counts, n_out, n_shot = m.counts()
+        assert int(counts.sum()) + n_out == n_shot
+    lm.lm_batch_destroy(b)
+    for m in maps:
+        m.close()
+    log("batched study: 80 maps, %.4g rays in %.2f s (%.4g rays/s); 800 light curves: "
+        "%d candidates, %d true peaks in %.2f s" % (rays, dt, rays / dt, n_cand, n_true, dt_peaks))
+    return {"maps": 80, "rays": rays, "seconds": dt, "rays_per_s": rays / dt,
+            "coefficients_ms": c_ms, "shoot_kernel_ms": s_ms,
+            "rays_scale": scale, "light_curves": 800, "candidate_peaks": n_cand,
+            "true_peaks": n_true, "peak_finding_s": dt_peaks}
+
+
 def copy_calibration():
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
     scale from counter units to bytes."""
@@ -153,6 +202,9 @@ def main():
                     help="rays of the per-map comparison runs")
     ap.add_argument("--rays", type=float, default=1e13,
                     help="rays per map (1e13 is the workload; smaller values are for profiling)")
+    ap.add_argument("--study-scale", type=float, default=0.02,
+                    help="fraction of the batched 80-map study's rays for its side measurement "
+                         "(0 skips it)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default execution parameters (8 rays per lane, tile scale 1, "
                          "all workgroups that fit), which the tuner picks on MI355X")
@@ -250,6 +302,10 @@ def main():
                          "sample": "%d x %d-ray band of the paper-scale lattice" % (ni, nj)}
         log("%s: %.4g rays/s" % (name, ni * nj / dt))
 
+    study = None
+    if args.study_scale > 0:
+        study = batched_study(lm, inputs, torch, args.study_scale)
+
     line = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
@@ -273,6 +329,8 @@ def main():
         "coefficients_ms": float(np.mean(coeff_ms)),
         "comparison": per_map,
     }
+    if study is not None:
+        line["batched_study"] = study
     if not args.no_cpu_baseline:
         cb, errors = cpu_baseline_leg(lm, w, g, lenses, mp, mp32, args.cpu_seconds)
         line["cpu_baseline"] = cb

@@ -198,6 +198,20 @@ lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int
 lm_status lm_find_peaks(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
                         uint8_t* flags);
 
+/* Analysis scales near a fold caustic (Sec. 4): kappa_c = (theta_E |d|)^(2/3),
+ * |sin a| with tan a = d_x/d_y, the micro-caustic band width s_w (Eq. 13),
+ * C_star and s_f = C_star theta_E kappa_star^(1/2), the micro-caustic count
+ * N_cf (Eq. 14), and the prefactor of the peak magnification of Eq. 15,
+ * mu_peak(|beta|) = mu_peak0 x (1 if |beta| < s_w else (s_w/|beta|)^(3/8)).
+ * theta_E in arcsec, d in arcmin^-1 (Table 1 units), ds_over_r = D_s / R
+ * (0 leaves mu_peak0 at 0); s_w and s_f in theta_E.  Host only. */
+typedef struct lm_fold_scales_t {
+    double kappa_c, sin_a, s_w, c_star, s_f, n_cf, mu_peak0;
+} lm_fold_scales_t;
+lm_status lm_fold_scales(double theta_e_arcsec, double d_x, double d_y, double kappa0,
+                         double kappa_star, double n_star, double ds_over_r,
+                         lm_fold_scales_t* out);
+
 /* Work of one shot, for throughput accounting: rays, ray-lens pairs of the
  * directly summed (near) lenses, and for the interpolated scheme the level-2
  * cells of the lattice and the (cell, far lens) pairs their Taylor

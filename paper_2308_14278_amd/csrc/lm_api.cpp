@@ -718,6 +718,36 @@ lm_status lm_find_peaks(lm_map* m, const int32_t* tracks, int32_t n_tracks, int3
     return ok();
 }
 
+lm_status lm_fold_scales(double theta_e_arcsec, double d_x, double d_y, double kappa0,
+                         double kappa_star, double n_star, double ds_over_r,
+                         lm_fold_scales_t* out)
+{
+    if (!out) return fail(LM_EINVAL, "out is NULL");
+    const double in[] = {theta_e_arcsec, d_x, d_y, kappa0, kappa_star, n_star, ds_over_r};
+    for (double v : in)
+        if (!isfin(v)) return fail(LM_EINVAL, "non-finite input");
+    const double dn = std::hypot(d_x, d_y);
+    if (!(theta_e_arcsec > 0) || !(dn > 0) || d_x == 0 || !(kappa_star > 0) || !(n_star > 0) ||
+        ds_over_r < 0 || kappa0 == 1.0)
+        return fail(LM_EINVAL, "out-of-domain input");
+    // theta_E |d| is dimensionless once theta_E is in arcmin (d is per arcmin)
+    const double kc = std::pow(theta_e_arcsec / 60.0 * dn, 2.0 / 3.0);
+    const double sin_a = std::fabs(d_x) / dn;  // tan a = d_x / d_y
+    const double r = kappa_star / kc;
+    const double cs = std::sqrt(std::log(3.05 * std::sqrt(n_star)));
+    out->kappa_c = kc;
+    out->sin_a = sin_a;
+    out->s_w = 2.0 / sin_a * std::sqrt(kc) * r * r;
+    out->c_star = cs;
+    out->s_f = cs * std::sqrt(kappa_star);
+    out->n_cf = std::sqrt(2.0 * cs / sin_a) * std::pow(r, 0.75);
+    const double d_per_rad = dn * (180.0 * 60.0 / M_PI);
+    out->mu_peak0 = ds_over_r > 0 ? 1.0 / std::fabs(1.0 - kappa0) *
+                                        std::sqrt(ds_over_r / d_per_rad) * std::pow(1.0 / r, 0.75)
+                                  : 0.0;
+    return ok();
+}
+
 lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj,
                         lm_stats* out)
 {

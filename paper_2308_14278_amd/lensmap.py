@@ -64,6 +64,11 @@ class lm_geometry(ctypes.Structure):
         return int(self.ray_nx) * int(self.ray_ny)
 
 
+class lm_fold_scales_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("kappa_c", "sin_a", "s_w", "c_star", "s_f", "n_cf", "mu_peak0")]
+
+
 class lm_stats(ctypes.Structure):
     _fields_ = [("rays", ctypes.c_int64), ("near_pairs", ctypes.c_double),
                 ("cells", ctypes.c_int64), ("far_pairs", ctypes.c_double)]
@@ -105,6 +110,7 @@ _SIGS = {
     "lm_batch_timing": [_vp, _P(ctypes.c_float), _P(ctypes.c_float)],
     "lm_measure_valu_peak": [_d, _d],
     "lm_find_peaks": [_vp, _i32, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_uint8)],
+    "lm_fold_scales": [ctypes.c_double] * 7 + [_P(lm_fold_scales_t)],
 }
 
 _lib = None
@@ -297,6 +303,13 @@ def lm_batch_params(b):
     _check(load().lm_batch_params(b, ctypes.byref(a), ctypes.byref(c), ctypes.byref(d)),
            "lm_batch_params")
     return int(a.value), int(c.value), int(d.value)
+
+
+def lm_fold_scales(theta_e_arcsec, d_x, d_y, kappa0, kappa_star, n_star, ds_over_r=0.0):
+    out = lm_fold_scales_t()
+    _check(load().lm_fold_scales(theta_e_arcsec, d_x, d_y, kappa0, kappa_star, n_star, ds_over_r,
+                                 ctypes.byref(out)), "lm_fold_scales")
+    return {n: getattr(out, n) for n, _ in out._fields_}
 
 
 PEAK_CANDIDATE = 1
