@@ -19,7 +19,7 @@ import subprocess
 
 import numpy as np
 
-from .geometry import OracleGeometry, derive_geometry  # noqa: F401
+from .geometry import OracleGeometry, derive_fold_geometry, derive_geometry  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lensoracle.c")
@@ -53,6 +53,7 @@ class _Params(ctypes.Structure):
         ("scheme", ctypes.c_int64), ("coarse", ctypes.c_int64),
         ("l1_kx", ctypes.c_int64), ("l1_ky", ctypes.c_int64),
         ("halo", ctypes.c_int64), ("terms", ctypes.c_int64),
+        ("macro", ctypes.c_int64), ("d_x", ctypes.c_double), ("d_y", ctypes.c_double),
     ]
 
 
@@ -79,6 +80,11 @@ def _load():
         lib.lmo_shoot.argtypes = [pp, _d, _d, _d, ctypes.c_int64, ctypes.c_int64,
                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _u64, _u64,
                                   ctypes.c_int]
+        lib.lmo_shoot_window.argtypes = [pp, _d, _d, _d, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int64, _u64, _u64, ctypes.c_int]
+        lib.lmo_shoot_window.restype = ctypes.c_int
         lib.lmo_mu_factor.argtypes = [pp]
         lib.lmo_mu_factor.restype = ctypes.c_double
         lib.lmo_num_threads.restype = ctypes.c_int
@@ -104,9 +110,16 @@ class Oracle:
     Lenses are copied to contiguous float64 arrays.
     """
 
-    def __init__(self, geom, kappa, gamma, kappa_star, lx, ly, lm):
+    def __init__(self, geom, kappa, gamma, kappa_star, lx, ly, lm, fold=None):
+        """fold=(kappa_0, d_x, d_y) selects the fold macro model of Eq. 5/6
+        (d in 1/theta_E); kappa and gamma are then ignored."""
         self.geom = geom
         self.kappa, self.gamma, self.kappa_star = float(kappa), float(gamma), float(kappa_star)
+        macro, dx, dy = 0, 0.0, 0.0
+        if fold is not None:
+            macro = 1
+            self.kappa, dx, dy = float(fold[0]), float(fold[1]), float(fold[2])
+            self.gamma = 0.0
         self.lx, self.ly, self.lm = _f64(lx), _f64(ly), _f64(lm)
         if not (self.lx.shape == self.ly.shape == self.lm.shape) or self.lx.ndim != 1:
             raise ValueError("lens arrays must be 1-D and of equal length")
@@ -115,7 +128,7 @@ class Oracle:
             g.src_x0, g.src_y0, g.src_dx, g.src_dy, g.src_nx, g.src_ny,
             g.ray_x0, g.ray_y0, g.ray_dx, g.ray_dy, g.ray_nx, g.ray_ny,
             self.kappa, self.gamma, self.kappa_star,
-            g.scheme, g.coarse, g.l1_kx, g.l1_ky, g.halo, g.terms)
+            g.scheme, g.coarse, g.l1_kx, g.l1_ky, g.halo, g.terms, macro, dx, dy)
 
     @property
     def n(self):
@@ -183,6 +196,19 @@ class Oracle:
                                int(nthreads))
         if rc:
             raise RuntimeError("lmo_shoot failed (%d)" % rc)
+        return counts, int(nout.value)
+
+    def shoot_window(self, i0, j0, ni, nj, p0, q0, np_, nq, nthreads=0):
+        """Counts of the pixel window [p0, p0+np_) x [q0, q0+nq) (uint64 [nq, np_])
+        from the lattice sub-rectangle; returns (counts, rays outside the window)."""
+        counts = np.zeros((nq, np_), dtype=np.uint64)
+        nout = ctypes.c_uint64(0)
+        rc = _load().lmo_shoot_window(ctypes.byref(self._p), *self._lens(), int(i0), int(j0),
+                                      int(ni), int(nj), int(p0), int(q0), int(np_), int(nq),
+                                      counts.ctypes.data_as(_u64), ctypes.byref(nout),
+                                      int(nthreads))
+        if rc:
+            raise RuntimeError("lmo_shoot_window failed (%d)" % rc)
         return counts, int(nout.value)
 
     def mu_factor(self):

@@ -102,3 +102,48 @@ def derive_geometry(src_lx, src_ly, src_nx, src_ny, kappa, gamma, kappa_star,
         ray_nx=int(ray_nx), ray_ny=int(ray_ny),
         scheme=int(scheme), coarse=int(R), l1_kx=int(kx), l1_ky=int(ky), halo=int(halo),
         terms=int(terms))
+
+
+def derive_fold_geometry(src_lx, src_ly, src_nx, src_ny, kappa0, d_x, kappa_star, n_rays,
+                         margin=None, mean_mass=1.0, scheme=1, coarse=0, halo=1, terms=4):
+    """Geometry of a map next to a fold caustic (Sec. 2 Eq. 5, Sec. 3.1, Sec. 4.1).
+
+    The source window spans beta_x in [-margin, src_lx] across the caustic (the
+    margin, 20 sqrt(kappa_star) by default, lies on the side without macro
+    images and is part of the map, as in Fig. 2) and beta_y in
+    [-src_ly/2, src_ly/2] along it.  The shooting region is the rectangle
+    L_ix = 2 sqrt(2 (src_lx + margin) / d_x) (both images of Eq. 5 with d_y
+    neglected), L_iy = src_ly / (2 (1 - kappa_0)), centred on the origin; with
+    Table 1 this reproduces N_star = 13745.  Rays and grid levels follow the
+    same rules as derive_geometry (Eq. 8, 10, 11)."""
+    w = 20.0 * math.sqrt(kappa_star) if margin is None else float(margin)
+    lsx = src_lx + w
+    lix = 2.0 * math.sqrt(2.0 * lsx / abs(d_x))
+    liy = src_ly / abs(2.0 * (1.0 - kappa0))
+    l3 = math.sqrt(lix * liy / float(n_rays))
+    ray_nx = max(1, _round_half_away(lix / l3))
+    ray_ny = max(1, _round_half_away(liy / l3))
+    l3x, l3y = lix / ray_nx, liy / ray_ny
+    R, kx, ky = int(coarse), 1, 1
+    if scheme == 1:
+        l0 = math.sqrt(math.pi * mean_mass / kappa_star) if kappa_star > 0 else math.inf
+        l1x, l1y = min(l0, lix / 10.0), min(l0, liy / 10.0)
+        if R <= 0:
+            l2 = min(l1x / 20.0 / l3x, l1y / 20.0 / l3y)
+            R = 64 * max(1, _round_half_away(l2 / 64.0))
+        kx = max(1, _round_half_away(l1x / (R * l3x)))
+        ky = max(1, _round_half_away(l1y / (R * l3y)))
+    elif R <= 0:
+        R = 64
+    return OracleGeometry(
+        src_x0=-w, src_y0=-0.5 * src_ly, src_dx=lsx / src_nx, src_dy=src_ly / src_ny,
+        src_nx=int(src_nx), src_ny=int(src_ny),
+        ray_x0=-0.5 * lix, ray_y0=-0.5 * liy, ray_dx=l3x, ray_dy=l3y,
+        ray_nx=int(ray_nx), ray_ny=int(ray_ny),
+        scheme=int(scheme), coarse=int(R), l1_kx=int(kx), l1_ky=int(ky), halo=int(halo),
+        terms=int(terms))
+
+
+def fold_n_star(g: OracleGeometry, kappa_star, mean_mass=1.0):
+    """Lenses in the shooting region, N_star = L_ix L_iy kappa_star / (pi <m>) (Sec. 3.1)."""
+    return g.ray_nx * g.ray_dx * g.ray_ny * g.ray_dy * kappa_star / (math.pi * mean_mass)

@@ -9,12 +9,17 @@
  *
  * What is computed (all lengths in Einstein radii, all arithmetic in FP64):
  *
- *  Lens equation with a constant macro Jacobian, point-mass microlenses and a
- *  compensating negative mass sheet (Sec. 2, Eq. 1 and Eq. 6):
- *      beta = diag(1-kappa-gamma, 1-kappa+gamma) theta + kappa_star theta
- *             - sum_k m_k (theta - theta_k) / |theta - theta_k|^2
+ *  Lens equation with point-mass microlenses and a compensating negative mass
+ *  sheet (Sec. 2, Eq. 6), with either macro model:
+ *   linear (Eq. 1): beta = diag(1-kappa-gamma, 1-kappa+gamma) theta
+ *                          + kappa_star theta - alpha(theta);
+ *   fold (Eq. 5, 6): beta_x = (d_x theta_x / 2 + d_y theta_y) theta_x
+ *                            + kappa_star theta_x - alpha_x,
+ *                    beta_y = 2 (1 - kappa_0) theta_y + kappa_star theta_y - alpha_y,
+ *  alpha(theta) = sum_k m_k (theta - theta_k) / |theta - theta_k|^2.
  *  The sheet of density -kappa_star is read as infinite and uniform about the
- *  coordinate origin, so its term is +kappa_star * theta.
+ *  coordinate origin, so its term is +kappa_star * theta.  In fold mode the
+ *  kappa field holds kappa_0 and d = (d_x, d_y) is in units of 1/theta_E.
  *
  *  Ray lattice (Sec. 3.2, level-3 grid, Eq. 11): ray (i,j) sits at the centre
  *  of level-3 pixel (i,j): theta = (X0 + (i+1/2) L3x, Y0 + (j+1/2) L3y).
@@ -61,6 +66,9 @@ typedef struct {
     double kappa, gamma, kappa_star;
     /* scheme: 0 direct, 1 interpolated */
     int64_t scheme, coarse, l1_kx, l1_ky, halo, terms;
+    /* macro model: 0 linear (kappa, gamma), 1 fold (kappa = kappa_0, d_x, d_y) */
+    int64_t macro;
+    double d_x, d_y;
 } lmo_params;
 
 typedef struct {
@@ -202,10 +210,16 @@ static void far_eval(int64_t P, const double *a, double dx, double dy, double *a
     *ay = -fy;
 }
 
-/* source-plane position (Eq. 6 with the constant Jacobian of Eq. 1) */
+/* source-plane position (Eq. 6 with the constant Jacobian of Eq. 1, or the
+ * fold mapping of Eq. 5) */
 static void lens_map(const lmo_params *p, double tx, double ty, double ax, double ay,
                      double *bx, double *by)
 {
+    if (p->macro == 1) {
+        *bx = (0.5 * p->d_x * tx + p->d_y * ty) * tx + p->kappa_star * tx - ax;
+        *by = 2.0 * (1.0 - p->kappa) * ty + p->kappa_star * ty - ay;
+        return;
+    }
     double lt = 1.0 - p->kappa - p->gamma, lr = 1.0 - p->kappa + p->gamma;
     *bx = (lt + p->kappa_star) * tx - ax;
     *by = (lr + p->kappa_star) * ty - ay;
@@ -222,6 +236,7 @@ static int64_t bin_of(const lmo_params *p, double bx, double by)
 
 static int check_params(const lmo_params *p)
 {
+    if (p->macro != 0 && p->macro != 1) return -1;
     if (!(p->src_dx > 0 && p->src_dy > 0 && p->ray_dx > 0 && p->ray_dy > 0)) return -1;
     if (p->src_nx <= 0 || p->src_ny <= 0 || p->ray_nx < 0 || p->ray_ny < 0) return -1;
     if (p->scheme == 1) {
@@ -346,13 +361,40 @@ int lmo_trace(const lmo_params *p, const double *lx, const double *ly, const dou
 }
 
 /* Shoot the rays of the lattice sub-rectangle [i0,i0+ni) x [j0,j0+nj) and add
- * them to counts[src_ny*src_nx] (row-major, q*src_nx + p); rays outside the
- * map are added to *n_out.  nthreads <= 0 uses the OpenMP default. */
+ * those landing in the pixel window [wp0, wp0+wnp) x [wq0, wq0+wnq) of the map
+ * to counts[wnq*wnp] (row-major); every other ray (outside the map or outside
+ * the window) is added to *n_out.  nthreads <= 0 uses the OpenMP default. */
+int lmo_shoot_window(const lmo_params *p, const double *lx, const double *ly, const double *lm,
+                     int64_t n, int64_t i0, int64_t j0, int64_t ni, int64_t nj, int64_t wp0,
+                     int64_t wq0, int64_t wnp, int64_t wnq, uint64_t *counts, uint64_t *n_out,
+                     int nthreads);
+
+/* Shoot into the whole map: counts[src_ny*src_nx] (row-major, q*src_nx + p). */
 int lmo_shoot(const lmo_params *p, const double *lx, const double *ly, const double *lm,
               int64_t n, int64_t i0, int64_t j0, int64_t ni, int64_t nj, uint64_t *counts,
               uint64_t *n_out, int nthreads)
 {
+    return lmo_shoot_window(p, lx, ly, lm, n, i0, j0, ni, nj, 0, 0, p->src_nx, p->src_ny, counts,
+                            n_out, nthreads);
+}
+
+/* index of a map pixel in the window, or -1 */
+static int64_t window_of(int64_t b, const lmo_params *p, int64_t wp0, int64_t wq0, int64_t wnp,
+                         int64_t wnq)
+{
+    if (b < 0) return -1;
+    int64_t q = b / p->src_nx, pp = b % p->src_nx;
+    if (pp < wp0 || pp >= wp0 + wnp || q < wq0 || q >= wq0 + wnq) return -1;
+    return (q - wq0) * wnp + (pp - wp0);
+}
+
+int lmo_shoot_window(const lmo_params *p, const double *lx, const double *ly, const double *lm,
+                     int64_t n, int64_t i0, int64_t j0, int64_t ni, int64_t nj, int64_t wp0,
+                     int64_t wq0, int64_t wnp, int64_t wnq, uint64_t *counts, uint64_t *n_out,
+                     int nthreads)
+{
     if (check_params(p)) return -1;
+    if (wnp <= 0 || wnq <= 0) return -1;
     if (ni < 0 || nj < 0 || i0 < 0 || j0 < 0 || i0 + ni > p->ray_nx || j0 + nj > p->ray_ny)
         return -1;
     if (ni == 0 || nj == 0) return 0;
@@ -374,7 +416,7 @@ int lmo_shoot(const lmo_params *p, const double *lx, const double *ly, const dou
                 double ax, ay, bx, by;
                 direct_sum(&L, NULL, 0, tx, ty, &ax, &ay);
                 lens_map(p, tx, ty, ax, ay, &bx, &by);
-                int64_t b = bin_of(p, bx, by);
+                int64_t b = window_of(bin_of(p, bx, by), p, wp0, wq0, wnp, wnq);
                 if (b < 0) {
                     ++outs;
                 } else {
@@ -418,7 +460,7 @@ int lmo_shoot(const lmo_params *p, const double *lx, const double *ly, const dou
                             direct_sum(&L, idx, nn, tx, ty, &nx, &ny);
                             far_eval(P, a, tx - zx, ty - zy, &fx, &fy);
                             lens_map(p, tx, ty, nx + fx, ny + fy, &bx, &by);
-                            int64_t b = bin_of(p, bx, by);
+                            int64_t b = window_of(bin_of(p, bx, by), p, wp0, wq0, wnp, wnq);
                             if (b < 0) {
                                 ++outs;
                             } else {

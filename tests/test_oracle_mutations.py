@@ -23,6 +23,11 @@ MUTATIONS = {
     "dropped_mass": ("nsum_add(&sx, L->m[k] * dx / r2);", "nsum_add(&sx, dx / r2);"),
     "cell_centre_offset": ("*zx = p->ray_x0 + ((double)ci + 0.5)", "*zx = p->ray_x0 + ((double)ci + 0.0)"),
     "power_transposed": ("double ny = tx * uy + ty * ux;", "double ny = tx * uy - ty * ux;"),
+    "fold_missing_half": ("*bx = (0.5 * p->d_x * tx + p->d_y * ty) * tx",
+                          "*bx = (p->d_x * tx + p->d_y * ty) * tx"),
+    "fold_missing_two": ("*by = 2.0 * (1.0 - p->kappa) * ty", "*by = (1.0 - p->kappa) * ty"),
+    "fold_sheet_dropped": ("+ p->kappa_star * tx - ax;\n        *by = 2.0",
+                           "- ax;\n        *by = 2.0"),
 }
 
 
@@ -42,6 +47,6 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     assert before in src
     (d / "oracle" / "lensoracle.c").write_text(src.replace(before, after))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py"], cwd=d, capture_output=True, text=True,
-                       timeout=600)
+                        "tests/test_oracle_pins.py", "tests/test_oracle_fold.py"], cwd=d,
+                       capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "planted mistake %r was not caught:\n%s" % (name, r.stdout[-2000:])
