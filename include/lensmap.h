@@ -55,6 +55,8 @@ typedef int32_t lm_status;
 
 #define LM_PREC_MIXED 0       /* rebased FP32 lens sums, FP64 bases and binning */
 #define LM_PREC_FP32 1        /* plain FP32 in global coordinates (comparison path) */
+#define LM_PREC_MIXED_FP64 2  /* as LM_PREC_MIXED with FP64 near-lens sums (interpolated
+                                 scheme only; for pixels much finer than 1e-3 theta_E) */
 
 #define LM_MAX_TERMS 7        /* largest supported P */
 
@@ -112,6 +114,22 @@ lm_status lm_geometry_derive(lm_geometry* g, double src_lx, double src_ly, int32
                              double protect, double n_rays, int64_t ray_nx, int64_t ray_ny,
                              int32_t scheme, int32_t coarse, double mean_mass);
 
+/*
+ * Geometry of a map next to a fold caustic (Sec. 2 Eq. 5, Sec. 3.1, Sec. 4.1):
+ * the source window spans beta_x in [-margin, src_lx] across the caustic (the
+ * margin lies on the side without macro images and is part of the map;
+ * margin < 0: 20 sqrt(kappa_star)) and beta_y in [-src_ly/2, src_ly/2] along it,
+ * in src_nx x src_ny pixels.  The shooting region is the rectangle
+ * L_ix = 2 sqrt(2 (src_lx + margin) / d_x), L_iy = src_ly / (2 (1 - kappa0)),
+ * centred on the origin (with Table 1 it holds N_star = 13745 lenses); rays and
+ * grid levels follow lm_geometry_derive (n_rays rays, Eq. 10, 11, level-2 =
+ * level-1 / 20 unless coarse > 0).  d_x in 1/theta_E, d_x > 0.
+ */
+lm_status lm_geometry_derive_fold(lm_geometry* g, double src_lx, double src_ly, int32_t src_nx,
+                                  int32_t src_ny, double kappa0, double d_x, double kappa_star,
+                                  double margin, double n_rays, int32_t scheme, int32_t coarse,
+                                  double mean_mass);
+
 typedef struct lm_map lm_map;
 typedef struct lm_batch lm_batch;
 
@@ -119,7 +137,7 @@ typedef struct lm_batch lm_batch;
  * start at zero; the macro model is kappa = gamma = kappa_star = 0 and there
  * are no lenses until set.  LM_EINVAL for an invalid geometry (non-positive
  * sizes, coarse not a positive multiple of 64, more than 2^31 rays per
- * workgroup tile, P outside 1..LM_MAX_TERMS, src_nx*src_ny >= 2^31). */
+ * workgroup tile, P outside 1..LM_MAX_TERMS, src_nx*src_ny >= 2^40). */
 lm_status lm_create(const lm_geometry* g, lm_map** out);
 
 /* Release every resource of the map (NULL is ignored).  Waits for the map's
@@ -127,8 +145,16 @@ lm_status lm_create(const lm_geometry* g, lm_map** out);
 void lm_destroy(lm_map* m);
 
 /* Macro convergence kappa, shear gamma and star convergence kappa_star of the
- * compensating sheet (Eq. 1, Eq. 6).  LM_ESTATE if the map has counts. */
+ * compensating sheet (Eq. 1, Eq. 6): the constant-Jacobian macro model.
+ * LM_ESTATE if the map has counts. */
 lm_status lm_set_macro(lm_map* m, double kappa, double gamma, double kappa_star);
+
+/* The fold macro model of Eq. 5/6 instead:
+ *   beta_x = (d_x theta_x / 2 + d_y theta_y) theta_x + kappa_star theta_x - alpha_x,
+ *   beta_y = (2 (1 - kappa0) + kappa_star) theta_y - alpha_y,
+ * with d = -(grad kappa)_0 - (grad gamma)_0 in 1/theta_E (Table 1 gives d in
+ * arcmin^-1: multiply by theta_E in arcmin).  LM_ESTATE if the map has counts. */
+lm_status lm_set_fold(lm_map* m, double kappa0, double d_x, double d_y, double kappa_star);
 
 /* Copy n lenses: positions (x[k], y[k]) and masses mass[k] > 0.  n may be 0.
  * Sorts them by level-1 cell on the host and uploads them.  LM_EINVAL for
@@ -161,6 +187,12 @@ lm_status lm_sync(lm_map* m);
  * left the map and the number of rays shot so far (either may be NULL) to the
  * host (Sec. 3.2.3: counts transferred to the CPU).  Synchronous. */
 lm_status lm_read_counts(lm_map* m, uint64_t* host_counts, uint64_t* n_out, uint64_t* n_shot);
+
+/* Copy the counts of the pixel window [p0, p0+np) x [q0, q0+nq) to host
+ * memory (nq rows of np uint64).  LM_ERANGE if the window leaves the map.
+ * Synchronous. */
+lm_status lm_read_counts_region(lm_map* m, int32_t p0, int32_t q0, int32_t np, int32_t nq,
+                                uint64_t* host_counts);
 
 /* Magnification of one ray count: (ray_dx ray_dy) / (src_dx src_dy) (Eq. 12). */
 lm_status lm_mu_factor(const lm_map* m, double* factor);

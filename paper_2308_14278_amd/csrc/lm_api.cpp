@@ -98,13 +98,16 @@ lm_status validate_geometry(const lm_geometry* g)
     if (!(g->src_dx > 0 && g->src_dy > 0 && g->ray_dx > 0 && g->ray_dy > 0))
         return fail(LM_EINVAL, "pixel and ray spacings must be positive");
     if (g->src_nx <= 0 || g->src_ny <= 0) return fail(LM_EINVAL, "source map must have pixels");
-    if ((int64_t)g->src_nx * g->src_ny >= (int64_t(1) << 31))
-        return fail(LM_EINVAL, "source map too large (src_nx*src_ny must be < 2^31)");
+    if ((int64_t)g->src_nx * g->src_ny >= (int64_t(1) << 40))
+        return fail(LM_EINVAL, "source map too large (src_nx*src_ny must be < 2^40)");
     if (g->ray_nx <= 0 || g->ray_ny <= 0) return fail(LM_EINVAL, "ray lattice must be non-empty");
     if (g->scheme != LM_SCHEME_DIRECT && g->scheme != LM_SCHEME_INTERP)
         return fail(LM_EINVAL, "unknown scheme %d", g->scheme);
-    if (g->precision != LM_PREC_MIXED && g->precision != LM_PREC_FP32)
+    if (g->precision != LM_PREC_MIXED && g->precision != LM_PREC_FP32 &&
+        g->precision != LM_PREC_MIXED_FP64)
         return fail(LM_EINVAL, "unknown precision %d", g->precision);
+    if (g->precision == LM_PREC_MIXED_FP64 && g->scheme != LM_SCHEME_INTERP)
+        return fail(LM_EUNSUPPORTED, "LM_PREC_MIXED_FP64 is built for the interpolated scheme only");
     if (g->coarse <= 0 || g->coarse % 64 != 0 || g->coarse > (1 << 15))
         return fail(LM_EINVAL, "coarse must be a positive multiple of 64 (at most 32768), got %d",
                     g->coarse);
@@ -128,6 +131,8 @@ struct lm_map {
     lm_geometry g{};
     int device = 0;
     double kappa = 0, gamma = 0, kappa_star = 0;
+    bool fold = false;
+    double fold_dx = 0, fold_dy = 0;  // 1/theta_E
     int64_t nlens = 0;
     // derived
     int64_t ncx = 0, ncy = 0, n1x = 0, n1y = 0;
@@ -174,8 +179,15 @@ Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scal
     while ((G * G * nrb * ncc) % LM_WAVES != 0) ncc *= 2;
     e.ncc = ncc;
     e.cw = (int)ceil_div(R, ncc);
-    const double mx = std::fabs(1.0 - m->kappa - m->gamma + m->kappa_star);
-    const double my = std::fabs(1.0 - m->kappa + m->gamma + m->kappa_star);
+    double mx = std::fabs(1.0 - m->kappa - m->gamma + m->kappa_star);
+    double my = std::fabs(1.0 - m->kappa + m->gamma + m->kappa_star);
+    if (m->fold) {
+        // largest Jacobian entries over the lattice
+        const double hx = 0.5 * g.ray_nx * g.ray_dx, hy = 0.5 * g.ray_ny * g.ray_dy;
+        mx = std::fabs(m->kappa_star) + std::fabs(m->fold_dx) * hx + 2.0 * std::fabs(m->fold_dy) * hx +
+             std::fabs(m->fold_dy) * hy;
+        my = std::fabs(2.0 * (1.0 - m->kappa) + m->kappa_star);
+    }
     // pixels spanned by the tile's smooth image, plus a margin of 0.1 theta_E
     // (at least 8 pixels) on each side for the variation of the near-lens
     // deflection across the tile
@@ -210,8 +222,16 @@ LmDesc make_desc(const lm_map* m, int64_t i0, int64_t j0, int64_t i1, int64_t j1
     d.y0 = g.ray_y0;
     d.dx = g.ray_dx;
     d.dy = g.ray_dy;
-    d.mx = 1.0 - m->kappa - m->gamma + m->kappa_star;
-    d.my = 1.0 - m->kappa + m->gamma + m->kappa_star;
+    if (m->fold) {
+        d.fold = 1;
+        d.mx = m->kappa_star;
+        d.my = 2.0 * (1.0 - m->kappa) + m->kappa_star;
+        d.qx = 0.5 * m->fold_dx;
+        d.qy = m->fold_dy;
+    } else {
+        d.mx = 1.0 - m->kappa - m->gamma + m->kappa_star;
+        d.my = 1.0 - m->kappa + m->gamma + m->kappa_star;
+    }
     d.bx0 = g.src_x0;
     d.by0 = g.src_y0;
     d.inv_sdx = 1.0 / g.src_dx;
@@ -371,6 +391,66 @@ lm_status lm_geometry_derive(lm_geometry* g, double src_lx, double src_ly, int32
     return ok();
 }
 
+lm_status lm_geometry_derive_fold(lm_geometry* g, double src_lx, double src_ly, int32_t src_nx,
+                                  int32_t src_ny, double kappa0, double d_x, double kappa_star,
+                                  double margin, double n_rays, int32_t scheme, int32_t coarse,
+                                  double mean_mass)
+{
+    if (!g) return fail(LM_EINVAL, "g is NULL");
+    if (!(isfin(src_lx) && isfin(src_ly) && isfin(kappa0) && isfin(d_x) && isfin(kappa_star) &&
+          isfin(margin) && isfin(mean_mass) && isfin(n_rays)))
+        return fail(LM_EINVAL, "non-finite input");
+    if (!(src_lx > 0 && src_ly > 0) || src_nx <= 0 || src_ny <= 0 || !(d_x > 0) ||
+        kappa0 == 1.0 || kappa_star < 0 || !(mean_mass > 0) || !(n_rays >= 1.0))
+        return fail(LM_EINVAL, "out-of-domain input");
+    if (scheme != LM_SCHEME_DIRECT && scheme != LM_SCHEME_INTERP)
+        return fail(LM_EINVAL, "unknown scheme %d", scheme);
+    // source window [-w, src_lx] x [-src_ly/2, src_ly/2]; the preimage rectangle
+    // of both fold images (Sec. 3.1, Eq. 5)
+    const double w = margin < 0 ? 20.0 * std::sqrt(kappa_star) : margin;
+    const double lsx = src_lx + w;
+    const double lix = 2.0 * std::sqrt(2.0 * lsx / d_x);
+    const double liy = src_ly / std::fabs(2.0 * (1.0 - kappa0));
+    const double l3 = std::sqrt(lix * liy / n_rays);  // Eq. 11
+    const int64_t ray_nx = std::max<int64_t>(1, round_half_away(lix / l3));
+    const int64_t ray_ny = std::max<int64_t>(1, round_half_away(liy / l3));
+    std::memset(g, 0, sizeof *g);
+    g->src_x0 = -w;
+    g->src_y0 = -0.5 * src_ly;
+    g->src_dx = lsx / src_nx;
+    g->src_dy = src_ly / src_ny;
+    g->src_nx = src_nx;
+    g->src_ny = src_ny;
+    g->ray_x0 = -0.5 * lix;
+    g->ray_y0 = -0.5 * liy;
+    g->ray_dx = lix / (double)ray_nx;
+    g->ray_dy = liy / (double)ray_ny;
+    g->ray_nx = ray_nx;
+    g->ray_ny = ray_ny;
+    g->scheme = scheme;
+    g->precision = LM_PREC_MIXED;
+    g->near_halo = 1;
+    g->taylor_terms = 4;
+    g->l1_kx = 1;
+    g->l1_ky = 1;
+    int64_t R = coarse;
+    if (scheme == LM_SCHEME_INTERP) {
+        const double l0 = kappa_star > 0 ? std::sqrt(M_PI * mean_mass / kappa_star) : INFINITY;
+        const double l1x = std::min(l0, lix / 10.0), l1y = std::min(l0, liy / 10.0);
+        if (R <= 0) {
+            const double l2 = std::min(l1x / 20.0 / g->ray_dx, l1y / 20.0 / g->ray_dy);
+            R = 64 * std::max<int64_t>(1, round_half_away(l2 / 64.0));
+        }
+        g->l1_kx = (int32_t)std::max<int64_t>(1, round_half_away(l1x / ((double)R * g->ray_dx)));
+        g->l1_ky = (int32_t)std::max<int64_t>(1, round_half_away(l1y / ((double)R * g->ray_dy)));
+    } else if (R <= 0) {
+        R = 64;
+    }
+    if (R > (1 << 15)) return fail(LM_EINVAL, "level-2 cells of %lld rays are too large", (long long)R);
+    g->coarse = (int32_t)R;
+    return ok();
+}
+
 lm_status lm_create(const lm_geometry* g, lm_map** out)
 {
     if (!out) return fail(LM_EINVAL, "out is NULL");
@@ -425,6 +505,23 @@ lm_status lm_set_macro(lm_map* m, double kappa, double gamma, double kappa_star)
     m->kappa = kappa;
     m->gamma = gamma;
     m->kappa_star = kappa_star;
+    m->fold = false;
+    m->fold_dx = m->fold_dy = 0.0;
+    return ok();
+}
+
+lm_status lm_set_fold(lm_map* m, double kappa0, double d_x, double d_y, double kappa_star)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (!(isfin(kappa0) && isfin(d_x) && isfin(d_y) && isfin(kappa_star)))
+        return fail(LM_EINVAL, "non-finite fold parameter");
+    if (m->has_counts) return fail(LM_ESTATE, "map has counts; call lm_reset_counts first");
+    m->kappa = kappa0;
+    m->gamma = 0.0;
+    m->kappa_star = kappa_star;
+    m->fold = true;
+    m->fold_dx = d_x;
+    m->fold_dy = d_y;
     return ok();
 }
 
@@ -588,6 +685,24 @@ lm_status lm_read_counts(lm_map* m, uint64_t* host_counts, uint64_t* n_out, uint
     return ok();
 }
 
+lm_status lm_read_counts_region(lm_map* m, int32_t p0, int32_t q0, int32_t np, int32_t nq,
+                                uint64_t* host_counts)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (np < 0 || nq < 0 || (np > 0 && nq > 0 && !host_counts)) return fail(LM_EINVAL, "bad arguments");
+    if (p0 < 0 || q0 < 0 || p0 > m->g.src_nx - np || q0 > m->g.src_ny - nq)
+        return fail(LM_ERANGE, "window leaves the map");
+    if (np == 0 || nq == 0) return ok();
+    lm_status st = use_device(m);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(m->last));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy2D(host_counts, (size_t)np * 8,
+                        m->counts + (size_t)q0 * m->g.src_nx + p0, (size_t)m->g.src_nx * 8,
+                        (size_t)np * 8, (size_t)nq, hipMemcpyDeviceToHost));
+    return ok();
+}
+
 lm_status lm_mu_factor(const lm_map* m, double* factor)
 {
     if (!m || !factor) return fail(LM_EINVAL, "NULL argument");
@@ -599,7 +714,12 @@ lm_status lm_read_mu(lm_map* m, double* host_mu)
 {
     if (!m || !host_mu) return fail(LM_EINVAL, "NULL argument");
     const size_t npix = (size_t)m->g.src_nx * m->g.src_ny;
-    std::vector<uint64_t> c(npix);
+    std::vector<uint64_t> c;
+    try {
+        c.resize(npix);
+    } catch (const std::bad_alloc&) {
+        return fail(LM_ENOMEM, "cannot allocate %zu host counts", npix);
+    }
     lm_status st = lm_read_counts(m, c.data(), nullptr, nullptr);
     if (st) return st;
     double f;

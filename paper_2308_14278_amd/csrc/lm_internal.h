@@ -21,7 +21,9 @@ struct LmCoef {
 struct LmDesc {
     // ray lattice and macro mapping (FP64)
     double x0, y0, dx, dy;
-    double mx, my;                 // 1-kappa-gamma+kappa_star, 1-kappa+gamma+kappa_star
+    double mx, my;                 // linear: 1-kappa-gamma+kappa_star, 1-kappa+gamma+kappa_star;
+                                   // fold: kappa_star, 2(1-kappa0)+kappa_star
+    double qx, qy;                 // fold: d_x/2, d_y (beta_x gains (qx theta_x + qy theta_y) theta_x)
     double bx0, by0, inv_sdx, inv_sdy;
     // FP32 copies: half ray spacing as float-float (rebased arithmetic) and
     // plain values (the global-FP32 comparison path)
@@ -30,6 +32,8 @@ struct LmDesc {
     float mxf, myf, bx0f, by0f;
     float inv_sdxf, inv_sdyf;
     int32_t snx, sny;
+    int32_t fold;                  // 1: fold macro model
+    int32_t pad_;
     // scheme and work decomposition
     int32_t R, Kx, Ky, H;
     int32_t G;                     // level-2 cells per workgroup-tile side

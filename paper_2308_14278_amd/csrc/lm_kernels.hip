@@ -36,6 +36,19 @@ struct Cap {
     static constexpr int value = SCHEME == 0 ? LM_LENS_CAP : LM_NEAR_CAP;
 };
 
+// Arithmetic of the ray-lens pairs: FP32 (rebased or plain global) or FP64
+// (rebased), and the staged lens record of each.
+template <int PREC>
+struct Prec {
+    using T = float;
+    using L = float4;
+};
+template <>
+struct Prec<2> {
+    using T = double;
+    using L = double4;
+};
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -60,6 +73,7 @@ __device__ __forceinline__ unsigned wave_sum_u32(unsigned v)
 struct Hot {
     double inv_sdx, inv_sdy, snxd, snyd;
     float mxf, myf, bx0f, by0f, inv_sdxf, inv_sdyf, snxf, snyf;
+    float qxf, qyf;  // fold: d_x/2, d_y
     int snx, wx, wy;
     unsigned long long* counts;
 };
@@ -73,6 +87,8 @@ __device__ __forceinline__ Hot make_hot(const LmDesc& d)
     h.snyd = (double)d.sny;
     h.mxf = d.mxf;
     h.myf = d.myf;
+    h.qxf = (float)d.qx;
+    h.qyf = (float)d.qy;
     h.bx0f = d.bx0f;
     h.by0f = d.by0f;
     h.inv_sdxf = d.inv_sdxf;
@@ -110,8 +126,10 @@ template <int SCHEME>
 __device__ __forceinline__ void cell_base(const LmDesc& d, int64_t ci, int64_t cj, double& ubx,
                                           double& uby)
 {
-    double bx = d.mx * cell_cx(d, ci);
-    double by = d.my * cell_cy(d, cj);
+    const double zx = cell_cx(d, ci), zy = cell_cy(d, cj);
+    double bx = d.mx * zx;
+    double by = d.my * zy;
+    if (d.fold) bx += (d.qx * zx + d.qy * zy) * zx;
     if (SCHEME == 1) {
         const LmCoef& c = d.coef[cj * d.ncx + ci];
         bx -= c.a0r;
@@ -134,10 +152,24 @@ __device__ __forceinline__ void pair(float px, float dy, float dy2, float lxv, f
     ay = __builtin_fmaf(dy, w, ay);
 }
 
-__device__ __forceinline__ void kahan_add(float& s, float& c, float v)
+// FP64 pair: hardware reciprocal refined by one Newton step.
+__device__ __forceinline__ void pair(double px, double dy, double dy2, double lxv, double lmv,
+                                     double& ax, double& ay)
 {
-    float y = v - c;
-    float t = s + y;
+    double dx = px - lxv;
+    double r2 = __builtin_fma(dx, dx, dy2);
+    double w0 = __builtin_amdgcn_rcp(r2);
+    double e = __builtin_fma(-r2, w0, 1.0);
+    double w = lmv * __builtin_fma(w0, e, w0);
+    ax = __builtin_fma(dx, w, ax);
+    ay = __builtin_fma(dy, w, ay);
+}
+
+template <class T>
+__device__ __forceinline__ void kahan_add(T& s, T& c, T v)
+{
+    T y = v - c;
+    T t = s + y;
     c = (t - s) - y;
     s = t;
 }
@@ -164,28 +196,92 @@ __device__ __forceinline__ void taylor(const float* ar, const float* ai, float d
     fi = __builtin_fmaf(gr, dy, gi * dx);
 }
 
-// Pixel of one ray from its local sums (mixed path).  p = -1: outside the map
-// (NaN coordinates included).
-template <int P>
-__device__ __forceinline__ void bin_mixed(const Hot& h, const float* ar, const float* ai,
-                                          double ubx, double uby, float dx, float dy, float ax,
-                                          float ay, int& p, int& q)
+// Macro mapping of offsets (dx, dy) from a level-2 cell centre z: the
+// constant Jacobian diag(mx, my), or for the fold model the Jacobian at z,
+// [[mx + d_x z_x + d_y z_y, d_y z_x], [0, my]], plus the quadratic remainder
+// (d_x dx / 2 + d_y dy) dx.  FP32 constants formed in FP64 per cell.
+struct CellMap {
+    float cxx, cxy, qx, qy;
+};
+
+__device__ __forceinline__ CellMap cell_map(const LmDesc& d, double zx, double zy)
+{
+    CellMap c;
+    if (d.fold) {
+        c.cxx = (float)(d.mx + 2.0 * d.qx * zx + d.qy * zy);
+        c.cxy = (float)(d.qy * zx);
+    } else {
+        c.cxx = d.mxf;
+        c.cxy = 0.f;
+    }
+    c.qx = (float)d.qx;
+    c.qy = (float)d.qy;
+    return c;
+}
+
+// FP64 pixel y coordinate of the image of a ray row before deflection: the
+// cell base plus the macro term of the row's offset l * (L3y / 2) from the cell
+// centre, l = 2 (j - cj R) - (R - 1).  Exact offsets here keep the rounding of
+// the FP32 offset out of the large macro term.
+__device__ __forceinline__ double row_base(const LmDesc& d, double uby, int l)
+{
+    return __builtin_fma(d.my * ((double)l * (0.5 * d.dy)), d.inv_sdy, uby);
+}
+
+// Pixel of one ray from its local sums (mixed path).  uby_row is row_base().
+// p = -1: outside the map (NaN coordinates included).
+template <int P, bool FOLD>
+__device__ __forceinline__ void bin_mixed(const Hot& h, const CellMap& cm, const float* ar,
+                                          const float* ai, double ubx, double uby_row, float dx,
+                                          float dy, float ax, float ay, int& p, int& q)
 {
     float fr, fi;
     taylor<P>(ar, ai, dx, dy, fr, fi);
     float tx = ax + fr;
     float ty = ay - fi;
-    float lx = __builtin_fmaf(h.mxf, dx, -tx);
-    float ly = __builtin_fmaf(h.myf, dy, -ty);
+    float lx;
+    if (FOLD) {
+        const float t2 = __builtin_fmaf(cm.qx, dx, cm.qy * dy);
+        lx = __builtin_fmaf(cm.cxx, dx, __builtin_fmaf(dx, t2, __builtin_fmaf(cm.cxy, dy, -tx)));
+    } else {
+        lx = __builtin_fmaf(cm.cxx, dx, -tx);
+    }
     double u = __builtin_fma((double)lx, h.inv_sdx, ubx);
-    double v = __builtin_fma((double)ly, h.inv_sdy, uby);
+    double v = __builtin_fma((double)(-ty), h.inv_sdy, uby_row);
+    bool in = (u >= 0.0) & (u < h.snxd) & (v >= 0.0) & (v < h.snyd);
+    p = in ? (int)u : -1;
+    q = in ? (int)v : -1;
+}
+
+// Pixel of one ray with FP64 near sums (rebased FP64 offsets); the far-field
+// Taylor part stays FP32.
+template <int P, bool FOLD>
+__device__ __forceinline__ void bin_mixed64(const Hot& h, const LmDesc& d, double zx, double zy,
+                                            const float* ar, const float* ai, double ubx,
+                                            double uby_row, double dx, double dy, double ax,
+                                            double ay, int& p, int& q)
+{
+    float fr, fi;
+    taylor<P>(ar, ai, (float)dx, (float)dy, fr, fi);
+    const double tx = ax + (double)fr;
+    const double ty = ay - (double)fi;
+    double lx;
+    if (FOLD) {
+        const double cxx = d.mx + 2.0 * d.qx * zx + d.qy * zy, cxy = d.qy * zx;
+        lx = __builtin_fma(cxx, dx, __builtin_fma(dx, __builtin_fma(d.qx, dx, d.qy * dy),
+                                                  __builtin_fma(cxy, dy, -tx)));
+    } else {
+        lx = __builtin_fma(d.mx, dx, -tx);
+    }
+    double u = __builtin_fma(lx, h.inv_sdx, ubx);
+    double v = __builtin_fma(-ty, h.inv_sdy, uby_row);
     bool in = (u >= 0.0) & (u < h.snxd) & (v >= 0.0) & (v < h.snyd);
     p = in ? (int)u : -1;
     q = in ? (int)v : -1;
 }
 
 // Pixel of one ray in the plain FP32 path (global coordinates).
-template <int P>
+template <int P, bool FOLD>
 __device__ __forceinline__ void bin_fp32(const Hot& h, const float* ar, const float* ai,
                                          float a0r, float a0i, float zcx, float zcy, float tx,
                                          float ty, float ax, float ay, int& p, int& q)
@@ -195,7 +291,9 @@ __device__ __forceinline__ void bin_fp32(const Hot& h, const float* ar, const fl
     taylor<P>(ar, ai, dx, dy, fr, fi);
     float alx = ax + (a0r + fr);
     float aly = ay - (a0i + fi);
-    float bx = __builtin_fmaf(h.mxf, tx, -alx);
+    float mx = h.mxf;
+    if (FOLD) mx = __builtin_fmaf(h.qxf, tx, __builtin_fmaf(h.qyf, ty, mx));
+    float bx = __builtin_fmaf(mx, tx, -alx);
     float by = __builtin_fmaf(h.myf, ty, -aly);
     float u = (bx - h.bx0f) * h.inv_sdxf;
     float v = (by - h.by0f) * h.inv_sdyf;
@@ -206,10 +304,14 @@ __device__ __forceinline__ void bin_fp32(const Hot& h, const float* ar, const fl
 
 // Offset of lattice index k from the centre of its level-2 cell, as
 // (2 (k - c R) - (R - 1)) * (spacing / 2) with the half spacing in float-float.
+__device__ __forceinline__ int local_index(int64_t k, int64_t c, int R)
+{
+    return 2 * (int)(k - c * (int64_t)R) - (R - 1);
+}
+
 __device__ __forceinline__ float local_offset(int64_t k, int64_t c, int R, float hh, float hl)
 {
-    int l = 2 * (int)(k - c * (int64_t)R) - (R - 1);
-    float fl = (float)l;
+    float fl = (float)local_index(k, c, R);
     return __builtin_fmaf(fl, hl, fl * hh);
 }
 
@@ -243,17 +345,22 @@ __device__ __forceinline__ int list_count(const LmDesc& d, int64_t ci, int64_t c
 
 // Lens value as the per-ray loop sees it.
 template <int PREC>
-__device__ __forceinline__ float4 lens_value(const LmDesc& d, int idx, double zcx, double zcy)
+__device__ __forceinline__ typename Prec<PREC>::L lens_value(const LmDesc& d, int idx, double zcx,
+                                                            double zcy)
 {
-    if (PREC == 0)
+    if constexpr (PREC == 2) {
+        return make_double4(d.lx[idx] - zcx, d.ly[idx] - zcy, d.lmd[idx], 0.0);
+    } else if constexpr (PREC == 0) {
         return make_float4((float)(d.lx[idx] - zcx), (float)(d.ly[idx] - zcy), d.lmf[idx], 0.f);
-    return make_float4(d.lxf[idx], d.lyf[idx], d.lmf[idx], 0.f);
+    } else {
+        return make_float4(d.lxf[idx], d.lyf[idx], d.lmf[idx], 0.f);
+    }
 }
 
 // Stage list positions [b0, b0+nb) of the cell's lens list into this wave's LDS slice.
 template <int SCHEME, int PREC>
 __device__ void stage(const LmDesc& d, int64_t ci, int64_t cj, int b0, int nb, double zcx,
-                      double zcy, float4* lb, int lane)
+                      double zcy, typename Prec<PREC>::L* lb, int lane)
 {
     if (SCHEME == 0) {
         for (int s = lane; s < nb; s += 64) lb[s] = lens_value<PREC>(d, b0 + s, zcx, zcy);
@@ -360,11 +467,12 @@ __device__ __forceinline__ void run_flush(const Hot& h, Run& r, int ax0, int ay0
 
 // --------------------------------------------------------------- units
 
-template <int SCHEME, int PREC, int NR, int P>
+template <int SCHEME, int PREC, int NR, int P, bool FOLD>
 __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_hi,
-                             int64_t j, bool row_ok, int ax0, int ay0, unsigned* win, float4* lb,
-                             int lane, unsigned& nout)
+                             int64_t j, bool row_ok, int ax0, int ay0, unsigned* win,
+                             typename Prec<PREC>::L* lb, int lane, unsigned& nout)
 {
+    using T = typename Prec<PREC>::T;
     const int R = d.R;
     const Hot h = make_hot(d);
     const float hxh = d.hxh, hxl = d.hxl;
@@ -375,13 +483,20 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
     float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
     if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
     const float zcxf = cell_cxf(d, ci), zcyf = cell_cyf(d, cj);
+    const CellMap cm = cell_map(d, zcx, zcy);
 
     // the lane's ray row
-    float py;
-    if (PREC == 0)
+    T py;
+    double uby_row = uby;
+    if constexpr (PREC == 2) {
+        py = (double)local_index(j, cj, R) * (0.5 * d.dy);
+        uby_row = row_base(d, uby, local_index(j, cj, R));
+    } else if constexpr (PREC == 0) {
         py = local_offset(j, cj, R, d.hyh, d.hyl);
-    else
+        uby_row = row_base(d, uby, local_index(j, cj, R));
+    } else {
         py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
+    }
 
     constexpr int kCap = Cap<SCHEME>::value;
     const int count = __builtin_amdgcn_readfirstlane(list_count<SCHEME>(d, ci, cj));
@@ -390,32 +505,34 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
 
     Run run{-2, -2, 0u};
     for (int64_t c0 = c_lo; c0 < c_hi; c0 += NR) {
-        float px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
+        T px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            if (PREC == 0)
+            if constexpr (PREC == 2)
+                px[c] = (double)local_index(c0 + c, ci, R) * (0.5 * d.dx);
+            else if constexpr (PREC == 0)
                 px[c] = local_offset(c0 + c, ci, R, hxh, hxl);
             else
                 px[c] = __builtin_fmaf((float)(c0 + c) + 0.5f, dxf, x0f);
-            ax[c] = 0.f;
-            ay[c] = 0.f;
-            kx[c] = 0.f;
-            ky[c] = 0.f;
+            ax[c] = 0;
+            ay[c] = 0;
+            kx[c] = 0;
+            ky[c] = 0;
         }
         for (int b = 0; b < nblk; ++b) {
             const int nb = __builtin_amdgcn_readfirstlane(min(kCap, count - b * kCap));
             if (nblk > 1) stage<SCHEME, PREC>(d, ci, cj, b * kCap, nb, zcx, zcy, lb, lane);
-            float bx[NR], by[NR];
+            T bx[NR], by[NR];
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
-                bx[c] = SCHEME == 0 ? 0.f : ax[c];
-                by[c] = SCHEME == 0 ? 0.f : ay[c];
+                bx[c] = SCHEME == 0 ? T(0) : ax[c];
+                by[c] = SCHEME == 0 ? T(0) : ay[c];
             }
 #pragma unroll 2
             for (int k = 0; k < nb; ++k) {
-                const float4 L = lb[k];
-                const float dy = py - L.y;
-                const float dy2 = dy * dy;
+                const auto L = lb[k];
+                const T dy = py - L.y;
+                const T dy2 = dy * dy;
 #pragma unroll
                 for (int c = 0; c < NR; ++c) pair(px[c], dy, dy2, L.x, L.z, bx[c], by[c]);
             }
@@ -435,10 +552,15 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
         for (int c = 0; c < NR; ++c) {
             if (c0 + c < c_hi) {
                 int p, q;
-                if (PREC == 0)
-                    bin_mixed<P>(h, ar, ai, ubx, uby, px[c], py, ax[c], ay[c], p, q);
+                if constexpr (PREC == 2)
+                    bin_mixed64<P, FOLD>(h, d, zcx, zcy, ar, ai, ubx, uby_row, px[c], py, ax[c],
+                                         ay[c], p, q);
+                else if constexpr (PREC == 0)
+                    bin_mixed<P, FOLD>(h, cm, ar, ai, ubx, uby_row, px[c], py, ax[c], ay[c], p,
+                                       q);
                 else
-                    bin_fp32<P>(h, ar, ai, a0r, a0i, zcxf, zcyf, px[c], py, ax[c], ay[c], p, q);
+                    bin_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcxf, zcyf, px[c], py, ax[c], ay[c], p,
+                                      q);
                 if (row_ok) run_push(h, run, p, q, ax0, ay0, win, nout);
             }
         }
@@ -481,7 +603,7 @@ __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_
 
 template <int SCHEME, int PREC, int NR, int P>
 __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsigned* win,
-                             float4* lb, int wave, int lane)
+                             typename Prec<PREC>::L* lb, int wave, int lane)
 {
     const int64_t tx = t % d.ntx, ty = t / d.ntx;
     const int64_t cib = (d.tcx0 + tx) * d.G, cjb = (d.tcy0 + ty) * d.G;
@@ -500,8 +622,12 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
         if (c_lo >= c_hi || r_lo + 64 <= d.j0 || r_lo >= d.j1) continue;
         const int64_t j = r_lo + lane;
         const bool row_ok = j >= d.j0 && j < d.j1;
-        process_unit<SCHEME, PREC, NR, P>(d, ci, cj, c_lo, c_hi, j, row_ok, ax0, ay0, win, lb, lane,
-                                          nout);
+        if (d.fold)
+            process_unit<SCHEME, PREC, NR, P, true>(d, ci, cj, c_lo, c_hi, j, row_ok, ax0, ay0, win,
+                                                    lb, lane, nout);
+        else
+            process_unit<SCHEME, PREC, NR, P, false>(d, ci, cj, c_lo, c_hi, j, row_ok, ax0, ay0,
+                                                     win, lb, lane, nout);
     }
     unsigned tot = wave_sum_u32(nout);
     if (lane == 0 && tot) atomicAdd(d.n_out, (unsigned long long)tot);
@@ -527,7 +653,7 @@ template <int SCHEME, int PREC, int NR, int P>
 __global__ __launch_bounds__(kWG) void k_shoot_map(LmDesc d)
 {
     __shared__ unsigned win[kWinMax];
-    __shared__ float4 lens[LM_WAVES][Cap<SCHEME>::value];
+    __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -549,7 +675,7 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
                                                      unsigned long long* queue)
 {
     __shared__ unsigned win[kWinMax];
-    __shared__ float4 lens[LM_WAVES][Cap<SCHEME>::value];
+    __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
     __shared__ long long s_item;
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
@@ -587,7 +713,7 @@ template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t cj0, int64_t nci,
                                                 int64_t ncj, LmCoef* __restrict__ out)
 {
-    typedef typename std::conditional<PREC == 0, double, float>::type T;
+    typedef typename std::conditional<PREC != 1, double, float>::type T;
     __shared__ T sx[kWG], sy[kWG], sm[kWG];
     __shared__ int sI[kWG], sJ[kWG];
     const int tid = threadIdx.x;
@@ -596,7 +722,7 @@ __global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t c
     const int64_t ci = ci0 + (valid ? c % nci : 0), cj = cj0 + (valid ? c / nci : 0);
     const int I = (int)(ci / d.Kx), J = (int)(cj / d.Ky);
     T zx, zy;
-    if (PREC == 0) {
+    if (PREC != 1) {
         zx = (T)cell_cx(d, ci);
         zy = (T)cell_cy(d, cj);
     } else {
@@ -613,7 +739,7 @@ __global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t c
         __syncthreads();
         const int64_t k = base + tid;
         if (k < d.nlens) {
-            if (PREC == 0) {
+            if (PREC != 1) {
                 sx[tid] = (T)d.lx[k];
                 sy[tid] = (T)d.ly[k];
                 sm[tid] = (T)d.lmd[k];
@@ -666,90 +792,24 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
         p[i] = v;
 }
 
-// Per-ray pixels with the shooting kernel's arithmetic, lens for lens.
-template <int SCHEME, int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restrict__ ii,
-                                               const int64_t* __restrict__ jj, int64_t n,
-                                               int32_t* __restrict__ po, int32_t* __restrict__ qo)
+// Near-field sum of one position (lens for lens as in the shooting kernel).
+template <int SCHEME, int PREC>
+__device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, double zcy,
+                         typename Prec<PREC>::T px, typename Prec<PREC>::T py,
+                         typename Prec<PREC>::T& ax, typename Prec<PREC>::T& ay)
 {
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (t >= n) return;
-    const int64_t i = ii[t], j = jj[t];
-    const int R = d.R;
-    const int64_t ci = i / R, cj = j / R;
-    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
-    double ubx, uby;
-    cell_base<SCHEME>(d, ci, cj, ubx, uby);
-    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
-    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
-    float px, py;
-    if (PREC == 0) {
-        px = local_offset(i, ci, R, d.hxh, d.hxl);
-        py = local_offset(j, cj, R, d.hyh, d.hyl);
-    } else {
-        px = __builtin_fmaf((float)i + 0.5f, d.dxf, d.x0f);
-        py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
-    }
+    using T = typename Prec<PREC>::T;
     constexpr int kCap = Cap<SCHEME>::value;
     const int count = list_count<SCHEME>(d, ci, cj);
-    float ax = 0.f, ay = 0.f, kx = 0.f, ky = 0.f;
+    T kx = 0, ky = 0;
+    ax = 0;
+    ay = 0;
     for (int b0 = 0; b0 < count; b0 += kCap) {
         const int nb = min(kCap, count - b0);
-        float bx = SCHEME == 0 ? 0.f : ax, by = SCHEME == 0 ? 0.f : ay;
+        T bx = SCHEME == 0 ? T(0) : ax, by = SCHEME == 0 ? T(0) : ay;
         for (int k = 0; k < nb; ++k) {
-            const float4 L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
-            const float dy = py - L.y;
-            const float dy2 = dy * dy;
-            pair(px, dy, dy2, L.x, L.z, bx, by);
-        }
-        if (SCHEME == 0) {
-            kahan_add(ax, kx, bx);
-            kahan_add(ay, ky, by);
-        } else {
-            ax = bx;
-            ay = by;
-        }
-    }
-    int p, q;
-    const Hot h = make_hot(d);
-    if (PREC == 0)
-        bin_mixed<P>(h, ar, ai, ubx, uby, px, py, ax, ay, p, q);
-    else
-        bin_fp32<P>(h, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, py, ax, ay, p, q);
-    po[t] = p;
-    qo[t] = q;
-}
-
-// Deflection at arbitrary positions, rebased on the level-2 cell holding them.
-template <int SCHEME, int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restrict__ th,
-                                                 int64_t n, double* __restrict__ al)
-{
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (t >= n) return;
-    const double tx = th[2 * t], ty = th[2 * t + 1];
-    const int64_t ci = (int64_t)floor((tx - d.x0) / ((double)d.R * d.dx));
-    const int64_t cj = (int64_t)floor((ty - d.y0) / ((double)d.R * d.dy));
-    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
-    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
-    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
-    float px, py;
-    if (PREC == 0) {
-        px = (float)(tx - zcx);
-        py = (float)(ty - zcy);
-    } else {
-        px = (float)tx;
-        py = (float)ty;
-    }
-    constexpr int kCap = Cap<SCHEME>::value;
-    const int count = list_count<SCHEME>(d, ci, cj);
-    float ax = 0.f, ay = 0.f, kx = 0.f, ky = 0.f;
-    for (int b0 = 0; b0 < count; b0 += kCap) {
-        const int nb = min(kCap, count - b0);
-        float bx = SCHEME == 0 ? 0.f : ax, by = SCHEME == 0 ? 0.f : ay;
-        for (int k = 0; k < nb; ++k) {
-            const float4 L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
-            const float dy = py - L.y;
+            const auto L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
+            const T dy = py - L.y;
             pair(px, dy, dy * dy, L.x, L.z, bx, by);
         }
         if (SCHEME == 0) {
@@ -760,18 +820,100 @@ __global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restr
             ay = by;
         }
     }
+}
+
+// Per-ray pixels with the shooting kernel's arithmetic, lens for lens.
+template <int SCHEME, int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restrict__ ii,
+                                               const int64_t* __restrict__ jj, int64_t n,
+                                               int32_t* __restrict__ po, int32_t* __restrict__ qo)
+{
+    using T = typename Prec<PREC>::T;
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = ii[t], j = jj[t];
+    const int R = d.R;
+    const int64_t ci = i / R, cj = j / R;
+    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
+    double ubx, uby;
+    cell_base<SCHEME>(d, ci, cj, ubx, uby);
+    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
+    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
+    T px, py;
+    if constexpr (PREC == 2) {
+        px = (double)local_index(i, ci, R) * (0.5 * d.dx);
+        py = (double)local_index(j, cj, R) * (0.5 * d.dy);
+    } else if constexpr (PREC == 0) {
+        px = local_offset(i, ci, R, d.hxh, d.hxl);
+        py = local_offset(j, cj, R, d.hyh, d.hyl);
+    } else {
+        px = __builtin_fmaf((float)i + 0.5f, d.dxf, d.x0f);
+        py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
+    }
+    T ax, ay;
+    near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, py, ax, ay);
+    int p, q;
+    const Hot h = make_hot(d);
+    if constexpr (PREC == 2) {
+        const double uby_row = row_base(d, uby, local_index(j, cj, R));
+        if (d.fold)
+            bin_mixed64<P, true>(h, d, zcx, zcy, ar, ai, ubx, uby_row, px, py, ax, ay, p, q);
+        else
+            bin_mixed64<P, false>(h, d, zcx, zcy, ar, ai, ubx, uby_row, px, py, ax, ay, p, q);
+    } else if constexpr (PREC == 0) {
+        const CellMap cm = cell_map(d, zcx, zcy);
+        const double uby_row = row_base(d, uby, local_index(j, cj, R));
+        if (d.fold)
+            bin_mixed<P, true>(h, cm, ar, ai, ubx, uby_row, px, py, ax, ay, p, q);
+        else
+            bin_mixed<P, false>(h, cm, ar, ai, ubx, uby_row, px, py, ax, ay, p, q);
+    } else {
+        const float zxf = cell_cxf(d, ci), zyf = cell_cyf(d, cj);
+        if (d.fold)
+            bin_fp32<P, true>(h, ar, ai, a0r, a0i, zxf, zyf, px, py, ax, ay, p, q);
+        else
+            bin_fp32<P, false>(h, ar, ai, a0r, a0i, zxf, zyf, px, py, ax, ay, p, q);
+    }
+    po[t] = p;
+    qo[t] = q;
+}
+
+// Deflection at arbitrary positions, rebased on the level-2 cell holding them.
+template <int SCHEME, int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restrict__ th,
+                                                 int64_t n, double* __restrict__ al)
+{
+    using T = typename Prec<PREC>::T;
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t >= n) return;
+    const double tx = th[2 * t], ty = th[2 * t + 1];
+    const int64_t ci = (int64_t)floor((tx - d.x0) / ((double)d.R * d.dx));
+    const int64_t cj = (int64_t)floor((ty - d.y0) / ((double)d.R * d.dy));
+    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
+    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
+    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
+    T px, py;
+    if (PREC != 1) {
+        px = (T)(tx - zcx);
+        py = (T)(ty - zcy);
+    } else {
+        px = (float)tx;
+        py = (float)ty;
+    }
+    T ax, ay;
+    near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, py, ax, ay);
     double outx = ax, outy = ay;
     if (SCHEME == 1) {
         float fr, fi, dx, dy;
-        if (PREC == 0) {
-            dx = px;
-            dy = py;
+        if (PREC != 1) {
+            dx = (float)px;
+            dy = (float)py;
         } else {
-            dx = px - cell_cxf(d, ci);
-            dy = py - cell_cyf(d, cj);
+            dx = (float)px - cell_cxf(d, ci);
+            dy = (float)py - cell_cyf(d, cj);
         }
         taylor<P>(ar, ai, dx, dy, fr, fi);
-        if (PREC == 0) {
+        if (PREC != 1) {
             const LmCoef& c = d.coef[cj * d.ncx + ci];
             outx = (double)ax + (double)fr + c.a0r;
             outy = (double)ay - (double)fi - c.a0i;
@@ -857,6 +999,7 @@ int dispatch(int scheme, int prec, int nr, int terms, F&& f)
     if (scheme == 0 && prec == 1) return dispatch_nr<0, 1>(nr, terms, f);
     if (scheme == 1 && prec == 0) return dispatch_nr<1, 0>(nr, terms, f);
     if (scheme == 1 && prec == 1) return dispatch_nr<1, 1>(nr, terms, f);
+    if (scheme == 1 && prec == 2) return dispatch_nr<1, 2>(nr, terms, f);
     return (int)hipErrorInvalidValue;
 }
 
@@ -868,6 +1011,7 @@ int dispatch_probe(int scheme, int prec, int terms, F&& f)
     if (scheme == 0 && prec == 1) return dispatch_p<0, 1, 4>(terms, f);
     if (scheme == 1 && prec == 0) return dispatch_p<1, 0, 4>(terms, f);
     if (scheme == 1 && prec == 1) return dispatch_p<1, 1, 4>(terms, f);
+    if (scheme == 1 && prec == 2) return dispatch_p<1, 2, 4>(terms, f);
     return (int)hipErrorInvalidValue;
 }
 
@@ -954,7 +1098,7 @@ int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int
     case 7: LM_COEF(PR, 7); break;            \
     default: return (int)hipErrorInvalidValue; \
     }
-    if (precision == 0) {
+    if (precision != 1) {
         LM_COEF_P(0)
     } else {
         LM_COEF_P(1)

@@ -90,6 +90,7 @@ class Workload:
     coarse: int = 0                   # 0: paper rule L2 = L1/20
     masses: str = "salpeter"          # "unit" or "salpeter"
     disk_radius: float | None = None  # disk field instead of the rectangle
+    fold: tuple | None = None         # (kappa_0, d_x, d_y) in 1/theta_E: fold macro model
     extra: dict = field(default_factory=dict)
 
     @property
@@ -104,13 +105,19 @@ class Workload:
     def mean_mass(self):
         return 1.0 if self.masses == "unit" else salpeter_mean()
 
-    def lenses(self):
+    def lenses(self, rect=None):
+        """Draw the lens field.  rect = (half_x, half_y) places the lenses in that
+        rectangle (e.g. the shooting region, as for the fold workload) instead of
+        the area rule."""
         rng = rng_for(self.workload_id, self.map_index)
         n = self.n_lenses
         if self.disk_radius is not None:
             x, y = uniform_disk(rng, n, self.disk_radius)
         else:
-            hx, hy = field_rect(n, self.mean_mass, self.kappa_star, self.lam_t, self.lam_r)
+            if rect is not None:
+                hx, hy = rect
+            else:
+                hx, hy = field_rect(n, self.mean_mass, self.kappa_star, self.lam_t, self.lam_r)
             x, y = uniform_rect(rng, n, hx, hy)
         m = np.ones(n) if self.masses == "unit" else salpeter_masses(rng, n)
         return np.ascontiguousarray(x), np.ascontiguousarray(y), np.ascontiguousarray(m)
@@ -175,6 +182,23 @@ def batched_study(n_maps: int = 80, rays_scale: float = 1.0) -> list[Workload]:
         out.append(Workload("batched-%02d" % m, 4, m, k, g, ks, n, side, 2000, n_rays=rays,
                             scheme=1, coarse=0))
     return out
+
+
+# Table 1 of the paper: theta_E = 1e-6 arcsec = 1e-6/60 arcmin, d in arcmin^-1.
+TABLE1_THETA_E_ARCMIN = 1e-6 / 60.0
+TABLE1_D = (3.62 * TABLE1_THETA_E_ARCMIN, -3.41 * TABLE1_THETA_E_ARCMIN)
+
+
+def paper_table1(n_rays: float = 1000.0 * 363635 * 73877) -> Workload:
+    """The paper's own map (Sec. 4.1, Table 1): fold model with kappa_0 = 0.83 and
+    d = (3.62, -3.41) arcmin^-1 at theta_E = 1e-6 arcsec, kappa_star = 0.001,
+    13745 unit lenses uniform in the shooting region, a 40 x 200 theta_E^2 map
+    (across x along the caustic) of 73877 x 363635 pixels, N_av = 1000
+    (2.69e13 rays).  Lenses: call lenses(rect=...) with the shooting region."""
+    return Workload("paper-table1", 6, 0, 0.83, 0.0, 0.001, 13745, 40.0, 73877,
+                    n_rays=n_rays, scheme=1, coarse=0, masses="unit",
+                    fold=(0.83, TABLE1_D[0], TABLE1_D[1]),
+                    extra={"src_ly": 200.0, "src_ny": 363635})
 
 
 WORKLOADS = {

@@ -30,6 +30,7 @@ LM_SCHEME_DIRECT = 0
 LM_SCHEME_INTERP = 1
 LM_PREC_MIXED = 0
 LM_PREC_FP32 = 1
+LM_PREC_MIXED_FP64 = 2
 LM_MAX_TERMS = 7
 
 _STATUS_NAMES = {0: "LM_OK", -1: "LM_EINVAL", -2: "LM_ENOMEM", -3: "LM_EDEVICE", -4: "LM_ESTATE",
@@ -86,6 +87,13 @@ _SIGS = {
                            ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                            ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
                            ctypes.c_int32, ctypes.c_int32, ctypes.c_double],
+    "lm_geometry_derive_fold": [_P(lm_geometry), ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_double],
+    "lm_set_fold": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "lm_read_counts_region": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              _u64],
     "lm_create": [_P(lm_geometry), _P(_vp)],
     "lm_set_macro": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "lm_set_lenses": [_vp, _d, _d, _d, ctypes.c_int64],
@@ -189,6 +197,28 @@ def lm_geometry_derive(src_lx, src_ly, src_nx, src_ny, kappa, gamma, kappa_star,
                                      int(ray_ny or 0), scheme, coarse, mean_mass),
            "lm_geometry_derive")
     return g
+
+
+def lm_geometry_derive_fold(src_lx, src_ly, src_nx, src_ny, kappa0, d_x, kappa_star,
+                            margin=-1.0, n_rays=1.0, scheme=LM_SCHEME_INTERP, coarse=0,
+                            mean_mass=1.0) -> lm_geometry:
+    g = lm_geometry()
+    _check(load().lm_geometry_derive_fold(ctypes.byref(g), src_lx, src_ly, src_nx, src_ny, kappa0,
+                                          d_x, kappa_star, -1.0 if margin is None else margin,
+                                          float(n_rays), scheme, coarse, mean_mass),
+           "lm_geometry_derive_fold")
+    return g
+
+
+def lm_set_fold(m, kappa0, d_x, d_y, kappa_star):
+    _check(load().lm_set_fold(m, kappa0, d_x, d_y, kappa_star), "lm_set_fold")
+
+
+def lm_read_counts_region(m, p0, q0, np_, nq):
+    out = np.empty((nq, np_), dtype=np.uint64)
+    _check(load().lm_read_counts_region(m, int(p0), int(q0), int(np_), int(nq),
+                                        out.ctypes.data_as(_u64)), "lm_read_counts_region")
+    return out
 
 
 def lm_create(g: lm_geometry):
@@ -358,10 +388,15 @@ def lm_batch_destroy(b):
 class Map:
     """Owning wrapper: geometry + macro + lenses, with the ABI's calls as methods."""
 
-    def __init__(self, g: lm_geometry, kappa=0.0, gamma=0.0, kappa_star=0.0, lenses=None):
+    def __init__(self, g: lm_geometry, kappa=0.0, gamma=0.0, kappa_star=0.0, lenses=None,
+                 fold=None):
+        """fold=(kappa0, d_x, d_y) selects the fold macro model (kappa, gamma ignored)."""
         self.g = g
         self.h = lm_create(g)
-        lm_set_macro(self.h, kappa, gamma, kappa_star)
+        if fold is None:
+            lm_set_macro(self.h, kappa, gamma, kappa_star)
+        else:
+            lm_set_fold(self.h, fold[0], fold[1], fold[2], kappa_star)
         if lenses is not None:
             lm_set_lenses(self.h, *lenses)
 

@@ -91,6 +91,14 @@ def test_create_rejects_invalid_geometry(field, value):
     assert lm.lm_last_error() != ""
 
 
+def test_fp64_near_mode_needs_the_interpolated_scheme():
+    g = lm.lm_geometry_derive(10, 10, 64, 64, 0.45, 0.5, 0.01, n_rays=1e6, scheme=0, coarse=64)
+    g.precision = lm.LM_PREC_MIXED_FP64
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_create(g)
+    assert e.value.status == lm.LM_EUNSUPPORTED
+
+
 def test_null_handles_are_rejected(lib):
     assert lib.lm_shoot(None, 0, 0, 1, 1, None) == lm.LM_EINVAL
     assert lib.lm_set_macro(None, 0.0, 0.0, 0.0) == lm.LM_EINVAL
@@ -98,3 +106,21 @@ def test_null_handles_are_rejected(lib):
     assert lib.lm_batch_shoot(None, None) == lm.LM_EINVAL
     lib.lm_destroy(None)
     lib.lm_batch_destroy(None)
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e-4])
+def test_fold_geometry_matches_oracle(scale):
+    from oracle.geometry import derive_fold_geometry
+    from paper_2308_14278_amd import inputs
+    w = inputs.paper_table1()
+    k0, dx, dy = w.fold
+    ny = int(w.extra["src_ny"] * scale) or 1
+    nx = int(w.src_pixels * scale) or 1
+    go = derive_fold_geometry(w.src_side, w.extra["src_ly"], nx, ny, k0, dx, w.kappa_star,
+                              n_rays=w.n_rays * scale)
+    gl = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], nx, ny, k0, dx, w.kappa_star,
+                                    n_rays=w.n_rays * scale)
+    for f in ("src_nx", "src_ny", "ray_nx", "ray_ny", "coarse", "l1_kx", "l1_ky"):
+        assert getattr(gl, f) == getattr(go, f), f
+    for f in ("src_x0", "src_y0", "src_dx", "src_dy", "ray_x0", "ray_y0", "ray_dx", "ray_dy"):
+        assert math.isclose(getattr(gl, f), getattr(go, f), rel_tol=1e-14), f
