@@ -137,7 +137,8 @@ typedef struct lm_batch lm_batch;
  * start at zero; the macro model is kappa = gamma = kappa_star = 0 and there
  * are no lenses until set.  LM_EINVAL for an invalid geometry (non-positive
  * sizes, coarse not a positive multiple of 64, more than 2^31 rays per
- * workgroup tile, P outside 1..LM_MAX_TERMS, src_nx*src_ny >= 2^40). */
+ * workgroup tile, P outside 1..LM_MAX_TERMS, src_nx or src_ny above 2^30,
+ * src_nx*src_ny >= 2^40). */
 lm_status lm_create(const lm_geometry* g, lm_map** out);
 
 /* Release every resource of the map (NULL is ignored).  Waits for the map's

@@ -98,6 +98,8 @@ lm_status validate_geometry(const lm_geometry* g)
     if (!(g->src_dx > 0 && g->src_dy > 0 && g->ray_dx > 0 && g->ray_dy > 0))
         return fail(LM_EINVAL, "pixel and ray spacings must be positive");
     if (g->src_nx <= 0 || g->src_ny <= 0) return fail(LM_EINVAL, "source map must have pixels");
+    if (g->src_nx > (1 << 30) || g->src_ny > (1 << 30))
+        return fail(LM_EINVAL, "a source map side must be at most 2^30 pixels");
     if ((int64_t)g->src_nx * g->src_ny >= (int64_t(1) << 40))
         return fail(LM_EINVAL, "source map too large (src_nx*src_ny must be < 2^40)");
     if (g->ray_nx <= 0 || g->ray_ny <= 0) return fail(LM_EINVAL, "ray lattice must be non-empty");
@@ -138,7 +140,7 @@ struct lm_map {
     int64_t ncx = 0, ncy = 0, n1x = 0, n1y = 0;
     int nl1x = 0, nl1y = 0;
     // device buffers
-    DevBuf lx, ly, lmd, lxf, lyf, lmf, lI, lJ, cell_start, coef, counts_own, n_out;
+    DevBuf lx, ly, lmd, lxf, lyf, lmf, lI, lJ, cell_start, coef, counts_own, n_out, ptab;
     std::vector<int32_t> h_start;  // host copy of the level-1 CSR
     uint64_t* counts = nullptr;  // own or bound
     bool bound = false;
@@ -290,6 +292,7 @@ LmDesc make_desc(const lm_map* m, int64_t i0, int64_t j0, int64_t i1, int64_t j1
     d.lJ = m->lJ.as<int32_t>();
     d.cell_start = m->cell_start.as<int32_t>();
     d.coef = m->coef.as<LmCoef>();
+    d.ptab = m->ptab.as<float>();
     d.counts = reinterpret_cast<unsigned long long*>(m->counts);
     d.n_out = m->n_out.as<unsigned long long>();
     return d;
@@ -479,6 +482,12 @@ lm_status lm_create(const lm_geometry* g, lm_map** out)
     m->counts = m->counts_own.as<uint64_t>();
     LAUNCH_TRY(lm_launch_fill_u64((unsigned long long*)m->counts, (int64_t)npix, 0ull, nullptr));
     LAUNCH_TRY(lm_launch_fill_u64(m->n_out.as<unsigned long long>(), 1, 0ull, nullptr));
+    // column offsets of a level-2 cell, read by the shooting kernels
+    const int nptab = g->coarse + LM_PTAB_PAD;
+    if (m->ptab.ensure((size_t)nptab * sizeof(float)) != hipSuccess)
+        return fail(LM_ENOMEM, "cannot allocate the column-offset table");
+    LAUNCH_TRY(lm_launch_ptab(make_desc(m.get(), 0, 0, 0, 0, Exec{}), m->ptab.as<float>(), nptab,
+                              nullptr));
     HIP_TRY(hipStreamSynchronize(nullptr));
     // empty lens set
     st = lm_set_lenses(m.get(), nullptr, nullptr, nullptr, 0);

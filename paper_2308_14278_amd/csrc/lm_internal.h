@@ -8,6 +8,7 @@
 #define LM_LENS_CAP 256    // direct sum: lenses staged per wave per block (the summation block)
 #define LM_NEAR_CAP 64     // interpolated scheme: near lenses staged per wave per block
 #define LM_WIN_MAX 8192    // uint32 bins of a workgroup's LDS window
+#define LM_PTAB_PAD 64     // column-offset table entries past R (last column group)
 
 // Taylor coefficients of one level-2 cell: a_0 in FP64 (it carries the large
 // far-field deflection of the cell centre), a_1..a_6 in FP32 (they multiply
@@ -60,11 +61,13 @@ struct LmDesc {
     const int32_t* lJ;
     const int32_t* cell_start;     // CSR over the padded level-1 grid
     const LmCoef* coef;            // [ncy][ncx]
+    const float* ptab;             // [R + LM_PTAB_PAD] column offsets of a level-2 cell
     unsigned long long* counts;    // [sny][snx]
     unsigned long long* n_out;
 };
 
 // Launchers implemented in lm_kernels.hip (return hipError_t as int).
+int lm_launch_ptab(const LmDesc& d, float* out, int n, void* stream);
 int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int64_t cj0,
                      int64_t nci, int64_t ncj, LmCoef* out, void* stream);
 int lm_launch_shoot_map(const LmDesc& d, int scheme, int precision, int terms, int rays_per_lane,

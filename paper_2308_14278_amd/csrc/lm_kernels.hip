@@ -74,7 +74,7 @@ struct Hot {
     double inv_sdx, inv_sdy, snxd, snyd;
     float mxf, myf, bx0f, by0f, inv_sdxf, inv_sdyf, snxf, snyf;
     float qxf, qyf;  // fold: d_x/2, d_y
-    int snx, wx, wy;
+    int snx, sny, wx, wy;
     unsigned long long* counts;
 };
 
@@ -96,6 +96,7 @@ __device__ __forceinline__ Hot make_hot(const LmDesc& d)
     h.snxf = (float)d.snx;
     h.snyf = (float)d.sny;
     h.snx = d.snx;
+    h.sny = d.sny;
     h.wx = d.wx;
     h.wy = d.wy;
     h.counts = d.counts;
@@ -228,56 +229,97 @@ __device__ __forceinline__ double row_base(const LmDesc& d, double uby, int l)
     return __builtin_fma(d.my * ((double)l * (0.5 * d.dy)), d.inv_sdy, uby);
 }
 
-// Pixel of one ray from its local sums (mixed path).  uby_row is row_base().
-// p = -1: outside the map (NaN coordinates included).
-template <int P, bool FOLD>
-__device__ __forceinline__ void bin_mixed(const Hot& h, const CellMap& cm, const float* ar,
-                                          const float* ai, double ubx, double uby_row, float dx,
-                                          float dy, float ax, float ay, int& p, int& q)
+// Pixel indices are biased by kBias and clamped to [kBias - 1, kBias + size]:
+// either end stands for "outside the map" (NaN coordinates included), so the
+// per-ray code needs no range test; the count step tests each run once.
+constexpr unsigned kBias = 1u << 22;
+constexpr double kBiasD = 4194304.0;
+
+// Saturating FP64 -> u32 conversion (negative and NaN give 0).
+__device__ __forceinline__ unsigned cvt_u32_sat(double v)
 {
-    float fr, fi;
-    taylor<P>(ar, ai, dx, dy, fr, fi);
-    float tx = ax + fr;
-    float ty = ay - fi;
-    float lx;
-    if (FOLD) {
-        const float t2 = __builtin_fmaf(cm.qx, dx, cm.qy * dy);
-        lx = __builtin_fmaf(cm.cxx, dx, __builtin_fmaf(dx, t2, __builtin_fmaf(cm.cxy, dy, -tx)));
-    } else {
-        lx = __builtin_fmaf(cm.cxx, dx, -tx);
-    }
-    double u = __builtin_fma((double)lx, h.inv_sdx, ubx);
-    double v = __builtin_fma((double)(-ty), h.inv_sdy, uby_row);
-    bool in = (u >= 0.0) & (u < h.snxd) & (v >= 0.0) & (v < h.snyd);
-    p = in ? (int)u : -1;
-    q = in ? (int)v : -1;
+    unsigned r;
+    asm("v_cvt_u32_f64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
 }
 
-// Pixel of one ray with FP64 near sums (rebased FP64 offsets); the far-field
-// Taylor part stays FP32.
-template <int P, bool FOLD>
-__device__ __forceinline__ void bin_mixed64(const Hot& h, const LmDesc& d, double zx, double zy,
-                                            const float* ar, const float* ai, double ubx,
-                                            double uby_row, double dx, double dy, double ax,
-                                            double ay, int& p, int& q)
+// min(max(v, lo), hi) in one instruction (lo <= hi).
+__device__ __forceinline__ unsigned clamp_u32(unsigned v, unsigned lo, unsigned hi)
 {
-    float fr, fi;
-    taylor<P>(ar, ai, (float)dx, (float)dy, fr, fi);
-    const double tx = ax + (double)fr;
-    const double ty = ay - (double)fi;
-    double lx;
-    if (FOLD) {
-        const double cxx = d.mx + 2.0 * d.qx * zx + d.qy * zy, cxy = d.qy * zx;
-        lx = __builtin_fma(cxx, dx, __builtin_fma(dx, __builtin_fma(d.qx, dx, d.qy * dy),
-                                                  __builtin_fma(cxy, dy, -tx)));
-    } else {
-        lx = __builtin_fma(d.mx, dx, -tx);
+    unsigned r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "v"(lo), "v"(hi));
+    return r;
+}
+
+// Degree of the per-row polynomial in the column offset.
+template <int P, bool FOLD>
+struct Deg {
+    static constexpr int value = (P - 1) > (FOLD ? 2 : 1) ? (P - 1) : (FOLD ? 2 : 1);
+};
+
+// Far field and macro map of one ray row as polynomials in the column offset dx
+// (Sec. 3.2.2 and Eq. 6).  With delta = dx + i dy and f = sum_{n>=1} a_n delta^n,
+// gx(dx) = Re f - (macro x displacement) and gy(dx) = -Im f: the x displacement
+// of a ray's image is then -(gx + near_x) and its y deflection gy + near_y, so
+// the near sums start from gx and gy.  The coefficients come from a Taylor
+// shift of f by i dy (synthetic division), once per row; per ray two Horner
+// evaluations remain.  Macro constants: Jacobian diag(cxx, .) at the cell
+// centre, cxy = d_y z_x and the fold's quadratic remainder (qx dx + qy dy) dx.
+template <int P, bool FOLD, class T>
+__device__ __forceinline__ void row_poly(const float* ar, const float* ai, T dy, T cxx, T cxy,
+                                         T qx, T qy, T* gx, T* gy)
+{
+    constexpr int D = Deg<P, FOLD>::value;
+    T cr[D + 1], cim[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        cr[k] = (k >= 1 && k < P) ? (T)ar[k < P ? k : 0] : T(0);
+        cim[k] = (k >= 1 && k < P) ? (T)ai[k < P ? k : 0] : T(0);
     }
-    double u = __builtin_fma(lx, h.inv_sdx, ubx);
-    double v = __builtin_fma(-ty, h.inv_sdy, uby_row);
-    bool in = (u >= 0.0) & (u < h.snxd) & (v >= 0.0) & (v < h.snyd);
-    p = in ? (int)u : -1;
-    q = in ? (int)v : -1;
+    // c_j += (i dy) c_{j+1}, j = N-1 .. k, for k = 0 .. N-1 (N = P - 1)
+#pragma unroll
+    for (int k = 0; k < P - 1; ++k) {
+#pragma unroll
+        for (int jj = P - 2; jj >= k; --jj) {
+            cr[jj] = fma(-cim[jj + 1], dy, cr[jj]);
+            cim[jj] = fma(cr[jj + 1], dy, cim[jj]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        gx[k] = cr[k];
+        gy[k] = -cim[k];
+    }
+    if (FOLD) {
+        gx[0] = fma(-cxy, dy, gx[0]);
+        gx[1] = gx[1] - fma(qy, dy, cxx);
+        gx[2] = gx[2] - qx;
+    } else {
+        gx[1] = gx[1] - cxx;
+    }
+}
+
+template <int D, class T>
+__device__ __forceinline__ T horner(const T* g, T x)
+{
+    T r = g[D];
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) r = fma(r, x, g[k]);
+    return r;
+}
+
+// Biased pixel of one ray of the rebased paths from its sums sx = gx + near_x,
+// sy = gy + near_y; ubxb and ubyb are the biased FP64 pixel coordinates of the
+// cell centre's image (x) and of the row (y, row_base).
+template <class T>
+__device__ __forceinline__ void bin_rebased(double inv_sdx, double inv_sdy, unsigned pmax,
+                                            unsigned qmax, double ubxb, double ubyb, T sx, T sy,
+                                            unsigned& p, unsigned& q)
+{
+    const double u = __builtin_fma(-(double)sx, inv_sdx, ubxb);
+    const double v = __builtin_fma(-(double)sy, inv_sdy, ubyb);
+    p = clamp_u32(cvt_u32_sat(u), kBias - 1, pmax);
+    q = clamp_u32(cvt_u32_sat(v), kBias - 1, qmax);
 }
 
 // Pixel of one ray in the plain FP32 path (global coordinates).
@@ -412,110 +454,201 @@ __device__ __forceinline__ void load_taylor(const LmDesc& d, int64_t ci, int64_t
 // ------------------------------------------------------------- counting
 
 struct Run {
-    int p, q;
+    unsigned p, q;  // biased pixel (kBias - 2: none yet)
     unsigned n;
 };
 
-__device__ __forceinline__ void emit(const Hot& h, int p, int q, unsigned n, int ax0, int ay0,
-                                     unsigned* win, unsigned& nout)
+// Add n rays at biased pixel (p, q): outside the map -> n_out, inside the
+// workgroup's window -> LDS, else a global atomic.  (axb, ayb) = biased window
+// origin.
+__device__ __forceinline__ void emit(const Hot& h, unsigned p, unsigned q, unsigned n,
+                                     unsigned axb, unsigned ayb, unsigned* win, unsigned& nout)
 {
-    if (p < 0) {
+    const unsigned pm = p - kBias, qm = q - kBias;
+    if ((pm >= (unsigned)h.snx) | (qm >= (unsigned)h.sny)) {
         nout += n;
         return;
     }
-    const unsigned wxi = (unsigned)p - (unsigned)ax0, wyi = (unsigned)q - (unsigned)ay0;
+    const unsigned wxi = p - axb, wyi = q - ayb;
     if ((wxi < (unsigned)h.wx) & (wyi < (unsigned)h.wy))
         atomicAdd(&win[wyi * (unsigned)h.wx + wxi], n);
     else
-        atomicAdd(&h.counts[(int64_t)q * h.snx + p], (unsigned long long)n);
+        atomicAdd(&h.counts[(int64_t)qm * h.snx + pm], (unsigned long long)n);
 }
 
-__device__ __forceinline__ void run_push(const Hot& h, Run& r, int p, int q, int ax0, int ay0,
-                                         unsigned* win, unsigned& nout)
+__device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsigned q,
+                                         unsigned axb, unsigned ayb, unsigned* win,
+                                         unsigned& nout)
 {
+    // (a unit starts with the empty run n = 0 at the sentinel pixel kBias - 2,
+    // which emit books as n_out += 0)
     const bool same = (p == r.p) & (q == r.q);
-    if (!same) {
-        if (r.n) emit(h, r.p, r.q, r.n, ax0, ay0, win, nout);
-        r.p = p;
-        r.q = q;
-        r.n = 0;
-    }
-    ++r.n;
+    const Run old = r;
+    r.n = (same ? r.n : 0u) + 1u;
+    r.p = p;
+    r.q = q;
+    if (!same) emit(h, old.p, old.q, old.n, axb, ayb, win, nout);
 }
 
 // End of a unit: lanes whose pending runs all name one pixel add it once.
-__device__ __forceinline__ void run_flush(const Hot& h, Run& r, int ax0, int ay0, unsigned* win,
-                                          unsigned& nout, int lane)
+__device__ __forceinline__ void run_flush(const Hot& h, Run& r, unsigned axb, unsigned ayb,
+                                          unsigned* win, unsigned& nout, int lane)
 {
     bool act = r.n > 0;
     unsigned long long am = __ballot(act);
     if (am) {
         int first = __builtin_ctzll(am);
-        int p0 = __shfl(r.p, first, 64), q0 = __shfl(r.q, first, 64);
+        unsigned p0 = __shfl(r.p, first, 64), q0 = __shfl(r.q, first, 64);
         unsigned long long diff = __ballot(act && (r.p != p0 || r.q != q0));
         if (diff == 0) {
             unsigned tot = wave_sum_u32(act ? r.n : 0u);
-            if (lane == first) emit(h, p0, q0, tot, ax0, ay0, win, nout);
+            if (lane == first) emit(h, p0, q0, tot, axb, ayb, win, nout);
         } else if (act) {
-            emit(h, r.p, r.q, r.n, ax0, ay0, win, nout);
+            emit(h, r.p, r.q, r.n, axb, ayb, win, nout);
         }
     }
     r.n = 0;
-    r.p = -2;
-    r.q = -2;
+    r.p = kBias - 2;
+    r.q = kBias - 2;
+}
+
+// Everything one ray row needs before its rays: the row offset, the biased
+// FP64 bases and (rebased paths) the row polynomials.
+template <int PREC, int P, bool FOLD>
+struct Row {
+    using T = typename Prec<PREC>::T;
+    static constexpr int D = Deg<P, FOLD>::value;
+    T py;
+    double ubxb, ubyb;
+    T gx[D + 1], gy[D + 1];
+};
+
+template <int PREC, int P, bool FOLD>
+__device__ __forceinline__ void row_setup(const LmDesc& d, int64_t cj, int64_t j, double zcx,
+                                          double zcy, double ubx, double uby, const float* ar,
+                                          const float* ai, Row<PREC, P, FOLD>& rw)
+{
+    using T = typename Prec<PREC>::T;
+    const int R = d.R;
+    if constexpr (PREC == 1) {
+        rw.py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
+        rw.ubxb = 0.0;
+        rw.ubyb = 0.0;
+    } else {
+        const int l = local_index(j, cj, R);
+        rw.ubxb = ubx + kBiasD;
+        rw.ubyb = row_base(d, uby + kBiasD, l);
+        T cxx, cxy, qx, qy;
+        if constexpr (PREC == 2) {
+            rw.py = (double)l * (0.5 * d.dy);
+            cxx = d.fold ? d.mx + 2.0 * d.qx * zcx + d.qy * zcy : d.mx;
+            cxy = d.fold ? d.qy * zcx : 0.0;
+            qx = d.qx;
+            qy = d.qy;
+        } else {
+            rw.py = local_offset(j, cj, R, d.hyh, d.hyl);
+            const CellMap cm = cell_map(d, zcx, zcy);
+            cxx = cm.cxx;
+            cxy = cm.cxy;
+            qx = cm.qx;
+            qy = cm.qy;
+        }
+        row_poly<P, FOLD, T>(ar, ai, rw.py, cxx, cxy, qx, qy, rw.gx, rw.gy);
+    }
+}
+
+// Column offset of lattice column k in level-2 cell ci (plain path: global).
+template <int PREC>
+__device__ __forceinline__ typename Prec<PREC>::T column_offset(const LmDesc& d, int64_t k,
+                                                                int64_t ci)
+{
+    if constexpr (PREC == 2)
+        return (double)local_index(k, ci, d.R) * (0.5 * d.dx);
+    else if constexpr (PREC == 0)
+        return local_offset(k, ci, d.R, d.hxh, d.hxl);
+    else
+        return __builtin_fmaf((float)k + 0.5f, d.dxf, d.x0f);
+}
+
+// Near sums of one ray started (rebased paths) from the row polynomials, and
+// its biased pixel.
+template <int PREC, int P, bool FOLD>
+__device__ __forceinline__ void ray_start(const Row<PREC, P, FOLD>& rw,
+                                          typename Prec<PREC>::T px, typename Prec<PREC>::T& ax,
+                                          typename Prec<PREC>::T& ay)
+{
+    if constexpr (PREC == 1) {
+        ax = 0.f;
+        ay = 0.f;
+    } else {
+        ax = horner<Row<PREC, P, FOLD>::D>(rw.gx, px);
+        ay = horner<Row<PREC, P, FOLD>::D>(rw.gy, px);
+    }
+}
+
+template <int PREC, int P, bool FOLD>
+__device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& rw,
+                                        const float* ar, const float* ai, float a0r, float a0i,
+                                        float zcxf, float zcyf, typename Prec<PREC>::T px,
+                                        typename Prec<PREC>::T ax, typename Prec<PREC>::T ay,
+                                        unsigned& p, unsigned& q)
+{
+    if constexpr (PREC == 1) {
+        int pi, qi;
+        bin_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcxf, zcyf, px, rw.py, ax, ay, pi, qi);
+        p = pi < 0 ? kBias - 1 : (unsigned)pi + kBias;
+        q = qi < 0 ? kBias - 1 : (unsigned)qi + kBias;
+    } else {
+        bin_rebased(h.inv_sdx, h.inv_sdy, kBias + (unsigned)h.snx, kBias + (unsigned)h.sny,
+                    rw.ubxb, rw.ubyb, ax, ay, p, q);
+    }
 }
 
 // --------------------------------------------------------------- units
 
+// Scalar (SMEM) loads of wave-uniform table entries.
+typedef const __attribute__((address_space(4))) float* ConstF;
+
 template <int SCHEME, int PREC, int NR, int P, bool FOLD>
 __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_hi,
-                             int64_t j, bool row_ok, int ax0, int ay0, unsigned* win,
+                             int64_t j, bool row_ok, unsigned axb, unsigned ayb, unsigned* win,
                              typename Prec<PREC>::L* lb, int lane, unsigned& nout)
 {
     using T = typename Prec<PREC>::T;
     const int R = d.R;
     const Hot h = make_hot(d);
-    const float hxh = d.hxh, hxl = d.hxl;
-    const float dxf = d.dxf, x0f = d.x0f;
     const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
     double ubx, uby;
     cell_base<SCHEME>(d, ci, cj, ubx, uby);
     float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
     if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
     const float zcxf = cell_cxf(d, ci), zcyf = cell_cyf(d, cj);
-    const CellMap cm = cell_map(d, zcx, zcy);
 
     // the lane's ray row
-    T py;
-    double uby_row = uby;
-    if constexpr (PREC == 2) {
-        py = (double)local_index(j, cj, R) * (0.5 * d.dy);
-        uby_row = row_base(d, uby, local_index(j, cj, R));
-    } else if constexpr (PREC == 0) {
-        py = local_offset(j, cj, R, d.hyh, d.hyl);
-        uby_row = row_base(d, uby, local_index(j, cj, R));
-    } else {
-        py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
-    }
+    Row<PREC, P, FOLD> rw;
+    row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
+    const T py = rw.py;
 
     constexpr int kCap = Cap<SCHEME>::value;
     const int count = __builtin_amdgcn_readfirstlane(list_count<SCHEME>(d, ci, cj));
     const int nblk = (count + kCap - 1) / kCap;
     if (nblk == 1) stage<SCHEME, PREC>(d, ci, cj, 0, count, zcx, zcy, lb, lane);
 
-    Run run{-2, -2, 0u};
+    Run run{kBias - 2, kBias - 2, 0u};
     for (int64_t c0 = c_lo; c0 < c_hi; c0 += NR) {
         T px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
+        if constexpr (PREC == 0) {
+            // wave-uniform column offsets from the map's table (scalar loads)
+            const ConstF tab = (ConstF)(d.ptab + (c0 - ci * (int64_t)R));
+#pragma unroll
+            for (int c = 0; c < NR; ++c) px[c] = tab[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) px[c] = column_offset<PREC>(d, c0 + c, ci);
+        }
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            if constexpr (PREC == 2)
-                px[c] = (double)local_index(c0 + c, ci, R) * (0.5 * d.dx);
-            else if constexpr (PREC == 0)
-                px[c] = local_offset(c0 + c, ci, R, hxh, hxl);
-            else
-                px[c] = __builtin_fmaf((float)(c0 + c) + 0.5f, dxf, x0f);
-            ax[c] = 0;
-            ay[c] = 0;
+            ray_start<PREC, P, FOLD>(rw, px[c], ax[c], ay[c]);
             kx[c] = 0;
             ky[c] = 0;
         }
@@ -551,21 +684,14 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
             if (c0 + c < c_hi) {
-                int p, q;
-                if constexpr (PREC == 2)
-                    bin_mixed64<P, FOLD>(h, d, zcx, zcy, ar, ai, ubx, uby_row, px[c], py, ax[c],
-                                         ay[c], p, q);
-                else if constexpr (PREC == 0)
-                    bin_mixed<P, FOLD>(h, cm, ar, ai, ubx, uby_row, px[c], py, ax[c], ay[c], p,
+                unsigned p, q;
+                ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c], ay[c], p,
                                        q);
-                else
-                    bin_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcxf, zcyf, px[c], py, ax[c], ay[c], p,
-                                      q);
-                if (row_ok) run_push(h, run, p, q, ax0, ay0, win, nout);
+                if (row_ok) run_push(h, run, p, q, axb, ayb, win, nout);
             }
         }
     }
-    run_flush(h, run, ax0, ay0, win, nout, lane);
+    run_flush(h, run, axb, ayb, win, nout, lane);
 }
 
 // Window origin of a tile: the pixel of the image of its centre cell's centre
@@ -605,6 +731,7 @@ template <int SCHEME, int PREC, int NR, int P>
 __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsigned* win,
                              typename Prec<PREC>::L* lb, int wave, int lane)
 {
+    const unsigned axb = (unsigned)ax0 + kBias, ayb = (unsigned)ay0 + kBias;
     const int64_t tx = t % d.ntx, ty = t / d.ntx;
     const int64_t cib = (d.tcx0 + tx) * d.G, cjb = (d.tcy0 + ty) * d.G;
     const int per_cell = d.nrb * d.ncc;
@@ -623,10 +750,10 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
         const int64_t j = r_lo + lane;
         const bool row_ok = j >= d.j0 && j < d.j1;
         if (d.fold)
-            process_unit<SCHEME, PREC, NR, P, true>(d, ci, cj, c_lo, c_hi, j, row_ok, ax0, ay0, win,
+            process_unit<SCHEME, PREC, NR, P, true>(d, ci, cj, c_lo, c_hi, j, row_ok, axb, ayb, win,
                                                     lb, lane, nout);
         else
-            process_unit<SCHEME, PREC, NR, P, false>(d, ci, cj, c_lo, c_hi, j, row_ok, ax0, ay0,
+            process_unit<SCHEME, PREC, NR, P, false>(d, ci, cj, c_lo, c_hi, j, row_ok, axb, ayb,
                                                      win, lb, lane, nout);
     }
     unsigned tot = wave_sum_u32(nout);
@@ -785,6 +912,14 @@ __global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t c
     }
 }
 
+// Column offsets local_offset(l) of a level-2 cell, l = 0 .. n-1 (entries past
+// R belong to masked columns of the last group).
+__global__ void k_ptab(LmDesc d, float* __restrict__ out, int n)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n) out[l] = local_offset(l, 0, d.R, d.hxh, d.hxl);
+}
+
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -792,7 +927,8 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
         p[i] = v;
 }
 
-// Near-field sum of one position (lens for lens as in the shooting kernel).
+// Near-field sum of one position (lens for lens as in the shooting kernel),
+// added to the start values ax, ay.
 template <int SCHEME, int PREC>
 __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, double zcy,
                          typename Prec<PREC>::T px, typename Prec<PREC>::T py,
@@ -802,8 +938,6 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
     constexpr int kCap = Cap<SCHEME>::value;
     const int count = list_count<SCHEME>(d, ci, cj);
     T kx = 0, ky = 0;
-    ax = 0;
-    ay = 0;
     for (int b0 = 0; b0 < count; b0 += kCap) {
         const int nb = min(kCap, count - b0);
         T bx = SCHEME == 0 ? T(0) : ax, by = SCHEME == 0 ? T(0) : ay;
@@ -823,15 +957,10 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
 }
 
 // Per-ray pixels with the shooting kernel's arithmetic, lens for lens.
-template <int SCHEME, int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restrict__ ii,
-                                               const int64_t* __restrict__ jj, int64_t n,
-                                               int32_t* __restrict__ po, int32_t* __restrict__ qo)
+template <int SCHEME, int PREC, int P, bool FOLD>
+__device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, int32_t& qo)
 {
     using T = typename Prec<PREC>::T;
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (t >= n) return;
-    const int64_t i = ii[t], j = jj[t];
     const int R = d.R;
     const int64_t ci = i / R, cj = j / R;
     const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
@@ -839,43 +968,33 @@ __global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restri
     cell_base<SCHEME>(d, ci, cj, ubx, uby);
     float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
     if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
-    T px, py;
-    if constexpr (PREC == 2) {
-        px = (double)local_index(i, ci, R) * (0.5 * d.dx);
-        py = (double)local_index(j, cj, R) * (0.5 * d.dy);
-    } else if constexpr (PREC == 0) {
-        px = local_offset(i, ci, R, d.hxh, d.hxl);
-        py = local_offset(j, cj, R, d.hyh, d.hyl);
-    } else {
-        px = __builtin_fmaf((float)i + 0.5f, d.dxf, d.x0f);
-        py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
-    }
+    Row<PREC, P, FOLD> rw;
+    row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
+    const T px = column_offset<PREC>(d, i, ci);
     T ax, ay;
-    near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, py, ax, ay);
-    int p, q;
+    ray_start<PREC, P, FOLD>(rw, px, ax, ay);
+    near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, rw.py, ax, ay);
     const Hot h = make_hot(d);
-    if constexpr (PREC == 2) {
-        const double uby_row = row_base(d, uby, local_index(j, cj, R));
-        if (d.fold)
-            bin_mixed64<P, true>(h, d, zcx, zcy, ar, ai, ubx, uby_row, px, py, ax, ay, p, q);
-        else
-            bin_mixed64<P, false>(h, d, zcx, zcy, ar, ai, ubx, uby_row, px, py, ax, ay, p, q);
-    } else if constexpr (PREC == 0) {
-        const CellMap cm = cell_map(d, zcx, zcy);
-        const double uby_row = row_base(d, uby, local_index(j, cj, R));
-        if (d.fold)
-            bin_mixed<P, true>(h, cm, ar, ai, ubx, uby_row, px, py, ax, ay, p, q);
-        else
-            bin_mixed<P, false>(h, cm, ar, ai, ubx, uby_row, px, py, ax, ay, p, q);
-    } else {
-        const float zxf = cell_cxf(d, ci), zyf = cell_cyf(d, cj);
-        if (d.fold)
-            bin_fp32<P, true>(h, ar, ai, a0r, a0i, zxf, zyf, px, py, ax, ay, p, q);
-        else
-            bin_fp32<P, false>(h, ar, ai, a0r, a0i, zxf, zyf, px, py, ax, ay, p, q);
-    }
-    po[t] = p;
-    qo[t] = q;
+    unsigned p, q;
+    ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, ax, ay, p,
+                           q);
+    const unsigned pm = p - kBias, qm = q - kBias;
+    const bool in = (pm < (unsigned)d.snx) & (qm < (unsigned)d.sny);
+    po = in ? (int32_t)pm : -1;
+    qo = in ? (int32_t)qm : -1;
+}
+
+template <int SCHEME, int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restrict__ ii,
+                                               const int64_t* __restrict__ jj, int64_t n,
+                                               int32_t* __restrict__ po, int32_t* __restrict__ qo)
+{
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t >= n) return;
+    if (d.fold)
+        trace_one<SCHEME, PREC, P, true>(d, ii[t], jj[t], po[t], qo[t]);
+    else
+        trace_one<SCHEME, PREC, P, false>(d, ii[t], jj[t], po[t], qo[t]);
 }
 
 // Deflection at arbitrary positions, rebased on the level-2 cell holding them.
@@ -900,7 +1019,7 @@ __global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restr
         px = (float)tx;
         py = (float)ty;
     }
-    T ax, ay;
+    T ax = 0, ay = 0;
     near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, py, ax, ay);
     double outx = ax, outy = ay;
     if (SCHEME == 1) {
@@ -1066,6 +1185,14 @@ int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int
 int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu)
 {
     return dispatch(scheme, precision, rays_per_lane, terms, Occupancy{wg_per_cu});
+}
+
+int lm_launch_ptab(const LmDesc& d, float* out, int n, void* stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_ptab, dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG), 0,
+                       (hipStream_t)stream, d, out, n);
+    return (int)hipGetLastError();
 }
 
 int lm_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream)
