@@ -7,7 +7,7 @@
 #define LM_WAVES 4
 #define LM_LENS_CAP 256    // direct sum: lenses staged per wave per block (the summation block)
 #define LM_NEAR_CAP 64     // interpolated scheme: near lenses staged per wave per block
-#define LM_WIN_MAX 8192    // uint32 bins of a workgroup's LDS window
+#define LM_WIN_MAX 7040    // uint32 bins of a workgroup's LDS window
 #define LM_PTAB_PAD 64     // column-offset table entries past R (last column group)
 
 // Taylor coefficients of one level-2 cell: a_0 in FP64 (it carries the large

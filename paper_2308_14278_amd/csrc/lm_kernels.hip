@@ -49,6 +49,14 @@ struct Prec<2> {
     using L = double4;
 };
 
+// The rebased FP32 interpolated path shares the column-lens differences of a
+// wave through an LDS table (TabCh lenses at a time).
+template <int SCHEME, int PREC>
+struct UseTab {
+    static constexpr bool value = SCHEME == 1 && PREC == 0;
+};
+constexpr int kTabCh = 16;
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -166,6 +174,17 @@ __device__ __forceinline__ void pair(double px, double dy, double dy2, double lx
     ay = __builtin_fma(dy, w, ay);
 }
 
+// Pair from the wave-shared differences dx = px - lx and mdx = m dx (one per
+// column and lens, the same for every row) and the row's dy^2 and m dy.
+__device__ __forceinline__ void pair_tab(float dx, float mdx, float dy2, float mdy, float& ax,
+                                         float& ay)
+{
+    const float r2 = __builtin_fmaf(dx, dx, dy2);
+    const float w = __builtin_amdgcn_rcpf(r2);
+    ax = __builtin_fmaf(mdx, w, ax);
+    ay = __builtin_fmaf(mdy, w, ay);
+}
+
 template <class T>
 __device__ __forceinline__ void kahan_add(T& s, T& c, T v)
 {
@@ -229,9 +248,10 @@ __device__ __forceinline__ double row_base(const LmDesc& d, double uby, int l)
     return __builtin_fma(d.my * ((double)l * (0.5 * d.dy)), d.inv_sdy, uby);
 }
 
-// Pixel indices are biased by kBias and clamped to [kBias - 1, kBias + size]:
-// either end stands for "outside the map" (NaN coordinates included), so the
-// per-ray code needs no range test; the count step tests each run once.
+// Pixel indices are biased by kBias and converted with saturation (NaN and
+// negative values give 0), so the per-ray code needs no range test: index
+// p - kBias outside [0, size) means "outside the map", which the count step
+// tests once per run of equal pixels.
 constexpr unsigned kBias = 1u << 22;
 constexpr double kBiasD = 4194304.0;
 
@@ -240,14 +260,6 @@ __device__ __forceinline__ unsigned cvt_u32_sat(double v)
 {
     unsigned r;
     asm("v_cvt_u32_f64 %0, %1" : "=v"(r) : "v"(v));
-    return r;
-}
-
-// min(max(v, lo), hi) in one instruction (lo <= hi).
-__device__ __forceinline__ unsigned clamp_u32(unsigned v, unsigned lo, unsigned hi)
-{
-    unsigned r;
-    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "v"(lo), "v"(hi));
     return r;
 }
 
@@ -312,14 +324,13 @@ __device__ __forceinline__ T horner(const T* g, T x)
 // sy = gy + near_y; ubxb and ubyb are the biased FP64 pixel coordinates of the
 // cell centre's image (x) and of the row (y, row_base).
 template <class T>
-__device__ __forceinline__ void bin_rebased(double inv_sdx, double inv_sdy, unsigned pmax,
-                                            unsigned qmax, double ubxb, double ubyb, T sx, T sy,
-                                            unsigned& p, unsigned& q)
+__device__ __forceinline__ void bin_rebased(double inv_sdx, double inv_sdy, double ubxb,
+                                            double ubyb, T sx, T sy, unsigned& p, unsigned& q)
 {
     const double u = __builtin_fma(-(double)sx, inv_sdx, ubxb);
     const double v = __builtin_fma(-(double)sy, inv_sdy, ubyb);
-    p = clamp_u32(cvt_u32_sat(u), kBias - 1, pmax);
-    q = clamp_u32(cvt_u32_sat(v), kBias - 1, qmax);
+    p = cvt_u32_sat(u);
+    q = cvt_u32_sat(v);
 }
 
 // Pixel of one ray in the plain FP32 path (global coordinates).
@@ -454,7 +465,7 @@ __device__ __forceinline__ void load_taylor(const LmDesc& d, int64_t ci, int64_t
 // ------------------------------------------------------------- counting
 
 struct Run {
-    unsigned p, q;  // biased pixel (kBias - 2: none yet)
+    unsigned p, q;  // biased pixel
     unsigned n;
 };
 
@@ -480,8 +491,8 @@ __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsig
                                          unsigned axb, unsigned ayb, unsigned* win,
                                          unsigned& nout)
 {
-    // (a unit starts with the empty run n = 0 at the sentinel pixel kBias - 2,
-    // which emit books as n_out += 0)
+    // (a unit starts with an empty run, n = 0, at the out-of-map pixel
+    // kBias - 2, which emit books as n_out += 0)
     const bool same = (p == r.p) & (q == r.q);
     const Run old = r;
     r.n = (same ? r.n : 0u) + 1u;
@@ -596,11 +607,10 @@ __device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& 
     if constexpr (PREC == 1) {
         int pi, qi;
         bin_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcxf, zcyf, px, rw.py, ax, ay, pi, qi);
-        p = pi < 0 ? kBias - 1 : (unsigned)pi + kBias;
-        q = qi < 0 ? kBias - 1 : (unsigned)qi + kBias;
+        p = pi < 0 ? 0u : (unsigned)pi + kBias;
+        q = qi < 0 ? 0u : (unsigned)qi + kBias;
     } else {
-        bin_rebased(h.inv_sdx, h.inv_sdy, kBias + (unsigned)h.snx, kBias + (unsigned)h.sny,
-                    rw.ubxb, rw.ubyb, ax, ay, p, q);
+        bin_rebased(h.inv_sdx, h.inv_sdy, rw.ubxb, rw.ubyb, ax, ay, p, q);
     }
 }
 
@@ -612,7 +622,7 @@ typedef const __attribute__((address_space(4))) float* ConstF;
 template <int SCHEME, int PREC, int NR, int P, bool FOLD>
 __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_hi,
                              int64_t j, bool row_ok, unsigned axb, unsigned ayb, unsigned* win,
-                             typename Prec<PREC>::L* lb, int lane, unsigned& nout)
+                             typename Prec<PREC>::L* lb, float* tb, int lane, unsigned& nout)
 {
     using T = typename Prec<PREC>::T;
     const int R = d.R;
@@ -623,6 +633,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
     float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
     if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
     const float zcxf = cell_cxf(d, ci), zcyf = cell_cyf(d, cj);
+    const float h_hxh = d.hxh, h_hxl = d.hxl;
 
     // the lane's ray row
     Row<PREC, P, FOLD> rw;
@@ -661,13 +672,47 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 bx[c] = SCHEME == 0 ? T(0) : ax[c];
                 by[c] = SCHEME == 0 ? T(0) : ay[c];
             }
+            if constexpr (UseTab<SCHEME, PREC>::value) {
+                // this lane's column in the table build: NR divides 64
+                const float pxl = local_offset(c0 + (lane & (NR - 1)), ci, R, h_hxh, h_hxl);
+                for (int k0 = 0; k0 < nb; k0 += kTabCh) {
+                    const int nk = min(kTabCh, nb - k0);
+                    // tb[k][0..NR) = dx, tb[k][NR..2NR) = m dx, for lenses k0 .. k0+nk
+                    for (int e = lane; e < nk * NR; e += 64) {
+                        const int k = e / NR, c = e & (NR - 1);
+                        const float4 L = lb[k0 + k];
+                        const float dx = pxl - L.x;
+                        tb[k * 2 * NR + c] = dx;
+                        tb[k * 2 * NR + NR + c] = L.z * dx;
+                    }
+                    wave_sync_lds();
 #pragma unroll 2
-            for (int k = 0; k < nb; ++k) {
-                const auto L = lb[k];
-                const T dy = py - L.y;
-                const T dy2 = dy * dy;
+                    for (int k = 0; k < nk; ++k) {
+                        const float4 L = lb[k0 + k];
+                        const float dy = py - L.y;
+                        const float dy2 = dy * dy;
+                        const float mdy = L.z * dy;
+                        const float4* row = reinterpret_cast<const float4*>(tb + k * 2 * NR);
 #pragma unroll
-                for (int c = 0; c < NR; ++c) pair(px[c], dy, dy2, L.x, L.z, bx[c], by[c]);
+                        for (int c4 = 0; c4 < NR / 4; ++c4) {
+                            const float4 D = row[c4], M = row[NR / 4 + c4];
+                            pair_tab(D.x, M.x, dy2, mdy, bx[4 * c4 + 0], by[4 * c4 + 0]);
+                            pair_tab(D.y, M.y, dy2, mdy, bx[4 * c4 + 1], by[4 * c4 + 1]);
+                            pair_tab(D.z, M.z, dy2, mdy, bx[4 * c4 + 2], by[4 * c4 + 2]);
+                            pair_tab(D.w, M.w, dy2, mdy, bx[4 * c4 + 3], by[4 * c4 + 3]);
+                        }
+                    }
+                    wave_sync_lds();
+                }
+            } else {
+#pragma unroll 2
+                for (int k = 0; k < nb; ++k) {
+                    const auto L = lb[k];
+                    const T dy = py - L.y;
+                    const T dy2 = dy * dy;
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) pair(px[c], dy, dy2, L.x, L.z, bx[c], by[c]);
+                }
             }
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
@@ -681,9 +726,10 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
             }
             if (nblk > 1) wave_sync_lds();
         }
+        const int ncol = (int)min((int64_t)NR, c_hi - c0);
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            if (c0 + c < c_hi) {
+            if (c < ncol) {
                 unsigned p, q;
                 ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c], ay[c], p,
                                        q);
@@ -729,7 +775,7 @@ __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_
 
 template <int SCHEME, int PREC, int NR, int P>
 __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsigned* win,
-                             typename Prec<PREC>::L* lb, int wave, int lane)
+                             typename Prec<PREC>::L* lb, float* tb, int wave, int lane)
 {
     const unsigned axb = (unsigned)ax0 + kBias, ayb = (unsigned)ay0 + kBias;
     const int64_t tx = t % d.ntx, ty = t / d.ntx;
@@ -751,10 +797,10 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
         const bool row_ok = j >= d.j0 && j < d.j1;
         if (d.fold)
             process_unit<SCHEME, PREC, NR, P, true>(d, ci, cj, c_lo, c_hi, j, row_ok, axb, ayb, win,
-                                                    lb, lane, nout);
+                                                    lb, tb, lane, nout);
         else
             process_unit<SCHEME, PREC, NR, P, false>(d, ci, cj, c_lo, c_hi, j, row_ok, axb, ayb,
-                                                     win, lb, lane, nout);
+                                                     win, lb, tb, lane, nout);
     }
     unsigned tot = wave_sum_u32(nout);
     if (lane == 0 && tot) atomicAdd(d.n_out, (unsigned long long)tot);
@@ -781,6 +827,7 @@ __global__ __launch_bounds__(kWG) void k_shoot_map(LmDesc d)
 {
     __shared__ unsigned win[kWinMax];
     __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
+    __shared__ float4 tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * NR / 2 : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -790,7 +837,8 @@ __global__ __launch_bounds__(kWG) void k_shoot_map(LmDesc d)
     int ax0, ay0;
     tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
     __syncthreads();
-    process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], wave, lane);
+    process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave],
+                                      reinterpret_cast<float*>(tab[wave]), wave, lane);
     __syncthreads();
     flush_window(d, win, ax0, ay0, tid);
 }
@@ -803,6 +851,7 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
 {
     __shared__ unsigned win[kWinMax];
     __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
+    __shared__ float4 tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * NR / 2 : 1];
     __shared__ long long s_item;
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
@@ -828,7 +877,8 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
         const int64_t tx = t % d.ntx, ty = t / d.ntx;
         int ax0, ay0;
         tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
-        process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], wave, lane);
+        process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave],
+                                          reinterpret_cast<float*>(tab[wave]), wave, lane);
         __syncthreads();
         flush_window(d, win, ax0, ay0, tid);
         __syncthreads();
@@ -944,7 +994,12 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
         for (int k = 0; k < nb; ++k) {
             const auto L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
             const T dy = py - L.y;
-            pair(px, dy, dy * dy, L.x, L.z, bx, by);
+            if constexpr (UseTab<SCHEME, PREC>::value) {
+                const float dx = px - L.x;
+                pair_tab(dx, L.z * dx, dy * dy, L.z * dy, bx, by);
+            } else {
+                pair(px, dy, dy * dy, L.x, L.z, bx, by);
+            }
         }
         if (SCHEME == 0) {
             kahan_add(ax, kx, bx);
