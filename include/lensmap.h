@@ -290,6 +290,11 @@ lm_status lm_batch_timing(lm_batch* b, float* coeff_ms, float* shoot_ms);
  * as fit).  Any pointer may be NULL. */
 lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* tile_cells,
                           int32_t* wg_per_cu);
+/* Set the execution parameters by hand instead of lm_batch_tune: rays per
+ * lane 4, 8 or 16, tile scale 1..8, workgroups per CU 0..8 (0: as many as
+ * fit).  Results never depend on them.  LM_EINVAL outside those ranges. */
+lm_status lm_batch_set_params(lm_batch* b, int32_t rays_per_lane, int32_t tile_cells,
+                              int32_t wg_per_cu);
 void lm_batch_destroy(lm_batch* b);
 
 /* Device micro-benchmarks on the current device (diagnostics for the

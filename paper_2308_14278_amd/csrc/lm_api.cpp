@@ -1288,6 +1288,21 @@ lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* ti
     return ok();
 }
 
+lm_status lm_batch_set_params(lm_batch* b, int32_t rays_per_lane, int32_t tile_cells,
+                              int32_t wg_per_cu)
+{
+    if (!b) return fail(LM_EINVAL, "batch is NULL");
+    if (!lm_supported_rays_per_lane(rays_per_lane))
+        return fail(LM_EINVAL, "rays_per_lane must be 4, 8 or 16, got %d", rays_per_lane);
+    if (tile_cells < 1 || tile_cells > 8) return fail(LM_EINVAL, "tile_cells must be in 1..8");
+    if (wg_per_cu < 0 || wg_per_cu > 8) return fail(LM_EINVAL, "wg_per_cu must be in 0..8");
+    b->rays_per_lane = rays_per_lane;
+    b->g_scale = tile_cells;
+    b->wg_per_cu = wg_per_cu;
+    b->dirty = true;
+    return ok();
+}
+
 void lm_batch_destroy(lm_batch* b)
 {
     if (!b) return;

@@ -174,15 +174,33 @@ __device__ __forceinline__ void pair(double px, double dy, double dy2, double lx
     ay = __builtin_fma(dy, w, ay);
 }
 
-// Pair from the wave-shared differences dx = px - lx and mdx = m dx (one per
-// column and lens, the same for every row) and the row's dy^2 and m dy.
-__device__ __forceinline__ void pair_tab(float dx, float mdx, float dy2, float mdy, float& ax,
+// Pair from the wave-shared dx^2 and m dx, dx = px - lx (one per column and
+// lens, the same for every row), and the row's dy^2 and m dy.  Every operation
+// but the reciprocal is a two-source VOP2 instruction.
+__device__ __forceinline__ void pair_tab(float dx2, float mdx, float dy2, float mdy, float& ax,
                                          float& ay)
 {
-    const float r2 = __builtin_fmaf(dx, dx, dy2);
+    const float r2 = dx2 + dy2;
     const float w = __builtin_amdgcn_rcpf(r2);
     ax = __builtin_fmaf(mdx, w, ax);
     ay = __builtin_fmaf(mdy, w, ay);
+}
+
+// Two pairs of one lens and the row's rays in columns a = 2m and b = 2m + 1
+// sharing one reciprocal: 1/r2a = r2b / (r2a r2b) and 1/r2b = r2a / (r2a r2b)
+// (the reciprocal is the expensive instruction of a pair).  The product stays a
+// normal FP32 number while both r2 exceed 1.1e-19 theta_E^2 (rays farther than
+// 3.3e-10 theta_E from the lens) and stay below 1e19.
+__device__ __forceinline__ void pair2(float dx2a, float dx2b, float mdxa, float mdxb, float dy2,
+                                      float mdy, float& axa, float& aya, float& axb, float& ayb)
+{
+    const float r2a = dx2a + dy2, r2b = dx2b + dy2;
+    const float r = __builtin_amdgcn_rcpf(r2a * r2b);
+    const float wa = r * r2b, wb = r * r2a;
+    axa = __builtin_fmaf(mdxa, wa, axa);
+    aya = __builtin_fmaf(mdy, wa, aya);
+    axb = __builtin_fmaf(mdxb, wb, axb);
+    ayb = __builtin_fmaf(mdy, wb, ayb);
 }
 
 template <class T>
@@ -619,10 +637,13 @@ __device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& 
 // Scalar (SMEM) loads of wave-uniform table entries.
 typedef const __attribute__((address_space(4))) float* ConstF;
 
+// Columns [c_lo, c_hi) of cell ci are computed (c_lo even, so columns 2m and
+// 2m + 1 share a group); rays of columns >= c_beg are counted.
 template <int SCHEME, int PREC, int NR, int P, bool FOLD>
-__device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_hi,
-                             int64_t j, bool row_ok, unsigned axb, unsigned ayb, unsigned* win,
-                             typename Prec<PREC>::L* lb, float* tb, int lane, unsigned& nout)
+__device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_beg,
+                             int64_t c_hi, int64_t j, bool row_ok, unsigned axb, unsigned ayb,
+                             unsigned* win, typename Prec<PREC>::L* lb, float* tb, int lane,
+                             unsigned& nout)
 {
     using T = typename Prec<PREC>::T;
     const int R = d.R;
@@ -677,12 +698,12 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 const float pxl = local_offset(c0 + (lane & (NR - 1)), ci, R, h_hxh, h_hxl);
                 for (int k0 = 0; k0 < nb; k0 += kTabCh) {
                     const int nk = min(kTabCh, nb - k0);
-                    // tb[k][0..NR) = dx, tb[k][NR..2NR) = m dx, for lenses k0 .. k0+nk
+                    // tb[k][0..NR) = dx^2, tb[k][NR..2NR) = m dx, for lenses k0 .. k0+nk
                     for (int e = lane; e < nk * NR; e += 64) {
                         const int k = e / NR, c = e & (NR - 1);
                         const float4 L = lb[k0 + k];
                         const float dx = pxl - L.x;
-                        tb[k * 2 * NR + c] = dx;
+                        tb[k * 2 * NR + c] = dx * dx;
                         tb[k * 2 * NR + NR + c] = L.z * dx;
                     }
                     wave_sync_lds();
@@ -696,10 +717,10 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
 #pragma unroll
                         for (int c4 = 0; c4 < NR / 4; ++c4) {
                             const float4 D = row[c4], M = row[NR / 4 + c4];
-                            pair_tab(D.x, M.x, dy2, mdy, bx[4 * c4 + 0], by[4 * c4 + 0]);
-                            pair_tab(D.y, M.y, dy2, mdy, bx[4 * c4 + 1], by[4 * c4 + 1]);
-                            pair_tab(D.z, M.z, dy2, mdy, bx[4 * c4 + 2], by[4 * c4 + 2]);
-                            pair_tab(D.w, M.w, dy2, mdy, bx[4 * c4 + 3], by[4 * c4 + 3]);
+                            pair2(D.x, D.y, M.x, M.y, dy2, mdy, bx[4 * c4 + 0], by[4 * c4 + 0],
+                                  bx[4 * c4 + 1], by[4 * c4 + 1]);
+                            pair2(D.z, D.w, M.z, M.w, dy2, mdy, bx[4 * c4 + 2], by[4 * c4 + 2],
+                                  bx[4 * c4 + 3], by[4 * c4 + 3]);
                         }
                     }
                     wave_sync_lds();
@@ -727,9 +748,10 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
             if (nblk > 1) wave_sync_lds();
         }
         const int ncol = (int)min((int64_t)NR, c_hi - c0);
+        const int cfirst = (int)max((int64_t)0, c_beg - c0);
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            if (c < ncol) {
+            if (c >= cfirst && c < ncol) {
                 unsigned p, q;
                 ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c], ay[c], p,
                                        q);
@@ -789,18 +811,20 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
         const int64_t ci = cib + cu % d.G, cj = cjb + cu / d.G;
         if (ci >= d.ncx || cj >= d.ncy) continue;
         const int64_t cell_lo = ci * d.R, cell_hi = cell_lo + d.R;
-        const int64_t c_lo = max(cell_lo + (int64_t)cc * d.cw, d.i0);
+        const int64_t c_beg = max(cell_lo + (int64_t)cc * d.cw, d.i0);
         const int64_t c_hi = min(min(cell_lo + (int64_t)(cc + 1) * d.cw, cell_hi), d.i1);
         const int64_t r_lo = cj * d.R + (int64_t)rb * 64;
-        if (c_lo >= c_hi || r_lo + 64 <= d.j0 || r_lo >= d.j1) continue;
+        if (c_beg >= c_hi || r_lo + 64 <= d.j0 || r_lo >= d.j1) continue;
+        // cells start at even columns (R is a multiple of 64), so c_lo stays in the cell
+        const int64_t c_lo = c_beg & ~(int64_t)1;
         const int64_t j = r_lo + lane;
         const bool row_ok = j >= d.j0 && j < d.j1;
         if (d.fold)
-            process_unit<SCHEME, PREC, NR, P, true>(d, ci, cj, c_lo, c_hi, j, row_ok, axb, ayb, win,
-                                                    lb, tb, lane, nout);
+            process_unit<SCHEME, PREC, NR, P, true>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, axb,
+                                                    ayb, win, lb, tb, lane, nout);
         else
-            process_unit<SCHEME, PREC, NR, P, false>(d, ci, cj, c_lo, c_hi, j, row_ok, axb, ayb,
-                                                     win, lb, tb, lane, nout);
+            process_unit<SCHEME, PREC, NR, P, false>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, axb,
+                                                     ayb, win, lb, tb, lane, nout);
     }
     unsigned tot = wave_sum_u32(nout);
     if (lane == 0 && tot) atomicAdd(d.n_out, (unsigned long long)tot);
@@ -979,10 +1003,13 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
 
 // Near-field sum of one position (lens for lens as in the shooting kernel),
 // added to the start values ax, ay.
-template <int SCHEME, int PREC>
+// PAIRED: the shooting kernel's two-column reciprocal, pxp = offset of the
+// partner column (column index ^ 1).
+template <int SCHEME, int PREC, bool PAIRED = false>
 __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, double zcy,
                          typename Prec<PREC>::T px, typename Prec<PREC>::T py,
-                         typename Prec<PREC>::T& ax, typename Prec<PREC>::T& ay)
+                         typename Prec<PREC>::T& ax, typename Prec<PREC>::T& ay,
+                         typename Prec<PREC>::T pxp = 0)
 {
     using T = typename Prec<PREC>::T;
     constexpr int kCap = Cap<SCHEME>::value;
@@ -994,9 +1021,13 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
         for (int k = 0; k < nb; ++k) {
             const auto L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
             const T dy = py - L.y;
-            if constexpr (UseTab<SCHEME, PREC>::value) {
+            if constexpr (UseTab<SCHEME, PREC>::value && PAIRED) {
+                const float dx = px - L.x, dxp = pxp - L.x;
+                float ayp = 0.f, axp = 0.f;
+                pair2(dx * dx, dxp * dxp, L.z * dx, L.z * dxp, dy * dy, L.z * dy, bx, by, axp, ayp);
+            } else if constexpr (UseTab<SCHEME, PREC>::value) {
                 const float dx = px - L.x;
-                pair_tab(dx, L.z * dx, dy * dy, L.z * dy, bx, by);
+                pair_tab(dx * dx, L.z * dx, dy * dy, L.z * dy, bx, by);
             } else {
                 pair(px, dy, dy * dy, L.x, L.z, bx, by);
             }
@@ -1028,7 +1059,8 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
     const T px = column_offset<PREC>(d, i, ci);
     T ax, ay;
     ray_start<PREC, P, FOLD>(rw, px, ax, ay);
-    near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, rw.py, ax, ay);
+    near_sum<SCHEME, PREC, true>(d, ci, cj, zcx, zcy, px, rw.py, ax, ay,
+                                 column_offset<PREC>(d, i ^ 1, ci));
     const Hot h = make_hot(d);
     unsigned p, q;
     ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, ax, ay, p,

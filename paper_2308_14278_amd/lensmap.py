@@ -113,6 +113,7 @@ _SIGS = {
     "lm_batch_tune": [_vp, ctypes.c_char_p],
     "lm_batch_shoot": [_vp, _vp],
     "lm_batch_params": [_vp, _i32, _i32, _i32],
+    "lm_batch_set_params": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "lm_shot_stats": [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                       _P(lm_stats)],
     "lm_batch_timing": [_vp, _P(ctypes.c_float), _P(ctypes.c_float)],
@@ -333,6 +334,11 @@ def lm_batch_params(b):
     _check(load().lm_batch_params(b, ctypes.byref(a), ctypes.byref(c), ctypes.byref(d)),
            "lm_batch_params")
     return int(a.value), int(c.value), int(d.value)
+
+
+def lm_batch_set_params(b, rays_per_lane, tile_cells, wg_per_cu):
+    _check(load().lm_batch_set_params(b, int(rays_per_lane), int(tile_cells), int(wg_per_cu)),
+           "lm_batch_set_params")
 
 
 def lm_fold_scales(theta_e_arcsec, d_x, d_y, kappa0, kappa_star, n_star, ds_over_r=0.0):
