@@ -54,6 +54,7 @@ class _Params(ctypes.Structure):
         ("l1_kx", ctypes.c_int64), ("l1_ky", ctypes.c_int64),
         ("halo", ctypes.c_int64), ("terms", ctypes.c_int64),
         ("macro", ctypes.c_int64), ("d_x", ctypes.c_double), ("d_y", ctypes.c_double),
+        ("far_order", ctypes.c_int64),
     ]
 
 
@@ -128,7 +129,8 @@ class Oracle:
             g.src_x0, g.src_y0, g.src_dx, g.src_dy, g.src_nx, g.src_ny,
             g.ray_x0, g.ray_y0, g.ray_dx, g.ray_dy, g.ray_nx, g.ray_ny,
             self.kappa, self.gamma, self.kappa_star,
-            g.scheme, g.coarse, g.l1_kx, g.l1_ky, g.halo, g.terms, macro, dx, dy)
+            g.scheme, g.coarse, g.l1_kx, g.l1_ky, g.halo, g.terms, macro, dx, dy,
+            getattr(g, "far_order", 0))
 
     @property
     def n(self):

@@ -49,6 +49,7 @@ class OracleGeometry:
     l1_ky: int = 1
     halo: int = 1
     terms: int = 4
+    far_order: int = 0  # 0: direct level-2 coefficients; Q: hierarchical, Q terms
 
     @property
     def n_rays(self) -> int:

@@ -45,6 +45,10 @@
  *  [Bx0 + p dx, Bx0 + (p+1) dx) x [By0 + q dy, By0 + (q+1) dy); a ray outside
  *  every pixel is counted in n_out; mu_pq = N_pq * (L3x L3y) / (dx dy).
  *
+ *  Hierarchical far field (optional, far_order = Q > 0): the coefficients of
+ *  a level-2 cell come from a Q-term series of the same far lenses about the
+ *  centre of its level-1 cell, re-expanded about z_c (see far_coeffs_hier).
+ *
  * Sums of many terms use Neumaier's compensated summation.
  */
 #include <math.h>
@@ -69,6 +73,9 @@ typedef struct {
     /* macro model: 0 linear (kappa, gamma), 1 fold (kappa = kappa_0, d_x, d_y) */
     int64_t macro;
     double d_x, d_y;
+    /* far field: 0 direct per level-2 cell; Q > 0 through a Q-term expansion
+     * per level-1 cell (hierarchical far field) */
+    int64_t far_order;
 } lmo_params;
 
 typedef struct {
@@ -196,6 +203,79 @@ static void far_coeffs(const lmo_params *p, const lmo_lenses *L, const unsigned 
     free(im);
 }
 
+/* Hierarchical far field: the far set of level-2 cell (ci,cj) is the far set
+ * of its level-1 cell (I,J) (Sec. 3.2.1), so its Taylor series about the
+ * level-2 centre z_c (Sec. 3.2.2) can be obtained from one series about the
+ * level-1 centre Z, truncated after Q terms:
+ *   A_n = - sum_{k far} m_k / (z_k - Z)^{n+1},                n < Q,
+ *   a_p = sum_{n=p}^{Q-1} C(n,p) A_n (z_c - Z)^{n-p},           p < P,
+ * which is the re-expansion of sum_n A_n (z - Z)^n about z_c.  Far lenses lie
+ * outside the (2H+1)^2 block of level-1 cells, so |z_c - Z| / |z_k - Z| stays
+ * below about 0.47 for square level-1 cells and the truncation error falls
+ * geometrically with Q. */
+static void far_coeffs_hier(const lmo_params *p, const lmo_lenses *L, const unsigned char *near,
+                            int64_t ci, int64_t cj, double *a)
+{
+    int64_t Q = p->far_order, P = p->terms;
+    int64_t I = floor_div_i64(ci, p->l1_kx), J = floor_div_i64(cj, p->l1_ky);
+    double Zx = p->ray_x0 + ((double)I + 0.5) * (double)(p->l1_kx * p->coarse) * p->ray_dx;
+    double Zy = p->ray_y0 + ((double)J + 0.5) * (double)(p->l1_ky * p->coarse) * p->ray_dy;
+    double zx, zy;
+    cell_centre(p, ci, cj, &zx, &zy);
+    /* level-1 expansion */
+    nsum *re = (nsum *)calloc((size_t)Q, sizeof(nsum));
+    nsum *im = (nsum *)calloc((size_t)Q, sizeof(nsum));
+    for (int64_t k = 0; k < L->n; ++k) {
+        if (near[k]) continue;
+        double wx = L->x[k] - Zx, wy = L->y[k] - Zy;
+        double w2 = wx * wx + wy * wy;
+        double ux = wx / w2, uy = -wy / w2;
+        double tx = L->m[k] * ux, ty = L->m[k] * uy;
+        for (int64_t n = 0; n < Q; ++n) {
+            nsum_add(&re[n], -tx);
+            nsum_add(&im[n], -ty);
+            double nx = tx * ux - ty * uy;
+            double ny = tx * uy + ty * ux;
+            tx = nx;
+            ty = ny;
+        }
+    }
+    /* re-expansion about z_c */
+    double sx = zx - Zx, sy = zy - Zy;
+    for (int64_t q = 0; q < P; ++q) {
+        nsum ar = {0.0, 0.0}, ai = {0.0, 0.0};
+        double px = 1.0, py = 0.0; /* (z_c - Z)^(n-q) */
+        double binom = 1.0;        /* C(n, q) */
+        for (int64_t n = q; n < Q; ++n) {
+            double Ax = nsum_get(&re[n]), Ay = nsum_get(&im[n]);
+            nsum_add(&ar, binom * (Ax * px - Ay * py));
+            nsum_add(&ai, binom * (Ax * py + Ay * px));
+            double nx = px * sx - py * sy;
+            double ny = px * sy + py * sx;
+            px = nx;
+            py = ny;
+            binom = binom * (double)(n + 1) / (double)(n + 1 - q);
+        }
+        a[2 * q] = nsum_get(&ar);
+        a[2 * q + 1] = nsum_get(&ai);
+    }
+    free(re);
+    free(im);
+}
+
+/* Coefficients of level-2 cell (ci,cj) by the configured far-field method. */
+static void cell_coeffs(const lmo_params *p, const lmo_lenses *L, const unsigned char *near,
+                        int64_t ci, int64_t cj, double *a)
+{
+    if (p->far_order > 0) {
+        far_coeffs_hier(p, L, near, ci, cj, a);
+    } else {
+        double zx, zy;
+        cell_centre(p, ci, cj, &zx, &zy);
+        far_coeffs(p, L, near, zx, zy, a);
+    }
+}
+
 /* alpha_far = conj( sum_n a_n d^n ), d = z - z_c, evaluated by Horner */
 static void far_eval(int64_t P, const double *a, double dx, double dy, double *ax, double *ay)
 {
@@ -242,6 +322,7 @@ static int check_params(const lmo_params *p)
     if (p->scheme == 1) {
         if (p->coarse <= 0 || p->l1_kx <= 0 || p->l1_ky <= 0 || p->halo < 0) return -1;
         if (p->terms <= 0 || p->terms > 16) return -1;
+        if (p->far_order < 0 || (p->far_order > 0 && p->far_order < p->terms)) return -1;
     } else if (p->scheme != 0) {
         return -1;
     }
@@ -269,9 +350,7 @@ int lmo_coeffs(const lmo_params *p, const double *lx, const double *ly, const do
     lmo_lenses L = {lx, ly, lm, n};
     unsigned char *near = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
     near_mask(p, &L, ci, cj, near);
-    double zx, zy;
-    cell_centre(p, ci, cj, &zx, &zy);
-    far_coeffs(p, &L, near, zx, zy, a);
+    cell_coeffs(p, &L, near, ci, cj, a);
     free(near);
     return 0;
 }
@@ -313,7 +392,7 @@ int lmo_deflect(const lmo_params *p, const double *lx, const double *ly, const d
                 double zx, zy, nx, ny, fx, fy;
                 near_mask(p, &L, ci, cj, near);
                 cell_centre(p, ci, cj, &zx, &zy);
-                far_coeffs(p, &L, near, zx, zy, a);
+                cell_coeffs(p, &L, near, ci, cj, a);
                 int64_t nn = near_list(near, n, idx);
                 direct_sum(&L, idx, nn, tx, ty, &nx, &ny);
                 far_eval(P, a, tx - zx, ty - zy, &fx, &fy);
@@ -446,7 +525,7 @@ int lmo_shoot_window(const lmo_params *p, const double *lx, const double *ly, co
                     double zx, zy;
                     near_mask(p, &L, ci, cj, near);
                     cell_centre(p, ci, cj, &zx, &zy);
-                    far_coeffs(p, &L, near, zx, zy, a);
+                    cell_coeffs(p, &L, near, ci, cj, a);
                     int64_t nn = near_list(near, n, idx);
                     int64_t ia = ci * R > i0 ? ci * R : i0;
                     int64_t ib = (ci + 1) * R < i0 + ni ? (ci + 1) * R : i0 + ni;

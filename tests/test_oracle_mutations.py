@@ -28,6 +28,14 @@ MUTATIONS = {
     "fold_missing_two": ("*by = 2.0 * (1.0 - p->kappa) * ty", "*by = (1.0 - p->kappa) * ty"),
     "fold_sheet_dropped": ("+ p->kappa_star * tx - ax;\n        *by = 2.0",
                            "- ax;\n        *by = 2.0"),
+    "hier_binomial_dropped": ("binom = binom * (double)(n + 1) / (double)(n + 1 - q);",
+                              "binom = 1.0;"),
+    "hier_shift_reversed": ("double sx = zx - Zx, sy = zy - Zy;",
+                            "double sx = Zx - zx, sy = Zy - zy;"),
+    "hier_level1_centre_offset": ("double Zx = p->ray_x0 + ((double)I + 0.5)",
+                                  "double Zx = p->ray_x0 + ((double)I + 0.0)"),
+    "hier_series_truncated_early": ("for (int64_t n = q; n < Q; ++n) {",
+                                    "for (int64_t n = q; n < Q - 1; ++n) {"),
 }
 
 
@@ -47,6 +55,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     assert before in src
     (d / "oracle" / "lensoracle.c").write_text(src.replace(before, after))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py", "tests/test_oracle_fold.py"], cwd=d,
+                        "tests/test_oracle_pins.py", "tests/test_oracle_fold.py",
+                        "tests/test_oracle_hier.py"], cwd=d,
                        capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "planted mistake %r was not caught:\n%s" % (name, r.stdout[-2000:])
