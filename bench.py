@@ -206,7 +206,7 @@ def main():
                     help="fraction of the batched 80-map study's rays for its side measurement "
                          "(0 skips it)")
     ap.add_argument("--no-tune", action="store_true",
-                    help="keep the default execution parameters (8 rays per lane, tile scale 1, "
+                    help="keep the default execution parameters (16 rays per lane, tile scale 1, "
                          "all workgroups that fit), which the tuner picks on MI355X")
     ap.add_argument("--no-comparison", action="store_true",
                     help="skip the per-map comparison runs (profiling)")
@@ -278,6 +278,8 @@ def main():
     avg_shoot_s = float(np.mean(shoot_ms)) / 1e3
     achieved = flops / avg_shoot_s / 1e12
     traffic = load_traffic(g.n_rays)
+    issue = lm.lm_measure_issue_rates()
+    pair_bound = issue["pair2_pairs"] / (stats.near_pairs / stats.rays)
     log("value %.4g rays/s; shoot kernel %.2f s -> %.1f TFLOP/s" % (value, avg_shoot_s, achieved))
 
     # plain per-map FP32 path and the mixed per-map path on the same band
@@ -325,7 +327,10 @@ def main():
                      "traffic": traffic, "kernel": "k_shoot_batch",
                      "flops_per_launch": flops, "avg_launch_s": avg_shoot_s,
                      "flop_per_ray": flops / stats.rays,
-                     "near_pairs_per_ray": stats.near_pairs / stats.rays},
+                     "near_pairs_per_ray": stats.near_pairs / stats.rays,
+                     "issue_rates": issue,
+                     "pair_issue_bound_rays_per_s": pair_bound,
+                     "frac_of_pair_issue_bound": g.n_rays / avg_shoot_s / pair_bound},
         "coefficients_ms": float(np.mean(coeff_ms)),
         "comparison": per_map,
     }

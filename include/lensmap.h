@@ -86,7 +86,11 @@ typedef struct lm_geometry {
     int32_t l1_kx, l1_ky;  /* level-2 cells per level-1 cell side */
     int32_t near_halo;     /* H */
     int32_t taylor_terms;  /* P, 1..LM_MAX_TERMS (interpolated scheme) */
-    int32_t reserved;
+    int32_t far_order;     /* 0: each level-2 cell's coefficients summed over its far
+                              lenses (Sec. 3.2.2); Q in [P, 64]: from one Q-term series
+                              of the same far lenses per level-1 cell, re-expanded about
+                              each level-2 centre (hierarchical far field; not with
+                              LM_PREC_FP32) */
 } lm_geometry;
 
 /*
@@ -105,7 +109,7 @@ typedef struct lm_geometry {
  *  - coarse = R given (> 0), or 64 * max(1, round(min(L1x/L3x, L1y/L3y)/20/64))
  *    (level-2 = level-1/20, Sec. 3.2.2);
  *    l1_kx = max(1, round(L1x / (R L3x))), l1_ky likewise;
- *  - near_halo = 1, taylor_terms = 4, precision = LM_PREC_MIXED.
+ *  - near_halo = 1, taylor_terms = 4, precision = LM_PREC_MIXED, far_order = 0.
  * Rounding is half away from zero.  Returns LM_EINVAL for non-finite or
  * non-positive inputs or a singular macro map.
  */
@@ -129,6 +133,16 @@ lm_status lm_geometry_derive_fold(lm_geometry* g, double src_lx, double src_ly, 
                                   int32_t src_ny, double kappa0, double d_x, double kappa_star,
                                   double margin, double n_rays, int32_t scheme, int32_t coarse,
                                   double mean_mass);
+
+/*
+ * Opt a geometry into the hierarchical far field: set g->far_order to the
+ * smallest Q in [taylor_terms, 64] for which the level-1 series meets its
+ * truncation bound on this geometry (rho^Q / (1 - rho) <= 1e-9, rho the
+ * largest ratio of a level-2 centre's and a far lens's distances from their
+ * level-1 centre).  LM_EUNSUPPORTED, far_order left at 0, when no Q does
+ * (level-1 cells too elongated) or for the direct scheme or LM_PREC_FP32.
+ */
+lm_status lm_geometry_far_order(lm_geometry* g);
 
 typedef struct lm_map lm_map;
 typedef struct lm_batch lm_batch;
@@ -204,6 +218,13 @@ lm_status lm_read_mu(lm_map* m, double* host_mu);
 
 /* Zero the counts, n_out and the number of rays shot. Asynchronous on `stream`. */
 lm_status lm_reset_counts(lm_map* m, void* stream);
+
+/* Far-field coefficients a_0..a_{P-1} of level-2 cell (ci, cj) as the shooting
+ * kernel reads them (Sec. 3.2.2): a[2n] = Re a_n, a[2n+1] = Im a_n, a_0 in FP64,
+ * a_1.. stored in FP32 and widened.  Computes the coefficients first if the
+ * lenses or the macro model changed.  Synchronous.  LM_ERANGE outside the
+ * lattice's level-2 cells; LM_EUNSUPPORTED for the direct scheme. */
+lm_status lm_read_coeffs(lm_map* m, int64_t ci, int64_t cj, double* a);
 
 /* Deflection alpha(theta) of the map's scheme and precision at n positions
  * theta_xy[2t], theta_xy[2t+1] (FP64, host), written to alpha_xy (host).  Uses
@@ -302,6 +323,14 @@ void lm_batch_destroy(lm_batch* b);
  * the rate of the near-lens pair instruction mix in 1e9 ray-lens pairs/s.
  * Either pointer may be NULL.  Synchronous; takes well under a second. */
 lm_status lm_measure_valu_peak(double* fma_tflops, double* pair_gpairs);
+/* Issue rates of single instruction kinds on the current device, in lane
+ * instructions per second: rates[0] v_mul_f32 (two-source VOP2), rates[1]
+ * v_fmac_f32 (VOP2), rates[2] v_fma_f32 with a scalar operand (VOP3), rates[3]
+ * v_rcp_f32; rates[4] the shooting kernel's near-pair pattern (two columns
+ * sharing one reciprocal) in pairs per second.  The first min(n, 5) entries
+ * are written.  Synchronous, well under a second.  LM_EINVAL for rates NULL
+ * or n < 0. */
+lm_status lm_measure_issue_rates(double* rates, int32_t n);
 
 /* Description of the last failure on this thread ("" if none). */
 const char* lm_last_error(void);

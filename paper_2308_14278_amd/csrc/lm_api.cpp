@@ -88,6 +88,17 @@ struct DevBuf {
     T* as() const { return static_cast<T*>(p); }
 };
 
+// Largest ratio |z_c - Z| / |z_k - Z| of the hierarchical far field: level-2
+// centres lie within ((Kx-1)/2 L2x, (Ky-1)/2 L2y) of their level-1 centre Z,
+// far lenses at least (H + 1/2) min(L1x, L1y) from it.
+double far_ratio(const lm_geometry& g)
+{
+    const double l2x = (double)g.coarse * g.ray_dx, l2y = (double)g.coarse * g.ray_dy;
+    const double wx = 0.5 * (g.l1_kx - 1) * l2x, wy = 0.5 * (g.l1_ky - 1) * l2y;
+    const double umin = (g.near_halo + 0.5) * std::min(g.l1_kx * l2x, g.l1_ky * l2y);
+    return std::sqrt(wx * wx + wy * wy) / umin;
+}
+
 lm_status validate_geometry(const lm_geometry* g)
 {
     if (!g) return fail(LM_EINVAL, "geometry is NULL");
@@ -110,6 +121,23 @@ lm_status validate_geometry(const lm_geometry* g)
         return fail(LM_EINVAL, "unknown precision %d", g->precision);
     if (g->precision == LM_PREC_MIXED_FP64 && g->scheme != LM_SCHEME_INTERP)
         return fail(LM_EUNSUPPORTED, "LM_PREC_MIXED_FP64 is built for the interpolated scheme only");
+    if (g->far_order != 0) {
+        if (g->scheme != LM_SCHEME_INTERP)
+            return fail(LM_EINVAL, "far_order needs the interpolated scheme");
+        if (g->precision == LM_PREC_FP32)
+            return fail(LM_EUNSUPPORTED, "far_order is built for the FP64-coefficient precisions");
+        if (g->far_order < g->taylor_terms || g->far_order > 64)
+            return fail(LM_EINVAL, "far_order must be 0 or in [taylor_terms, 64], got %d",
+                        g->far_order);
+        // truncation: |z_c - Z| / |z_k - Z| <= rho for every level-2 centre z_c
+        // of a level-1 cell and every far lens z_k; the series must reach
+        // rho^Q / (1 - rho) <= 1e-9
+        const double rho = far_ratio(*g);
+        if (!(rho < 1.0) || std::pow(rho, g->far_order) / (1.0 - rho) > 1e-9)
+            return fail(LM_EINVAL,
+                        "far_order %d is too small for this geometry (convergence ratio %.3f)",
+                        g->far_order, rho);
+    }
     if (g->coarse <= 0 || g->coarse % 64 != 0 || g->coarse > (1 << 15))
         return fail(LM_EINVAL, "coarse must be a positive multiple of 64 (at most 32768), got %d",
                     g->coarse);
@@ -140,7 +168,7 @@ struct lm_map {
     int64_t ncx = 0, ncy = 0, n1x = 0, n1y = 0;
     int nl1x = 0, nl1y = 0;
     // device buffers
-    DevBuf lx, ly, lmd, lxf, lyf, lmf, lI, lJ, cell_start, coef, counts_own, n_out, ptab;
+    DevBuf lx, ly, lmd, lxf, lyf, lmf, lI, lJ, cell_start, coef, counts_own, n_out, ptab, l1exp;
     std::vector<int32_t> h_start;  // host copy of the level-1 CSR
     uint64_t* counts = nullptr;  // own or bound
     bool bound = false;
@@ -148,7 +176,7 @@ struct lm_map {
     bool has_counts = false;
     uint64_t n_shot = 0;
     hipStream_t last = nullptr;
-    int rays_per_lane = 8;
+    int rays_per_lane = 16;
 };
 
 namespace {
@@ -195,14 +223,16 @@ Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scal
     // deflection across the tile
     const double ext_x = (double)G * R * g.ray_dx * mx / g.src_dx + 2.0 * std::max(8.0, 0.1 / g.src_dx);
     const double ext_y = (double)G * R * g.ray_dy * my / g.src_dy + 2.0 * std::max(8.0, 0.1 / g.src_dy);
-    int wx = 8, wy = 8;
-    while (wx < ext_x && wx < LM_WIN_MAX / 8) wx *= 2;
-    while (wy < ext_y && wy < LM_WIN_MAX / 8) wy *= 2;
+    // use the whole LDS window in the extents' aspect ratio (sides multiples
+    // of 8): more rays counted in LDS, fewer global atomics
+    const double fill = std::sqrt((double)LM_WIN_MAX / (ext_x * ext_y));
+    int wx = std::max(8, std::min(LM_WIN_MAX / 8, (int)(ext_x * fill) / 8 * 8));
+    int wy = std::max(8, std::min(LM_WIN_MAX / 8, (int)(ext_y * fill) / 8 * 8));
     while (wx * wy > LM_WIN_MAX) {
-        if (wx / ext_x > wy / ext_y)
-            wx /= 2;
+        if (wy <= 8 || (wx > 8 && wx / ext_x > wy / ext_y))
+            wx -= 8;
         else
-            wy /= 2;
+            wy -= 8;
     }
     e.wx = wx;
     e.wy = wy;
@@ -293,6 +323,10 @@ LmDesc make_desc(const lm_map* m, int64_t i0, int64_t j0, int64_t i1, int64_t j1
     d.cell_start = m->cell_start.as<int32_t>();
     d.coef = m->coef.as<LmCoef>();
     d.ptab = m->ptab.as<float>();
+    d.Q = g.scheme == LM_SCHEME_INTERP ? g.far_order : 0;
+    d.n1x = m->n1x;
+    d.n1y = m->n1y;
+    d.l1exp = m->l1exp.as<double>();
     d.counts = reinterpret_cast<unsigned long long*>(m->counts);
     d.n_out = m->n_out.as<unsigned long long>();
     return d;
@@ -304,7 +338,19 @@ lm_status ensure_coef(lm_map* m)
     if (m->coef.ensure((size_t)(m->ncx * m->ncy) * sizeof(LmCoef)) != hipSuccess)
         return fail(LM_ENOMEM, "cannot allocate %lld level-2 coefficient records",
                     (long long)(m->ncx * m->ncy));
+    if (m->g.far_order > 0 &&
+        m->l1exp.ensure((size_t)(m->n1x * m->n1y) * m->g.far_order * 16) != hipSuccess)
+        return fail(LM_ENOMEM, "cannot allocate the level-1 series");
     return LM_OK;
+}
+
+// Coefficients of every level-2 cell of a map (direct, or hierarchical).
+int launch_coefficients(const lm_map* m, const LmDesc& d, hipStream_t s)
+{
+    if (m->g.far_order > 0)
+        return lm_launch_coeffs_hier(d, m->g.taylor_terms, m->coef.as<LmCoef>(), s);
+    return lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
+                            m->coef.as<LmCoef>(), s);
 }
 
 lm_status prepare(lm_map* m, hipStream_t s)
@@ -315,8 +361,7 @@ lm_status prepare(lm_map* m, hipStream_t s)
     lm_status st = ensure_coef(m);
     if (st) return st;
     LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
-    LAUNCH_TRY(lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
-                                m->coef.as<LmCoef>(), s));
+    LAUNCH_TRY(launch_coefficients(m, d, s));
     m->coef_valid = true;
     m->last = s;
     return LM_OK;
@@ -452,6 +497,23 @@ lm_status lm_geometry_derive_fold(lm_geometry* g, double src_lx, double src_ly, 
     if (R > (1 << 15)) return fail(LM_EINVAL, "level-2 cells of %lld rays are too large", (long long)R);
     g->coarse = (int32_t)R;
     return ok();
+}
+
+lm_status lm_geometry_far_order(lm_geometry* g)
+{
+    if (!g) return fail(LM_EINVAL, "g is NULL");
+    g->far_order = 0;
+    if (g->scheme != LM_SCHEME_INTERP || g->precision == LM_PREC_FP32)
+        return fail(LM_EUNSUPPORTED, "the hierarchical far field needs the interpolated scheme "
+                                     "and FP64 coefficients");
+    const double rho = far_ratio(*g);
+    if (!(rho < 1.0)) return fail(LM_EUNSUPPORTED, "level-1 cells too elongated (ratio %.3f)", rho);
+    for (int q = std::max(1, g->taylor_terms); q <= 64; ++q)
+        if (std::pow(rho, q) / (1.0 - rho) <= 1e-9) {
+            g->far_order = q;
+            return ok();
+        }
+    return fail(LM_EUNSUPPORTED, "no series order up to 64 converges (ratio %.3f)", rho);
 }
 
 lm_status lm_create(const lm_geometry* g, lm_map** out)
@@ -752,6 +814,34 @@ lm_status lm_reset_counts(lm_map* m, void* stream)
     return ok();
 }
 
+lm_status lm_read_coeffs(lm_map* m, int64_t ci, int64_t cj, double* a)
+{
+    if (!m || !a) return fail(LM_EINVAL, "map or output is NULL");
+    if (m->g.scheme != LM_SCHEME_INTERP)
+        return fail(LM_EUNSUPPORTED, "the direct scheme has no far-field coefficients");
+    if (ci < 0 || cj < 0 || ci >= m->ncx || cj >= m->ncy)
+        return fail(LM_ERANGE, "level-2 cell (%lld, %lld) outside the lattice", (long long)ci,
+                    (long long)cj);
+    lm_status st = use_device(m);
+    if (st) return st;
+    if (!m->coef_valid) {
+        st = prepare(m, nullptr);
+        if (st) return st;
+    }
+    if (m->last) HIP_TRY(hipStreamSynchronize(m->last));
+    HIP_TRY(hipDeviceSynchronize());
+    LmCoef c;
+    HIP_TRY(hipMemcpy(&c, m->coef.as<LmCoef>() + (cj * m->ncx + ci), sizeof c,
+                      hipMemcpyDeviceToHost));
+    a[0] = c.a0r;
+    a[1] = c.a0i;
+    for (int n = 1; n < m->g.taylor_terms; ++n) {
+        a[2 * n] = (double)c.a[2 * (n - 1)];
+        a[2 * n + 1] = (double)c.a[2 * (n - 1) + 1];
+    }
+    return ok();
+}
+
 lm_status lm_deflect(lm_map* m, const double* theta_xy, int64_t n, double* alpha_xy)
 {
     if (!m) return fail(LM_EINVAL, "map is NULL");
@@ -931,7 +1021,7 @@ struct lm_batch {
     std::vector<lm_map*> maps;
     std::vector<int64_t> rect;  // 4 per map: i0, j0, ni, nj
     int scheme = 0, precision = 0, terms = 4, device = 0;
-    int rays_per_lane = 8, g_scale = 1, wg_per_cu = 0;
+    int rays_per_lane = 16, g_scale = 1, wg_per_cu = 0;
     DevBuf descs, offs, order, queue;
     int64_t total = 0;
     int grid = 0;
@@ -1016,8 +1106,7 @@ lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs, bool pre =
             lm_map* m = b->maps[k];
             if (m->g.scheme != LM_SCHEME_INTERP) continue;
             LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
-            LAUNCH_TRY(lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
-                                        m->coef.as<LmCoef>(), s));
+            LAUNCH_TRY(launch_coefficients(m, d, s));
         }
     if (pre) LAUNCH_TRY(lm_launch_fill_u64(b->queue.as<unsigned long long>(), 1, 0ull, s));
     if (shoot && b->total > 0)

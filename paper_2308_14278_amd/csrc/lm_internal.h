@@ -34,7 +34,7 @@ struct LmDesc {
     float inv_sdxf, inv_sdyf;
     int32_t snx, sny;
     int32_t fold;                  // 1: fold macro model
-    int32_t pad_;
+    int32_t Q;                     // terms of the level-1 series (0: direct coefficients)
     // scheme and work decomposition
     int32_t R, Kx, Ky, H;
     int32_t G;                     // level-2 cells per workgroup-tile side
@@ -43,6 +43,7 @@ struct LmDesc {
     int32_t nrb;                   // 64-row blocks per level-2 cell (R / 64)
     int32_t wx, wy;                // LDS window (pixels)
     int32_t nl1x, nl1y;            // padded level-1 grid (N1 + 2H per side)
+    int64_t n1x, n1y;              // level-1 cells holding level-2 cells of the lattice
     int64_t nx, ny;                // lattice
     int64_t i0, j0, i1, j1;        // shot rectangle [i0,i1) x [j0,j1)
     int64_t ncx, ncy;              // level-2 cells of the lattice
@@ -62,6 +63,7 @@ struct LmDesc {
     const int32_t* cell_start;     // CSR over the padded level-1 grid
     const LmCoef* coef;            // [ncy][ncx]
     const float* ptab;             // [R + LM_PTAB_PAD] column offsets of a level-2 cell
+    double* l1exp;                 // [n1y][n1x][Q] level-1 series, complex (re, im)
     unsigned long long* counts;    // [sny][snx]
     unsigned long long* n_out;
 };
@@ -70,6 +72,9 @@ struct LmDesc {
 int lm_launch_ptab(const LmDesc& d, float* out, int n, void* stream);
 int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int64_t cj0,
                      int64_t nci, int64_t ncj, LmCoef* out, void* stream);
+// Hierarchical far field: level-1 series (d.Q terms) into d.l1exp, then the
+// coefficients of every level-2 cell.
+int lm_launch_coeffs_hier(const LmDesc& d, int terms, LmCoef* out, void* stream);
 int lm_launch_shoot_map(const LmDesc& d, int scheme, int precision, int terms, int rays_per_lane,
                         void* stream);
 int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int32_t* order,

@@ -10,6 +10,8 @@
 //                 count (Sec. 3.2.3) through a per-lane run, a wave merge and
 //                 an LDS window flushed to the uint64 map.  The batch kernel is
 //                 persistent and pulls tiles of many maps from a queue.
+//  k_l1_expand    hierarchical far field (optional): series per level-1 cell,
+//  k_l1_shift     re-expanded about every level-2 centre.
 //  k_trace        per-ray pixels with the same arithmetic (test probe).
 //  k_deflect      deflection at arbitrary positions (test probe).
 //
@@ -994,6 +996,116 @@ __global__ void k_ptab(LmDesc d, float* __restrict__ out, int n)
     if (l < n) out[l] = local_offset(l, 0, d.R, d.hxh, d.hxl);
 }
 
+// Hierarchical far field, step 1: the series of the far lenses of level-1 cell
+// (I, J) about its centre Z, A_n = -sum_far m_k / (z_k - Z)^(n+1), n < Q <= 64
+// (the level-2 series of Sec. 3.2.2 taken one level up).  One workgroup per
+// level-1 cell; thread t sums terms 8 s .. 8 s + 7 (s = t mod 8) over every
+// 32nd far lens, then threads n < Q add the 32 partial sums in a fixed order.
+__global__ __launch_bounds__(kWG) void k_l1_expand(LmDesc d)
+{
+    __shared__ double2 part[32][64];
+    const int tid = threadIdx.x, s = tid & 7, grp = tid >> 3;
+    const int64_t cell = blockIdx.x;
+    const int64_t I = cell % d.n1x, J = cell / d.n1x;
+    const double Zx = d.x0 + ((double)I + 0.5) * (double)((int64_t)d.Kx * d.R) * d.dx;
+    const double Zy = d.y0 + ((double)J + 0.5) * (double)((int64_t)d.Ky * d.R) * d.dy;
+    double ar[8], ai[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        ar[j] = 0.0;
+        ai[j] = 0.0;
+    }
+    if (8 * s < d.Q) {
+        for (int64_t k = grp; k < d.nlens; k += 32) {
+            if (abs(d.lI[k] - (int)I) <= d.H && abs(d.lJ[k] - (int)J) <= d.H) continue;
+            const double wx = d.lx[k] - Zx, wy = d.ly[k] - Zy;
+            const double w2 = wx * wx + wy * wy;
+            const double ux = wx / w2, uy = -wy / w2;  // 1 / (z_k - Z)
+            // t = m u^(8 s + 1)
+            double px = ux, py = uy;  // u^8 by three squarings
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const double nx = px * px - py * py, ny = 2.0 * px * py;
+                px = nx;
+                py = ny;
+            }
+            double tx = d.lmd[k] * ux, ty = d.lmd[k] * uy;
+            for (int q = 0; q < s; ++q) {
+                const double nx = tx * px - ty * py, ny = tx * py + ty * px;
+                tx = nx;
+                ty = ny;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                ar[j] -= tx;
+                ai[j] -= ty;
+                const double nx = tx * ux - ty * uy, ny = tx * uy + ty * ux;
+                tx = nx;
+                ty = ny;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) part[grp][8 * s + j] = make_double2(ar[j], ai[j]);
+    __syncthreads();
+    if (tid < d.Q) {
+        double sr = 0.0, si = 0.0;
+        for (int g = 0; g < 32; ++g) {
+            sr += part[g][tid].x;
+            si += part[g][tid].y;
+        }
+        d.l1exp[2 * (cell * d.Q + tid)] = sr;
+        d.l1exp[2 * (cell * d.Q + tid) + 1] = si;
+    }
+}
+
+// Hierarchical far field, step 2: the series of step 1 re-expanded about the
+// centre z_c of each level-2 cell, a_p = sum_{n>=p} C(n,p) A_n (z_c - Z)^(n-p),
+// with T_n[p] = C(n,p) w^(n-p) advanced by T_{n+1}[p] = w T_n[p] + T_n[p-1].
+template <int P>
+__global__ __launch_bounds__(kWG) void k_l1_shift(LmDesc d, LmCoef* __restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (c >= d.ncx * d.ncy) return;
+    const int64_t ci = c % d.ncx, cj = c / d.ncx;
+    const int64_t I = ci / d.Kx, J = cj / d.Ky;
+    const double Zx = d.x0 + ((double)I + 0.5) * (double)((int64_t)d.Kx * d.R) * d.dx;
+    const double Zy = d.y0 + ((double)J + 0.5) * (double)((int64_t)d.Ky * d.R) * d.dy;
+    const double wx = cell_cx(d, ci) - Zx, wy = cell_cy(d, cj) - Zy;
+    double tr[P], ti[P], ar[P], ai[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        tr[p] = p == 0 ? 1.0 : 0.0;
+        ti[p] = 0.0;
+        ar[p] = 0.0;
+        ai[p] = 0.0;
+    }
+    const double* A = d.l1exp + 2 * ((J * d.n1x + I) * d.Q);
+    for (int n = 0; n < d.Q; ++n) {
+        const double Ar = A[2 * n], Ai = A[2 * n + 1];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            ar[p] += Ar * tr[p] - Ai * ti[p];
+            ai[p] += Ar * ti[p] + Ai * tr[p];
+        }
+#pragma unroll
+        for (int p = P - 1; p >= 0; --p) {
+            const double nr = tr[p] * wx - ti[p] * wy + (p > 0 ? tr[p > 0 ? p - 1 : 0] : 0.0);
+            const double ni = tr[p] * wy + ti[p] * wx + (p > 0 ? ti[p > 0 ? p - 1 : 0] : 0.0);
+            tr[p] = nr;
+            ti[p] = ni;
+        }
+    }
+    LmCoef& o = out[cj * d.ncx + ci];
+    o.a0r = ar[0];
+    o.a0i = ai[0];
+#pragma unroll
+    for (int n = 1; n < 7; ++n) {
+        o.a[2 * (n - 1)] = n < P ? (float)ar[n < P ? n : 0] : 0.f;
+        o.a[2 * (n - 1) + 1] = n < P ? (float)ai[n < P ? n : 0] : 0.f;
+    }
+}
+
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1272,6 +1384,29 @@ int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int
 int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu)
 {
     return dispatch(scheme, precision, rays_per_lane, terms, Occupancy{wg_per_cu});
+}
+
+int lm_launch_coeffs_hier(const LmDesc& d, int terms, LmCoef* out, void* stream)
+{
+    const int64_t n1 = d.n1x * d.n1y, n2 = d.ncx * d.ncy;
+    if (n1 <= 0 || n2 <= 0) return 0;
+    if (d.Q < terms || d.Q > 64) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_l1_expand, dim3((unsigned)n1), dim3(kWG), 0, s, d);
+    const int e = (int)hipGetLastError();
+    if (e) return e;
+    const dim3 grid((unsigned)((n2 + kWG - 1) / kWG));
+    switch (terms) {
+    case 1: hipLaunchKernelGGL(k_l1_shift<1>, grid, dim3(kWG), 0, s, d, out); break;
+    case 2: hipLaunchKernelGGL(k_l1_shift<2>, grid, dim3(kWG), 0, s, d, out); break;
+    case 3: hipLaunchKernelGGL(k_l1_shift<3>, grid, dim3(kWG), 0, s, d, out); break;
+    case 4: hipLaunchKernelGGL(k_l1_shift<4>, grid, dim3(kWG), 0, s, d, out); break;
+    case 5: hipLaunchKernelGGL(k_l1_shift<5>, grid, dim3(kWG), 0, s, d, out); break;
+    case 6: hipLaunchKernelGGL(k_l1_shift<6>, grid, dim3(kWG), 0, s, d, out); break;
+    case 7: hipLaunchKernelGGL(k_l1_shift<7>, grid, dim3(kWG), 0, s, d, out); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
 }
 
 int lm_launch_ptab(const LmDesc& d, float* out, int n, void* stream)

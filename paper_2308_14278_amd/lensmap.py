@@ -54,11 +54,11 @@ class lm_geometry(ctypes.Structure):
         ("scheme", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("coarse", ctypes.c_int32), ("l1_kx", ctypes.c_int32), ("l1_ky", ctypes.c_int32),
         ("near_halo", ctypes.c_int32), ("taylor_terms", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("far_order", ctypes.c_int32),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
     @property
     def n_rays(self):
@@ -118,6 +118,9 @@ _SIGS = {
                       _P(lm_stats)],
     "lm_batch_timing": [_vp, _P(ctypes.c_float), _P(ctypes.c_float)],
     "lm_measure_valu_peak": [_d, _d],
+    "lm_read_coeffs": [_vp, ctypes.c_int64, ctypes.c_int64, _d],
+    "lm_geometry_far_order": [_P(lm_geometry)],
+    "lm_measure_issue_rates": [_d, ctypes.c_int32],
     "lm_find_peaks": [_vp, _i32, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_uint8)],
     "lm_fold_scales": [ctypes.c_double] * 7 + [_P(lm_fold_scales_t)],
 }
@@ -374,6 +377,35 @@ def lm_batch_timing(b):
     a, c = ctypes.c_float(), ctypes.c_float()
     _check(load().lm_batch_timing(b, ctypes.byref(a), ctypes.byref(c)), "lm_batch_timing")
     return float(a.value), float(c.value)
+
+
+def lm_geometry_far_order(g):
+    """Opt g into the hierarchical far field (smallest adequate series order);
+    returns the order, or 0 (g unchanged apart from far_order = 0) when the
+    geometry does not allow it."""
+    rc = load().lm_geometry_far_order(ctypes.byref(g))
+    if rc == LM_EUNSUPPORTED:
+        return 0
+    _check(rc, "lm_geometry_far_order")
+    return int(g.far_order)
+
+
+def lm_read_coeffs(m, ci, cj, terms):
+    """Complex far-field coefficients a_0..a_{terms-1} of level-2 cell (ci, cj)."""
+    import numpy as np
+    a = np.zeros(2 * terms, dtype=np.float64)
+    _check(load().lm_read_coeffs(m, int(ci), int(cj), a.ctypes.data_as(_d)), "lm_read_coeffs")
+    return a[0::2] + 1j * a[1::2]
+
+
+def lm_measure_issue_rates():
+    """Measured issue rates on the current device: dict of lane instructions/s
+    for VOP2 mul, VOP2 fmac, VOP3 fma (scalar operand), rcp, and near pairs/s
+    of the shooting kernel's shared-reciprocal pattern."""
+    r = (ctypes.c_double * 5)()
+    _check(load().lm_measure_issue_rates(r, 5), "lm_measure_issue_rates")
+    return {"v_mul_f32": r[0], "v_fmac_f32": r[1], "v_fma_f32_sgpr": r[2], "v_rcp_f32": r[3],
+            "pair2_pairs": r[4]}
 
 
 def lm_measure_valu_peak():

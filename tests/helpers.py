@@ -10,7 +10,7 @@ _FIELDS = ("src_x0", "src_y0", "src_dx", "src_dy", "src_nx", "src_ny", "ray_x0",
 def oracle_geom(g):
     """OracleGeometry with the same numbers as a library lm_geometry."""
     return OracleGeometry(**{k: getattr(g, k) for k in _FIELDS}, halo=g.near_halo,
-                          terms=g.taylor_terms)
+                          terms=g.taylor_terms, far_order=g.far_order)
 
 
 def mismatch_fraction(a, b, rays):

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import paper_2308_14278_amd.lensmap as lm
+from paper_2308_14278_amd import inputs
 from oracle.geometry import derive_geometry
 
 
@@ -99,11 +100,52 @@ def test_fp64_near_mode_needs_the_interpolated_scheme():
     assert e.value.status == lm.LM_EUNSUPPORTED
 
 
+def test_far_order_validation():
+    g = lm.lm_geometry_derive(20, 20, 200, 200, 0.45, 0.5, 0.01, n_rays=1e9, scheme=1)
+    assert g.far_order == 0
+    for q, status in ((3, lm.LM_EINVAL), (65, lm.LM_EINVAL), (8, lm.LM_EINVAL)):
+        g.far_order = q  # below P, above 64, and elongated level-1 cells (no convergence)
+        with pytest.raises(lm.LensmapError) as e:
+            lm.lm_create(g)
+        assert e.value.status == status
+    g.far_order = 48
+    g.precision = lm.LM_PREC_FP32
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_create(g)
+    assert e.value.status == lm.LM_EUNSUPPORTED
+    g2 = lm.lm_geometry_derive(10, 10, 64, 64, 0.45, 0.5, 0.01, n_rays=1e6, scheme=0, coarse=64)
+    g2.far_order = 32
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_create(g2)
+    assert e.value.status == lm.LM_EINVAL
+
+
+def test_far_order_choice():
+    """The chosen order is the smallest meeting rho^Q / (1 - rho) <= 1e-9, with
+    rho recomputed here from the geometry."""
+    import math
+    w = inputs.paper_scale()
+    g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                              w.gamma, w.kappa_star, n_rays=w.n_rays, scheme=1,
+                              mean_mass=w.mean_mass)
+    q = lm.lm_geometry_far_order(g)
+    l2x, l2y = g.coarse * g.ray_dx, g.coarse * g.ray_dy
+    rho = math.hypot(0.5 * (g.l1_kx - 1) * l2x, 0.5 * (g.l1_ky - 1) * l2y) / (
+        (g.near_halo + 0.5) * min(g.l1_kx * l2x, g.l1_ky * l2y))
+    assert 0.4 < rho < 0.5 and q == g.far_order
+    assert rho ** q / (1 - rho) <= 1e-9 < rho ** (q - 1) / (1 - rho)
+    # elongated level-1 cells: no order converges
+    g2 = lm.lm_geometry_derive(20, 20, 200, 200, 0.45, 0.5, 0.01, n_rays=1e9, scheme=1)
+    assert lm.lm_geometry_far_order(g2) == 0 and g2.far_order == 0
+
+
 def test_null_handles_are_rejected(lib):
     assert lib.lm_shoot(None, 0, 0, 1, 1, None) == lm.LM_EINVAL
     assert lib.lm_set_macro(None, 0.0, 0.0, 0.0) == lm.LM_EINVAL
     assert lib.lm_read_counts(None, None, None, None) == lm.LM_EINVAL
     assert lib.lm_batch_shoot(None, None) == lm.LM_EINVAL
+    assert lib.lm_batch_set_params(None, 8, 1, 0) == lm.LM_EINVAL
+    assert lib.lm_read_coeffs(None, 0, 0, None) == lm.LM_EINVAL
     lib.lm_destroy(None)
     lib.lm_batch_destroy(None)
 

@@ -1,0 +1,139 @@
+"""GPU parity of the far-field coefficients, direct (Sec. 3.2.2) and
+hierarchical (a series per level-1 cell re-expanded about each level-2 centre),
+against the FP64 oracle; maps shot with the hierarchical far field against
+the oracle of the same scheme and against the direct scheme."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2308_14278_amd.lensmap as lm
+from helpers import max_pixel_rel, mismatch_fraction, oracle_geom
+from paper_2308_14278_amd import inputs
+
+pytestmark = pytest.mark.gpu
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    lm.load()
+    oracle.build()
+
+
+def _geom(w, far_order=0, **over):
+    g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                              w.gamma, w.kappa_star, protect=w.protect, n_rays=w.n_rays or 0.0,
+                              ray_nx=w.ray_nx or 0, ray_ny=w.ray_ny or 0, scheme=w.scheme,
+                              coarse=w.coarse, mean_mass=w.mean_mass)
+    g.far_order = far_order
+    for k, v in over.items():
+        setattr(g, k, v)
+    return g
+
+
+def _pair(w, far_order, lenses=None):
+    g = _geom(w, far_order)
+    x, y, m = lenses if lenses is not None else w.lenses()
+    mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, (x, y, m))
+    orc = oracle.Oracle(oracle_geom(g), w.kappa, w.gamma, w.kappa_star, x, y, m)
+    return g, mp, orc
+
+
+@pytest.mark.parametrize("far_order", [0, 40])
+def test_coefficients_vs_oracle(far_order):
+    """a_0 (FP64) to 1e-12 relative, a_1..a_3 (stored in FP32) to FP32 rounding,
+    at cells spread over the paper-scale lattice."""
+    w = inputs.paper_scale()
+    g, mp, orc = _pair(w, far_order)
+    rng = np.random.default_rng(3)
+    ncx, ncy = -(-g.ray_nx // g.coarse), -(-g.ray_ny // g.coarse)
+    cells = [(0, 0), (ncx - 1, ncy - 1), (ncx // 2, ncy // 2)]
+    cells += [(int(rng.integers(ncx)), int(rng.integers(ncy))) for _ in range(12)]
+    worst0 = worst = 0.0
+    for ci, cj in cells:
+        got = lm.lm_read_coeffs(mp.h, ci, cj, g.taylor_terms)
+        ref = orc.coeffs(ci, cj)
+        worst0 = max(worst0, abs(got[0] - ref[0]) / abs(ref[0]))
+        rel = np.abs(got[1:] - ref[1:]) / np.maximum(np.abs(ref[1:]), 1e-30)
+        worst = max(worst, float(rel.max()))
+    print("far_order %d: a_0 rel err %.2e, a_1..3 rel err %.2e" % (far_order, worst0, worst))
+    assert worst0 <= 1e-12
+    assert worst <= 2e-7
+    mp.close()
+
+
+def test_hierarchical_map_vs_oracle():
+    """A 2.2e7-ray region of the paper-scale lattice with the hierarchical far
+    field (Q = 40) against the oracle of the same scheme."""
+    w = inputs.paper_scale()
+    g, mp, orc = _pair(w, 40)
+    ni, nj = 40_000, 550
+    i0, j0 = int(0.4 * g.ray_nx) + 17, g.ray_ny // 2 - 300
+    mp.shoot(i0, j0, ni, nj)
+    counts, n_out, _ = mp.counts()
+    ref, ref_out = orc.shoot(i0, j0, ni, nj, nthreads=NTHREADS)
+    mis = mismatch_fraction(counts, ref, ni * nj)
+    print("hierarchical paper-scale region: mismatch %.2e, worst pixel %.2e" %
+          (mis, max_pixel_rel(counts, ref)))
+    assert int(counts.sum()) + n_out == ni * nj
+    assert mis <= 1e-5
+    assert max_pixel_rel(counts, ref) <= 1e-3
+    mp.close()
+
+
+def test_hierarchical_equals_direct_scheme_closely():
+    """Direct and hierarchical coefficients give the same map up to rays within
+    the series' truncation error of a pixel edge; the hierarchical
+    coefficients cost a small fraction of the direct ones."""
+    w = inputs.paper_scale()
+    x, y, m = w.lenses()
+    gd, md, _ = _pair(w, 0, (x, y, m))
+    gh, mh, _ = _pair(w, 40, (x, y, m))
+    ni, nj = 2_000_000, 2_000
+    i0, j0 = gd.ray_nx // 2 - ni // 2, gd.ray_ny // 2
+    times = {}
+    for name, mp in (("direct", md), ("hierarchical", mh)):
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lm.lm_prepare(mp.h, None)
+        torch.cuda.synchronize()
+        times[name] = time.perf_counter() - t0
+        mp.shoot(i0, j0, ni, nj)
+    cd, od, _ = md.counts()
+    ch, oh, _ = mh.counts()
+    mis = mismatch_fraction(cd, ch, ni * nj)
+    print("direct vs hierarchical: mismatch %.2e; coefficients %.1f ms vs %.1f ms" %
+          (mis, 1e3 * times["direct"], 1e3 * times["hierarchical"]))
+    assert mis <= 1e-6
+    assert times["hierarchical"] < times["direct"]
+    md.close()
+    mh.close()
+
+
+def test_hierarchical_batch_equals_per_map():
+    ws = inputs.batched_study(4, 1e-3)
+    maps, ref = [], []
+    for w in ws:
+        g = _geom(w)
+        assert lm.lm_geometry_far_order(g) > 0
+        mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses())
+        mp.shoot()
+        ref.append(mp.counts())
+        mp.reset()
+        maps.append(mp)
+    b = lm.lm_batch_create([mp.h for mp in maps])
+    lm.lm_batch_shoot(b)
+    for mp, (c, o, s) in zip(maps, ref):
+        c2, o2, s2 = mp.counts()
+        np.testing.assert_array_equal(c, c2)
+        assert (o, s) == (o2, s2)
+    lm.lm_batch_destroy(b)
+    for mp in maps:
+        mp.close()

@@ -283,6 +283,17 @@ def test_batch_equals_per_map_and_tuned_equals_default(tmp_path):
     # the cache is reused
     lm.lm_batch_tune(b, cache)
     assert lm.lm_batch_params(b) == params
+    # every hand-set execution shape gives the same counts
+    for nr, gs, wg in ((4, 2, 0), (16, 1, 2), (8, 3, 1)):
+        for _, _, mp in maps:
+            mp.reset()
+        lm.lm_batch_set_params(b, nr, gs, wg)
+        assert lm.lm_batch_params(b) == (nr, gs, wg)
+        lm.lm_batch_shoot(b)
+        for (w, g, mp), (c, o, s) in zip(maps, ref):
+            c2, o2, s2 = mp.counts()
+            np.testing.assert_array_equal(c, c2)
+            assert (o, s) == (o2, s2)
     lm.lm_batch_destroy(b)
     for _, _, mp in maps:
         mp.close()
@@ -362,4 +373,10 @@ def test_error_paths():
     with pytest.raises(lm.LensmapError) as e:
         mp.trace([g.ray_nx], [0])
     assert e.value.status == lm.LM_ERANGE
+    b = lm.lm_batch_create([mp.h])
+    for bad in ((5, 1, 0), (8, 0, 0), (8, 9, 0), (8, 1, -1), (8, 1, 9)):
+        with pytest.raises(lm.LensmapError) as e:
+            lm.lm_batch_set_params(b, *bad)
+        assert e.value.status == lm.LM_EINVAL
+    lm.lm_batch_destroy(b)
     mp.close()
