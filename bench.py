@@ -128,17 +128,22 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
             "seconds": dt}, errors
 
 
-def batched_study(lm, inputs, torch, scale):
+def batched_study(lm, inputs, torch, scale, hierarchical=False):
     """The 80-map study at a fraction of its rays: one batch (coefficients of
     every map, one persistent shooting kernel over all maps' tiles), then ten
-    light curves per map through the peak finder."""
+    light curves per map through the peak finder.  hierarchical: maps whose
+    level-1 cells allow it take their far-field coefficients from level-1
+    series (lm_geometry_far_order), the others sum them directly."""
     import numpy as np
     ws = inputs.batched_study(80, scale)
     maps, geoms = [], []
+    n_hier = 0
     for w in ws:
         g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
                                   w.gamma, w.kappa_star, n_rays=w.n_rays, scheme=w.scheme,
                                   coarse=w.coarse, mean_mass=w.mean_mass)
+        if hierarchical and lm.lm_geometry_far_order(g) > 0:
+            n_hier += 1
         maps.append(lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses()))
         geoms.append(g)
     rays = sum(g.n_rays for g in geoms)
@@ -169,12 +174,52 @@ def batched_study(lm, inputs, torch, scale):
     lm.lm_batch_destroy(b)
     for m in maps:
         m.close()
-    log("batched study: 80 maps, %.4g rays in %.2f s (%.4g rays/s); 800 light curves: "
-        "%d candidates, %d true peaks in %.2f s" % (rays, dt, rays / dt, n_cand, n_true, dt_peaks))
+    log("batched study%s: 80 maps, %.4g rays in %.2f s (%.4g rays/s, coefficients %.0f ms); "
+        "800 light curves: %d candidates, %d true peaks in %.2f s" %
+        (" (hierarchical far field)" if hierarchical else "", rays, dt, rays / dt, c_ms, n_cand,
+         n_true, dt_peaks))
     return {"maps": 80, "rays": rays, "seconds": dt, "rays_per_s": rays / dt,
             "coefficients_ms": c_ms, "shoot_kernel_ms": s_ms,
             "rays_scale": scale, "light_curves": 800, "candidate_peaks": n_cand,
-            "true_peaks": n_true, "peak_finding_s": dt_peaks}
+            "true_peaks": n_true, "peak_finding_s": dt_peaks,
+            "far_field": ("hierarchical for %d maps, direct for %d" % (n_hier, 80 - n_hier)
+                          if hierarchical else "direct (Sec. 3.2.2) for all maps")}
+
+
+def paper_table1_leg(lm, inputs, torch, precision):
+    """The paper's own map (Table 1, Sec. 4.1): fold model, 13745 unit lenses,
+    2.69e13 rays into a 73877 x 363635 uint64 map (215 GB, resident in HBM).
+    One step as in the headline (reset, coefficients, persistent shoot), then
+    a device-side check that every ray was counted."""
+    w = inputs.paper_table1()
+    k0, dx, dy = w.fold
+    g = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], w.src_pixels, w.extra["src_ny"],
+                                   k0, dx, w.kappa_star, n_rays=w.n_rays)
+    g.precision = precision
+    lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
+    mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold)
+    b = lm.lm_batch_create([mp.h])
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lm.lm_reset_counts(mp.h, stream)
+    lm.lm_batch_shoot(b, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    c_ms, s_ms = lm.lm_batch_timing(b)
+    total = lm.lm_sum_counts(mp.h)
+    _, n_out, n_shot = lm.lm_read_counts(mp.h, g, with_counts=False)
+    assert total + n_out == n_shot == g.n_rays, "ray count not conserved"
+    lm.lm_batch_destroy(b)
+    mp.close()
+    name = "fp64-near" if precision == lm.LM_PREC_MIXED_FP64 else "mixed"
+    log("paper Table 1 map (%s): %d x %d rays (%.4g), R=%d: %.1f s (shoot %.1f s, "
+        "coefficients %.0f ms), %.4g rays/s; %d rays in the map" %
+        (name, g.ray_nx, g.ray_ny, g.n_rays, g.coarse, dt, s_ms / 1e3, c_ms, g.n_rays / dt, total))
+    return {"precision": name, "rays": g.n_rays, "seconds": dt, "rays_per_s": g.n_rays / dt,
+            "shoot_kernel_ms": s_ms, "coefficients_ms": c_ms, "rays_in_map": total,
+            "map_pixels": [g.src_nx, g.src_ny], "coarse": g.coarse,
+            "paper_seconds_context": 7000.0}
 
 
 def copy_calibration():
@@ -210,6 +255,9 @@ def main():
                          "all workgroups that fit), which the tuner picks on MI355X")
     ap.add_argument("--no-comparison", action="store_true",
                     help="skip the per-map comparison runs (profiling)")
+    ap.add_argument("--paper-map", choices=("none", "mixed", "fp64", "both"), default="none",
+                    help="also shoot the paper's own Table 1 map (2.69e13 rays, 215 GB map) once "
+                         "per chosen precision (side measurement, about a minute each)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM "
                          "byte counters) and exit")
@@ -307,6 +355,8 @@ def main():
     study = None
     if args.study_scale > 0:
         study = batched_study(lm, inputs, torch, args.study_scale)
+        study["hierarchical_far_field"] = batched_study(lm, inputs, torch, args.study_scale,
+                                                        hierarchical=True)
 
     line = {
         "metric": METRIC, "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
@@ -336,6 +386,10 @@ def main():
     }
     if study is not None:
         line["batched_study"] = study
+    if args.paper_map != "none":
+        precs = {"mixed": [lm.LM_PREC_MIXED], "fp64": [lm.LM_PREC_MIXED_FP64],
+                 "both": [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64]}[args.paper_map]
+        line["paper_table1_map"] = [paper_table1_leg(lm, inputs, torch, pr) for pr in precs]
     if not args.no_cpu_baseline:
         cb, errors = cpu_baseline_leg(lm, w, g, lenses, mp, mp32, args.cpu_seconds)
         line["cpu_baseline"] = cb

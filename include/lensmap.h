@@ -203,6 +203,10 @@ lm_status lm_sync(lm_map* m);
  * host (Sec. 3.2.3: counts transferred to the CPU).  Synchronous. */
 lm_status lm_read_counts(lm_map* m, uint64_t* host_counts, uint64_t* n_out, uint64_t* n_shot);
 
+/* Sum of all counts, reduced on the device (for maps too large to copy back:
+ * with n_out it checks that every shot ray was counted).  Synchronous. */
+lm_status lm_sum_counts(lm_map* m, uint64_t* total);
+
 /* Copy the counts of the pixel window [p0, p0+np) x [q0, q0+nq) to host
  * memory (nq rows of np uint64).  LM_ERANGE if the window leaves the map.
  * Synchronous. */

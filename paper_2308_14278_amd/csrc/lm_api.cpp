@@ -756,6 +756,23 @@ lm_status lm_read_counts(lm_map* m, uint64_t* host_counts, uint64_t* n_out, uint
     return ok();
 }
 
+lm_status lm_sum_counts(lm_map* m, uint64_t* total)
+{
+    if (!m || !total) return fail(LM_EINVAL, "map or output is NULL");
+    lm_status st = use_device(m);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(m->last));
+    HIP_TRY(hipDeviceSynchronize());
+    DevBuf acc;
+    if (acc.ensure(8) != hipSuccess) return fail(LM_ENOMEM, "cannot allocate the sum");
+    LAUNCH_TRY(lm_launch_fill_u64(acc.as<unsigned long long>(), 1, 0ull, nullptr));
+    LAUNCH_TRY(lm_launch_sum_u64(reinterpret_cast<const unsigned long long*>(m->counts),
+                                 (int64_t)m->g.src_nx * m->g.src_ny, acc.as<unsigned long long>(),
+                                 nullptr));
+    HIP_TRY(hipMemcpy(total, acc.p, 8, hipMemcpyDeviceToHost));
+    return ok();
+}
+
 lm_status lm_read_counts_region(lm_map* m, int32_t p0, int32_t q0, int32_t np, int32_t nq,
                                 uint64_t* host_counts)
 {

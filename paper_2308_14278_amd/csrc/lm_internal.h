@@ -81,6 +81,9 @@ int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int
                           int nmaps, unsigned long long* queue, int scheme, int precision,
                           int terms, int rays_per_lane, int grid, void* stream);
 int lm_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
+// *total (zeroed by the caller) += sum of p[0..n)
+int lm_launch_sum_u64(const unsigned long long* p, int64_t n, unsigned long long* total,
+                      void* stream);
 int lm_launch_trace(const LmDesc& d, int scheme, int precision, int terms, const int64_t* ii,
                     const int64_t* jj, int64_t n, int32_t* p, int32_t* q, void* stream);
 int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, const double* th,

@@ -1106,6 +1106,16 @@ __global__ __launch_bounds__(kWG) void k_l1_shift(LmDesc d, LmCoef* __restrict__
     }
 }
 
+__global__ __launch_bounds__(kWG) void k_sum_u64(const unsigned long long* __restrict__ p,
+                                                 int64_t n, unsigned long long* total)
+{
+    unsigned long long s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+        s += p[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(total, s);
+}
+
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1414,6 +1424,17 @@ int lm_launch_ptab(const LmDesc& d, float* out, int n, void* stream)
     if (n <= 0) return 0;
     hipLaunchKernelGGL(k_ptab, dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG), 0,
                        (hipStream_t)stream, d, out, n);
+    return (int)hipGetLastError();
+}
+
+int lm_launch_sum_u64(const unsigned long long* p, int64_t n, unsigned long long* total,
+                      void* stream)
+{
+    if (n <= 0) return 0;
+    int64_t blocks = (n + kWG - 1) / kWG;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_sum_u64, dim3((unsigned)blocks), dim3(kWG), 0, (hipStream_t)stream, p, n,
+                       total);
     return (int)hipGetLastError();
 }
 

@@ -119,6 +119,7 @@ _SIGS = {
     "lm_batch_timing": [_vp, _P(ctypes.c_float), _P(ctypes.c_float)],
     "lm_measure_valu_peak": [_d, _d],
     "lm_read_coeffs": [_vp, ctypes.c_int64, ctypes.c_int64, _d],
+    "lm_sum_counts": [_vp, _P(ctypes.c_uint64)],
     "lm_geometry_far_order": [_P(lm_geometry)],
     "lm_measure_issue_rates": [_d, ctypes.c_int32],
     "lm_find_peaks": [_vp, _i32, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_uint8)],
@@ -377,6 +378,13 @@ def lm_batch_timing(b):
     a, c = ctypes.c_float(), ctypes.c_float()
     _check(load().lm_batch_timing(b, ctypes.byref(a), ctypes.byref(c)), "lm_batch_timing")
     return float(a.value), float(c.value)
+
+
+def lm_sum_counts(m):
+    """Sum of the map's counts, reduced on the device."""
+    t = ctypes.c_uint64()
+    _check(load().lm_sum_counts(m, ctypes.byref(t)), "lm_sum_counts")
+    return int(t.value)
 
 
 def lm_geometry_far_order(g):

@@ -47,6 +47,7 @@ def test_fold_map_vs_oracle(precision):
     print("fold map: rays %d, mismatch %.2e, worst pixel %.2e" %
           (g.n_rays, mis, max_pixel_rel(counts, ref)))
     assert int(counts.sum()) + n_out == n_shot == g.n_rays
+    assert lm.lm_sum_counts(mp.h) == int(counts.sum())
     assert mis <= 1e-5
     assert max_pixel_rel(counts, ref) <= 1e-3
     # both images of the fold are present: rays from theta_x < 0 and > 0 land in the map
