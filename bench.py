@@ -199,6 +199,7 @@ def paper_table1_leg(lm, inputs, torch, precision):
     lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
     mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold)
     b = lm.lm_batch_create([mp.h])
+    lm.lm_batch_tune(b, None)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -210,13 +211,15 @@ def paper_table1_leg(lm, inputs, torch, precision):
     total = lm.lm_sum_counts(mp.h)
     _, n_out, n_shot = lm.lm_read_counts(mp.h, g, with_counts=False)
     assert total + n_out == n_shot == g.n_rays, "ray count not conserved"
+    params = list(lm.lm_batch_params(b))
     lm.lm_batch_destroy(b)
     mp.close()
     name = "fp64-near" if precision == lm.LM_PREC_MIXED_FP64 else "mixed"
     log("paper Table 1 map (%s): %d x %d rays (%.4g), R=%d: %.1f s (shoot %.1f s, "
         "coefficients %.0f ms), %.4g rays/s; %d rays in the map" %
         (name, g.ray_nx, g.ray_ny, g.n_rays, g.coarse, dt, s_ms / 1e3, c_ms, g.n_rays / dt, total))
-    return {"precision": name, "rays": g.n_rays, "seconds": dt, "rays_per_s": g.n_rays / dt,
+    return {"precision": name, "exec_params": params,
+            "rays": g.n_rays, "seconds": dt, "rays_per_s": g.n_rays / dt,
             "shoot_kernel_ms": s_ms, "coefficients_ms": c_ms, "rays_in_map": total,
             "map_pixels": [g.src_nx, g.src_ny], "coarse": g.coarse,
             "paper_seconds_context": 7000.0}

@@ -51,11 +51,12 @@ struct Prec<2> {
     using L = double4;
 };
 
-// The rebased FP32 interpolated path shares the column-lens differences of a
-// wave through an LDS table (TabCh lenses at a time).
+// The rebased interpolated paths (FP32 or FP64 near sums) share the
+// column-lens differences of a wave through an LDS table (kTabCh lenses at a
+// time).
 template <int SCHEME, int PREC>
 struct UseTab {
-    static constexpr bool value = SCHEME == 1 && PREC == 0;
+    static constexpr bool value = SCHEME == 1 && PREC != 1;
 };
 constexpr int kTabCh = 16;
 
@@ -179,13 +180,22 @@ __device__ __forceinline__ void pair(double px, double dy, double dy2, double lx
 // Pair from the wave-shared dx^2 and m dx, dx = px - lx (one per column and
 // lens, the same for every row), and the row's dy^2 and m dy.  Every operation
 // but the reciprocal is a two-source VOP2 instruction.
-__device__ __forceinline__ void pair_tab(float dx2, float mdx, float dy2, float mdy, float& ax,
-                                         float& ay)
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// FP64 reciprocal: hardware estimate refined by one Newton step.
+__device__ __forceinline__ double recip(double x)
 {
-    const float r2 = dx2 + dy2;
-    const float w = __builtin_amdgcn_rcpf(r2);
-    ax = __builtin_fmaf(mdx, w, ax);
-    ay = __builtin_fmaf(mdy, w, ay);
+    const double r0 = __builtin_amdgcn_rcp(x);
+    return __builtin_fma(r0, __builtin_fma(-x, r0, 1.0), r0);
+}
+
+template <class T>
+__device__ __forceinline__ void pair_tab(T dx2, T mdx, T dy2, T mdy, T& ax, T& ay)
+{
+    const T r2 = dx2 + dy2;
+    const T w = recip(r2);
+    ax = fma(mdx, w, ax);
+    ay = fma(mdy, w, ay);
 }
 
 // Two pairs of one lens and the row's rays in columns a = 2m and b = 2m + 1
@@ -193,16 +203,17 @@ __device__ __forceinline__ void pair_tab(float dx2, float mdx, float dy2, float 
 // (the reciprocal is the expensive instruction of a pair).  The product stays a
 // normal FP32 number while both r2 exceed 1.1e-19 theta_E^2 (rays farther than
 // 3.3e-10 theta_E from the lens) and stay below 1e19.
-__device__ __forceinline__ void pair2(float dx2a, float dx2b, float mdxa, float mdxb, float dy2,
-                                      float mdy, float& axa, float& aya, float& axb, float& ayb)
+template <class T>
+__device__ __forceinline__ void pair2(T dx2a, T dx2b, T mdxa, T mdxb, T dy2, T mdy, T& axa,
+                                      T& aya, T& axb, T& ayb)
 {
-    const float r2a = dx2a + dy2, r2b = dx2b + dy2;
-    const float r = __builtin_amdgcn_rcpf(r2a * r2b);
-    const float wa = r * r2b, wb = r * r2a;
-    axa = __builtin_fmaf(mdxa, wa, axa);
-    aya = __builtin_fmaf(mdy, wa, aya);
-    axb = __builtin_fmaf(mdxb, wb, axb);
-    ayb = __builtin_fmaf(mdy, wb, ayb);
+    const T r2a = dx2a + dy2, r2b = dx2b + dy2;
+    const T r = recip(r2a * r2b);
+    const T wa = r * r2b, wb = r * r2a;
+    axa = fma(mdxa, wa, axa);
+    aya = fma(mdy, wa, aya);
+    axb = fma(mdxb, wb, axb);
+    ayb = fma(mdy, wb, ayb);
 }
 
 template <class T>
@@ -644,8 +655,8 @@ typedef const __attribute__((address_space(4))) float* ConstF;
 template <int SCHEME, int PREC, int NR, int P, bool FOLD>
 __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_beg,
                              int64_t c_hi, int64_t j, bool row_ok, unsigned axb, unsigned ayb,
-                             unsigned* win, typename Prec<PREC>::L* lb, float* tb, int lane,
-                             unsigned& nout)
+                             unsigned* win, typename Prec<PREC>::L* lb,
+                             typename Prec<PREC>::T* tb, int lane, unsigned& nout)
 {
     using T = typename Prec<PREC>::T;
     const int R = d.R;
@@ -697,33 +708,33 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
             }
             if constexpr (UseTab<SCHEME, PREC>::value) {
                 // this lane's column in the table build: NR divides 64
-                const float pxl = local_offset(c0 + (lane & (NR - 1)), ci, R, h_hxh, h_hxl);
+                T pxl;
+                if constexpr (PREC == 0)
+                    pxl = local_offset(c0 + (lane & (NR - 1)), ci, R, h_hxh, h_hxl);
+                else
+                    pxl = column_offset<PREC>(d, c0 + (lane & (NR - 1)), ci);
                 for (int k0 = 0; k0 < nb; k0 += kTabCh) {
                     const int nk = min(kTabCh, nb - k0);
                     // tb[k][0..NR) = dx^2, tb[k][NR..2NR) = m dx, for lenses k0 .. k0+nk
                     for (int e = lane; e < nk * NR; e += 64) {
                         const int k = e / NR, c = e & (NR - 1);
-                        const float4 L = lb[k0 + k];
-                        const float dx = pxl - L.x;
+                        const auto L = lb[k0 + k];
+                        const T dx = pxl - L.x;
                         tb[k * 2 * NR + c] = dx * dx;
                         tb[k * 2 * NR + NR + c] = L.z * dx;
                     }
                     wave_sync_lds();
 #pragma unroll 2
                     for (int k = 0; k < nk; ++k) {
-                        const float4 L = lb[k0 + k];
-                        const float dy = py - L.y;
-                        const float dy2 = dy * dy;
-                        const float mdy = L.z * dy;
-                        const float4* row = reinterpret_cast<const float4*>(tb + k * 2 * NR);
+                        const auto L = lb[k0 + k];
+                        const T dy = py - L.y;
+                        const T dy2 = dy * dy;
+                        const T mdy = L.z * dy;
+                        const T* row = tb + k * 2 * NR;
 #pragma unroll
-                        for (int c4 = 0; c4 < NR / 4; ++c4) {
-                            const float4 D = row[c4], M = row[NR / 4 + c4];
-                            pair2(D.x, D.y, M.x, M.y, dy2, mdy, bx[4 * c4 + 0], by[4 * c4 + 0],
-                                  bx[4 * c4 + 1], by[4 * c4 + 1]);
-                            pair2(D.z, D.w, M.z, M.w, dy2, mdy, bx[4 * c4 + 2], by[4 * c4 + 2],
-                                  bx[4 * c4 + 3], by[4 * c4 + 3]);
-                        }
+                        for (int c = 0; c < NR; c += 2)
+                            pair2(row[c], row[c + 1], row[NR + c], row[NR + c + 1], dy2, mdy, bx[c],
+                                  by[c], bx[c + 1], by[c + 1]);
                     }
                     wave_sync_lds();
                 }
@@ -799,7 +810,8 @@ __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_
 
 template <int SCHEME, int PREC, int NR, int P>
 __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsigned* win,
-                             typename Prec<PREC>::L* lb, float* tb, int wave, int lane)
+                             typename Prec<PREC>::L* lb, typename Prec<PREC>::T* tb, int wave,
+                             int lane)
 {
     const unsigned axb = (unsigned)ax0 + kBias, ayb = (unsigned)ay0 + kBias;
     const int64_t tx = t % d.ntx, ty = t / d.ntx;
@@ -853,7 +865,8 @@ __global__ __launch_bounds__(kWG) void k_shoot_map(LmDesc d)
 {
     __shared__ unsigned win[kWinMax];
     __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
-    __shared__ float4 tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * NR / 2 : 1];
+    __shared__ __align__(16) typename Prec<PREC>::T
+        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * 2 * NR : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -863,8 +876,7 @@ __global__ __launch_bounds__(kWG) void k_shoot_map(LmDesc d)
     int ax0, ay0;
     tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
     __syncthreads();
-    process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave],
-                                      reinterpret_cast<float*>(tab[wave]), wave, lane);
+    process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave, lane);
     __syncthreads();
     flush_window(d, win, ax0, ay0, tid);
 }
@@ -877,7 +889,8 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
 {
     __shared__ unsigned win[kWinMax];
     __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
-    __shared__ float4 tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * NR / 2 : 1];
+    __shared__ __align__(16) typename Prec<PREC>::T
+        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * 2 * NR : 1];
     __shared__ long long s_item;
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
@@ -903,8 +916,8 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
         const int64_t tx = t % d.ntx, ty = t / d.ntx;
         int ax0, ay0;
         tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
-        process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave],
-                                          reinterpret_cast<float*>(tab[wave]), wave, lane);
+        process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave,
+                                          lane);
         __syncthreads();
         flush_window(d, win, ax0, ay0, tid);
         __syncthreads();
@@ -1144,11 +1157,11 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
             const auto L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
             const T dy = py - L.y;
             if constexpr (UseTab<SCHEME, PREC>::value && PAIRED) {
-                const float dx = px - L.x, dxp = pxp - L.x;
-                float ayp = 0.f, axp = 0.f;
+                const T dx = px - L.x, dxp = pxp - L.x;
+                T ayp = 0, axp = 0;
                 pair2(dx * dx, dxp * dxp, L.z * dx, L.z * dxp, dy * dy, L.z * dy, bx, by, axp, ayp);
             } else if constexpr (UseTab<SCHEME, PREC>::value) {
-                const float dx = px - L.x;
+                const T dx = px - L.x;
                 pair_tab(dx * dx, L.z * dx, dy * dy, L.z * dy, bx, by);
             } else {
                 pair(px, dy, dy * dy, L.x, L.z, bx, by);
