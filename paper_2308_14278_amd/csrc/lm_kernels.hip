@@ -4,9 +4,10 @@
 //                 a_n = -sum_{far k} m_k / (z_k - z_c)^(n+1); lens tiles staged
 //                 in LDS, FP64 arithmetic (full-rate FP64 VALU on gfx950).
 //  k_shoot_map    one workgroup per tile of level-2 cells: per ray the near-lens
-//  k_shoot_batch  direct sum (Eq. 9) in FP32 on offsets rebased to the cell
-//                 centre, the Taylor evaluation of the far field, the macro map
-//                 with the sheet term (Eq. 6), FP64 pixel coordinates, and the
+//  k_shoot_batch  direct sum (Eq. 9) on offsets rebased to the cell centre
+//                 (FP32, or FP64 in the FP64 near-sum mode), the far-field
+//                 Taylor series and the macro map with the sheet term (Eq. 6)
+//                 re-expanded per ray row, FP64 pixel coordinates, and the
 //                 count (Sec. 3.2.3) through a per-lane run, a wave merge and
 //                 an LDS window flushed to the uint64 map.  The batch kernel is
 //                 persistent and pulls tiles of many maps from a queue.
@@ -19,7 +20,11 @@
 // (one ray row per lane) by a run of columns of one level-2 cell; the lane
 // walks its row NR columns at a time.  Every ray of a unit shares the cell's
 // near-lens list, which the wave stages once in its own LDS slice, so the
-// lens loop is uniform and reads lenses as LDS broadcasts.
+// lens loop is uniform and reads lenses as LDS broadcasts.  Quantities that
+// are the same for all 64 rows -- the column offsets (scalar loads), and per
+// column and lens dx^2 and m dx (an LDS table the wave fills 64 entries at a
+// time) -- are computed once per wave, and the rays of columns 2m and 2m+1
+// share one reciprocal per lens.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -82,7 +87,7 @@ __device__ __forceinline__ unsigned wave_sum_u32(unsigned v)
 // Map constants the per-ray code reads, copied into registers once per unit so
 // that the global atomics of the counting step do not force reloads.
 struct Hot {
-    double inv_sdx, inv_sdy, snxd, snyd;
+    double inv_sdx, inv_sdy;
     float mxf, myf, bx0f, by0f, inv_sdxf, inv_sdyf, snxf, snyf;
     float qxf, qyf;  // fold: d_x/2, d_y
     int snx, sny, wx, wy;
@@ -94,8 +99,6 @@ __device__ __forceinline__ Hot make_hot(const LmDesc& d)
     Hot h;
     h.inv_sdx = d.inv_sdx;
     h.inv_sdy = d.inv_sdy;
-    h.snxd = (double)d.snx;
-    h.snyd = (double)d.sny;
     h.mxf = d.mxf;
     h.myf = d.myf;
     h.qxf = (float)d.qx;
@@ -164,18 +167,6 @@ __device__ __forceinline__ void pair(float px, float dy, float dy2, float lxv, f
     ay = __builtin_fmaf(dy, w, ay);
 }
 
-// FP64 pair: hardware reciprocal refined by one Newton step.
-__device__ __forceinline__ void pair(double px, double dy, double dy2, double lxv, double lmv,
-                                     double& ax, double& ay)
-{
-    double dx = px - lxv;
-    double r2 = __builtin_fma(dx, dx, dy2);
-    double w0 = __builtin_amdgcn_rcp(r2);
-    double e = __builtin_fma(-r2, w0, 1.0);
-    double w = lmv * __builtin_fma(w0, e, w0);
-    ax = __builtin_fma(dx, w, ax);
-    ay = __builtin_fma(dy, w, ay);
-}
 
 // Pair from the wave-shared dx^2 and m dx, dx = px - lx (one per column and
 // lens, the same for every row), and the row's dy^2 and m dy.  Every operation
