@@ -128,6 +128,52 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
             "seconds": dt}, errors
 
 
+def precision_stress_leg(lm, inputs):
+    """Precision stress (lambda_t = 0.001, 20000 lenses, 4e12-ray lattice,
+    4000^2 map): the mixed path (FP64 along the critical direction) and the
+    plain FP32 path against the FP64 oracle on a 1e9-ray sub-region at the
+    centre of the lattice."""
+    import numpy as np
+
+    import oracle
+    from oracle.geometry import OracleGeometry
+    w = inputs.precision_stress()
+    lenses = w.lenses()
+    out = {}
+    ref = None
+    for name, prec in (("mixed", lm.LM_PREC_MIXED), ("plain_fp32", lm.LM_PREC_FP32)):
+        g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                                  w.gamma, w.kappa_star, protect=w.protect, n_rays=w.n_rays,
+                                  scheme=w.scheme, coarse=w.coarse, mean_mass=w.mean_mass)
+        g.precision = prec
+        nj = 8 * g.coarse
+        ni = int(1e9 // nj)
+        i0, j0 = g.ray_nx // 2 - ni // 2, g.ray_ny // 2 - nj // 2
+        mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, lenses)
+        mp.shoot(i0, j0, ni, nj)
+        c, o, _ = mp.counts()
+        mp.close()
+        if ref is None:
+            og = OracleGeometry(**{k: getattr(g, k) for k in
+                                   ("src_x0", "src_y0", "src_dx", "src_dy", "src_nx", "src_ny",
+                                    "ray_x0", "ray_y0", "ray_dx", "ray_dy", "ray_nx", "ray_ny",
+                                    "scheme", "coarse", "l1_kx", "l1_ky")},
+                                halo=g.near_halo, terms=g.taylor_terms)
+            t0 = time.perf_counter()
+            ref, ref_out = oracle.Oracle(og, w.kappa, w.gamma, w.kappa_star, *lenses).shoot(
+                i0, j0, ni, nj)
+            log("precision stress: oracle %d rays in %.1f s" % (ni * nj, time.perf_counter() - t0))
+        d = np.abs(c.astype(np.int64) - ref.astype(np.int64))
+        big = ref >= 10000
+        out[name] = {"bin_mismatch": 0.5 * float(d.sum()) / (ni * nj),
+                     "max_pixel_rel_err_counts_ge_1e4":
+                         float((d[big] / ref[big]).max()) if big.any() else 0.0,
+                     "n_out_diff": int(o) - int(ref_out)}
+        log("precision stress %s: mismatch %.3g" % (name, out[name]["bin_mismatch"]))
+    out["sample"] = "%d x %d rays at the centre of the 4e12-ray lattice" % (ni, nj)
+    return out
+
+
 def batched_study(lm, inputs, torch, scale, hierarchical=False):
     """The 80-map study at a fraction of its rays: one batch (coefficients of
     every map, one persistent shooting kernel over all maps' tiles), then ten
@@ -396,6 +442,7 @@ def main():
     if not args.no_cpu_baseline:
         cb, errors = cpu_baseline_leg(lm, w, g, lenses, mp, mp32, args.cpu_seconds)
         line["cpu_baseline"] = cb
+        errors["precision_stress"] = precision_stress_leg(lm, inputs)
         line["map_error_vs_fp64"] = errors
     lm.lm_batch_destroy(b)
     mp.close()
