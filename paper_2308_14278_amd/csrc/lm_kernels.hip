@@ -509,9 +509,11 @@ __device__ __forceinline__ void emit(const Hot& h, unsigned p, unsigned q, unsig
         atomicAdd(&h.counts[(int64_t)qm * h.snx + pm], (unsigned long long)n);
 }
 
+// Lanes whose row lies outside the shot rectangle (row_ok false) keep runs like
+// every lane but never emit them, so the per-ray path needs no lane mask.
 __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsigned q,
                                          unsigned axb, unsigned ayb, unsigned* win,
-                                         unsigned& nout)
+                                         unsigned& nout, bool row_ok)
 {
     // (a unit starts with an empty run, n = 0, at the out-of-map pixel
     // kBias - 2, which emit books as n_out += 0)
@@ -520,14 +522,14 @@ __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsig
     r.n = (same ? r.n : 0u) + 1u;
     r.p = p;
     r.q = q;
-    if (!same) emit(h, old.p, old.q, old.n, axb, ayb, win, nout);
+    if (!same && row_ok) emit(h, old.p, old.q, old.n, axb, ayb, win, nout);
 }
 
 // End of a unit: lanes whose pending runs all name one pixel add it once.
 __device__ __forceinline__ void run_flush(const Hot& h, Run& r, unsigned axb, unsigned ayb,
-                                          unsigned* win, unsigned& nout, int lane)
+                                          unsigned* win, unsigned& nout, int lane, bool row_ok)
 {
-    bool act = r.n > 0;
+    bool act = row_ok && r.n > 0;
     unsigned long long am = __ballot(act);
     if (am) {
         int first = __builtin_ctzll(am);
@@ -753,17 +755,28 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
         }
         const int ncol = (int)min((int64_t)NR, c_hi - c0);
         const int cfirst = (int)max((int64_t)0, c_beg - c0);
+        if (cfirst == 0 && ncol == NR) {
+            // a whole group (every group but a unit's first and last)
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            if (c >= cfirst && c < ncol) {
+            for (int c = 0; c < NR; ++c) {
                 unsigned p, q;
                 ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c], ay[c], p,
                                        q);
-                if (row_ok) run_push(h, run, p, q, axb, ayb, win, nout);
+                run_push(h, run, p, q, axb, ayb, win, nout, row_ok);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                if (c >= cfirst && c < ncol) {
+                    unsigned p, q;
+                    ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
+                                           ay[c], p, q);
+                    run_push(h, run, p, q, axb, ayb, win, nout, row_ok);
+                }
             }
         }
     }
-    run_flush(h, run, axb, ayb, win, nout, lane);
+    run_flush(h, run, axb, ayb, win, nout, lane, row_ok);
 }
 
 // Window origin of a tile: the pixel of the image of its centre cell's centre
