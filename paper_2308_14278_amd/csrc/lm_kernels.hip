@@ -724,10 +724,28 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                         const T dy2 = dy * dy;
                         const T mdy = L.z * dy;
                         const T* row = tb + k * 2 * NR;
+                        // pair2 for all columns, staged so that the reciprocals issue
+                        // back to back instead of each right before its use
+                        T r2[NR], md[NR], rr[NR / 2];
 #pragma unroll
-                        for (int c = 0; c < NR; c += 2)
-                            pair2(row[c], row[c + 1], row[NR + c], row[NR + c + 1], dy2, mdy, bx[c],
-                                  by[c], bx[c + 1], by[c + 1]);
+                        for (int c = 0; c < NR; ++c) {
+                            r2[c] = row[c] + dy2;
+                            md[c] = row[NR + c];
+                        }
+#pragma unroll
+                        for (int c = 0; c < NR; c += 2) rr[c / 2] = r2[c] * r2[c + 1];
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int c = 0; c < NR / 2; ++c) rr[c] = recip(rr[c]);
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int c = 0; c < NR; c += 2) {
+                            const T wa = rr[c / 2] * r2[c + 1], wb = rr[c / 2] * r2[c];
+                            bx[c] = fma(md[c], wa, bx[c]);
+                            by[c] = fma(mdy, wa, by[c]);
+                            bx[c + 1] = fma(md[c + 1], wb, bx[c + 1]);
+                            by[c + 1] = fma(mdy, wb, by[c + 1]);
+                        }
                     }
                     wave_sync_lds();
                 }
