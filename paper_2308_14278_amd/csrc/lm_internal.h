@@ -9,6 +9,7 @@
 #define LM_NEAR_CAP 64     // interpolated scheme: near lenses staged per wave per block
 #define LM_WIN_MAX 7040    // uint32 bins of a workgroup's LDS window
 #define LM_PTAB_PAD 64     // column-offset table entries past R (last column group)
+#define LM_PTAB_POW 6      // powers dx .. dx^6 per column (row polynomials, P <= 7)
 
 // Taylor coefficients of one level-2 cell: a_0 in FP64 (it carries the large
 // far-field deflection of the cell centre), a_1..a_6 in FP32 (they multiply
@@ -62,7 +63,8 @@ struct LmDesc {
     const int32_t* lJ;
     const int32_t* cell_start;     // CSR over the padded level-1 grid
     const LmCoef* coef;            // [ncy][ncx]
-    const float* ptab;             // [R + LM_PTAB_PAD] column offsets of a level-2 cell
+    const float* ptab;             // [LM_PTAB_POW][R + LM_PTAB_PAD] column offsets of a
+                                   // level-2 cell and their powers
     double* l1exp;                 // [n1y][n1x][Q] level-1 series, complex (re, im)
     unsigned long long* counts;    // [sny][snx]
     unsigned long long* n_out;

@@ -296,8 +296,9 @@ struct Deg {
 // gx(dx) = Re f - (macro x displacement) and gy(dx) = -Im f: the x displacement
 // of a ray's image is then -(gx + near_x) and its y deflection gy + near_y, so
 // the near sums start from gx and gy.  The coefficients come from a Taylor
-// shift of f by i dy (synthetic division), once per row; per ray two Horner
-// evaluations remain.  Macro constants: Jacobian diag(cxx, .) at the cell
+// shift of f by i dy (synthetic division), once per row.  The constant terms
+// gx[0], gy[0] go into the row's FP64 pixel bases (row_setup); per ray the
+// rest is summed from the wave-uniform powers of dx (ray_start).  Macro constants: Jacobian diag(cxx, .) at the cell
 // centre, cxy = d_y z_x and the fold's quadratic remainder (qx dx + qy dy) dx.
 template <int P, bool FOLD, class T>
 __device__ __forceinline__ void row_poly(const float* ar, const float* ai, T dy, T cxx, T cxy,
@@ -333,18 +334,20 @@ __device__ __forceinline__ void row_poly(const float* ar, const float* ai, T dy,
     }
 }
 
+// Powers dx, dx^2, .., dx^D of a column offset, in this order of products
+// (the per-cell column table holds the same values).
 template <int D, class T>
-__device__ __forceinline__ T horner(const T* g, T x)
+__device__ __forceinline__ void col_powers(T x, T* pw)
 {
-    T r = g[D];
+    pw[0] = x;
 #pragma unroll
-    for (int k = D - 1; k >= 0; --k) r = fma(r, x, g[k]);
-    return r;
+    for (int k = 1; k < D; ++k) pw[k] = pw[k - 1] * x;
 }
 
-// Biased pixel of one ray of the rebased paths from its sums sx = gx + near_x,
-// sy = gy + near_y; ubxb and ubyb are the biased FP64 pixel coordinates of the
-// cell centre's image (x) and of the row (y, row_base).
+// Biased pixel of one ray of the rebased paths from its sums sx = gx - gx[0] +
+// near_x, sy = gy - gy[0] + near_y; ubxb and ubyb are the biased FP64 pixel
+// coordinates of the cell centre's image (x) and of the row (y, row_base), each
+// with its row polynomial's constant term.
 template <class T>
 __device__ __forceinline__ void bin_rebased(double inv_sdx, double inv_sdy, double ubxb,
                                             double ubyb, T sx, T sy, unsigned& p, unsigned& q)
@@ -517,12 +520,13 @@ __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsig
 {
     // (a unit starts with an empty run, n = 0, at the out-of-map pixel
     // kBias - 2, which emit books as n_out += 0)
-    const bool same = (p == r.p) & (q == r.q);
-    const Run old = r;
-    r.n = (same ? r.n : 0u) + 1u;
-    r.p = p;
-    r.q = q;
-    if (!same && row_ok) emit(h, old.p, old.q, old.n, axb, ayb, win, nout);
+    if ((p != r.p) | (q != r.q)) {
+        if (row_ok) emit(h, r.p, r.q, r.n, axb, ayb, win, nout);
+        r.n = 0;
+        r.p = p;
+        r.q = q;
+    }
+    r.n += 1;
 }
 
 // End of a unit: lanes whose pending runs all name one pixel add it once.
@@ -589,6 +593,8 @@ __device__ __forceinline__ void row_setup(const LmDesc& d, int64_t cj, int64_t j
             qy = cm.qy;
         }
         row_poly<P, FOLD, T>(ar, ai, rw.py, cxx, cxy, qx, qy, rw.gx, rw.gy);
+        rw.ubxb = __builtin_fma(-(double)rw.gx[0], d.inv_sdx, rw.ubxb);
+        rw.ubyb = __builtin_fma(-(double)rw.gy[0], d.inv_sdy, rw.ubyb);
     }
 }
 
@@ -605,19 +611,46 @@ __device__ __forceinline__ typename Prec<PREC>::T column_offset(const LmDesc& d,
         return __builtin_fmaf((float)k + 0.5f, d.dxf, d.x0f);
 }
 
-// Near sums of one ray started (rebased paths) from the row polynomials, and
-// its biased pixel.
+// Start values of one ray's near sums (rebased paths): the row polynomials
+// without their constant terms, g1 dx + g2 dx^2 + .., from the column's powers
+// pw[k] = dx^(k+1) (one multiply and D - 1 FMAs per axis with wave-uniform
+// powers).
+// (NEG: ay is the negated y sum; every step is an exact negation of the
+// plain one, and the coefficients -gy = Im(...) need no sign modifier)
+template <bool NEG, int PREC, int P, bool FOLD>
+__device__ __forceinline__ void ray_start_first(const Row<PREC, P, FOLD>& rw,
+                                                typename Prec<PREC>::T p1,
+                                                typename Prec<PREC>::T& ax,
+                                                typename Prec<PREC>::T& ay)
+{
+    ax = p1 * rw.gx[1];
+    ay = p1 * (NEG ? -rw.gy[1] : rw.gy[1]);
+}
+
+// term k + 1 (k >= 1) with pk = dx^(k+1)
+template <bool NEG, int PREC, int P, bool FOLD>
+__device__ __forceinline__ void ray_start_next(const Row<PREC, P, FOLD>& rw, int k,
+                                               typename Prec<PREC>::T pk,
+                                               typename Prec<PREC>::T& ax,
+                                               typename Prec<PREC>::T& ay)
+{
+    ax = fma(pk, rw.gx[k + 1], ax);
+    ay = fma(pk, NEG ? -rw.gy[k + 1] : rw.gy[k + 1], ay);
+}
+
 template <int PREC, int P, bool FOLD>
 __device__ __forceinline__ void ray_start(const Row<PREC, P, FOLD>& rw,
-                                          typename Prec<PREC>::T px, typename Prec<PREC>::T& ax,
-                                          typename Prec<PREC>::T& ay)
+                                          const typename Prec<PREC>::T* pw,
+                                          typename Prec<PREC>::T& ax, typename Prec<PREC>::T& ay)
 {
     if constexpr (PREC == 1) {
         ax = 0.f;
         ay = 0.f;
     } else {
-        ax = horner<Row<PREC, P, FOLD>::D>(rw.gx, px);
-        ay = horner<Row<PREC, P, FOLD>::D>(rw.gy, px);
+        constexpr int D = Row<PREC, P, FOLD>::D;
+        ray_start_first<false, PREC, P, FOLD>(rw, pw[0], ax, ay);
+#pragma unroll
+        for (int k = 1; k < D; ++k) ray_start_next<false, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
     }
 }
 
@@ -642,6 +675,37 @@ __device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& 
 
 // Scalar (SMEM) loads of wave-uniform table entries.
 typedef const __attribute__((address_space(4))) float* ConstF;
+
+// One lens (row offset dy, mass m; called with dy = y_k - y, so that by holds
+// negated y sums) against the NR rays of a lane from its
+// table row (dx^2 and m dx per column): pair2 for all columns, staged so that
+// the reciprocals issue back to back instead of each right before its use.
+template <int NR, class T>
+__device__ __forceinline__ void lens_pairs(const T* row, T dy, T m, T* bx, T* by)
+{
+    const T dy2 = dy * dy;
+    const T mdy = m * dy;
+    T r2[NR], md[NR], rr[NR / 2];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        r2[c] = row[c] + dy2;
+        md[c] = row[NR + c];
+    }
+#pragma unroll
+    for (int c = 0; c < NR; c += 2) rr[c / 2] = r2[c] * r2[c + 1];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < NR / 2; ++c) rr[c] = recip(rr[c]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < NR; c += 2) {
+        const T wa = rr[c / 2] * r2[c + 1], wb = rr[c / 2] * r2[c];
+        bx[c] = fma(md[c], wa, bx[c]);
+        by[c] = fma(mdy, wa, by[c]);
+        bx[c + 1] = fma(md[c + 1], wb, bx[c + 1]);
+        by[c + 1] = fma(mdy, wb, by[c + 1]);
+    }
+}
 
 // Columns [c_lo, c_hi) of cell ci are computed (c_lo even, so columns 2m and
 // 2m + 1 share a group); rays of columns >= c_beg are counted.
@@ -674,19 +738,44 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
 
     Run run{kBias - 2, kBias - 2, 0u};
     for (int64_t c0 = c_lo; c0 < c_hi; c0 += NR) {
+        constexpr int D = Row<PREC, P, FOLD>::D;
+        static_assert(D <= LM_PTAB_POW, "column table holds too few powers");
+        // the table path carries the y sums negated (lens offsets y_k - y):
+        // the row coefficients -gy and the FP64 binning take the sign for free
+        constexpr bool NEGY = UseTab<SCHEME, PREC>::value;
         T px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
         if constexpr (PREC == 0) {
-            // wave-uniform column offsets from the map's table (scalar loads)
+            // wave-uniform column offsets and their powers from the map's table
+            // (scalar loads), one power at a time so that only NR of them are
+            // live in scalar registers
             const ConstF tab = (ConstF)(d.ptab + (c0 - ci * (int64_t)R));
 #pragma unroll
-            for (int c = 0; c < NR; ++c) px[c] = tab[c];
+            for (int k = 0; k < D; ++k) {
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    const T pk = tab[k * (R + LM_PTAB_PAD) + c];
+                    if (k == 0) {
+                        px[c] = pk;
+                        ray_start_first<NEGY, PREC, P, FOLD>(rw, pk, ax[c], ay[c]);
+                    } else {
+                        ray_start_next<NEGY, PREC, P, FOLD>(rw, k, pk, ax[c], ay[c]);
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
         } else {
 #pragma unroll
-            for (int c = 0; c < NR; ++c) px[c] = column_offset<PREC>(d, c0 + c, ci);
+            for (int c = 0; c < NR; ++c) {
+                T pw[D];
+                px[c] = column_offset<PREC>(d, c0 + c, ci);
+                col_powers<D>(px[c], pw);
+                ray_start<PREC, P, FOLD>(rw, pw, ax[c], ay[c]);
+                if (NEGY) ay[c] = -ay[c];
+            }
         }
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            ray_start<PREC, P, FOLD>(rw, px[c], ax[c], ay[c]);
             kx[c] = 0;
             ky[c] = 0;
         }
@@ -707,7 +796,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 else
                     pxl = column_offset<PREC>(d, c0 + (lane & (NR - 1)), ci);
                 for (int k0 = 0; k0 < nb; k0 += kTabCh) {
-                    const int nk = min(kTabCh, nb - k0);
+                    // wave-uniform count: scalar loop control
+                    const int nk = __builtin_amdgcn_readfirstlane(min(kTabCh, nb - k0));
                     // tb[k][0..NR) = dx^2, tb[k][NR..2NR) = m dx, for lenses k0 .. k0+nk
                     for (int e = lane; e < nk * NR; e += 64) {
                         const int k = e / NR, c = e & (NR - 1);
@@ -717,35 +807,16 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                         tb[k * 2 * NR + NR + c] = L.z * dx;
                     }
                     wave_sync_lds();
-#pragma unroll 2
-                    for (int k = 0; k < nk; ++k) {
+                    // two lenses per step: their LDS reads share base addresses
+                    int k = 0;
+                    for (; k + 2 <= nk; k += 2) {
+                        const auto L0 = lb[k0 + k], L1 = lb[k0 + k + 1];
+                        lens_pairs<NR>(tb + k * 2 * NR, L0.y - py, L0.z, bx, by);
+                        lens_pairs<NR>(tb + (k + 1) * 2 * NR, L1.y - py, L1.z, bx, by);
+                    }
+                    if (k < nk) {
                         const auto L = lb[k0 + k];
-                        const T dy = py - L.y;
-                        const T dy2 = dy * dy;
-                        const T mdy = L.z * dy;
-                        const T* row = tb + k * 2 * NR;
-                        // pair2 for all columns, staged so that the reciprocals issue
-                        // back to back instead of each right before its use
-                        T r2[NR], md[NR], rr[NR / 2];
-#pragma unroll
-                        for (int c = 0; c < NR; ++c) {
-                            r2[c] = row[c] + dy2;
-                            md[c] = row[NR + c];
-                        }
-#pragma unroll
-                        for (int c = 0; c < NR; c += 2) rr[c / 2] = r2[c] * r2[c + 1];
-                        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                        for (int c = 0; c < NR / 2; ++c) rr[c] = recip(rr[c]);
-                        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                        for (int c = 0; c < NR; c += 2) {
-                            const T wa = rr[c / 2] * r2[c + 1], wb = rr[c / 2] * r2[c];
-                            bx[c] = fma(md[c], wa, bx[c]);
-                            by[c] = fma(mdy, wa, by[c]);
-                            bx[c + 1] = fma(md[c + 1], wb, bx[c + 1]);
-                            by[c + 1] = fma(mdy, wb, by[c + 1]);
-                        }
+                        lens_pairs<NR>(tb + k * 2 * NR, L.y - py, L.z, bx, by);
                     }
                     wave_sync_lds();
                 }
@@ -778,8 +849,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
                 unsigned p, q;
-                ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c], ay[c], p,
-                                       q);
+                ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
+                                       NEGY ? -ay[c] : ay[c], p, q);
                 run_push(h, run, p, q, axb, ayb, win, nout, row_ok);
             }
         } else {
@@ -788,7 +859,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 if (c >= cfirst && c < ncol) {
                     unsigned p, q;
                     ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
-                                           ay[c], p, q);
+                                           NEGY ? -ay[c] : ay[c], p, q);
                     run_push(h, run, p, q, axb, ayb, win, nout, row_ok);
                 }
             }
@@ -1023,12 +1094,18 @@ __global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t c
     }
 }
 
-// Column offsets local_offset(l) of a level-2 cell, l = 0 .. n-1 (entries past
-// R belong to masked columns of the last group).
+// Column offsets dx = local_offset(l) of a level-2 cell and their powers:
+// out[k n + l] = dx^(k+1), k < LM_PTAB_POW, l = 0 .. n-1 (entries past R belong
+// to masked columns of the last group).
 __global__ void k_ptab(LmDesc d, float* __restrict__ out, int n)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < n) out[l] = local_offset(l, 0, d.R, d.hxh, d.hxl);
+    if (l < n) {
+        float pw[LM_PTAB_POW];
+        col_powers<LM_PTAB_POW>(local_offset(l, 0, d.R, d.hxh, d.hxl), pw);
+#pragma unroll
+        for (int k = 0; k < LM_PTAB_POW; ++k) out[(int64_t)k * n + l] = pw[k];
+    }
 }
 
 // Hierarchical far field, step 1: the series of the far lenses of level-1 cell
@@ -1214,8 +1291,9 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
     Row<PREC, P, FOLD> rw;
     row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
     const T px = column_offset<PREC>(d, i, ci);
-    T ax, ay;
-    ray_start<PREC, P, FOLD>(rw, px, ax, ay);
+    T pw[Row<PREC, P, FOLD>::D], ax, ay;
+    col_powers<Row<PREC, P, FOLD>::D>(px, pw);
+    ray_start<PREC, P, FOLD>(rw, pw, ax, ay);
     near_sum<SCHEME, PREC, true>(d, ci, cj, zcx, zcy, px, rw.py, ax, ay,
                                  column_offset<PREC>(d, i ^ 1, ci));
     const Hot h = make_hot(d);
