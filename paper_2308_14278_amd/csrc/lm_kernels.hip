@@ -65,6 +65,16 @@ struct UseTab {
 };
 constexpr int kTabCh = 16;
 
+// Waves per SIMD the shooting kernels must keep: the FP32 table path is
+// issue-bound and needs 4 (at most 128 VGPRs with 256-thread workgroups, 4 per
+// CU).  The per-map kernel, whose descriptor arrives by value, would otherwise
+// allocate a few registers more than that and drop to 3; the hint makes the
+// compiler spill a few per-unit values instead.
+template <int SCHEME, int PREC>
+struct MinWaves {
+    static constexpr int value = (SCHEME == 1 && PREC == 0) ? 4 : 1;
+};
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -954,7 +964,8 @@ __device__ __forceinline__ void flush_window(const LmDesc& d, unsigned* win, int
 // ------------------------------------------------------------- kernels
 
 template <int SCHEME, int PREC, int NR, int P>
-__global__ __launch_bounds__(kWG) void k_shoot_map(LmDesc d)
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(MinWaves<SCHEME, PREC>::value))) void k_shoot_map(LmDesc d)
 {
     __shared__ unsigned win[kWinMax];
     __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
