@@ -308,8 +308,9 @@ struct Deg {
 // the near sums start from gx and gy.  The coefficients come from a Taylor
 // shift of f by i dy (synthetic division), once per row.  The constant terms
 // gx[0], gy[0] go into the row's FP64 pixel bases (row_setup); per ray the
-// rest is summed from the wave-uniform powers of dx (ray_start).  Macro constants: Jacobian diag(cxx, .) at the cell
-// centre, cxy = d_y z_x and the fold's quadratic remainder (qx dx + qy dy) dx.
+// rest is summed from the wave-uniform powers of dx (ray_start).  Macro
+// constants: Jacobian diag(cxx, .) at the cell centre, cxy = d_y z_x and the
+// fold's quadratic remainder (qx dx + qy dy) dx.
 template <int P, bool FOLD, class T>
 __device__ __forceinline__ void row_poly(const float* ar, const float* ai, T dy, T cxx, T cxy,
                                          T qx, T qy, T* gx, T* gy)
