@@ -1038,19 +1038,31 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
     }
 }
 
+// A lens as staged for the coefficient sums: position, mass, level-1 cell.
+template <class T>
+struct alignas(16) CoefLens {
+    T x, y, m;
+    int I, J;
+};
+
 // Far-field coefficients: one level-2 cell per thread, lens tiles in LDS.
 template <int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t cj0, int64_t nci,
                                                 int64_t ncj, LmCoef* __restrict__ out)
 {
     typedef typename std::conditional<PREC != 1, double, float>::type T;
-    __shared__ T sx[kWG], sy[kWG], sm[kWG];
-    __shared__ int sI[kWG], sJ[kWG];
+    __shared__ CoefLens<T> sl[kWG];
     const int tid = threadIdx.x;
     const int64_t c = (int64_t)blockIdx.x * kWG + tid;
     const bool valid = c < nci * ncj;
     const int64_t ci = ci0 + (valid ? c % nci : 0), cj = cj0 + (valid ? c / nci : 0);
     const int I = (int)(ci / d.Kx), J = (int)(cj / d.Ky);
+    // near: |I_k - I| <= H and |J_k - J| <= H, as one unsigned range test per axis
+    const int Ilo = I - d.H, Jlo = J - d.H;
+    const unsigned span = 2u * (unsigned)d.H;
+    // keeps r^2 of a lens at the cell centre (always near) away from zero; no
+    // effect on any far lens
+    const T tiny = PREC != 1 ? (T)1e-300 : (T)1e-30f;
     T zx, zy;
     if (PREC != 1) {
         zx = (T)cell_cx(d, ci);
@@ -1069,26 +1081,28 @@ __global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t c
         __syncthreads();
         const int64_t k = base + tid;
         if (k < d.nlens) {
+            CoefLens<T> L;
             if (PREC != 1) {
-                sx[tid] = (T)d.lx[k];
-                sy[tid] = (T)d.ly[k];
-                sm[tid] = (T)d.lmd[k];
+                L.x = (T)d.lx[k];
+                L.y = (T)d.ly[k];
+                L.m = (T)d.lmd[k];
             } else {
-                sx[tid] = (T)d.lxf[k];
-                sy[tid] = (T)d.lyf[k];
-                sm[tid] = (T)d.lmf[k];
+                L.x = (T)d.lxf[k];
+                L.y = (T)d.lyf[k];
+                L.m = (T)d.lmf[k];
             }
-            sI[tid] = d.lI[k];
-            sJ[tid] = d.lJ[k];
+            L.I = d.lI[k];
+            L.J = d.lJ[k];
+            sl[tid] = L;
         }
         __syncthreads();
         const int nb = (int)min((int64_t)kWG, d.nlens - base);
         for (int k2 = 0; k2 < nb; ++k2) {
-            const bool near = abs(sI[k2] - I) <= d.H && abs(sJ[k2] - J) <= d.H;
-            T wx = sx[k2] - zx, wy = sy[k2] - zy;
-            T r2 = fma(wx, wx, wy * wy);
-            r2 = near ? (T)1 : r2;
-            const T m = near ? (T)0 : sm[k2];
+            const CoefLens<T> L = sl[k2];
+            const bool near = ((unsigned)(L.I - Ilo) <= span) & ((unsigned)(L.J - Jlo) <= span);
+            T wx = L.x - zx, wy = L.y - zy;
+            const T r2 = fma(wx, wx, fma(wy, wy, tiny));
+            const T m = near ? (T)0 : L.m;
             // u = 1 / (z_k - z_c) = conj(w) / |w|^2; t = m u^(n+1)
             const T inv = recip_nr2(r2);
             const T ux = wx * inv, uy = -wy * inv;
