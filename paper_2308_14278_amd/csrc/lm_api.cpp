@@ -1082,6 +1082,8 @@ lm_status batch_build(lm_batch* b, int64_t limit_items)
                              r[3] > 0 ? (r[1] + r[3] - 1) / R - r[1] / R + 1 : 1, b->g_scale);
         ds[k] = make_desc(m, r[0], r[1], r[0] + r[2], r[1] + r[3], e);
         if (r[2] == 0 || r[3] == 0) ds[k].ntiles = 0;
+        if (ds[k].ntiles > 0x7fffffffLL)
+            return fail(LM_EUNSUPPORTED, "map %d: too many workgroup tiles", k);
         const double lenses = m->g.scheme == LM_SCHEME_INTERP
                                   ? 9.0 * std::max(1.0, (double)m->nlens / std::max<int64_t>(1, m->n1x * m->n1y))
                                   : (double)m->nlens;

@@ -415,15 +415,24 @@ __device__ __forceinline__ float local_offset(int64_t k, int64_t c, int R, float
 
 // ------------------------------------------------------------ lens lists
 
-// Near-lens rows of the level-1 cell holding level-2 cell (ci, cj): row r in
-// [0, 2H] is the contiguous sorted range [start, end) of level-1 cells
-// (I-H..I+H, J-H+r).
-__device__ __forceinline__ void near_row(const LmDesc& d, int64_t ci, int64_t cj, int r, int& s,
-                                         int& e)
+// Level-1 cell (I, J) of level-2 cell (ci, cj).  The interpolated scheme keeps
+// fewer than 2^30 level-2 cells, so 32-bit division does (a 64-bit division
+// is a long scalar sequence, and this runs once per unit of 64 x R rays).
+struct L1Cell {
+    int I, J;
+};
+
+__device__ __forceinline__ L1Cell l1_of(const LmDesc& d, int64_t ci, int64_t cj)
 {
-    int I = (int)(ci / d.Kx), J = (int)(cj / d.Ky);
-    int row = J + r;  // padded row of J - H + r is (J - H + r) + H
-    int base = row * d.nl1x + I;  // padded column of I - H is I
+    return L1Cell{(int)ci / d.Kx, (int)cj / d.Ky};
+}
+
+// Near-lens rows of level-1 cell c: row r in [0, 2H] is the contiguous sorted
+// range [start, end) of level-1 cells (I-H..I+H, J-H+r).
+__device__ __forceinline__ void near_row(const LmDesc& d, L1Cell c, int r, int& s, int& e)
+{
+    int row = c.J + r;  // padded row of J - H + r is (J - H + r) + H
+    int base = row * d.nl1x + c.I;  // padded column of I - H is I
     s = d.cell_start[base];
     e = d.cell_start[base + 2 * d.H + 1];
 }
@@ -432,10 +441,11 @@ template <int SCHEME>
 __device__ __forceinline__ int list_count(const LmDesc& d, int64_t ci, int64_t cj)
 {
     if (SCHEME == 0) return (int)d.nlens;
+    const L1Cell c = l1_of(d, ci, cj);
     int n = 0;
     for (int r = 0; r <= 2 * d.H; ++r) {
         int s, e;
-        near_row(d, ci, cj, r, s, e);
+        near_row(d, c, r, s, e);
         n += e - s;
     }
     return n;
@@ -463,10 +473,11 @@ __device__ void stage(const LmDesc& d, int64_t ci, int64_t cj, int b0, int nb, d
     if (SCHEME == 0) {
         for (int s = lane; s < nb; s += 64) lb[s] = lens_value<PREC>(d, b0 + s, zcx, zcy);
     } else {
+        const L1Cell c = l1_of(d, ci, cj);
         int off = 0;
         for (int r = 0; r <= 2 * d.H; ++r) {
             int s, e;
-            near_row(d, ci, cj, r, s, e);
+            near_row(d, c, r, s, e);
             int lo = max(off, b0), hi = min(off + (e - s), b0 + nb);
             for (int k = lo + lane; k < hi; k += 64)
                 lb[k - b0] = lens_value<PREC>(d, s + (k - off), zcx, zcy);
@@ -481,10 +492,11 @@ template <int SCHEME>
 __device__ __forceinline__ int list_index(const LmDesc& d, int64_t ci, int64_t cj, int pos)
 {
     if (SCHEME == 0) return pos;
+    const L1Cell c = l1_of(d, ci, cj);
     int off = 0;
     for (int r = 0; r <= 2 * d.H; ++r) {
         int s, e;
-        near_row(d, ci, cj, r, s, e);
+        near_row(d, c, r, s, e);
         if (pos < off + (e - s)) return s + (pos - off);
         off += e - s;
     }
@@ -898,16 +910,25 @@ __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_
     double ubx, uby;
     cell_base<SCHEME>(d, cic, cjc, ubx, uby);
     const double zcx = cell_cx(d, cic), zcy = cell_cy(d, cjc);
-    const int count = list_count<SCHEME>(d, cic, cjc);
     double sx = 0.0, sy = 0.0;
-    for (int k = 0; k < count; ++k) {
-        const int idx = list_index<SCHEME>(d, cic, cjc, k);
+    auto add = [&](int idx) {
         const double dx = zcx - d.lx[idx], dy = zcy - d.ly[idx];
         const double r2 = dx * dx + dy * dy;
         if (r2 > 0.0) {
             const double w = d.lmd[idx] / r2;
             sx += dx * w;
             sy += dy * w;
+        }
+    };
+    // the cell's lens list in list order
+    if (SCHEME == 0) {
+        for (int k = 0; k < (int)d.nlens; ++k) add(k);
+    } else {
+        const L1Cell c = l1_of(d, cic, cjc);
+        for (int r = 0; r <= 2 * d.H; ++r) {
+            int s, e;
+            near_row(d, c, r, s, e);
+            for (int idx = s; idx < e; ++idx) add(idx);
         }
     }
     ubx -= sx * d.inv_sdx;
@@ -927,7 +948,9 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
                              int lane)
 {
     const unsigned axb = (unsigned)ax0 + kBias, ayb = (unsigned)ay0 + kBias;
-    const int64_t tx = t % d.ntx, ty = t / d.ntx;
+    // fewer than 2^31 tiles per launch (checked on the host)
+    const int ntx = (int)d.ntx;
+    const int64_t tx = (int)t % ntx, ty = (int)t / ntx;
     const int64_t cib = (d.tcx0 + tx) * d.G, cjb = (d.tcy0 + ty) * d.G;
     const int per_cell = d.nrb * d.ncc;
     const int U = d.G * d.G * per_cell;
@@ -986,7 +1009,8 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<SCHEME, PREC>::value))) void k_shoot
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t t = d.tile0 + blockIdx.x;
     for (int b = tid; b < d.wx * d.wy; b += kWG) win[b] = 0u;
-    const int64_t tx = t % d.ntx, ty = t / d.ntx;
+    // fewer than 2^31 tiles per map (checked on the host)
+    const int64_t tx = (int)t % (int)d.ntx, ty = (int)t / (int)d.ntx;
     int ax0, ay0;
     tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
     __syncthreads();
@@ -1027,7 +1051,8 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
         }
         const LmDesc& d = descs[order[lo]];
         const int64_t t = item - offs[lo];
-        const int64_t tx = t % d.ntx, ty = t / d.ntx;
+        // fewer than 2^31 tiles per map (checked on the host)
+        const int64_t tx = (int)t % (int)d.ntx, ty = (int)t / (int)d.ntx;
         int ax0, ay0;
         tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
         process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave,
