@@ -521,10 +521,18 @@ __device__ __forceinline__ void load_taylor(const LmDesc& d, int64_t ci, int64_t
 
 // ------------------------------------------------------------- counting
 
+// A lane's pending run: biased pixel (p, q) as one 64-bit key (one compare per
+// ray) and the unit-local column of its first ray; its length is only formed
+// when the run is emitted.
 struct Run {
-    unsigned p, q;  // biased pixel
-    unsigned n;
+    unsigned long long key;  // p | q << 32
+    int start;
 };
+
+__device__ __forceinline__ unsigned long long run_key(unsigned p, unsigned q)
+{
+    return (unsigned long long)p | ((unsigned long long)q << 32);
+}
 
 // Add n rays at biased pixel (p, q): outside the map -> n_out, inside the
 // workgroup's window -> LDS, else a global atomic.  (axb, ayb) = biased window
@@ -545,42 +553,45 @@ __device__ __forceinline__ void emit(const Hot& h, unsigned p, unsigned q, unsig
 }
 
 // Lanes whose row lies outside the shot rectangle (row_ok false) keep runs like
-// every lane but never emit them, so the per-ray path needs no lane mask.
-__device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsigned q,
+// every lane but never emit them, so the per-ray path needs no lane mask.  col
+// is the unit-local column of the ray (rays are pushed column by column).
+__device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsigned q, int col,
                                          unsigned axb, unsigned ayb, unsigned* win,
                                          unsigned& nout, bool row_ok)
 {
-    // (a unit starts with an empty run, n = 0, at the out-of-map pixel
-    // kBias - 2, which emit books as n_out += 0)
-    if ((p != r.p) | (q != r.q)) {
-        if (row_ok) emit(h, r.p, r.q, r.n, axb, ayb, win, nout);
-        r.n = 0;
-        r.p = p;
-        r.q = q;
+    // (a unit starts with an empty run at the out-of-map pixel kBias - 2,
+    // which emit books as n_out += 0)
+    const unsigned long long key = run_key(p, q);
+    if (key != r.key) {
+        // one divergent region for every lane whose run ends
+        const unsigned n = row_ok ? (unsigned)(col - r.start) : 0u;
+        if (n) emit(h, (unsigned)r.key, (unsigned)(r.key >> 32), n, axb, ayb, win, nout);
+        r.key = key;
+        r.start = col;
     }
-    r.n += 1;
 }
 
-// End of a unit: lanes whose pending runs all name one pixel add it once.
-__device__ __forceinline__ void run_flush(const Hot& h, Run& r, unsigned axb, unsigned ayb,
-                                          unsigned* win, unsigned& nout, int lane, bool row_ok)
+// End of a unit (col_end = unit-local column after its last ray): lanes whose
+// pending runs all name one pixel add it once.
+__device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_end, unsigned axb,
+                                          unsigned ayb, unsigned* win, unsigned& nout, int lane,
+                                          bool row_ok)
 {
-    bool act = row_ok && r.n > 0;
+    const unsigned n = (unsigned)(col_end - r.start);
+    const unsigned rp = (unsigned)r.key, rq = (unsigned)(r.key >> 32);
+    bool act = row_ok && n > 0;
     unsigned long long am = __ballot(act);
     if (am) {
         int first = __builtin_ctzll(am);
-        unsigned p0 = __shfl(r.p, first, 64), q0 = __shfl(r.q, first, 64);
-        unsigned long long diff = __ballot(act && (r.p != p0 || r.q != q0));
+        unsigned p0 = __shfl(rp, first, 64), q0 = __shfl(rq, first, 64);
+        unsigned long long diff = __ballot(act && (rp != p0 || rq != q0));
         if (diff == 0) {
-            unsigned tot = wave_sum_u32(act ? r.n : 0u);
+            unsigned tot = wave_sum_u32(act ? n : 0u);
             if (lane == first) emit(h, p0, q0, tot, axb, ayb, win, nout);
         } else if (act) {
-            emit(h, r.p, r.q, r.n, axb, ayb, win, nout);
+            emit(h, rp, rq, n, axb, ayb, win, nout);
         }
     }
-    r.n = 0;
-    r.p = kBias - 2;
-    r.q = kBias - 2;
 }
 
 // Everything one ray row needs before its rays: the row offset, the biased
@@ -768,7 +779,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
     const int nblk = (count + kCap - 1) / kCap;
     if (nblk == 1) stage<SCHEME, PREC>(d, ci, cj, 0, count, zcx, zcy, lb, lane);
 
-    Run run{kBias - 2, kBias - 2, 0u};
+    Run run{run_key(kBias - 2, kBias - 2), (int)(c_beg - c_lo)};
     for (int64_t c0 = c_lo; c0 < c_hi; c0 += NR) {
         constexpr int D = Row<PREC, P, FOLD>::D;
         static_assert(D <= LM_PTAB_POW, "column table holds too few powers");
@@ -876,6 +887,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
         }
         const int ncol = (int)min((int64_t)NR, c_hi - c0);
         const int cfirst = (int)max((int64_t)0, c_beg - c0);
+        const int col0 = (int)(c0 - c_lo);
         if (cfirst == 0 && ncol == NR) {
             // a whole group (every group but a unit's first and last)
 #pragma unroll
@@ -883,7 +895,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 unsigned p, q;
                 ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
                                        NEGY ? -ay[c] : ay[c], p, q);
-                run_push(h, run, p, q, axb, ayb, win, nout, row_ok);
+                run_push(h, run, p, q, col0 + c, axb, ayb, win, nout, row_ok);
             }
         } else {
 #pragma unroll
@@ -892,12 +904,12 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                     unsigned p, q;
                     ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
                                            NEGY ? -ay[c] : ay[c], p, q);
-                    run_push(h, run, p, q, axb, ayb, win, nout, row_ok);
+                    run_push(h, run, p, q, col0 + c, axb, ayb, win, nout, row_ok);
                 }
             }
         }
     }
-    run_flush(h, run, axb, ayb, win, nout, lane, row_ok);
+    run_flush(h, run, (int)(c_hi - c_lo), axb, ayb, win, nout, lane, row_ok);
 }
 
 // Window origin of a tile: the pixel of the image of its centre cell's centre
