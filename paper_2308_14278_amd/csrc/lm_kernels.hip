@@ -2,7 +2,8 @@
 //
 //  k_coeffs       far-field Taylor coefficients of every level-2 cell (Sec. 3.2.2):
 //                 a_n = -sum_{far k} m_k / (z_k - z_c)^(n+1); lens tiles staged
-//                 in LDS, FP64 arithmetic (full-rate FP64 VALU on gfx950).
+//                 in LDS, FP64 arithmetic (FP64 FMA issues at the unpacked
+//                 FP32 rate on gfx950).
 //  k_shoot_map    one workgroup per tile of level-2 cells: per ray the near-lens
 //  k_shoot_batch  direct sum (Eq. 9) on offsets rebased to the cell centre
 //                 (FP32, or FP64 in the FP64 near-sum mode), the far-field
@@ -21,10 +22,10 @@
 // walks its row NR columns at a time.  Every ray of a unit shares the cell's
 // near-lens list, which the wave stages once in its own LDS slice, so the
 // lens loop is uniform and reads lenses as LDS broadcasts.  Quantities that
-// are the same for all 64 rows -- the column offsets (scalar loads), and per
-// column and lens dx^2 and m dx (an LDS table the wave fills 64 entries at a
-// time) -- are computed once per wave, and the rays of columns 2m and 2m+1
-// share one reciprocal per lens.
+// are the same for all 64 rows -- the column offsets and their powers (scalar
+// loads), and per column and lens dx^2 and m dx (an LDS table the wave fills
+// 64 entries at a time) -- are computed once per wave, and the rays of columns
+// 2m and 2m+1 share one reciprocal per lens.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -68,8 +69,8 @@ constexpr int kTabCh = 16;
 // Waves per SIMD the shooting kernels must keep: the FP32 table path is
 // issue-bound and needs 4 (at most 128 VGPRs with 256-thread workgroups, 4 per
 // CU).  The per-map kernel, whose descriptor arrives by value, would otherwise
-// allocate a few registers more than that and drop to 3; the hint makes the
-// compiler spill a few per-unit values instead.
+// allocate a few registers more than that and drop to 3; the hint holds it at
+// 128 (spilling per-unit values to scratch if it must).
 template <int SCHEME, int PREC>
 struct MinWaves {
     static constexpr int value = (SCHEME == 1 && PREC == 0) ? 4 : 1;

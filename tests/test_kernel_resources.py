@@ -7,47 +7,11 @@ VGPRs (no AGPRs) and 40 KiB of LDS per workgroup, no register spills to
 scratch memory.  A change that crosses the VGPR line drops occupancy to 3
 waves per SIMD and costs more than 10% of the shooting rate."""
 import os
-import re
-import shutil
-import subprocess
 
 import pytest
 
 import paper_2308_14278_amd.lensmap as lm
-
-LLVM = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin")
-TOOLS = ("llvm-objcopy", "clang-offload-bundler", "llvm-readelf")
-
-
-def _kernel_metadata(tmp_path):
-    if not all(os.path.exists(os.path.join(LLVM, t)) for t in TOOLS):
-        pytest.skip("ROCm LLVM tools not found")
-    if not os.path.exists(lm.LIB_PATH):
-        pytest.fail("liblensmap.so is not built")
-    fat = str(tmp_path / "fatbin")
-    co = str(tmp_path / "gfx950.co")
-    shutil.copy(lm.LIB_PATH, str(tmp_path / "lib.so"))
-    subprocess.run([os.path.join(LLVM, "llvm-objcopy"), "--dump-section", ".hip_fatbin=" + fat,
-                    str(tmp_path / "lib.so"), str(tmp_path / "stripped.so")], check=True)
-    subprocess.run([os.path.join(LLVM, "clang-offload-bundler"), "--type=o",
-                    "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + fat,
-                    "--output=" + co, "--unbundle"], check=True)
-    notes = subprocess.run([os.path.join(LLVM, "llvm-readelf"), "--notes", co], check=True,
-                           capture_output=True, text=True).stdout
-    kernels, cur = {}, {}
-    for line in notes.splitlines():
-        m = re.match(r"\s+-?\s*\.(\w+):\s+(\S+)\s*$", line)
-        if not m:
-            continue
-        key, val = m.groups()
-        if key == "agpr_count" and cur:
-            kernels[cur.get("name", "")] = cur
-            cur = {}
-        cur[key] = val
-    if cur:
-        kernels[cur.get("name", "")] = cur
-    return kernels
-
+from paper_2308_14278_amd import codeobj
 
 # <scheme 1 (interpolated), precision 0 (mixed), NR 16, P 4>; the batch kernel
 # must fit without spills, the per-map kernel (descriptor by value, held to 4
@@ -56,8 +20,12 @@ DEFAULT = (("_ZN12_GLOBAL__N_113k_shoot_batchILi1ELi0ELi16ELi4EEEvPK6LmDescPKlPK
            ("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi0ELi16ELi4EEEv6LmDesc", 4))
 
 
-def test_default_shooting_kernels_fit_four_waves_per_simd(tmp_path):
-    kernels = _kernel_metadata(tmp_path)
+def test_default_shooting_kernels_fit_four_waves_per_simd():
+    if not codeobj.tools_available():
+        pytest.skip("ROCm LLVM tools not found")
+    if not os.path.exists(lm.LIB_PATH):
+        pytest.fail("liblensmap.so is not built")
+    kernels = codeobj.kernel_metadata()
     for name, max_spill in DEFAULT:
         assert name in kernels, "kernel %s not in the code object" % name
         k = kernels[name]
@@ -69,3 +37,12 @@ def test_default_shooting_kernels_fit_four_waves_per_simd(tmp_path):
         assert int(k["private_segment_fixed_size"]) <= 4 * max_spill
         assert int(k["group_segment_fixed_size"]) <= 40 * 1024
         assert int(k["max_flat_workgroup_size"]) == 256
+
+
+def test_code_hash_ignores_rebuild_identity():
+    """The machine-code hash that keys the traffic measurements is a pure
+    function of the code: two reads of the same library agree."""
+    if not codeobj.tools_available():
+        pytest.skip("ROCm LLVM tools not found")
+    a, b = codeobj.code_sha(), codeobj.code_sha()
+    assert a is not None and a == b and len(a) == 16
