@@ -301,7 +301,9 @@ lm_status lm_batch_set_rect(lm_batch* b, int32_t index, int64_t i0, int64_t j0, 
  * shape.  Synchronous. */
 lm_status lm_batch_tune(lm_batch* b, const char* cache_path);
 
-/* Shoot every map's rectangle once (one graph launch). Asynchronous on `stream`. */
+/* Shoot every map's rectangle once (one graph launch). Asynchronous on `stream`.
+ * LM_EUNSUPPORTED if a map's rectangle needs 2^31 or more workgroup tiles
+ * (only the direct scheme on an extreme lattice can). */
 lm_status lm_batch_shoot(lm_batch* b, void* stream);
 
 /* Device time of the last lm_batch_shoot, from events recorded on its stream
