@@ -49,9 +49,10 @@ def load_traffic(launch_rays):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    # the counters hold for the machine code they were taken on
+    # the counters hold for the machine code of the kernel they were taken on
     from paper_2308_14278_amd import codeobj
-    if t.get("code_sha") is None or t.get("code_sha") != codeobj.code_sha():
+    sym = t.get("kernel_symbol")
+    if not sym or t.get("kernel_code_sha") != codeobj.kernel_code_sha(sym):
         return None
     return t["bytes_per_ray"] * launch_rays
 

@@ -1,10 +1,11 @@
 """The gfx950 code object inside the built liblensmap.so: kernel resource
-metadata (registers, LDS, spills) and a hash of its machine code.
+metadata (registers, LDS, spills) and per-kernel hashes of the machine code.
 
-The hash covers the code object's .text only: it is stable across rebuilds of
-the same source (symbol names carry a per-build id) and changes exactly when
-the generated code changes, so measurements of a kernel (HBM traffic counters)
-can be tied to the code they were taken on.
+A kernel's hash covers its function bytes only: it is stable across rebuilds
+of the same source (symbol names carry a per-build id) and across changes to
+other kernels, and changes exactly when that kernel's generated code changes,
+so measurements of a kernel (HBM traffic counters) can be tied to the code
+they were taken on.
 """
 from __future__ import annotations
 
@@ -60,14 +61,32 @@ def kernel_metadata(lib: str = lensmap.LIB_PATH) -> dict:
     return kernels
 
 
-def code_sha(lib: str = lensmap.LIB_PATH) -> str | None:
-    """sha256[:16] of the code object's .text, or None without the tools."""
+def kernel_code_sha(symbol: str, lib: str = lensmap.LIB_PATH) -> str | None:
+    """sha256[:16] of one kernel's machine code (its function bytes in .text),
+    or None without the tools or the symbol.  Other kernels changing size or
+    place leave it unchanged (branches are relative and the shooting kernels
+    address no global data)."""
     if not tools_available() or not os.path.exists(lib):
         return None
     with tempfile.TemporaryDirectory() as tmp:
         co = _extract(lib, tmp)
-        text = os.path.join(tmp, "text.bin")
-        subprocess.run([os.path.join(LLVM, "llvm-objcopy"), "--dump-section", ".text=" + text, co,
-                        os.path.join(tmp, "co2.o")], check=True, capture_output=True)
-        with open(text, "rb") as f:
-            return hashlib.sha256(f.read()).hexdigest()[:16]
+        readelf = os.path.join(LLVM, "llvm-readelf")
+        syms = subprocess.run([readelf, "--symbols", co], check=True, capture_output=True,
+                              text=True).stdout
+        secs = subprocess.run([readelf, "-S", "-W", co], check=True, capture_output=True,
+                              text=True).stdout
+        addr = size = None
+        for line in syms.splitlines():
+            f = line.split()
+            if len(f) >= 8 and f[-1] == symbol and f[3] == "FUNC":
+                addr, size = int(f[1], 16), int(f[2])
+        text = None
+        for line in secs.splitlines():
+            m = re.search(r"\]\s+\.text\s+\S+\s+([0-9a-f]+)\s+([0-9a-f]+)\s+([0-9a-f]+)", line)
+            if m:
+                text = (int(m.group(1), 16), int(m.group(2), 16), int(m.group(3), 16))
+        if addr is None or text is None or not (text[0] <= addr and addr + size <= text[0] + text[2]):
+            return None
+        with open(co, "rb") as fh:
+            fh.seek(text[1] + (addr - text[0]))
+            return hashlib.sha256(fh.read(size)).hexdigest()[:16]

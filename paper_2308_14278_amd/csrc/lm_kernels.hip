@@ -57,23 +57,23 @@ struct Prec<2> {
     using L = double4;
 };
 
-// The rebased interpolated paths (FP32 or FP64 near sums) share the
-// column-lens differences of a wave through an LDS table (kTabCh lenses at a
-// time).
+// The interpolated scheme shares the column-lens differences of a wave through
+// an LDS table (kTabCh lenses at a time), in every precision: rebased FP32 or
+// FP64 offsets, and the plain path's global FP32 coordinates.
 template <int SCHEME, int PREC>
 struct UseTab {
-    static constexpr bool value = SCHEME == 1 && PREC != 1;
+    static constexpr bool value = SCHEME == 1;
 };
 constexpr int kTabCh = 16;
 
-// Waves per SIMD the shooting kernels must keep: the FP32 table path is
+// Waves per SIMD the shooting kernels must keep: the FP32 table paths are
 // issue-bound and needs 4 (at most 128 VGPRs with 256-thread workgroups, 4 per
 // CU).  The per-map kernel, whose descriptor arrives by value, would otherwise
 // allocate a few registers more than that and drop to 3; the hint holds it at
 // 128 (spilling per-unit values to scratch if it must).
 template <int SCHEME, int PREC>
 struct MinWaves {
-    static constexpr int value = (SCHEME == 1 && PREC == 0) ? 4 : 1;
+    static constexpr int value = (SCHEME == 1 && PREC != 2) ? 4 : 1;
 };
 
 __device__ __forceinline__ void wave_sync_lds()

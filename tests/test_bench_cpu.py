@@ -24,15 +24,15 @@ def test_algorithmic_flops_formula():
 
 
 def test_traffic_only_for_the_measured_machine_code(monkeypatch, tmp_path):
-    rec = {"code_sha": "0123456789abcdef", "bytes_per_ray": 0.5}
+    rec = {"kernel_symbol": "k", "kernel_code_sha": "0123456789abcdef", "bytes_per_ray": 0.5}
     path = tmp_path / "traffic.json"
     path.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
-    monkeypatch.setattr(codeobj, "code_sha", lambda lib=None: "0123456789abcdef")
+    monkeypatch.setattr(codeobj, "kernel_code_sha", lambda sym, lib=None: "0123456789abcdef")
     assert bench.load_traffic(1000) == 500.0
-    monkeypatch.setattr(codeobj, "code_sha", lambda lib=None: "fedcba9876543210")
+    monkeypatch.setattr(codeobj, "kernel_code_sha", lambda sym, lib=None: "fedcba9876543210")
     assert bench.load_traffic(1000) is None
-    monkeypatch.setattr(codeobj, "code_sha", lambda lib=None: None)
+    monkeypatch.setattr(codeobj, "kernel_code_sha", lambda sym, lib=None: None)
     assert bench.load_traffic(1000) is None
     path.write_text("not json")
     assert bench.load_traffic(1000) is None
@@ -41,7 +41,7 @@ def test_traffic_only_for_the_measured_machine_code(monkeypatch, tmp_path):
 def test_stored_traffic_record_names_its_code():
     with open(bench.TRAFFIC_FILE) as f:
         rec = json.load(f)
-    assert len(rec["code_sha"]) == 16
+    assert len(rec["kernel_code_sha"]) == 16 and rec["kernel_symbol"].startswith("_Z")
     assert rec["bytes"] == pytest.approx(rec["bytes_per_ray"] * rec["rays"])
     assert rec["bytes"] == pytest.approx(rec["fetch_kib"] * 1024 * rec["fetch_scale"]
                                          + rec["write_kib"] * 1024 * rec["write_scale"])

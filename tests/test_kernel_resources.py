@@ -39,10 +39,13 @@ def test_default_shooting_kernels_fit_four_waves_per_simd():
         assert int(k["max_flat_workgroup_size"]) == 256
 
 
-def test_code_hash_ignores_rebuild_identity():
-    """The machine-code hash that keys the traffic measurements is a pure
-    function of the code: two reads of the same library agree."""
+def test_kernel_code_hash_is_a_function_of_the_code():
+    """The per-kernel machine-code hash that keys the traffic measurements: two
+    reads of the same library agree, and distinct kernels hash apart."""
     if not codeobj.tools_available():
         pytest.skip("ROCm LLVM tools not found")
-    a, b = codeobj.code_sha(), codeobj.code_sha()
-    assert a is not None and a == b and len(a) == 16
+    a = codeobj.kernel_code_sha(DEFAULT[0][0])
+    assert a is not None and len(a) == 16
+    assert codeobj.kernel_code_sha(DEFAULT[0][0]) == a
+    assert codeobj.kernel_code_sha(DEFAULT[1][0]) not in (None, a)
+    assert codeobj.kernel_code_sha("no_such_kernel") is None
