@@ -333,9 +333,9 @@ lm_status lm_measure_valu_peak(double* fma_tflops, double* pair_gpairs);
  * instructions per second: rates[0] v_mul_f32 (two-source VOP2), rates[1]
  * v_fmac_f32 (VOP2), rates[2] v_fma_f32 with a scalar operand (VOP3), rates[3]
  * v_rcp_f32; rates[4] the shooting kernel's near-pair pattern (two columns
- * sharing one reciprocal) in pairs per second.  The first min(n, 5) entries
- * are written.  Synchronous, well under a second.  LM_EINVAL for rates NULL
- * or n < 0. */
+ * sharing one reciprocal) in pairs per second; rates[5] v_fma_f64.  The first
+ * min(n, 6) entries are written.  Synchronous, well under a second.  LM_EINVAL
+ * for rates NULL or n < 0. */
 lm_status lm_measure_issue_rates(double* rates, int32_t n);
 
 /* Description of the last failure on this thread ("" if none). */

@@ -60,6 +60,31 @@ __global__ __launch_bounds__(256) void k_pair_peak(float* out, int iters, float 
 // (VOP2, accumulator form); 2: v_fma_f32 with a scalar operand (VOP3); 3:
 // v_rcp_f32; 4: the shooting kernel's pair pattern, two columns sharing one
 // reciprocal (add, add, mul, rcp, mul, mul, 4 fmac per two pairs).
+// FP64 issue probe: 8 independent v_fma_f64 accumulator chains per lane, 4
+// instructions per chain and iteration (the coefficient kernel's and the FP64
+// near-sum mode's workhorse).
+__global__ __launch_bounds__(256) void k_issue_f64(float* out, int iters)
+{
+    double a[kChains], b[kChains], x[kChains];
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) {
+        a[k] = 1.0 + 1e-3 * (double)threadIdx.x + (double)k;
+        b[k] = 0.999 - 1e-4 * (double)k;
+        x[k] = 1.0 + 0.01 * (double)k;
+    }
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[k] = __builtin_fma(a[k], u & 1 ? b[k] : -b[k], x[k]);
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) s += x[k];
+    if (s == 1234.5) out[threadIdx.x] = (float)s;  // keeps the chains alive
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_issue(float* out, int iters, float s0, float s1)
 {
@@ -106,9 +131,15 @@ __global__ __launch_bounds__(256) void k_issue(float* out, int iters, float s0, 
 template <int MODE>
 float time_issue(dim3 grid, float* out, int iters, hipEvent_t e0, hipEvent_t e1)
 {
-    hipLaunchKernelGGL(k_issue<MODE>, grid, dim3(256), 0, nullptr, out, iters, 0.999f, 1e-3f);
-    (void)hipEventRecord(e0, nullptr);
-    hipLaunchKernelGGL(k_issue<MODE>, grid, dim3(256), 0, nullptr, out, iters, 0.999f, 1e-3f);
+    // MODE 5: the FP64 probe
+    for (int rep = 0; rep < 2; ++rep) {
+        if (rep == 1) (void)hipEventRecord(e0, nullptr);
+        if constexpr (MODE == 5)
+            hipLaunchKernelGGL(k_issue_f64, grid, dim3(256), 0, nullptr, out, iters);
+        else
+            hipLaunchKernelGGL(k_issue<MODE>, grid, dim3(256), 0, nullptr, out, iters, 0.999f,
+                               1e-3f);
+    }
     (void)hipEventRecord(e1, nullptr);
     float ms = -1.f;
     if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
@@ -133,20 +164,21 @@ extern "C" lm_status lm_measure_issue_rates(double* rates, int32_t n)
     const int iters = 1 << 11;
     const dim3 grid(cus * 16);
     const double lanes = (double)grid.x * 256;
-    float ms[5];
+    float ms[6];
     ms[0] = time_issue<0>(grid, out, iters, e0, e1);
     ms[1] = time_issue<1>(grid, out, iters, e0, e1);
     ms[2] = time_issue<2>(grid, out, iters, e0, e1);
     ms[3] = time_issue<3>(grid, out, iters, e0, e1);
     ms[4] = time_issue<4>(grid, out, iters, e0, e1);
+    ms[5] = time_issue<5>(grid, out, iters, e0, e1);
     lm_status st = LM_OK;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
         if (ms[k] <= 0.f) {
             st = LM_EDEVICE;
             break;
         }
-        // modes 0-3: lane instructions per second; mode 4: near pairs per second
-        const double units = k < 4 ? lanes * iters * kChains * 4 : lanes * iters * kChains;
+        // modes 0-3 and 5: lane instructions per second; mode 4: near pairs per second
+        const double units = k != 4 ? lanes * iters * kChains * 4 : lanes * iters * kChains;
         if (k < n) rates[k] = units / (ms[k] * 1e-3);
     }
     (void)hipEventDestroy(e0);

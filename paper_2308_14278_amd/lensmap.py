@@ -408,12 +408,12 @@ def lm_read_coeffs(m, ci, cj, terms):
 
 def lm_measure_issue_rates():
     """Measured issue rates on the current device: dict of lane instructions/s
-    for VOP2 mul, VOP2 fmac, VOP3 fma (scalar operand), rcp, and near pairs/s
-    of the shooting kernel's shared-reciprocal pattern."""
-    r = (ctypes.c_double * 5)()
-    _check(load().lm_measure_issue_rates(r, 5), "lm_measure_issue_rates")
+    for VOP2 mul, VOP2 fmac, VOP3 fma (scalar operand), rcp, FP64 fma, and near
+    pairs/s of the shooting kernel's shared-reciprocal pattern."""
+    r = (ctypes.c_double * 6)()
+    _check(load().lm_measure_issue_rates(r, 6), "lm_measure_issue_rates")
     return {"v_mul_f32": r[0], "v_fmac_f32": r[1], "v_fma_f32_sgpr": r[2], "v_rcp_f32": r[3],
-            "pair2_pairs": r[4]}
+            "pair2_pairs": r[4], "v_fma_f64": r[5]}
 
 
 def lm_measure_valu_peak():
