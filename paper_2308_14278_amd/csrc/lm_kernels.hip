@@ -560,8 +560,8 @@ __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsig
                                          unsigned axb, unsigned ayb, unsigned* win,
                                          unsigned& nout, bool row_ok)
 {
-    // (a unit starts with an empty run at the out-of-map pixel kBias - 2,
-    // which emit books as n_out += 0)
+    // (a unit starts with an empty run at the out-of-map pixel kBias - 2;
+    // runs of length 0 are never emitted)
     const unsigned long long key = run_key(p, q);
     if (key != r.key) {
         // one divergent region for every lane whose run ends
