@@ -48,7 +48,7 @@ typedef int32_t lm_status;
 #define LM_EDEVICE (-3)       /* a HIP call failed */
 #define LM_ESTATE (-4)        /* call not allowed in the current state */
 #define LM_ERANGE (-5)        /* index range outside the lattice or map */
-#define LM_EUNSUPPORTED (-6)  /* valid request this build does not handle */
+#define LM_EUNSUPPORTED (-6)  /* valid request the library does not handle */
 
 #define LM_SCHEME_DIRECT 0    /* every lens summed for every ray */
 #define LM_SCHEME_INTERP 1    /* near lenses direct, far lenses by Taylor coefficients */
