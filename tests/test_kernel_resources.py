@@ -17,7 +17,10 @@ from paper_2308_14278_amd import codeobj
 # must fit without spills, the per-map kernel (descriptor by value, held to 4
 # waves by an attribute) may spill a few per-unit values to scratch
 DEFAULT = (("_ZN12_GLOBAL__N_113k_shoot_batchILi1ELi0ELi16ELi4EEEvPK6LmDescPKlPKiiPy", 0),
-           ("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi0ELi16ELi4EEEv6LmDesc", 4))
+           ("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi0ELi16ELi4EEEv6LmDesc", 4),
+           # the plain FP32 comparison path (precision 1), per map and batched
+           ("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi1ELi16ELi4EEEv6LmDesc", 4),
+           ("_ZN12_GLOBAL__N_113k_shoot_batchILi1ELi1ELi16ELi4EEEvPK6LmDescPKlPKiiPy", 0))
 
 
 def test_default_shooting_kernels_fit_four_waves_per_simd():
