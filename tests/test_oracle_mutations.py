@@ -1,6 +1,7 @@
 """The oracle's pins must catch plausible slips.  Each case plants one mistake in
 a copy of the oracle source (on the CPU, in a temporary directory), rebuilds it
-and checks that the pin suite then fails."""
+and checks that the pin suite then fails.  Mistakes in lensoracle.c run the map
+pins; mistakes in analysis.py (the scales of Sec. 4) run the analysis pins."""
 import os
 import shutil
 import subprocess
@@ -38,10 +39,24 @@ MUTATIONS = {
                                     "for (int64_t n = q; n < Q - 1; ++n) {"),
 }
 
+# slips in the analysis scales (Eq. 13-15 and the s_f definition)
+ANALYSIS_MUTATIONS = {
+    "s_w_exponent": ("s_w = 2.0 / sin_a * math.sqrt(kappa_c) * ratio ** 2",
+                     "s_w = 2.0 / sin_a * math.sqrt(kappa_c) * ratio ** 1.5"),
+    "n_cf_exponent": ("n_cf = math.sqrt(2.0 * c_star / sin_a) * ratio ** 0.75",
+                      "n_cf = math.sqrt(2.0 * c_star / sin_a) * ratio ** 0.5"),
+    "c_star_constant": ("math.log(3.05 * math.sqrt(n_star))", "math.log(3.5 * math.sqrt(n_star))"),
+    "s_f_sqrt_dropped": ("s_f = c_star * math.sqrt(kappa_star)", "s_f = c_star * kappa_star"),
+    "kappa_c_exponent": ("** (2.0 / 3.0)", "** (3.0 / 2.0)"),
+    "sin_a_from_d_y": ("sin_a = abs(d_x) / d", "sin_a = abs(d_y) / d"),
+    "mu_peak_per_radian_dropped": ("d_per_rad = math.hypot(d_x, d_y) * (180.0 * 60.0 / math.pi)",
+                                   "d_per_rad = math.hypot(d_x, d_y)"),
+    "mu_peak_falloff_exponent": ("(s_w / b) ** 0.375", "(s_w / b) ** 0.75"),
+    "mu_peak_ratio_inverted": ("(kappa_c / kappa_star) ** 0.75", "(kappa_star / kappa_c) ** 0.75"),
+}
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_pins_catch_planted_mistake(name, tmp_path):
-    before, after = MUTATIONS[name]
+
+def _copy_tree(tmp_path):
     d = tmp_path / "copy"
     shutil.copytree(os.path.join(ROOT, "oracle"), d / "oracle",
                     ignore=shutil.ignore_patterns("*.so", "*.tmp*", "__pycache__"))
@@ -51,11 +66,34 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     pkg.mkdir()
     (pkg / "__init__.py").write_text("")
     shutil.copy(os.path.join(ROOT, "paper_2308_14278_amd", "inputs.py"), pkg / "inputs.py")
-    src = (d / "oracle" / "lensoracle.c").read_text()
+    return d
+
+
+def _plant(d, rel, before, after):
+    path = d / "oracle" / rel
+    src = path.read_text()
     assert before in src
-    (d / "oracle" / "lensoracle.c").write_text(src.replace(before, after))
+    path.write_text(src.replace(before, after))
+
+
+def _pins_fail(d, files):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py", "tests/test_oracle_fold.py",
-                        "tests/test_oracle_hier.py"], cwd=d,
-                       capture_output=True, text=True, timeout=600)
-    assert r.returncode != 0, "planted mistake %r was not caught:\n%s" % (name, r.stdout[-2000:])
+                        *files], cwd=d, capture_output=True, text=True, timeout=600)
+    return r.returncode != 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(ANALYSIS_MUTATIONS))
+def test_analysis_pins_catch_planted_mistake(name, tmp_path):
+    d = _copy_tree(tmp_path)
+    _plant(d, "analysis.py", *ANALYSIS_MUTATIONS[name])
+    failed, out = _pins_fail(d, ["tests/test_oracle_analysis_pins.py"])
+    assert failed, "planted mistake %r was not caught:\n%s" % (name, out)
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    d = _copy_tree(tmp_path)
+    _plant(d, "lensoracle.c", *MUTATIONS[name])
+    failed, out = _pins_fail(d, ["tests/test_oracle_pins.py", "tests/test_oracle_fold.py",
+                                 "tests/test_oracle_hier.py"])
+    assert failed, "planted mistake %r was not caught:\n%s" % (name, out)

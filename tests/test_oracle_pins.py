@@ -140,7 +140,10 @@ def _rect_lenses(seed, n, hx, hy):
 def test_mean_magnification_and_protection_zone(oracle_lib):
     """Sec. 3.1: lenses plus the compensating sheet leave the mean macro
     magnification 1/|lt lr|; a protection zone of 10 sqrt(kappa_star) brings the
-    map to ~98% of it.  Without the zone the loss at the edges is larger."""
+    map to ~98% of it.  Without the zone the loss at the edges is larger.
+    The mean over these four seeded fields is 1.7% below macro (single fields
+    range from 0.3% to 2.5% below, so a 2.5% bound on the mean leaves about
+    two standard errors of margin)."""
     lt, lr, ks, side = 0.3, 0.5, 0.05, 40.0
     kappa, gamma = 1 - 0.5 * (lt + lr), 0.5 * (lr - lt)
     wbig = 60 * math.sqrt(ks)
@@ -158,7 +161,7 @@ def test_mean_magnification_and_protection_zone(oracle_lib):
             assert int(counts.sum()) + n_out == g.ray_nx * g.ray_ny
             rel[wm].append(counts.mean() * o.mu_factor() * lt * lr - 1.0)
     with_zone, without = np.mean(rel[10.0]), np.mean(rel[0.0])
-    assert -0.04 < with_zone < 0.0
+    assert -0.025 < with_zone < 0.0
     assert without < with_zone - 0.01
 
 
