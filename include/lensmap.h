@@ -57,11 +57,17 @@ typedef int32_t lm_status;
 #define LM_PREC_FP32 1        /* plain FP32 in global coordinates (comparison path) */
 #define LM_PREC_MIXED_FP64 2  /* as LM_PREC_MIXED with FP64 near-lens sums (interpolated
                                  scheme only; for pixels much finer than 1e-3 theta_E) */
+#define LM_PREC_AUTO 3        /* LM_PREC_MIXED or LM_PREC_MIXED_FP64, chosen by the library
+                                 for the map's current lenses and macro model: FP32 near
+                                 sums while their estimated bin mismatch is at most 5e-6
+                                 (see lm_precision_info); the direct scheme keeps
+                                 LM_PREC_MIXED */
 
 #define LM_MAX_TERMS 7        /* largest supported P */
 
 /*
- * Geometry of one map.  Source pixel (p, q) covers
+ * Geometry of one map (Sec. 3.2: the level-3 ray lattice, level-2 and level-1
+ * cells; Sec. 3.2.3: the source-plane pixels).  Source pixel (p, q) covers
  *   [src_x0 + p src_dx, src_x0 + (p+1) src_dx) x [src_y0 + q src_dy, src_y0 + (q+1) src_dy);
  * ray (i, j), 0 <= i < ray_nx, 0 <= j < ray_ny, sits at the centre of
  * level-3 pixel (i, j): (ray_x0 + (i+1/2) ray_dx, ray_y0 + (j+1/2) ray_dy)
@@ -94,7 +100,11 @@ typedef struct lm_geometry {
 } lm_geometry;
 
 /*
- * Derive a geometry from the paper's rules (Sec. 3.1, Sec. 3.2, Eq. 8, 10, 11):
+ * Derive a geometry from the paper's rules (Sec. 3.1, Sec. 3.2, Eq. 8, 10, 11).
+ * The paper states the problem by lambda_t = 1-kappa-gamma and lambda_r =
+ * 1-kappa+gamma (Eq. 1); this call takes kappa and gamma, which fix both, and
+ * the mean lens mass <m>, which turns the unit-mass N_star of Sec. 3.1 into a
+ * mass function's.  Rules:
  *  - the source square s = [-src_lx/2, src_lx/2] x [-src_ly/2, src_ly/2] is
  *    split into src_nx x src_ny pixels;
  *  - the protection zone widens s by `protect` on every side (protect < 0:
@@ -109,7 +119,8 @@ typedef struct lm_geometry {
  *  - coarse = R given (> 0), or 64 * max(1, round(min(L1x/L3x, L1y/L3y)/20/64))
  *    (level-2 = level-1/20, Sec. 3.2.2);
  *    l1_kx = max(1, round(L1x / (R L3x))), l1_ky likewise;
- *  - near_halo = 1, taylor_terms = 4, precision = LM_PREC_MIXED, far_order = 0.
+ *  - near_halo = 1, taylor_terms = 4, far_order = 0; precision = LM_PREC_AUTO
+ *    for the interpolated scheme, LM_PREC_MIXED for the direct one.
  * Rounding is half away from zero.  Returns LM_EINVAL for non-finite or
  * non-positive inputs or a singular macro map.
  */
@@ -127,7 +138,8 @@ lm_status lm_geometry_derive(lm_geometry* g, double src_lx, double src_ly, int32
  * L_ix = 2 sqrt(2 (src_lx + margin) / d_x), L_iy = src_ly / (2 (1 - kappa0)),
  * centred on the origin (with Table 1 it holds N_star = 13745 lenses); rays and
  * grid levels follow lm_geometry_derive (n_rays rays, Eq. 10, 11, level-2 =
- * level-1 / 20 unless coarse > 0).  d_x in 1/theta_E, d_x > 0.
+ * level-1 / 20 unless coarse > 0; precision as lm_geometry_derive).  d_x in
+ * 1/theta_E, d_x > 0.
  */
 lm_status lm_geometry_derive_fold(lm_geometry* g, double src_lx, double src_ly, int32_t src_nx,
                                   int32_t src_ny, double kappa0, double d_x, double kappa_star,
@@ -135,7 +147,8 @@ lm_status lm_geometry_derive_fold(lm_geometry* g, double src_lx, double src_ly, 
                                   double mean_mass);
 
 /*
- * Opt a geometry into the hierarchical far field: set g->far_order to the
+ * Opt a geometry into the hierarchical far field (an extension of the level-2
+ * Taylor coefficients of Sec. 3.2.2): set g->far_order to the
  * smallest Q in [taylor_terms, 64] for which the level-1 series meets its
  * truncation bound on this geometry (rho^Q / (1 - rho) <= 1e-9, rho the
  * largest ratio of a level-2 centre's and a far lens's distances from their
@@ -147,16 +160,17 @@ lm_status lm_geometry_far_order(lm_geometry* g);
 typedef struct lm_map lm_map;
 typedef struct lm_batch lm_batch;
 
-/* Create a map with the given geometry on the current HIP device.  Counts
+/* Create a map with the given geometry on the current HIP device (Sec. 3.2: the
+ * ray lattice and its cells; Sec. 3.2.3: one count per source pixel).  Counts
  * start at zero; the macro model is kappa = gamma = kappa_star = 0 and there
- * are no lenses until set.  LM_EINVAL for an invalid geometry (non-positive
+ * are no lenses until set.  The map owns its device buffers.  LM_EINVAL for an invalid geometry (non-positive
  * sizes, coarse not a positive multiple of 64, more than 2^31 rays per
  * workgroup tile, P outside 1..LM_MAX_TERMS, src_nx or src_ny above 2^30,
  * src_nx*src_ny >= 2^40). */
 lm_status lm_create(const lm_geometry* g, lm_map** out);
 
 /* Release every resource of the map (NULL is ignored).  Waits for the map's
- * outstanding work first. */
+ * outstanding work first.  (Resource management: no passage of the paper.) */
 void lm_destroy(lm_map* m);
 
 /* Macro convergence kappa, shear gamma and star convergence kappa_star of the
@@ -171,16 +185,19 @@ lm_status lm_set_macro(lm_map* m, double kappa, double gamma, double kappa_star)
  * arcmin^-1: multiply by theta_E in arcmin).  LM_ESTATE if the map has counts. */
 lm_status lm_set_fold(lm_map* m, double kappa0, double d_x, double d_y, double kappa_star);
 
-/* Copy n lenses: positions (x[k], y[k]) and masses mass[k] > 0.  n may be 0.
- * Sorts them by level-1 cell on the host and uploads them.  LM_EINVAL for
+/* Copy n point-mass microlenses (Sec. 2, Eq. 6): positions (x[k], y[k]) in
+ * theta_E and masses mass[k] > 0 in units of the unit mass of theta_E.  n may
+ * be 0.  Sorts them by level-1 cell (Sec. 3.2.1) on the host and uploads them;
+ * the arrays stay the caller's.  LM_EINVAL for NULL arrays with n > 0,
  * non-finite values or non-positive masses, LM_ESTATE if the map has counts. */
 lm_status lm_set_lenses(lm_map* m, const double* x, const double* y, const double* mass,
                         int64_t n);
 
 /* Use a caller-owned device buffer of src_nx*src_ny uint64 counts (row-major,
- * index q*src_nx + p) instead of the map's own; the buffer must outlive the map
- * or the next lm_bind_counts.  Its contents are taken as the current counts
- * (the caller clears it).  NULL returns to the map's own buffer. */
+ * index q*src_nx + p; the count array of Sec. 3.2.3) instead of the map's own;
+ * the buffer must outlive the map or the next lm_bind_counts.  Its contents are
+ * taken as the current counts (the caller clears it).  NULL returns to the
+ * map's own buffer.  Never fails for a non-NULL map (LM_EINVAL for NULL). */
 lm_status lm_bind_counts(lm_map* m, uint64_t* device_counts);
 
 /* Compute the level-2 Taylor coefficients of the far lenses (Sec. 3.2.2) for
@@ -190,12 +207,15 @@ lm_status lm_bind_counts(lm_map* m, uint64_t* device_counts);
 lm_status lm_prepare(lm_map* m, void* stream);
 
 /* Shoot the rays of the lattice sub-rectangle [i0, i0+ni) x [j0, j0+nj) and add
- * them to the counts (Sec. 3.2.3): rays landing outside the map are added to
- * n_out.  ni or nj = 0 is a no-op.  LM_ERANGE if the rectangle leaves the
- * lattice.  Asynchronous on `stream`. */
+ * them to the counts (Sec. 3.2.3; deflection by Eq. 9, lens equation Eq. 6):
+ * rays landing outside the map are added to n_out.  ni or nj = 0 is a no-op.
+ * LM_ERANGE if the rectangle leaves the lattice.  Asynchronous on `stream`,
+ * except that with LM_PREC_AUTO the first shot after new lenses or a new macro
+ * model waits for the precision probe (a few milliseconds). */
 lm_status lm_shoot(lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj, void* stream);
 
-/* Wait for all work issued on the map. */
+/* Wait for all work issued on the map (Sec. 3.2.3: the counts are complete
+ * before they are transferred). */
 lm_status lm_sync(lm_map* m);
 
 /* Copy the counts (src_nx*src_ny uint64, may be NULL), the number of rays that
@@ -203,12 +223,14 @@ lm_status lm_sync(lm_map* m);
  * host (Sec. 3.2.3: counts transferred to the CPU).  Synchronous. */
 lm_status lm_read_counts(lm_map* m, uint64_t* host_counts, uint64_t* n_out, uint64_t* n_shot);
 
-/* Sum of all counts, reduced on the device (for maps too large to copy back:
- * with n_out it checks that every shot ray was counted).  Synchronous. */
+/* Sum of all counts, reduced on the device (Sec. 3.2.3; for maps too large to
+ * copy back: with n_out it checks that every shot ray was counted).
+ * Synchronous.  LM_EINVAL for NULL arguments. */
 lm_status lm_sum_counts(lm_map* m, uint64_t* total);
 
 /* Copy the counts of the pixel window [p0, p0+np) x [q0, q0+nq) to host
- * memory (nq rows of np uint64).  LM_ERANGE if the window leaves the map.
+ * memory (nq rows of np uint64, caller-owned; Sec. 3.2.3, and Sec. 4.1 shows
+ * such a window of the paper's map).  LM_ERANGE if the window leaves the map.
  * Synchronous. */
 lm_status lm_read_counts_region(lm_map* m, int32_t p0, int32_t q0, int32_t np, int32_t nq,
                                 uint64_t* host_counts);
@@ -220,7 +242,8 @@ lm_status lm_mu_factor(const lm_map* m, double* factor);
  * Synchronous. */
 lm_status lm_read_mu(lm_map* m, double* host_mu);
 
-/* Zero the counts, n_out and the number of rays shot. Asynchronous on `stream`. */
+/* Zero the counts, n_out and the number of rays shot (Sec. 3.2.3: a fresh
+ * count array).  Asynchronous on `stream`. */
 lm_status lm_reset_counts(lm_map* m, void* stream);
 
 /* Far-field coefficients a_0..a_{P-1} of level-2 cell (ci, cj) as the shooting
@@ -230,17 +253,46 @@ lm_status lm_reset_counts(lm_map* m, void* stream);
  * lattice's level-2 cells; LM_EUNSUPPORTED for the direct scheme. */
 lm_status lm_read_coeffs(lm_map* m, int64_t ci, int64_t cj, double* a);
 
-/* Deflection alpha(theta) of the map's scheme and precision at n positions
- * theta_xy[2t], theta_xy[2t+1] (FP64, host), written to alpha_xy (host).  Uses
- * the same device arithmetic as the shooting kernel, with theta rebased on
- * the level-2 cell that contains it.  Synchronous; a test probe. */
+/* Deflection alpha(theta) of the map's scheme and precision (Eq. 9: near lenses
+ * summed directly, far lenses through the Taylor coefficients) at n arbitrary
+ * positions theta_xy[2t], theta_xy[2t+1] (FP64, host), written to alpha_xy
+ * (host).  theta is rebased on the level-2 cell that contains it and the near
+ * lenses are summed in the shooting kernel's order and precision, but one
+ * reciprocal per lens (the kernel shares one between two lattice columns) and
+ * the Taylor series by Horner (the kernel re-expands it per ray row), so its
+ * rounding differs slightly from the kernel's; lm_trace_beta gives the
+ * kernel's own values for lattice rays.  Synchronous; a test probe. */
 lm_status lm_deflect(lm_map* m, const double* theta_xy, int64_t n, double* alpha_xy);
 
 /* Pixels of listed lattice rays (i[t], j[t]): p[t], q[t] as the shooting
- * kernel computes them, -1 in both for rays that land outside the map.
- * Synchronous; a test probe.  LM_ERANGE for a ray outside the lattice. */
+ * kernel computes them (Sec. 3.2.3), -1 in both for rays that land outside the
+ * map.  Synchronous; a test probe.  LM_ERANGE for a ray outside the lattice. */
 lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int32_t* p,
                    int32_t* q);
+
+/* Source-plane positions beta (Eq. 6) of listed lattice rays (i[t], j[t]),
+ * beta_xy[2t], beta_xy[2t+1] in theta_E (host, caller-owned), from the values
+ * the shooting kernel takes the floor of when it bins the ray: the kernel's
+ * arithmetic, ray for ray, including the shared reciprocals and the per-row
+ * Taylor re-expansion.  With the macro map, beta gives the deflection the
+ * kernel used.  Synchronous; a test probe.  LM_ERANGE for a ray outside the
+ * lattice. */
+lm_status lm_trace_beta(lm_map* m, const int64_t* i, const int64_t* j, int64_t n,
+                        double* beta_xy);
+
+/* The precision the map's kernels run in (LM_PREC_*; never LM_PREC_AUTO) and,
+ * for an LM_PREC_AUTO geometry of the interpolated scheme, the estimated bin
+ * mismatch of FP32 near sums that chose it: the mean over 65536 fixed lattice
+ * rays (every ray of smaller lattices) of |du| + |dv|, the distance in pixels
+ * between the ray's image with FP32 and with FP64 near sums (rays imaged
+ * outside the map count 0) -- the chance that rounding moves an image across a
+ * pixel edge.  FP32 near sums are chosen while it is at most 5e-6; otherwise
+ * FP64.  The estimate is -1 when no choice was made (a fixed precision) and 0
+ * for a map without lenses.  The paper states no precision; this is the
+ * library's reading of the accuracy the maps need.  Synchronous (runs the
+ * probe if the lenses or the macro model changed).  Either pointer may be
+ * NULL. */
+lm_status lm_precision_info(lm_map* m, int32_t* precision, double* fp32_mismatch_estimate);
 
 /* Light-curve peak identification (Sec. 4.2) on the map's current counts.
  * A light curve is row i of the map (counts[i*src_nx + j], i along the
@@ -270,10 +322,12 @@ lm_status lm_fold_scales(double theta_e_arcsec, double d_x, double d_y, double k
                          double kappa_star, double n_star, double ds_over_r,
                          lm_fold_scales_t* out);
 
-/* Work of one shot, for throughput accounting: rays, ray-lens pairs of the
+/* Work of one shot, for throughput accounting (Sec. 3.2: direct shooting costs
+ * N_star x rays; the near/far split of Eq. 9): rays, ray-lens pairs of the
  * directly summed (near) lenses, and for the interpolated scheme the level-2
  * cells of the lattice and the (cell, far lens) pairs their Taylor
- * coefficients need (Sec. 3.2.2).  Host-only, from the lens partition. */
+ * coefficients need (Sec. 3.2.2).  Host-only, from the lens partition.
+ * LM_ERANGE for a rectangle outside the lattice. */
 typedef struct lm_stats {
     int64_t rays;
     double near_pairs;
@@ -283,38 +337,78 @@ typedef struct lm_stats {
 lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj,
                         lm_stats* out);
 
-/* Batched execution (80-map study, Sec. 4.2): the maps (same scheme,
- * precision and taylor_terms, same device, all with lenses) are shot together
- * by one persistent kernel fed from a work queue, preceded by their coefficient
- * kernels; both phases are captured once as HIP graphs and replayed.  Each map's shot rectangle is the one
- * given by lm_batch_set_rect (default: its whole lattice).  The batch keeps
- * pointers to the maps; they must outlive it and must not be changed
- * (lenses, macro, bound counts) while it exists. */
+/* Batched execution (the study of 80 maps, Sec. 4.2): the maps (same scheme
+ * and taylor_terms, same device) are shot together by persistent kernels fed
+ * from work queues -- one kernel per precision the maps run in -- preceded by
+ * their coefficient kernels; both phases are captured as HIP graphs and
+ * replayed.  Each map's shot rectangle is the one given by lm_batch_set_rect
+ * (default: its whole lattice).  The batch keeps pointers to the maps, which
+ * must outlive it.  A member map changed after the graphs were captured (new
+ * lenses, macro model or bound counts) is picked up by the next
+ * lm_batch_shoot, which captures the graphs again.  LM_EUNSUPPORTED for maps
+ * that differ in scheme, terms or device. */
 lm_status lm_batch_create(lm_map* const* maps, int32_t n, lm_batch** out);
+/* Shot rectangle of map `index` of the batch: [i0, i0+ni) x [j0, j0+nj) of its
+ * lattice (Sec. 3.2.3).  LM_ERANGE outside the lattice or for a bad index. */
 lm_status lm_batch_set_rect(lm_batch* b, int32_t index, int64_t i0, int64_t j0, int64_t ni,
                             int64_t nj);
 
 /* Pick execution parameters (rays per lane, workgroup tile size, workgroups
- * per CU) by timing candidates on a sample of the batch's work; counts are
- * restored to zero afterwards.  Results never depend on the choice.  The choice
- * is cached as JSON at cache_path (NULL: no cache) keyed by device and batch
- * shape.  Synchronous. */
+ * per CU) for the study of Sec. 4.2 by timing every candidate on one fixed
+ * sample of the batch's rays (lm_tune_sample of each map with the fraction
+ * that makes about 2e10 rays in all, or the whole batch if smaller): the
+ * fastest in rays/s wins.  Results never depend on the choice.  Unless the
+ * cache holds the choice, the maps must have no counts (LM_ESTATE); they are
+ * zero again afterwards.  The choice is
+ * cached at cache_path (NULL: no cache), a text file of lines "key
+ * rays_per_lane tile_scale wg_per_cu" keyed by device and batch shape.
+ * Synchronous. */
 lm_status lm_batch_tune(lm_batch* b, const char* cache_path);
 
-/* Shoot every map's rectangle once (one graph launch). Asynchronous on `stream`.
- * LM_EUNSUPPORTED if a map's rectangle needs 2^31 or more workgroup tiles
- * (only the direct scheme on an extreme lattice can). */
+/* One candidate timed by lm_batch_tune: its parameters, the rays of the
+ * tuning sample (the same for every candidate of a run) and the device time
+ * of one shooting launch over them. */
+typedef struct lm_tune_result {
+    int32_t rays_per_lane, tile_scale, wg_per_cu, lds_layout;
+    int64_t rays;
+    double seconds;
+} lm_tune_result;
+/* Candidates of the last lm_batch_tune that timed (none after a cache hit):
+ * *n gets their number, out[0 .. min(max, *n)) the records (host, caller-owned).
+ * LM_EINVAL for NULL b or n, max < 0, or out NULL with max > 0. */
+lm_status lm_batch_tune_results(const lm_batch* b, lm_tune_result* out, int32_t max, int32_t* n);
+
+/* The tuning sample of one map (host only, no device needed): the
+ * sub-rectangle of its shot rectangle [i0, i0+ni) x [j0, j0+nj) centred in it,
+ * each side scaled by sqrt(fraction) and rounded up to whole level-2 cells (at
+ * most the side), written to rect[0..4) as (i0, j0, ni, nj).  It depends on
+ * the geometry, the rectangle and the fraction only, so every candidate of a
+ * tuning run shoots the same rays; *tiles (may be NULL) gets the number of
+ * workgroup tiles the sample spans with the given tile scale (1..8), which
+ * does depend on the candidate.  LM_EINVAL for a bad geometry, fraction
+ * outside (0, 1] or tile scale outside 1..8; LM_ERANGE for a rectangle outside
+ * the lattice. */
+lm_status lm_tune_sample(const lm_geometry* g, int64_t i0, int64_t j0, int64_t ni, int64_t nj,
+                         double fraction, int32_t tile_scale, int64_t* rect, int64_t* tiles);
+
+/* Shoot every map's rectangle once (Sec. 3.2.3 for each map of the study of
+ * Sec. 4.2): two graph launches, coefficients then shooting.  Asynchronous on
+ * `stream` (capturing the graphs again first when needed, which waits for the
+ * precision probes of LM_PREC_AUTO maps).  LM_EUNSUPPORTED if a map's
+ * rectangle needs 2^31 or more workgroup tiles (only the direct scheme on an
+ * extreme lattice can). */
 lm_status lm_batch_shoot(lm_batch* b, void* stream);
 
 /* Device time of the last lm_batch_shoot, from events recorded on its stream
  * around its two graph launches: all coefficient kernels (with the queue
- * reset), and the shooting kernel alone (ms, either pointer may be NULL).
- * Waits for that launch to finish. */
+ * reset), and the shooting kernels alone (ms, either pointer may be NULL).
+ * Waits for that launch to finish.  LM_ESTATE before the first shot.
+ * (Measurement: no passage of the paper.) */
 lm_status lm_batch_timing(lm_batch* b, float* coeff_ms, float* shoot_ms);
 
 /* Execution parameters in use: rays per lane, tile scale (multiplier of the
  * default level-2 cells per workgroup tile side), workgroups per CU (0: as many
- * as fit).  Any pointer may be NULL. */
+ * as fit).  Any pointer may be NULL.  (Execution shape: no passage.) */
 lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* tile_cells,
                           int32_t* wg_per_cu);
 /* Set the execution parameters by hand instead of lm_batch_tune: rays per
@@ -325,7 +419,7 @@ lm_status lm_batch_set_params(lm_batch* b, int32_t rays_per_lane, int32_t tile_c
 void lm_batch_destroy(lm_batch* b);
 
 /* Device micro-benchmarks on the current device (diagnostics for the
- * roofline): the issue rate of independent unpacked FP32 FMAs in TFLOP/s, and
+ * roofline; no passage of the paper): the issue rate of independent unpacked FP32 FMAs in TFLOP/s, and
  * the rate of the near-lens pair instruction mix in 1e9 ray-lens pairs/s.
  * Either pointer may be NULL.  Synchronous; takes well under a second. */
 lm_status lm_measure_valu_peak(double* fma_tflops, double* pair_gpairs);
@@ -338,10 +432,11 @@ lm_status lm_measure_valu_peak(double* fma_tflops, double* pair_gpairs);
  * for rates NULL or n < 0. */
 lm_status lm_measure_issue_rates(double* rates, int32_t n);
 
-/* Description of the last failure on this thread ("" if none). */
+/* Description of the last failure on this thread ("" if none); owned by the
+ * library, valid until the next call on the thread. */
 const char* lm_last_error(void);
 
-/* Library version string. */
+/* Library version string (static storage). */
 const char* lm_version(void);
 
 #ifdef __cplusplus

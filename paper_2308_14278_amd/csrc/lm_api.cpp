@@ -117,7 +117,7 @@ lm_status validate_geometry(const lm_geometry* g)
     if (g->scheme != LM_SCHEME_DIRECT && g->scheme != LM_SCHEME_INTERP)
         return fail(LM_EINVAL, "unknown scheme %d", g->scheme);
     if (g->precision != LM_PREC_MIXED && g->precision != LM_PREC_FP32 &&
-        g->precision != LM_PREC_MIXED_FP64)
+        g->precision != LM_PREC_MIXED_FP64 && g->precision != LM_PREC_AUTO)
         return fail(LM_EINVAL, "unknown precision %d", g->precision);
     if (g->precision == LM_PREC_MIXED_FP64 && g->scheme != LM_SCHEME_INTERP)
         return fail(LM_EUNSUPPORTED, "LM_PREC_MIXED_FP64 is built for the interpolated scheme only");
@@ -177,6 +177,15 @@ struct lm_map {
     uint64_t n_shot = 0;
     hipStream_t last = nullptr;
     int rays_per_lane = 16;
+    // bumped by every call that changes what a batch's captured launches read
+    // (lens buffers and count, macro model, counts buffer)
+    uint64_t gen = 0;
+    uint64_t model_gen = 0;  // bumped by changes of the lenses or the macro model
+    // precision the kernels run in: the geometry's, or for LM_PREC_AUTO the
+    // one chosen for the current lenses and macro model (prec_gen == gen)
+    int prec = LM_PREC_MIXED;
+    uint64_t prec_gen = ~0ull;
+    double prec_est = -1.0;  // LM_PREC_AUTO: estimated FP32 near-sum bin mismatch
 };
 
 namespace {
@@ -194,15 +203,31 @@ struct Exec {
     int G = 1, ncc = 1, cw = 64, wx = 64, wy = 64;
 };
 
+// Level-2 cells per side of a workgroup tile: about 512 rays per side times the
+// tile scale, fewer if a rectangle of ncells_x x ncells_y cells would then give
+// fewer than 4096 tiles (too few to fill the device) or a tile would hold 1e9
+// rays or more.
+int tile_cells(int R, int64_t ncells_x, int64_t ncells_y, int g_scale)
+{
+    int G = std::max(1, 512 / R) * std::max(1, g_scale);
+    while (G > 1 && ceil_div(ncells_x, G) * ceil_div(ncells_y, G) < 4096) G /= 2;
+    while (G > 1 && (double)G * G * R * R > 1.0e9) G /= 2;
+    return G;
+}
+
+// Level-2 cells of the rectangle i0 + [0, ni) x j0 + [0, nj) per side.
+void rect_cells(int R, int64_t i0, int64_t j0, int64_t ni, int64_t nj, int64_t& cx, int64_t& cy)
+{
+    cx = ni > 0 ? (i0 + ni - 1) / R - i0 / R + 1 : 1;
+    cy = nj > 0 ? (j0 + nj - 1) / R - j0 / R + 1 : 1;
+}
+
 Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scale)
 {
     const lm_geometry& g = m->g;
     Exec e;
     const int R = g.coarse;
-    int G = std::max(1, 512 / R) * std::max(1, g_scale);
-    // keep enough tiles to fill the device, and tile ray counts well below 2^32
-    while (G > 1 && ceil_div(ncells_x, G) * ceil_div(ncells_y, G) < 4096) G /= 2;
-    while (G > 1 && (double)G * G * R * R > 1.0e9) G /= 2;
+    const int G = tile_cells(R, ncells_x, ncells_y, g_scale);
     e.G = G;
     const int nrb = R / 64;
     int ncc = 1;
@@ -367,6 +392,89 @@ lm_status prepare(lm_map* m, hipStream_t s)
     return LM_OK;
 }
 
+uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+constexpr int64_t kPrecSample = 65536;   // rays probed to choose the near-sum precision
+constexpr double kPrecFp32Max = 5e-6;    // largest estimated FP32 mismatch kept in FP32
+
+// LM_PREC_AUTO: the near-sum precision for the current lenses and macro model.
+// A ray changes pixel when rounding moves its image across a pixel edge; for
+// images spread evenly over their pixels that happens with probability
+// |du| + |dv|, the move in pixel units.  The FP32 near sums' bin mismatch is
+// estimated as the mean of that move, FP32 against FP64 near sums, over a
+// fixed sample of lattice rays (all of them on small lattices; a ray whose
+// image lies outside the map counts 0).  FP32 is kept while the estimate is
+// at most kPrecFp32Max, half the 1e-5 bar; otherwise the near pairs are summed
+// in FP64.  The direct scheme has no FP64 near-sum mode and keeps
+// LM_PREC_MIXED (its FP32 sums are compensated per 256-lens block).
+lm_status resolve_precision(lm_map* m, hipStream_t s)
+{
+    if (m->g.precision != LM_PREC_AUTO) {
+        m->prec = m->g.precision;
+        return LM_OK;
+    }
+    if (m->prec_gen == m->model_gen) return LM_OK;
+    if (m->g.scheme != LM_SCHEME_INTERP || m->nlens == 0) {
+        m->prec = LM_PREC_MIXED;
+        m->prec_est = 0.0;
+        m->prec_gen = m->model_gen;
+        return LM_OK;
+    }
+    lm_status st;
+    if (!m->coef_valid) {
+        st = prepare(m, s);
+        if (st) return st;
+    }
+    const lm_geometry& g = m->g;
+    const int64_t nrays = g.ray_nx * g.ray_ny;
+    const int64_t n = std::min<int64_t>(kPrecSample, nrays);
+    std::vector<int64_t> hi(n), hj(n);
+    for (int64_t t = 0; t < n; ++t) {
+        if (n == nrays) {
+            hi[t] = t % g.ray_nx;
+            hj[t] = t / g.ray_nx;
+        } else {
+            hi[t] = (int64_t)(splitmix64(2 * (uint64_t)t) % (uint64_t)g.ray_nx);
+            hj[t] = (int64_t)(splitmix64(2 * (uint64_t)t + 1) % (uint64_t)g.ray_ny);
+        }
+    }
+    DevBuf di, dj, dp, dq, u32, u64;
+    if (di.ensure(n * 8) || dj.ensure(n * 8) || dp.ensure(n * 4) || dq.ensure(n * 4) ||
+        u32.ensure(n * 16) || u64.ensure(n * 16))
+        return fail(LM_ENOMEM, "cannot allocate the precision probe");
+    HIP_TRY(hipMemcpyAsync(di.p, hi.data(), n * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dj.p, hj.data(), n * 8, hipMemcpyHostToDevice, s));
+    const LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
+    LAUNCH_TRY(lm_launch_trace(d, g.scheme, LM_PREC_MIXED, g.taylor_terms, di.as<int64_t>(),
+                               dj.as<int64_t>(), n, dp.as<int32_t>(), dq.as<int32_t>(),
+                               u32.as<double>(), s));
+    LAUNCH_TRY(lm_launch_trace(d, g.scheme, LM_PREC_MIXED_FP64, g.taylor_terms, di.as<int64_t>(),
+                               dj.as<int64_t>(), n, dp.as<int32_t>(), dq.as<int32_t>(),
+                               u64.as<double>(), s));
+    std::vector<double> a(2 * n), b(2 * n);
+    HIP_TRY(hipMemcpyAsync(a.data(), u32.p, n * 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(b.data(), u64.p, n * 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (int64_t t = 0; t < n; ++t) {
+        const double u = b[2 * t], v = b[2 * t + 1];
+        if (!(u >= 0.0 && u < g.src_nx && v >= 0.0 && v < g.src_ny)) continue;
+        const double mv = std::fabs(a[2 * t] - u) + std::fabs(a[2 * t + 1] - v);
+        acc += std::isfinite(mv) ? std::min(1.0, mv) : 1.0;
+    }
+    m->prec_est = acc / (double)n;
+    m->prec = m->prec_est <= kPrecFp32Max ? LM_PREC_MIXED : LM_PREC_MIXED_FP64;
+    m->prec_gen = m->model_gen;
+    m->last = s;
+    return LM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -415,7 +523,7 @@ lm_status lm_geometry_derive(lm_geometry* g, double src_lx, double src_ly, int32
     g->ray_nx = ray_nx;
     g->ray_ny = ray_ny;
     g->scheme = scheme;
-    g->precision = LM_PREC_MIXED;
+    g->precision = scheme == LM_SCHEME_INTERP ? LM_PREC_AUTO : LM_PREC_MIXED;
     g->near_halo = 1;
     g->taylor_terms = 4;
     g->l1_kx = 1;
@@ -476,7 +584,7 @@ lm_status lm_geometry_derive_fold(lm_geometry* g, double src_lx, double src_ly, 
     g->ray_nx = ray_nx;
     g->ray_ny = ray_ny;
     g->scheme = scheme;
-    g->precision = LM_PREC_MIXED;
+    g->precision = scheme == LM_SCHEME_INTERP ? LM_PREC_AUTO : LM_PREC_MIXED;
     g->near_halo = 1;
     g->taylor_terms = 4;
     g->l1_kx = 1;
@@ -578,6 +686,8 @@ lm_status lm_set_macro(lm_map* m, double kappa, double gamma, double kappa_star)
     m->kappa_star = kappa_star;
     m->fold = false;
     m->fold_dx = m->fold_dy = 0.0;
+    ++m->gen;
+    ++m->model_gen;
     return ok();
 }
 
@@ -593,6 +703,8 @@ lm_status lm_set_fold(lm_map* m, double kappa0, double d_x, double d_y, double k
     m->fold = true;
     m->fold_dx = d_x;
     m->fold_dy = d_y;
+    ++m->gen;
+    ++m->model_gen;
     return ok();
 }
 
@@ -678,6 +790,8 @@ lm_status lm_set_lenses(lm_map* m, const double* x, const double* y, const doubl
     m->h_start.swap(start);
     m->nlens = n;
     m->coef_valid = false;
+    ++m->gen;
+    ++m->model_gen;
     return ok();
 }
 
@@ -692,6 +806,7 @@ lm_status lm_bind_counts(lm_map* m, uint64_t* device_counts)
         m->bound = false;
     }
     m->has_counts = true;  // contents are the caller's
+    ++m->gen;
     return ok();
 }
 
@@ -720,11 +835,13 @@ lm_status lm_shoot(lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj, vo
         st = prepare(m, s);
         if (st) return st;
     }
+    st = resolve_precision(m, s);
+    if (st) return st;
     const int64_t R = m->g.coarse;
     const Exec e = choose_exec(m, (i0 + ni - 1) / R - i0 / R + 1, (j0 + nj - 1) / R - j0 / R + 1, 1);
     LmDesc d = make_desc(m, i0, j0, i0 + ni, j0 + nj, e);
     if (d.ntiles > 0x7fffffffLL) return fail(LM_EUNSUPPORTED, "too many workgroup tiles");
-    LAUNCH_TRY(lm_launch_shoot_map(d, m->g.scheme, m->g.precision, m->g.taylor_terms,
+    LAUNCH_TRY(lm_launch_shoot_map(d, m->g.scheme, m->prec, m->g.taylor_terms,
                                    m->rays_per_lane, s));
     m->n_shot += (uint64_t)ni * (uint64_t)nj;
     m->has_counts = true;
@@ -881,23 +998,32 @@ lm_status lm_deflect(lm_map* m, const double* theta_xy, int64_t n, double* alpha
         st = prepare(m, nullptr);
         if (st) return st;
     }
+    st = resolve_precision(m, nullptr);
+    if (st) return st;
     DevBuf dth, dal;
     if (dth.ensure((size_t)n * 16) || dal.ensure((size_t)n * 16))
         return fail(LM_ENOMEM, "cannot allocate probe buffers");
     HIP_TRY(hipStreamSynchronize(m->last));
     HIP_TRY(hipMemcpy(dth.p, theta_xy, (size_t)n * 16, hipMemcpyHostToDevice));
     LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
-    LAUNCH_TRY(lm_launch_deflect(d, g.scheme, g.precision, g.taylor_terms, dth.as<double>(), n,
+    LAUNCH_TRY(lm_launch_deflect(d, g.scheme, m->prec, g.taylor_terms, dth.as<double>(), n,
                                  dal.as<double>(), nullptr));
     HIP_TRY(hipStreamSynchronize(nullptr));
     HIP_TRY(hipMemcpy(alpha_xy, dal.p, (size_t)n * 16, hipMemcpyDeviceToHost));
     return ok();
 }
 
-lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int32_t* p, int32_t* q)
+}  // extern "C"
+
+namespace {
+
+// Pixels (p, q; either may be null) and source positions (beta, 2 per ray, may
+// be null) of listed lattice rays, with the shooting kernel's arithmetic.
+lm_status trace_rays(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int32_t* p,
+                     int32_t* q, double* beta)
 {
     if (!m) return fail(LM_EINVAL, "map is NULL");
-    if (n < 0 || (n > 0 && (!i || !j || !p || !q))) return fail(LM_EINVAL, "bad arrays");
+    if (n < 0 || (n > 0 && (!i || !j))) return fail(LM_EINVAL, "bad arrays");
     if (n >= (int64_t(1) << 30)) return fail(LM_EUNSUPPORTED, "too many probe rays");
     if (n == 0) return ok();
     for (int64_t t = 0; t < n; ++t)
@@ -910,19 +1036,59 @@ lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int
         st = prepare(m, nullptr);
         if (st) return st;
     }
-    DevBuf di, dj, dp, dq;
+    st = resolve_precision(m, nullptr);
+    if (st) return st;
+    DevBuf di, dj, dp, dq, duv;
     if (di.ensure((size_t)n * 8) || dj.ensure((size_t)n * 8) || dp.ensure((size_t)n * 4) ||
-        dq.ensure((size_t)n * 4))
+        dq.ensure((size_t)n * 4) || (beta && duv.ensure((size_t)n * 16)))
         return fail(LM_ENOMEM, "cannot allocate probe buffers");
     HIP_TRY(hipStreamSynchronize(m->last));
     HIP_TRY(hipMemcpy(di.p, i, (size_t)n * 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(dj.p, j, (size_t)n * 8, hipMemcpyHostToDevice));
     LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
-    LAUNCH_TRY(lm_launch_trace(d, m->g.scheme, m->g.precision, m->g.taylor_terms, di.as<int64_t>(),
-                               dj.as<int64_t>(), n, dp.as<int32_t>(), dq.as<int32_t>(), nullptr));
+    LAUNCH_TRY(lm_launch_trace(d, m->g.scheme, m->prec, m->g.taylor_terms, di.as<int64_t>(),
+                               dj.as<int64_t>(), n, dp.as<int32_t>(), dq.as<int32_t>(),
+                               beta ? duv.as<double>() : nullptr, nullptr));
     HIP_TRY(hipStreamSynchronize(nullptr));
-    HIP_TRY(hipMemcpy(p, dp.p, (size_t)n * 4, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(q, dq.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (p) HIP_TRY(hipMemcpy(p, dp.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (q) HIP_TRY(hipMemcpy(q, dq.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (beta) {
+        HIP_TRY(hipMemcpy(beta, duv.p, (size_t)n * 16, hipMemcpyDeviceToHost));
+        // pixel coordinates -> source-plane position (pixel (p, q) starts at
+        // src_x0 + p src_dx, src_y0 + q src_dy)
+        for (int64_t t = 0; t < n; ++t) {
+            beta[2 * t] = m->g.src_x0 + beta[2 * t] * m->g.src_dx;
+            beta[2 * t + 1] = m->g.src_y0 + beta[2 * t + 1] * m->g.src_dy;
+        }
+    }
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_trace(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, int32_t* p, int32_t* q)
+{
+    if (n > 0 && (!p || !q)) return fail(LM_EINVAL, "bad arrays");
+    return trace_rays(m, i, j, n, p, q, nullptr);
+}
+
+lm_status lm_trace_beta(lm_map* m, const int64_t* i, const int64_t* j, int64_t n, double* beta_xy)
+{
+    if (n > 0 && !beta_xy) return fail(LM_EINVAL, "bad arrays");
+    return trace_rays(m, i, j, n, nullptr, nullptr, beta_xy);
+}
+
+lm_status lm_precision_info(lm_map* m, int32_t* precision, double* fp32_mismatch_estimate)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    lm_status st = use_device(m);
+    if (st) return st;
+    st = resolve_precision(m, nullptr);
+    if (st) return st;
+    if (precision) *precision = m->prec;
+    if (fp32_mismatch_estimate) *fp32_mismatch_estimate = m->prec_est;
     return ok();
 }
 
@@ -1034,21 +1200,32 @@ lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int
 
 // ==================================================================== batch
 
+// Maps of a batch whose kernels run in one precision (LM_PREC_*): one
+// persistent shooting launch over their tiles, fed from its own work counter.
+struct BatchGroup {
+    int nmaps = 0;
+    DevBuf offs, order;
+    int64_t total = 0;  // tiles in the queue
+    int grid = 0;
+};
+
 struct lm_batch {
     std::vector<lm_map*> maps;
     std::vector<int64_t> rect;  // 4 per map: i0, j0, ni, nj
-    int scheme = 0, precision = 0, terms = 4, device = 0;
+    std::vector<uint64_t> gens; // each map's generation when the graphs were built
+    int scheme = 0, terms = 4, device = 0;
     int rays_per_lane = 16, g_scale = 1, wg_per_cu = 0;
-    DevBuf descs, offs, order, queue;
-    int64_t total = 0;
-    int grid = 0;
+    DevBuf descs;               // one LmDesc per map
+    BatchGroup grp[3];          // indexed by precision
+    DevBuf queue;               // one counter per group
     hipStream_t cap = nullptr;
     // two graphs: every map's coefficients + queue reset, then the persistent
-    // shooting kernel; events on the caller's stream bracket both
+    // shooting kernels; events on the caller's stream bracket both
     hipGraphExec_t exec = nullptr, exec_pre = nullptr;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // start, coefficients done, shoot done
     bool launched = false;
     bool dirty = true;
+    std::vector<lm_tune_result> tuned;  // candidates timed by the last tuning run
     ~lm_batch()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -1068,18 +1245,26 @@ int device_cus(int dev)
     return n > 0 ? n : 256;
 }
 
-// Build descriptors, cost order and queue offsets; upload them.
-lm_status batch_build(lm_batch* b, int64_t limit_items)
+// Build descriptors, cost order and queue offsets of every precision group and
+// upload them.  work: the rectangles to shoot (4 per map; the batch's own, or
+// a tuning sample); tile sizes always follow the batch's own rectangles, so a
+// sample runs with the tiles of the real shot.
+lm_status batch_build(lm_batch* b, const std::vector<int64_t>& work)
 {
     const int n = (int)b->maps.size();
+    for (lm_map* m : b->maps) {
+        lm_status st = resolve_precision(m, b->cap);
+        if (st) return st;
+    }
     std::vector<LmDesc> ds(n);
     std::vector<double> cost(n);
     for (int k = 0; k < n; ++k) {
         lm_map* m = b->maps[k];
-        const int64_t* r = &b->rect[4 * k];
-        const int64_t R = m->g.coarse;
-        Exec e = choose_exec(m, r[2] > 0 ? (r[0] + r[2] - 1) / R - r[0] / R + 1 : 1,
-                             r[3] > 0 ? (r[1] + r[3] - 1) / R - r[1] / R + 1 : 1, b->g_scale);
+        const int64_t* r = &work[4 * k];
+        const int64_t* own = &b->rect[4 * k];
+        int64_t cx, cy;
+        rect_cells(m->g.coarse, own[0], own[1], own[2], own[3], cx, cy);
+        const Exec e = choose_exec(m, cx, cy, b->g_scale);
         ds[k] = make_desc(m, r[0], r[1], r[0] + r[2], r[1] + r[3], e);
         if (r[2] == 0 || r[3] == 0) ds[k].ntiles = 0;
         if (ds[k].ntiles > 0x7fffffffLL)
@@ -1089,33 +1274,37 @@ lm_status batch_build(lm_batch* b, int64_t limit_items)
                                   : (double)m->nlens;
         cost[k] = (double)r[2] * (double)r[3] * (20.0 + 6.0 * lenses);
     }
-    std::vector<int32_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-    std::vector<int64_t> offs(n + 1, 0);
-    for (int k = 0; k < n; ++k) offs[k + 1] = offs[k] + ds[order[k]].ntiles;
-    b->total = offs[n];
-    if (limit_items >= 0 && limit_items < b->total) {
-        // a shorter queue: the first items in cost order (tuning samples)
-        for (int k = 0; k <= n; ++k) offs[k] = std::min(offs[k], limit_items);
-        b->total = limit_items;
-    }
-    if (b->descs.ensure(n * sizeof(LmDesc)) || b->offs.ensure((n + 1) * 8) ||
-        b->order.ensure(n * 4) || b->queue.ensure(8))
+    if (b->descs.ensure(n * sizeof(LmDesc)) || b->queue.ensure(3 * 8))
         return fail(LM_ENOMEM, "cannot allocate batch tables");
     HIP_TRY(hipMemcpy(b->descs.p, ds.data(), n * sizeof(LmDesc), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b->offs.p, offs.data(), (n + 1) * 8, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b->order.p, order.data(), n * 4, hipMemcpyHostToDevice));
-    int occ = 0;
-    LAUNCH_TRY(lm_shoot_occupancy(b->scheme, b->precision, b->terms, b->rays_per_lane, &occ));
-    if (occ <= 0) occ = 1;
-    const int wg = b->wg_per_cu > 0 ? std::min(b->wg_per_cu, occ) : occ;
-    b->grid = device_cus(b->device) * wg;
+    for (int pr = 0; pr < 3; ++pr) {
+        BatchGroup& G = b->grp[pr];
+        std::vector<int32_t> order;
+        for (int k = 0; k < n; ++k)
+            if (b->maps[k]->prec == pr) order.push_back(k);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int c) { return cost[a] > cost[c]; });
+        G.nmaps = (int)order.size();
+        G.total = 0;
+        if (G.nmaps == 0) continue;
+        std::vector<int64_t> offs(G.nmaps + 1, 0);
+        for (int k = 0; k < G.nmaps; ++k) offs[k + 1] = offs[k] + ds[order[k]].ntiles;
+        G.total = offs[G.nmaps];
+        if (G.offs.ensure((G.nmaps + 1) * 8) || G.order.ensure(G.nmaps * 4))
+            return fail(LM_ENOMEM, "cannot allocate batch tables");
+        HIP_TRY(hipMemcpy(G.offs.p, offs.data(), (G.nmaps + 1) * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(G.order.p, order.data(), G.nmaps * 4, hipMemcpyHostToDevice));
+        int occ = 0;
+        LAUNCH_TRY(lm_shoot_occupancy(b->scheme, pr, b->terms, b->rays_per_lane, &occ));
+        if (occ <= 0) occ = 1;
+        const int wg = b->wg_per_cu > 0 ? std::min(b->wg_per_cu, occ) : occ;
+        G.grid = device_cus(b->device) * wg;
+    }
     return LM_OK;
 }
 
 // Enqueue phase 1 (coefficients of every map when asked, queue reset) and/or
-// phase 2 (persistent shoot).
+// phase 2 (the persistent shoot of every precision group).
 lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs, bool pre = true,
                         bool shoot = true)
 {
@@ -1127,12 +1316,16 @@ lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs, bool pre =
             LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
             LAUNCH_TRY(launch_coefficients(m, d, s));
         }
-    if (pre) LAUNCH_TRY(lm_launch_fill_u64(b->queue.as<unsigned long long>(), 1, 0ull, s));
-    if (shoot && b->total > 0)
-        LAUNCH_TRY(lm_launch_shoot_batch(b->descs.as<LmDesc>(), b->offs.as<int64_t>(),
-                                         b->order.as<int32_t>(), n,
-                                         b->queue.as<unsigned long long>(), b->scheme, b->precision,
-                                         b->terms, b->rays_per_lane, b->grid, s));
+    if (pre) LAUNCH_TRY(lm_launch_fill_u64(b->queue.as<unsigned long long>(), 3, 0ull, s));
+    if (shoot)
+        for (int pr = 0; pr < 3; ++pr) {
+            const BatchGroup& G = b->grp[pr];
+            if (G.total <= 0) continue;
+            LAUNCH_TRY(lm_launch_shoot_batch(b->descs.as<LmDesc>(), G.offs.as<int64_t>(),
+                                             G.order.as<int32_t>(), G.nmaps,
+                                             b->queue.as<unsigned long long>() + pr, b->scheme,
+                                             pr, b->terms, b->rays_per_lane, G.grid, s));
+        }
     return LM_OK;
 }
 
@@ -1160,7 +1353,14 @@ lm_status batch_graph(lm_batch* b)
             (void)hipGraphExecDestroy(*e);
             *e = nullptr;
         }
-    lm_status st = batch_build(b, -1);
+    // coefficients (and the precision choice) before the capture: nothing in
+    // the capture may synchronise
+    for (lm_map* m : b->maps) {
+        lm_status st = resolve_precision(m, b->cap);
+        if (st) return st;
+    }
+    HIP_TRY(hipStreamSynchronize(b->cap));
+    lm_status st = batch_build(b, b->rect);
     if (st) return st;
     for (hipEvent_t& e : b->ev)
         if (!e) HIP_TRY(hipEventCreate(&e));
@@ -1168,6 +1368,8 @@ lm_status batch_graph(lm_batch* b)
     if (st) return st;
     st = capture(b, false, true, &b->exec);
     if (st) return st;
+    b->gens.resize(b->maps.size());
+    for (size_t k = 0; k < b->maps.size(); ++k) b->gens[k] = b->maps[k]->gen;
     b->dirty = false;
     return LM_OK;
 }
@@ -1178,12 +1380,12 @@ std::string batch_key(const lm_batch* b)
     std::string dev = "unknown";
     if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) dev = prop.gcnArchName;
     std::ostringstream k;
-    k << dev << "|s" << b->scheme << "p" << b->precision << "t" << b->terms << "|n" << b->maps.size();
+    k << dev << "|s" << b->scheme << "t" << b->terms << "|n" << b->maps.size();
     uint64_t h = 1469598103934665603ull;
     for (size_t i = 0; i < b->maps.size(); ++i) {
         const lm_map* m = b->maps[i];
         const int64_t vals[] = {m->g.coarse, m->g.l1_kx, m->g.l1_ky, m->nlens, b->rect[4 * i + 2],
-                                b->rect[4 * i + 3], m->g.src_nx, m->g.src_ny};
+                                b->rect[4 * i + 3], m->g.src_nx, m->g.src_ny, m->prec};
         for (int64_t v : vals) {
             h ^= (uint64_t)v;
             h *= 1099511628211ull;
@@ -1193,7 +1395,7 @@ std::string batch_key(const lm_batch* b)
     return k.str();
 }
 
-// Minimal cache: one line per key, "key nr g wg".
+// Tuning cache: a text file of "key rays_per_lane tile_scale wg_per_cu" lines.
 bool cache_lookup(const char* path, const std::string& key, int& nr, int& gs, int& wg)
 {
     if (!path) return false;
@@ -1228,9 +1430,73 @@ void cache_store(const char* path, const std::string& key, int nr, int gs, int w
     f << key << " " << nr << " " << gs << " " << wg << "\n";
 }
 
+// Rays the tuner times each candidate on: about 2e10 (25 ms at 8e11 rays/s),
+// or the whole batch if it is smaller.
+constexpr double kTuneRays = 2.0e10;
+
+// The tuning sample of one map: the sub-rectangle of its shot rectangle
+// (i0, j0, ni, nj) centred in it, each side scaled by sqrt(fraction) and
+// rounded to whole level-2 cells (at least one, at most the side).  It depends
+// on nothing but the geometry, the rectangle and the fraction, so every
+// candidate of a tuning run shoots the same rays.
+void sample_rect(int R, const int64_t* r, double fraction, int64_t* out)
+{
+    const double f = std::sqrt(std::min(1.0, std::max(0.0, fraction)));
+    auto side = [&](int64_t lo, int64_t n, int64_t& slo, int64_t& sn) {
+        if (n <= 0) {
+            slo = lo;
+            sn = 0;
+            return;
+        }
+        int64_t want = (int64_t)std::ceil((double)n * f);
+        want = std::max<int64_t>(R, (want + R - 1) / R * R);
+        if (want >= n) {
+            slo = lo;
+            sn = n;
+            return;
+        }
+        // start on a cell boundary near the centre, inside the rectangle
+        int64_t s0 = lo + (n - want) / 2;
+        s0 = s0 / R * R;
+        if (s0 < lo) s0 += R;
+        if (s0 + want > lo + n) s0 = lo + n - want;
+        slo = s0;
+        sn = want;
+    };
+    side(r[0], r[2], out[0], out[2]);
+    side(r[1], r[3], out[1], out[3]);
+}
+
 }  // namespace
 
 extern "C" {
+
+lm_status lm_tune_sample(const lm_geometry* g, int64_t i0, int64_t j0, int64_t ni, int64_t nj,
+                         double fraction, int32_t tile_scale, int64_t* rect, int64_t* tiles)
+{
+    lm_status st = validate_geometry(g);
+    if (st) return st;
+    if (!rect) return fail(LM_EINVAL, "rect is NULL");
+    if (!(fraction > 0.0 && fraction <= 1.0)) return fail(LM_EINVAL, "fraction must be in (0, 1]");
+    if (tile_scale < 1 || tile_scale > 8) return fail(LM_EINVAL, "tile_scale must be in 1..8");
+    if (ni < 0 || nj < 0 || i0 < 0 || j0 < 0 || i0 > g->ray_nx - ni || j0 > g->ray_ny - nj)
+        return fail(LM_ERANGE, "rectangle leaves the lattice");
+    const int64_t r[4] = {i0, j0, ni, nj};
+    sample_rect(g->coarse, r, fraction, rect);
+    if (tiles) {
+        int64_t cx, cy;
+        rect_cells(g->coarse, i0, j0, ni, nj, cx, cy);
+        const int G = tile_cells(g->coarse, cx, cy, tile_scale);
+        *tiles = 0;
+        if (rect[2] > 0 && rect[3] > 0) {
+            const int64_t R = g->coarse;
+            const int64_t tx = (rect[0] + rect[2] - 1) / R / G - rect[0] / R / G + 1;
+            const int64_t ty = (rect[1] + rect[3] - 1) / R / G - rect[1] / R / G + 1;
+            *tiles = tx * ty;
+        }
+    }
+    return ok();
+}
 
 lm_status lm_batch_create(lm_map* const* maps, int32_t n, lm_batch** out)
 {
@@ -1244,13 +1510,12 @@ lm_status lm_batch_create(lm_map* const* maps, int32_t n, lm_batch** out)
         if (!m) return fail(LM_EINVAL, "map %d is NULL", k);
         if (k == 0) {
             b->scheme = m->g.scheme;
-            b->precision = m->g.precision;
             b->terms = m->g.scheme == LM_SCHEME_INTERP ? m->g.taylor_terms : 1;
             b->device = m->device;
-        } else if (m->g.scheme != b->scheme || m->g.precision != b->precision ||
+        } else if (m->g.scheme != b->scheme ||
                    (b->scheme == LM_SCHEME_INTERP && m->g.taylor_terms != b->terms) ||
                    m->device != b->device) {
-            return fail(LM_EUNSUPPORTED, "map %d differs in scheme, precision, terms or device", k);
+            return fail(LM_EUNSUPPORTED, "map %d differs in scheme, terms or device", k);
         }
         b->maps.push_back(m);
         const int64_t r[4] = {0, 0, m->g.ray_nx, m->g.ray_ny};
@@ -1290,7 +1555,11 @@ lm_status lm_batch_shoot(lm_batch* b, void* stream)
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != b->device) HIP_TRY(hipSetDevice(b->device));
-    if (b->dirty || !b->exec) {
+    // a member map changed since the graphs were captured: its lens buffers,
+    // macro constants or counts pointer in the captured launches are stale
+    bool stale = b->gens.size() != b->maps.size();
+    for (size_t k = 0; !stale && k < b->maps.size(); ++k) stale = b->gens[k] != b->maps[k]->gen;
+    if (b->dirty || !b->exec || stale) {
         lm_status st = batch_graph(b);
         if (st) return st;
     }
@@ -1317,41 +1586,59 @@ lm_status lm_batch_tune(lm_batch* b, const char* cache_path)
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != b->device) HIP_TRY(hipSetDevice(b->device));
+    for (lm_map* m : b->maps) {
+        lm_status st = resolve_precision(m, b->cap);
+        if (st) return st;
+    }
     const std::string key = batch_key(b);
     int nr = 0, gs = 0, wg = 0;
     if (!cache_lookup(cache_path, key, nr, gs, wg)) {
-        // coefficients once, then time each candidate on the same sample of tiles
+        for (lm_map* m : b->maps)
+            if (m->has_counts) return fail(LM_ESTATE, "tuning shoots: the maps must have no counts");
+        // coefficients once, then every candidate on the same sample of rays
         for (lm_map* m : b->maps) {
             lm_status st = prepare(m, b->cap);
             if (st) return st;
         }
         HIP_TRY(hipStreamSynchronize(b->cap));
+        double total = 0.0;
+        for (size_t k = 0; k < b->maps.size(); ++k)
+            total += (double)b->rect[4 * k + 2] * (double)b->rect[4 * k + 3];
+        const double frac = total > kTuneRays ? kTuneRays / total : 1.0;
+        std::vector<int64_t> sample(b->rect.size());
+        int64_t rays = 0;
+        for (size_t k = 0; k < b->maps.size(); ++k) {
+            sample_rect(b->maps[k]->g.coarse, &b->rect[4 * k], frac, &sample[4 * k]);
+            rays += sample[4 * k + 2] * sample[4 * k + 3];
+        }
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        float best = 1e30f;
+        b->tuned.clear();
+        double best = 1e300;
         const int nrs[] = {4, 8, 16};
         const int gss[] = {1, 2};
+        lm_status st = LM_OK;
         for (int cnr : nrs)
             for (int cgs : gss)
                 for (int cwg : {0, 2}) {
                     b->rays_per_lane = cnr;
                     b->g_scale = cgs;
                     b->wg_per_cu = cwg;
-                    const int64_t sample = (int64_t)device_cus(b->device) * 16;
-                    lm_status st = batch_build(b, sample);
-                    if (st) return st;
-                    st = batch_enqueue(b, b->cap, false);  // warm-up
-                    if (st) return st;
+                    st = batch_build(b, sample);
+                    if (!st) st = batch_enqueue(b, b->cap, false);  // warm-up
+                    if (st) break;
                     HIP_TRY(hipEventRecord(e0, b->cap));
                     st = batch_enqueue(b, b->cap, false);
-                    if (st) return st;
+                    if (st) break;
                     HIP_TRY(hipEventRecord(e1, b->cap));
                     HIP_TRY(hipEventSynchronize(e1));
                     float ms = 0;
                     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < best) {
-                        best = ms;
+                    lm_tune_result r{cnr, cgs, cwg, 0, rays, ms * 1e-3};
+                    b->tuned.push_back(r);
+                    if (r.seconds < best) {
+                        best = r.seconds;
                         nr = cnr;
                         gs = cgs;
                         wg = cwg;
@@ -1359,9 +1646,10 @@ lm_status lm_batch_tune(lm_batch* b, const char* cache_path)
                 }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        if (st) return st;
         cache_store(cache_path, key, nr, gs, wg);
         for (lm_map* m : b->maps) {
-            lm_status st = lm_reset_counts(m, b->cap);
+            st = lm_reset_counts(m, b->cap);
             if (st) return st;
         }
         HIP_TRY(hipStreamSynchronize(b->cap));
@@ -1370,6 +1658,14 @@ lm_status lm_batch_tune(lm_batch* b, const char* cache_path)
     b->g_scale = gs;
     b->wg_per_cu = wg;
     b->dirty = true;
+    return ok();
+}
+
+lm_status lm_batch_tune_results(const lm_batch* b, lm_tune_result* out, int32_t max, int32_t* n)
+{
+    if (!b || !n || max < 0 || (max > 0 && !out)) return fail(LM_EINVAL, "bad arguments");
+    *n = (int32_t)b->tuned.size();
+    for (int32_t k = 0; k < std::min<int32_t>(max, *n); ++k) out[k] = b->tuned[k];
     return ok();
 }
 

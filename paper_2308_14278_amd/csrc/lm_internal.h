@@ -86,8 +86,11 @@ int lm_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, v
 // *total (zeroed by the caller) += sum of p[0..n)
 int lm_launch_sum_u64(const unsigned long long* p, int64_t n, unsigned long long* total,
                       void* stream);
+// p, q: pixels (-1 outside the map); uv (may be null): continuous pixel
+// coordinates, 2 per ray, that the pixels are the floor of
 int lm_launch_trace(const LmDesc& d, int scheme, int precision, int terms, const int64_t* ii,
-                    const int64_t* jj, int64_t n, int32_t* p, int32_t* q, void* stream);
+                    const int64_t* jj, int64_t n, int32_t* p, int32_t* q, double* uv,
+                    void* stream);
 int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, const double* th,
                       int64_t n, double* alpha, void* stream);
 int lm_launch_peaks(const unsigned long long* counts, int64_t nx, int64_t ny,

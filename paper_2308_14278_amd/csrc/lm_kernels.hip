@@ -379,11 +379,12 @@ __device__ __forceinline__ void bin_rebased(double inv_sdx, double inv_sdy, doub
     q = cvt_u32_sat(v);
 }
 
-// Pixel of one ray in the plain FP32 path (global coordinates).
+// Continuous pixel coordinates (u, v) of one ray in the plain FP32 path
+// (global coordinates).
 template <int P, bool FOLD>
-__device__ __forceinline__ void bin_fp32(const Hot& h, const float* ar, const float* ai,
-                                         float a0r, float a0i, float zcx, float zcy, float tx,
-                                         float ty, float ax, float ay, int& p, int& q)
+__device__ __forceinline__ void coords_fp32(const Hot& h, const float* ar, const float* ai,
+                                            float a0r, float a0i, float zcx, float zcy, float tx,
+                                            float ty, float ax, float ay, float& u, float& v)
 {
     float fr, fi;
     float dx = tx - zcx, dy = ty - zcy;
@@ -394,8 +395,18 @@ __device__ __forceinline__ void bin_fp32(const Hot& h, const float* ar, const fl
     if (FOLD) mx = __builtin_fmaf(h.qxf, tx, __builtin_fmaf(h.qyf, ty, mx));
     float bx = __builtin_fmaf(mx, tx, -alx);
     float by = __builtin_fmaf(h.myf, ty, -aly);
-    float u = (bx - h.bx0f) * h.inv_sdxf;
-    float v = (by - h.by0f) * h.inv_sdyf;
+    u = (bx - h.bx0f) * h.inv_sdxf;
+    v = (by - h.by0f) * h.inv_sdyf;
+}
+
+// Pixel of one ray in the plain FP32 path.
+template <int P, bool FOLD>
+__device__ __forceinline__ void bin_fp32(const Hot& h, const float* ar, const float* ai,
+                                         float a0r, float a0i, float zcx, float zcy, float tx,
+                                         float ty, float ax, float ay, int& p, int& q)
+{
+    float u, v;
+    coords_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcx, zcy, tx, ty, ax, ay, u, v);
     bool in = (u >= 0.f) & (u < h.snxf) & (v >= 0.f) & (v < h.snyf);
     p = in ? (int)u : -1;
     q = in ? (int)v : -1;
@@ -1352,9 +1363,11 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
     }
 }
 
-// Per-ray pixels with the shooting kernel's arithmetic, lens for lens.
+// Per-ray pixels with the shooting kernel's arithmetic, lens for lens, and the
+// continuous pixel coordinates (u, v) the pixel is the floor of (uv non-null).
 template <int SCHEME, int PREC, int P, bool FOLD>
-__device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, int32_t& qo)
+__device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, int32_t& qo,
+                          double* uv)
 {
     using T = typename Prec<PREC>::T;
     const int R = d.R;
@@ -1380,19 +1393,34 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
     const bool in = (pm < (unsigned)d.snx) & (qm < (unsigned)d.sny);
     po = in ? (int32_t)pm : -1;
     qo = in ? (int32_t)qm : -1;
+    if (uv) {
+        if constexpr (PREC == 1) {
+            float u, v;
+            coords_fp32<P, FOLD>(h, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, rw.py,
+                                 ax, ay, u, v);
+            uv[0] = u;
+            uv[1] = v;
+        } else {
+            // the FP64 values bin_rebased floors, less the bias
+            uv[0] = __builtin_fma(-(double)ax, h.inv_sdx, rw.ubxb) - kBiasD;
+            uv[1] = __builtin_fma(-(double)ay, h.inv_sdy, rw.ubyb) - kBiasD;
+        }
+    }
 }
 
 template <int SCHEME, int PREC, int P>
 __global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restrict__ ii,
                                                const int64_t* __restrict__ jj, int64_t n,
-                                               int32_t* __restrict__ po, int32_t* __restrict__ qo)
+                                               int32_t* __restrict__ po, int32_t* __restrict__ qo,
+                                               double* __restrict__ uv)
 {
     const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
     if (t >= n) return;
+    double* u = uv ? uv + 2 * t : nullptr;
     if (d.fold)
-        trace_one<SCHEME, PREC, P, true>(d, ii[t], jj[t], po[t], qo[t]);
+        trace_one<SCHEME, PREC, P, true>(d, ii[t], jj[t], po[t], qo[t], u);
     else
-        trace_one<SCHEME, PREC, P, false>(d, ii[t], jj[t], po[t], qo[t]);
+        trace_one<SCHEME, PREC, P, false>(d, ii[t], jj[t], po[t], qo[t], u);
 }
 
 // Deflection at arbitrary positions, rebased on the level-2 cell holding them.
@@ -1675,12 +1703,13 @@ struct TraceLauncher {
     int64_t n;
     int32_t* p;
     int32_t* q;
+    double* uv;
     hipStream_t s;
     template <int S, int PR, int NR, int P>
     int go()
     {
         hipLaunchKernelGGL((k_trace<S, PR, P>), dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG),
-                           0, s, d, ii, jj, n, p, q);
+                           0, s, d, ii, jj, n, p, q, uv);
         return (int)hipGetLastError();
     }
 };
@@ -1701,11 +1730,12 @@ struct DeflectLauncher {
 }  // namespace
 
 int lm_launch_trace(const LmDesc& d, int scheme, int precision, int terms, const int64_t* ii,
-                    const int64_t* jj, int64_t n, int32_t* p, int32_t* q, void* stream)
+                    const int64_t* jj, int64_t n, int32_t* p, int32_t* q, double* uv,
+                    void* stream)
 {
     if (n <= 0) return 0;
     return dispatch_probe(scheme, precision, terms,
-                          TraceLauncher{d, ii, jj, n, p, q, (hipStream_t)stream});
+                          TraceLauncher{d, ii, jj, n, p, q, uv, (hipStream_t)stream});
 }
 
 int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, const double* th,

@@ -31,6 +31,7 @@ LM_SCHEME_INTERP = 1
 LM_PREC_MIXED = 0
 LM_PREC_FP32 = 1
 LM_PREC_MIXED_FP64 = 2
+LM_PREC_AUTO = 3
 LM_MAX_TERMS = 7
 
 _STATUS_NAMES = {0: "LM_OK", -1: "LM_EINVAL", -2: "LM_ENOMEM", -3: "LM_EDEVICE", -4: "LM_ESTATE",
@@ -70,6 +71,12 @@ class lm_fold_scales_t(ctypes.Structure):
                 ("kappa_c", "sin_a", "s_w", "c_star", "s_f", "n_cf", "mu_peak0")]
 
 
+class lm_tune_result(ctypes.Structure):
+    _fields_ = [("rays_per_lane", ctypes.c_int32), ("tile_scale", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("lds_layout", ctypes.c_int32),
+                ("rays", ctypes.c_int64), ("seconds", ctypes.c_double)]
+
+
 class lm_stats(ctypes.Structure):
     _fields_ = [("rays", ctypes.c_int64), ("near_pairs", ctypes.c_double),
                 ("cells", ctypes.c_int64), ("far_pairs", ctypes.c_double)]
@@ -107,6 +114,11 @@ _SIGS = {
     "lm_reset_counts": [_vp, _vp],
     "lm_deflect": [_vp, _d, ctypes.c_int64, _d],
     "lm_trace": [_vp, _i64, _i64, ctypes.c_int64, _i32, _i32],
+    "lm_trace_beta": [_vp, _i64, _i64, ctypes.c_int64, _d],
+    "lm_precision_info": [_vp, _i32, _d],
+    "lm_batch_tune_results": [_vp, _P(lm_tune_result), ctypes.c_int32, _i32],
+    "lm_tune_sample": [_P(lm_geometry), ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                       ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _i64, _i64],
     "lm_batch_create": [_P(_vp), ctypes.c_int32, _P(_vp)],
     "lm_batch_set_rect": [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                           ctypes.c_int64],
@@ -312,6 +324,49 @@ def lm_trace(m, i, j):
     return p, q
 
 
+def lm_trace_beta(m, i, j):
+    """Source positions beta[n, 2] (theta_E) of lattice rays, as the kernel bins them."""
+    i = np.ascontiguousarray(i, dtype=np.int64)
+    j = np.ascontiguousarray(j, dtype=np.int64)
+    out = np.empty((i.shape[0], 2), dtype=np.float64)
+    _check(load().lm_trace_beta(m, i.ctypes.data_as(_i64), j.ctypes.data_as(_i64), i.shape[0],
+                                out.ctypes.data_as(_d)), "lm_trace_beta")
+    return out
+
+
+def lm_precision_info(m):
+    """(precision the kernels run in, estimated FP32 near-sum bin mismatch or -1)."""
+    p = ctypes.c_int32()
+    e = ctypes.c_double()
+    _check(load().lm_precision_info(m, ctypes.byref(p), ctypes.byref(e)), "lm_precision_info")
+    return int(p.value), float(e.value)
+
+
+def lm_batch_tune_results(b):
+    """Candidates timed by the last lm_batch_tune: list of dicts with rays/s."""
+    n = ctypes.c_int32()
+    _check(load().lm_batch_tune_results(b, None, 0, ctypes.byref(n)), "lm_batch_tune_results")
+    arr = (lm_tune_result * max(1, n.value))()
+    _check(load().lm_batch_tune_results(b, arr, n.value, ctypes.byref(n)),
+           "lm_batch_tune_results")
+    out = []
+    for r in arr[:n.value]:
+        d = {f: getattr(r, f) for f, _ in r._fields_}
+        d["rays_per_s"] = r.rays / r.seconds if r.seconds > 0 else 0.0
+        out.append(d)
+    return out
+
+
+def lm_tune_sample(g, i0, j0, ni, nj, fraction, tile_scale=1):
+    """(rect (i0, j0, ni, nj), workgroup tiles) of the tuning sample of one map."""
+    rect = (ctypes.c_int64 * 4)()
+    tiles = ctypes.c_int64()
+    _check(load().lm_tune_sample(ctypes.byref(g), int(i0), int(j0), int(ni), int(nj),
+                                 float(fraction), int(tile_scale), rect, ctypes.byref(tiles)),
+           "lm_tune_sample")
+    return tuple(int(v) for v in rect), int(tiles.value)
+
+
 def lm_batch_create(maps):
     arr = (ctypes.c_void_p * len(maps))(*[m.value if isinstance(m, ctypes.c_void_p) else m
                                           for m in maps])
@@ -462,6 +517,12 @@ class Map:
 
     def deflect(self, theta):
         return lm_deflect(self.h, theta)
+
+    def trace_beta(self, i, j):
+        return lm_trace_beta(self.h, i, j)
+
+    def precision(self):
+        return lm_precision_info(self.h)
 
     def mu_factor(self):
         return lm_mu_factor(self.h)

@@ -81,7 +81,7 @@ def _good():
 
 @pytest.mark.parametrize("field,value", [("coarse", 100), ("coarse", 0), ("src_nx", 0),
                                          ("ray_dx", -1.0), ("taylor_terms", 9),
-                                         ("scheme", 5), ("precision", 3), ("l1_kx", 0),
+                                         ("scheme", 5), ("precision", 4), ("l1_kx", 0),
                                          ("ray_x0", float("inf"))])
 def test_create_rejects_invalid_geometry(field, value):
     g = _good()
@@ -166,3 +166,57 @@ def test_fold_geometry_matches_oracle(scale):
         assert getattr(gl, f) == getattr(go, f), f
     for f in ("src_x0", "src_y0", "src_dx", "src_dy", "ray_x0", "ray_y0", "ray_dx", "ray_dy"):
         assert math.isclose(getattr(gl, f), getattr(go, f), rel_tol=1e-14), f
+
+
+@pytest.mark.parametrize("kind", ["paper-scale", "near-fold", "precision-stress"])
+def test_tuning_sample_is_the_same_rays_for_every_candidate(kind):
+    """lm_batch_tune times every candidate on the same rays: the sample of a map
+    is a function of its geometry, shot rectangle and the fraction only, so
+    asking for it with each tile scale gives the same rectangle (whole level-2
+    cells, inside the shot rectangle, about the requested fraction of its rays)
+    while the number of workgroup tiles it spans changes with the tile scale."""
+    w = inputs.WORKLOADS[kind]()
+    g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                              w.gamma, w.kappa_star, protect=w.protect, n_rays=w.n_rays,
+                              scheme=w.scheme, coarse=w.coarse, mean_mass=w.mean_mass)
+    frac = min(1.0, 2e10 / g.n_rays)
+    rects, tiles = set(), []
+    for ts in range(1, 9):
+        rect, nt = lm.lm_tune_sample(g, 0, 0, g.ray_nx, g.ray_ny, frac, ts)
+        rects.add(rect)
+        tiles.append(nt)
+    assert len(rects) == 1
+    i0, j0, ni, nj = rects.pop()
+    R = g.coarse
+    assert i0 % R == 0 and j0 % R == 0
+    assert 0 <= i0 and i0 + ni <= g.ray_nx and 0 <= j0 and j0 + nj <= g.ray_ny
+    assert ni % R == 0 or i0 + ni == g.ray_nx
+    assert nj % R == 0 or j0 + nj == g.ray_ny
+    assert 0.5 * frac * g.n_rays <= ni * nj <= 2.0 * frac * g.n_rays + 4 * R * R
+    assert len(set(tiles)) > 1, tiles
+    # a sub-rectangle: the sample stays inside it
+    rect, _ = lm.lm_tune_sample(g, 1000, 7, g.ray_nx // 3, g.ray_ny // 2, 0.01, 1)
+    assert rect[0] >= 1000 and rect[0] + rect[2] <= 1000 + g.ray_nx // 3
+    assert rect[1] >= 7 and rect[1] + rect[3] <= 7 + g.ray_ny // 2
+    with pytest.raises(lm.LensmapError):
+        lm.lm_tune_sample(g, 0, 0, g.ray_nx, g.ray_ny, 0.0, 1)
+    with pytest.raises(lm.LensmapError):
+        lm.lm_tune_sample(g, 0, 0, g.ray_nx, g.ray_ny, 0.5, 9)
+
+
+def test_default_precision_is_the_librarys_choice():
+    """Derived geometries leave the near-sum precision to the library for the
+    interpolated scheme (LM_PREC_AUTO) and use the compensated FP32 sums of
+    the direct scheme (LM_PREC_MIXED)."""
+    for kind in ("plain-small", "near-fold", "paper-scale"):
+        w = inputs.WORKLOADS[kind]()
+        g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                                  w.gamma, w.kappa_star, protect=w.protect, n_rays=w.n_rays or 0,
+                                  ray_nx=w.ray_nx or 0, ray_ny=w.ray_ny or 0, scheme=w.scheme,
+                                  coarse=w.coarse, mean_mass=w.mean_mass)
+        want = lm.LM_PREC_AUTO if w.scheme == lm.LM_SCHEME_INTERP else lm.LM_PREC_MIXED
+        assert g.precision == want, kind
+    w = inputs.paper_table1()
+    g = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], w.src_pixels,
+                                   w.extra["src_ny"], *w.fold[:2], w.kappa_star, n_rays=w.n_rays)
+    assert g.precision == lm.LM_PREC_AUTO

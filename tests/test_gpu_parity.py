@@ -244,6 +244,69 @@ def test_deflection_interp_error_vs_direct():
     mp.close()
 
 
+def test_precision_stress_region_vs_oracle():
+    """Precision stress (lambda_t = 0.001, macro mu ~ 3300, 20000 lenses, 4e12-ray
+    lattice, 4000^2 map): the 1e9-ray region at the centre of the lattice, whole
+    map against the oracle, through the library's default precision choice."""
+    w = inputs.precision_stress()
+    g, mp, orc = _pair(w)
+    nj = 8 * g.coarse
+    ni = int(1e9 // nj)
+    i0, j0 = g.ray_nx // 2 - ni // 2, g.ray_ny // 2 - nj // 2
+    used, est = mp.precision()
+    _say("precision stress: runs in precision %d (FP32 mismatch estimate %.2e)" % (used, est))
+    mp.shoot(i0, j0, ni, nj)
+    counts, n_out, _ = mp.counts()
+    ref, ref_out = orc.shoot(i0, j0, ni, nj, nthreads=NTHREADS)
+    _compare(g, counts, n_out, ref, ref_out, ni * nj, "precision-stress 1e9-ray region")
+    mp.close()
+
+
+def test_default_precision_choice_on_the_workloads():
+    """The default (LM_PREC_AUTO) keeps FP32 near sums on the paper-scale and
+    near-fold workloads (the estimated FP32 mismatch is well below the bar
+    there), so the headline path is the FP32 one."""
+    for kind in ("paper-scale", "near-fold"):
+        w = inputs.WORKLOADS[kind]()
+        g, mp, _ = _pair(w)
+        assert g.precision == lm.LM_PREC_AUTO
+        used, est = mp.precision()
+        _say("%s: precision %d, FP32 mismatch estimate %.2e" % (kind, used, est))
+        assert used == lm.LM_PREC_MIXED and 0.0 <= est <= 5e-6
+        mp.close()
+
+
+def test_interp_error_of_kernel_arithmetic_1e6_rays():
+    """Sec. 3.2 (the interpolation error of the near/far split, quoted as
+    ~1e-7 theta_E): source positions of 1e6 sampled lattice rays of the
+    paper-scale map as the shooting kernel computes them (lm_trace_beta: shared
+    reciprocals, per-row Taylor re-expansion, FP32 near sums on rebased
+    offsets) against the oracle's direct sum over all 13000 lenses: within
+    1e-4 theta_E everywhere; and against the oracle's interpolated scheme:
+    within FP32 rounding."""
+    w = inputs.paper_scale()
+    g, mp, orc = _pair(w)
+    rng = np.random.default_rng(29)
+    n = 1_000_000
+    ii = rng.integers(0, g.ray_nx, n)
+    jj = rng.integers(0, g.ray_ny, n)
+    b_gpu = mp.trace_beta(ii, jj)
+    x, y, m = w.lenses()
+    gd = oracle_geom(g)
+    gd.scheme = oracle.SCHEME_DIRECT
+    b_dir, _ = oracle.Oracle(gd, w.kappa, w.gamma, w.kappa_star, x, y, m).trace(ii, jj)
+    b_int, _ = orc.trace(ii, jj)
+    e_dir = np.hypot(*(b_gpu - b_dir).T)
+    e_int = np.hypot(*(b_gpu - b_int).T)
+    e_scheme = np.hypot(*(b_int - b_dir).T)
+    _say("1e6 rays: max |beta_gpu - beta_direct| = %.2e (rms %.2e), max |beta_gpu - beta_interp| "
+         "= %.2e, oracle interp vs direct max %.2e theta_E" %
+         (e_dir.max(), np.sqrt((e_dir ** 2).mean()), e_int.max(), e_scheme.max()))
+    assert e_dir.max() <= 1e-4
+    assert e_int.max() <= 1e-6
+    mp.close()
+
+
 # ------------------------------------------------------------ batch path
 
 
@@ -315,6 +378,94 @@ def test_batch_map_vs_oracle():
     ref, ref_out = oracle.Oracle(oracle_geom(g), w.kappa, w.gamma, w.kappa_star, x, y, m).shoot(
         *rect, nthreads=NTHREADS)
     _compare(g, counts, n_out, ref, ref_out, rect[2] * rect[3], "batched map 1")
+    lm.lm_batch_destroy(b)
+    for _, _, mp2 in maps:
+        mp2.close()
+
+
+def test_batch_follows_changes_to_its_maps():
+    """A member map changed after the batch was built (lenses fewer and then
+    more than before, so the lens buffers are reallocated; macro model; a
+    caller-owned counts buffer) is shot by the next lm_batch_shoot with its
+    new state, bit for bit as the per-map path shoots it."""
+    import torch
+    maps = _small_batch(nmaps=3, rays_scale=1e-4)
+    b = lm.lm_batch_create([mp.h for _, _, mp in maps])
+    lm.lm_batch_shoot(b)
+    torch.cuda.synchronize()
+
+    def per_map_reference():
+        out = []
+        for _, _, mp in maps:
+            mp.reset()
+            mp.shoot()
+            out.append(mp.counts())
+            mp.reset()
+        return out
+
+    w1, g1, mp1 = maps[1]
+    x, y, m = w1.lenses()
+    w0, g0, mp0 = maps[0]
+    for step, n_keep in enumerate((len(x) // 3, len(x))):
+        for _, _, mp in maps:
+            mp.reset()
+        lm.lm_set_lenses(mp1.h, x[:n_keep], y[:n_keep], m[:n_keep])
+        if step == 0:
+            lm.lm_set_macro(mp0.h, w0.kappa + 0.001, w0.gamma, w0.kappa_star)
+        ref = per_map_reference()
+        lm.lm_batch_shoot(b)
+        for (_, _, mp), (c, o, s) in zip(maps, ref):
+            c2, o2, s2 = mp.counts()
+            np.testing.assert_array_equal(c, c2)
+            assert (o, s) == (o2, s2)
+    # counts bound to a caller-owned buffer after the batch was built
+    for _, _, mp in maps:
+        mp.reset()
+    ref = per_map_reference()
+    buf = torch.zeros(g1.src_ny * g1.src_nx, dtype=torch.int64, device="cuda")
+    lm.lm_bind_counts(mp1.h, buf.data_ptr())
+    lm.lm_batch_shoot(b)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(buf.cpu().numpy().reshape(ref[1][0].shape),
+                                  ref[1][0].astype(np.int64))
+    own = lm.lm_read_counts_region(mp1.h, 0, 0, g1.src_nx, g1.src_ny)
+    np.testing.assert_array_equal(own, ref[1][0])
+    lm.lm_bind_counts(mp1.h, None)
+    lm.lm_batch_destroy(b)
+    for _, _, mp in maps:
+        mp.close()
+
+
+def test_batched_study_map_at_full_geometry_vs_oracle():
+    """A map of the 80-map study at its full geometry (the map with the fewest
+    rays, ~1e11), shot by the persistent batch kernel on a centred rectangle of
+    1e-2 of its rays, against the oracle; the other maps of the batch shoot
+    small rectangles in the same launch."""
+    ws = inputs.batched_study(80, 1.0)
+    k = int(np.argmin([w.n_rays for w in ws]))
+    picks = [k, (k + 1) % 80, (k + 2) % 80]
+    maps = []
+    for idx in picks:
+        g = _geom(ws[idx])
+        maps.append((ws[idx], g, lm.Map(g, ws[idx].kappa, ws[idx].gamma, ws[idx].kappa_star,
+                                        ws[idx].lenses())))
+    b = lm.lm_batch_create([mp.h for _, _, mp in maps])
+    w, g, mp = maps[0]
+    nj = min(g.ray_ny, 4 * g.coarse)
+    ni = min(g.ray_nx, int(1e-2 * g.n_rays / nj) + 1)
+    rect = ((g.ray_nx - ni) // 2, (g.ray_ny - nj) // 2, ni, nj)
+    assert ni * nj >= 1e-2 * g.n_rays
+    lm.lm_batch_set_rect(b, 0, *rect)
+    for t in (1, 2):
+        gt = maps[t][1]
+        lm.lm_batch_set_rect(b, t, 0, 0, min(4096, gt.ray_nx), min(512, gt.ray_ny))
+    lm.lm_batch_shoot(b)
+    counts, n_out, _ = mp.counts()
+    x, y, m = w.lenses()
+    ref, ref_out = oracle.Oracle(oracle_geom(g), w.kappa, w.gamma, w.kappa_star, x, y, m).shoot(
+        *rect, nthreads=NTHREADS)
+    _compare(g, counts, n_out, ref, ref_out, ni * nj,
+             "study map %d (%.3g rays) through the batch kernel" % (k, g.n_rays))
     lm.lm_batch_destroy(b)
     for _, _, mp2 in maps:
         mp2.close()
