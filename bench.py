@@ -65,9 +65,27 @@ def make_map(lm, w, g, lenses, precision):
     return lm.Map(g2, w.kappa, w.gamma, w.kappa_star, lenses), g2
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _timed_shoot(orc, rect, nthreads):
+    t0 = time.perf_counter()
+    out = orc.shoot(*rect, nthreads=nthreads)
+    return time.perf_counter() - t0, out
+
+
 def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
-    """The FP64 oracle on a bounded sample of the workload, and the errors of
-    the mixed and plain-FP32 GPU maps against it."""
+    """The FP64 oracle on a bounded sample of the workload (median of three
+    runs on all host threads, and of three on one thread), and the errors of
+    the batched GPU path and the plain-FP32 per-map path against it."""
     import numpy as np
 
     import oracle
@@ -80,25 +98,30 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
     orc = oracle.Oracle(og, w.kappa, w.gamma, w.kappa_star, *lenses)
     cores = oracle.num_threads()
     # calibrate on growing blocks until one takes a second, then size the
-    # sample to the time budget
+    # all-thread sample so that three runs fit the time budget
     nj = g.coarse
     i0, j0 = g.ray_nx // 2, g.ray_ny // 2 - nj // 2
     ni = g.coarse
     while True:
-        t0 = time.perf_counter()
-        orc.shoot(i0, j0, ni, nj)
-        dt0 = time.perf_counter() - t0
+        dt0, _ = _timed_shoot(orc, (i0, j0, ni, nj), 0)
         if dt0 > 1.0 or ni >= g.ray_nx // 4:
             break
         ni *= 4
     rate0 = ni * nj / dt0
-    ni = int(max(g.coarse, min(g.ray_nx // 2, rate0 * budget_s / nj)))
+    ni = int(max(g.coarse, min(g.ray_nx // 2, rate0 * budget_s / 3 / nj)))
     ni -= ni % g.coarse
-    t0 = time.perf_counter()
-    ref, ref_out = orc.shoot(i0, j0, ni, nj)
-    dt = time.perf_counter() - t0
+    runs = [_timed_shoot(orc, (i0, j0, ni, nj), 0) for _ in range(3)]
+    ref, ref_out = runs[0][1]
+    times = sorted(r[0] for r in runs)
+    dt = times[1]
     rays = ni * nj
-    log("oracle: %d rays in %.1f s on %d threads" % (rays, dt, cores))
+    log("oracle: %d rays in %.1f s (median of %s) on %d threads" %
+        (rays, dt, ", ".join("%.1f" % t for t in times), cores))
+    # one thread: a sample with about the same run time per thread count ratio
+    ni1 = max(g.coarse, (ni // max(1, cores)) // g.coarse * g.coarse)
+    runs1 = sorted(_timed_shoot(orc, (i0, j0, ni1, nj), 1)[0] for _ in range(3))
+    rate1 = ni1 * nj / runs1[1]
+    log("oracle: %d rays in %.1f s (median of 3) on 1 thread" % (ni1 * nj, runs1[1]))
     errors = {}
     rng = np.random.default_rng(2308)
     ii = rng.integers(0, g.ray_nx, 4000)
@@ -106,7 +129,14 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
     _, pix = orc.trace(ii, jj)
     for name, mp in (("batched_mixed", mp_mixed), ("plain_fp32", mp_fp32)):
         mp.reset()
-        mp.shoot(i0, j0, ni, nj)
+        if name == "batched_mixed":
+            # the timed path: the oracle's rectangle through the batch kernel
+            bb = lm.lm_batch_create([mp.h])
+            lm.lm_batch_set_rect(bb, 0, i0, j0, ni, nj)
+            lm.lm_batch_shoot(bb)
+            lm.lm_batch_destroy(bb)
+        else:
+            mp.shoot(i0, j0, ni, nj)
         c, o, _ = mp.counts()
         d = np.abs(c.astype(np.int64) - ref.astype(np.int64))
         big = ref >= 10000
@@ -121,8 +151,12 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
         mp.reset()
     return {"value": rays / dt, "unit": "rays/s", "cores": cores, "kind": "oracle",
             "sample": "FP64 oracle, interpolated scheme, %d x %d-ray sub-rectangle (%.3g rays) "
-                      "of the paper-scale lattice at i0=%d, j0=%d" % (ni, nj, rays, i0, j0),
-            "seconds": dt}, errors
+                      "of the paper-scale lattice at i0=%d, j0=%d; median of 3 runs" %
+                      (ni, nj, rays, i0, j0),
+            "seconds": dt, "run_seconds": times, "cpu_model": cpu_model(),
+            "one_core": {"value": rate1, "unit": "rays/s", "cores": 1,
+                         "sample": "%d x %d rays, same origin; median of 3 runs" % (ni1, nj),
+                         "run_seconds": runs1}}, errors
 
 
 def precision_stress_leg(lm, inputs):
@@ -247,6 +281,7 @@ def paper_table1_leg(lm, inputs, torch, precision):
     g.precision = precision
     lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
     mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold)
+    used, est = mp.precision()
     flops = algorithmic_flops(lm.lm_shot_stats(mp.h, 0, 0, g.ray_nx, g.ray_ny), g.taylor_terms)
     b = lm.lm_batch_create([mp.h])
     lm.lm_batch_tune(b, None)
@@ -264,15 +299,17 @@ def paper_table1_leg(lm, inputs, torch, precision):
     params = list(lm.lm_batch_params(b))
     lm.lm_batch_destroy(b)
     mp.close()
-    name = "fp64-near" if precision == lm.LM_PREC_MIXED_FP64 else "mixed"
+    name = {lm.LM_PREC_MIXED_FP64: "fp64-near", lm.LM_PREC_MIXED: "mixed",
+            lm.LM_PREC_AUTO: "auto"}[precision]
     # near pairs in FP64 are priced against the FP64 vector peak
-    peak = PEAK_FP64_TFLOPS if precision == lm.LM_PREC_MIXED_FP64 else PEAK_FP32_TFLOPS
+    peak = PEAK_FP64_TFLOPS if used == lm.LM_PREC_MIXED_FP64 else PEAK_FP32_TFLOPS
     tflops = flops / (s_ms * 1e-3) / 1e12
     log("paper Table 1 map (%s): %d x %d rays (%.4g), R=%d: %.1f s (shoot %.1f s = %.1f TFLOP/s "
         "algorithmic, %.2f of peak; coefficients %.0f ms), %.4g rays/s; %d rays in the map" %
         (name, g.ray_nx, g.ray_ny, g.n_rays, g.coarse, dt, s_ms / 1e3, tflops, tflops / peak,
          c_ms, g.n_rays / dt, total))
-    return {"precision": name, "exec_params": params,
+    return {"precision": name, "precision_used": used, "fp32_mismatch_estimate": est,
+            "exec_params": params,
             "rays": g.n_rays, "seconds": dt, "rays_per_s": g.n_rays / dt,
             "shoot_algorithmic_tflops": tflops, "shoot_frac_of_peak": tflops / peak,
             "near_pairs_per_ray": (flops / g.n_rays - 8.0 * g.taylor_terms) / 11.0,
@@ -306,7 +343,7 @@ def main():
                     help="rays of the per-map comparison runs")
     ap.add_argument("--rays", type=float, default=1e13,
                     help="rays per map (1e13 is the workload; smaller values are for profiling)")
-    ap.add_argument("--study-scale", type=float, default=0.02,
+    ap.add_argument("--study-scale", type=float, default=0.25,
                     help="fraction of the batched 80-map study's rays for its side measurement "
                          "(0 skips it)")
     ap.add_argument("--no-tune", action="store_true",
@@ -314,9 +351,11 @@ def main():
                          "all workgroups that fit), which the tuner picks on MI355X")
     ap.add_argument("--no-comparison", action="store_true",
                     help="skip the per-map comparison runs (profiling)")
-    ap.add_argument("--paper-map", choices=("none", "mixed", "fp64", "both"), default="none",
+    ap.add_argument("--paper-map", choices=("none", "auto", "mixed", "fp64", "both"),
+                    default="none",
                     help="also shoot the paper's own Table 1 map (2.69e13 rays, 215 GB map) once "
-                         "per chosen precision (side measurement, about a minute each)")
+                         "per chosen precision (auto: the library's choice; both: FP32 and FP64 "
+                         "near sums; side measurement, about a minute each)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM "
                          "byte counters) and exit")
@@ -345,7 +384,9 @@ def main():
     lenses = w.lenses()
     log("geometry: %d x %d rays (%.4g), R=%d, K=%dx%d, %d lenses" %
         (g.ray_nx, g.ray_ny, g.n_rays, g.coarse, g.l1_kx, g.l1_ky, w.n_lenses))
-    mp, _ = make_map(lm, w, g, lenses, lm.LM_PREC_MIXED)
+    mp, _ = make_map(lm, w, g, lenses, g.precision)  # the library's default (LM_PREC_AUTO)
+    prec_used, prec_est = mp.precision()
+    log("precision: %d (FP32 near-sum mismatch estimate %.2e)" % (prec_used, prec_est))
     stats = lm.lm_shot_stats(mp.h, 0, 0, g.ray_nx, g.ray_ny)
     flops = algorithmic_flops(stats, g.taylor_terms)
     log("near pairs per ray %.3f, FLOP per ray %.1f" % (stats.near_pairs / stats.rays,
@@ -356,6 +397,10 @@ def main():
         t0 = time.perf_counter()
         lm.lm_batch_tune(b, os.environ.get("LENSMAP_TUNE_CACHE"))
         log("tuned %s in %.1f s" % (lm.lm_batch_params(b), time.perf_counter() - t0))
+    tune_results = lm.lm_batch_tune_results(b)
+    for r in tune_results:
+        log("  candidate rays/lane %d, tile scale %d, WG/CU %d: %.4g rays/s on %.3g rays" %
+            (r["rays_per_lane"], r["tile_scale"], r["wg_per_cu"], r["rays_per_s"], r["rays"]))
 
     def step():
         lm.lm_reset_counts(mp.h, stream)
@@ -430,7 +475,13 @@ def main():
                    "rays": g.n_rays, "lenses": w.n_lenses, "map_pixels": [g.src_nx, g.src_ny],
                    "precision": "FP32 lens sums on rebased offsets, FP64 cell bases and pixel "
                                 "coordinates, FP64 Taylor coefficients",
-                   "exec_params": list(lm.lm_batch_params(b))},
+                   "precision_choice": {"requested": "LM_PREC_AUTO", "used": prec_used,
+                                        "fp32_mismatch_estimate": prec_est},
+                   "exec_params": list(lm.lm_batch_params(b)),
+                   "tuner_candidates": [{"params": [r["rays_per_lane"], r["tile_scale"],
+                                                    r["wg_per_cu"]],
+                                         "rays_per_s": r["rays_per_s"], "rays": r["rays"]}
+                                        for r in tune_results]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": traffic, "kernel": "k_shoot_batch",
@@ -446,7 +497,8 @@ def main():
     if study is not None:
         line["batched_study"] = study
     if args.paper_map != "none":
-        precs = {"mixed": [lm.LM_PREC_MIXED], "fp64": [lm.LM_PREC_MIXED_FP64],
+        precs = {"auto": [lm.LM_PREC_AUTO], "mixed": [lm.LM_PREC_MIXED],
+                 "fp64": [lm.LM_PREC_MIXED_FP64],
                  "both": [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64]}[args.paper_map]
         line["paper_table1_map"] = [paper_table1_leg(lm, inputs, torch, pr) for pr in precs]
     if not args.no_cpu_baseline:

@@ -60,8 +60,8 @@ typedef int32_t lm_status;
 #define LM_PREC_AUTO 3        /* LM_PREC_MIXED or LM_PREC_MIXED_FP64, chosen by the library
                                  for the map's current lenses and macro model: FP32 near
                                  sums while their estimated bin mismatch is at most 5e-6
-                                 (see lm_precision_info); the direct scheme keeps
-                                 LM_PREC_MIXED */
+                                 and near lists are short (see lm_precision_info); the
+                                 direct scheme keeps LM_PREC_MIXED */
 
 #define LM_MAX_TERMS 7        /* largest supported P */
 
@@ -282,12 +282,14 @@ lm_status lm_trace_beta(lm_map* m, const int64_t* i, const int64_t* j, int64_t n
 
 /* The precision the map's kernels run in (LM_PREC_*; never LM_PREC_AUTO) and,
  * for an LM_PREC_AUTO geometry of the interpolated scheme, the estimated bin
- * mismatch of FP32 near sums that chose it: the mean over 65536 fixed lattice
- * rays (every ray of smaller lattices) of |du| + |dv|, the distance in pixels
- * between the ray's image with FP32 and with FP64 near sums (rays imaged
- * outside the map count 0) -- the chance that rounding moves an image across a
- * pixel edge.  FP32 near sums are chosen while it is at most 5e-6; otherwise
- * FP64.  The estimate is -1 when no choice was made (a fixed precision) and 0
+ * mismatch of FP32 near sums that chose it: the mean of |du| + |dv|, the
+ * distance in pixels between a ray's image with FP32 and with FP64 near sums --
+ * the chance that rounding moves the image across a pixel edge -- over the
+ * rays of a fixed sample of 65536 lattice rays (every ray of smaller lattices)
+ * whose images lie in the map.  FP32 near sums are chosen while it is at most
+ * 5e-6 and the mean near list over the lattice holds at most 32 lenses (FP32
+ * rounding of a running sum grows with its length, and with long lists varies
+ * strongly from region to region); otherwise FP64.  The estimate is -1 when no choice was made (a fixed precision) and 0
  * for a map without lenses.  The paper states no precision; this is the
  * library's reading of the accuracy the maps need.  Synchronous (runs the
  * probe if the lenses or the macro model changed).  Either pointer may be

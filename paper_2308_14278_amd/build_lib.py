@@ -38,25 +38,35 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False) -> str:
+# (scheme, precision) pairs the shooting kernels are instantiated for, one
+# compilation of lm_shoot_inst.hip each
+PAIRS = ((0, 0), (0, 1), (1, 0), (1, 1), (1, 2))
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     cc = hipcc()
+    arch = ["--offload-arch=" + ARCH]
     with tempfile.TemporaryDirectory() as tmp:
-        ko = os.path.join(tmp, "lm_kernels.o")
-        ao = os.path.join(tmp, "lm_api.o")
-        po = os.path.join(tmp, "lm_peak.o")
-        _run([cc, "--offload-arch=" + ARCH, *COMMON, "-c",
-              os.path.join(CSRC, "lm_kernels.hip"), "-o", ko])
-        _run([cc, "--offload-arch=" + ARCH, *COMMON, "-c",
-              os.path.join(CSRC, "lm_peak.hip"), "-o", po])
-        yo = os.path.join(tmp, "lm_analysis.o")
-        _run([cc, "--offload-arch=" + ARCH, *COMMON, "-c",
-              os.path.join(CSRC, "lm_analysis.hip"), "-o", yo])
+        steps = []
+        for name in ("lm_kernels", "lm_peak", "lm_analysis"):
+            o = os.path.join(tmp, name + ".o")
+            steps.append((o, [cc, *arch, *COMMON, "-c", os.path.join(CSRC, name + ".hip"),
+                              "-o", o]))
+        for s_, p_ in PAIRS:
+            o = os.path.join(tmp, "lm_shoot_s%dp%d.o" % (s_, p_))
+            steps.append((o, [cc, *arch, *COMMON, "-DLM_S=%d" % s_, "-DLM_PR=%d" % p_, "-c",
+                              os.path.join(CSRC, "lm_shoot_inst.hip"), "-o", o]))
         # host-only C++: plain g++ against the HIP runtime headers
-        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
-              "-I" + os.path.join(ROCM, "include"), "-c", os.path.join(CSRC, "lm_api.cpp"),
-              "-o", ao])
+        ao = os.path.join(tmp, "lm_api.o")
+        steps.append((ao, ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
+                           "-I" + os.path.join(ROCM, "include"), "-c",
+                           os.path.join(CSRC, "lm_api.cpp"), "-o", ao]))
+        n = jobs or min(len(steps), max(1, os.cpu_count() or 1))
+        with ThreadPoolExecutor(max_workers=n) as ex:
+            list(ex.map(lambda st: _run(st[1]), steps))
         out = LIB + ".tmp%d" % os.getpid()
-        _run([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out, ko, po, yo, ao])
+        _run([cc, *arch, "-shared", "-fPIC", "-o", out, *[o for o, _ in steps]])
         os.replace(out, LIB)
     if verbose:
         print("built", LIB)

@@ -402,16 +402,51 @@ uint64_t splitmix64(uint64_t x)
 
 constexpr int64_t kPrecSample = 65536;   // rays probed to choose the near-sum precision
 constexpr double kPrecFp32Max = 5e-6;    // largest estimated FP32 mismatch kept in FP32
+constexpr double kPrecFp32MaxNear = 32;  // longest mean near list kept in FP32
+
+// Near lenses of level-1 cell (I, J): its 2H+1 rows of the padded CSR.
+int64_t near_count(const lm_map* m, int64_t I, int64_t J)
+{
+    const int H = m->g.near_halo;
+    int64_t n = 0;
+    for (int r = 0; r <= 2 * H; ++r) {
+        const int64_t base = (J + r) * m->nl1x + I;
+        n += m->h_start[base + 2 * H + 1] - m->h_start[base];
+    }
+    return n;
+}
+
+// Mean near-list length over the rays of the whole lattice.
+double mean_near(const lm_map* m)
+{
+    const lm_geometry& g = m->g;
+    const int64_t sx = (int64_t)g.coarse * g.l1_kx, sy = (int64_t)g.coarse * g.l1_ky;
+    double pairs = 0.0;
+    for (int64_t J = 0; J < m->n1y; ++J) {
+        const double ry = (double)(std::min(g.ray_ny, (J + 1) * sy) - J * sy);
+        for (int64_t I = 0; I < m->n1x; ++I) {
+            const double rx = (double)(std::min(g.ray_nx, (I + 1) * sx) - I * sx);
+            pairs += rx * ry * (double)near_count(m, I, J);
+        }
+    }
+    return pairs / ((double)g.ray_nx * (double)g.ray_ny);
+}
 
 // LM_PREC_AUTO: the near-sum precision for the current lenses and macro model.
 // A ray changes pixel when rounding moves its image across a pixel edge; for
 // images spread evenly over their pixels that happens with probability
 // |du| + |dv|, the move in pixel units.  The FP32 near sums' bin mismatch is
-// estimated as the mean of that move, FP32 against FP64 near sums, over a
-// fixed sample of lattice rays (all of them on small lattices; a ray whose
-// image lies outside the map counts 0).  FP32 is kept while the estimate is
-// at most kPrecFp32Max, half the 1e-5 bar; otherwise the near pairs are summed
-// in FP64.  The direct scheme has no FP64 near-sum mode and keeps
+// estimated as the mean of that move, FP32 against FP64 near sums, over the
+// rays of a fixed lattice sample (all rays of small lattices) whose images lie
+// in the map.  FP32 is kept while the estimate is
+// at most kPrecFp32Max, half the 1e-5 bar, and the mean near list holds at most
+// kPrecFp32MaxNear lenses; otherwise the near pairs are summed in FP64.  The
+// second condition covers what a lattice mean misses: the rounding of an FP32
+// running sum grows with the number of its terms and, with long lists, varies
+// strongly from one region to the next (with ~110 near lenses a lattice mean of
+// 3.4e-6 came with 1.8e-5 in a 2e6-ray region).  The paper's level-1 size
+// gives about 9 near lenses; lists of 32 and more arise only when a caller
+// enlarges the level-1 cells.  The direct scheme has no FP64 near-sum mode and keeps
 // LM_PREC_MIXED (its FP32 sums are compensated per 256-lens block).
 lm_status resolve_precision(lm_map* m, hipStream_t s)
 {
@@ -462,14 +497,20 @@ lm_status resolve_precision(lm_map* m, hipStream_t s)
     HIP_TRY(hipMemcpyAsync(b.data(), u64.p, n * 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     double acc = 0.0;
+    int64_t n_in = 0;
     for (int64_t t = 0; t < n; ++t) {
         const double u = b[2 * t], v = b[2 * t + 1];
         if (!(u >= 0.0 && u < g.src_nx && v >= 0.0 && v < g.src_ny)) continue;
+        ++n_in;
         const double mv = std::fabs(a[2 * t] - u) + std::fabs(a[2 * t + 1] - v);
         acc += std::isfinite(mv) ? std::min(1.0, mv) : 1.0;
     }
-    m->prec_est = acc / (double)n;
-    m->prec = m->prec_est <= kPrecFp32Max ? LM_PREC_MIXED : LM_PREC_MIXED_FP64;
+    // per ray imaged into the map: a shot region that lands inside the map
+    // sees this rate, however few of the lattice's rays reach the map
+    m->prec_est = n_in > 0 ? acc / (double)n_in : 0.0;
+    m->prec = m->prec_est <= kPrecFp32Max && mean_near(m) <= kPrecFp32MaxNear
+                  ? LM_PREC_MIXED
+                  : LM_PREC_MIXED_FP64;
     m->prec_gen = m->model_gen;
     m->last = s;
     return LM_OK;
@@ -1163,23 +1204,14 @@ lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int
         return ok();
     }
     const lm_geometry& g = m->g;
-    const int H = g.near_halo;
     const int64_t sx = (int64_t)g.coarse * g.l1_kx, sy = (int64_t)g.coarse * g.l1_ky;
-    auto near_count = [&](int64_t I, int64_t J) {
-        int64_t n = 0;
-        for (int r = 0; r <= 2 * H; ++r) {
-            const int64_t base = (J + r) * m->nl1x + I;
-            n += m->h_start[base + 2 * H + 1] - m->h_start[base];
-        }
-        return n;
-    };
     double pairs = 0;
     if (ni > 0 && nj > 0)
         for (int64_t J = j0 / sy; J <= (j0 + nj - 1) / sy; ++J) {
             const int64_t ry = std::min(j0 + nj, (J + 1) * sy) - std::max(j0, J * sy);
             for (int64_t I = i0 / sx; I <= (i0 + ni - 1) / sx; ++I) {
                 const int64_t rx = std::min(i0 + ni, (I + 1) * sx) - std::max(i0, I * sx);
-                pairs += (double)rx * (double)ry * (double)near_count(I, J);
+                pairs += (double)rx * (double)ry * (double)near_count(m, I, J);
             }
         }
     out->near_pairs = pairs;
@@ -1189,7 +1221,7 @@ lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int
         const int64_t cy = std::min(m->ncy, (J + 1) * (int64_t)g.l1_ky) - J * g.l1_ky;
         for (int64_t I = 0; I < m->n1x; ++I) {
             const int64_t cx = std::min(m->ncx, (I + 1) * (int64_t)g.l1_kx) - I * g.l1_kx;
-            far += (double)cx * (double)cy * (double)(m->nlens - near_count(I, J));
+            far += (double)cx * (double)cy * (double)(m->nlens - near_count(m, I, J));
         }
     }
     out->far_pairs = far;

@@ -97,3 +97,25 @@ int lm_launch_peaks(const unsigned long long* counts, int64_t nx, int64_t ny,
                     const int32_t* tracks, int64_t nt, int k, uint8_t* flags, void* stream);
 int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu);
 bool lm_supported_rays_per_lane(int r);
+
+// Per-pair instances of the shooting kernels, probes and their launchers
+// (lm_shoot_inst.hip, compiled once per (scheme, precision) pair).
+#define LM_INST_CAT2(base, s, p) base##_s##s##_p##p
+#define LM_INST_CAT(base, s, p) LM_INST_CAT2(base, s, p)
+#define LM_INST_DECLARE(S, PR)                                                                \
+    int LM_INST_CAT(lm_inst_shoot_map, S, PR)(const LmDesc& d, int nr, int terms, void* stream); \
+    int LM_INST_CAT(lm_inst_shoot_batch, S, PR)(const LmDesc* descs, const int64_t* offs,     \
+                                                const int32_t* order, int nmaps,              \
+                                                unsigned long long* queue, int nr, int terms, \
+                                                int grid, void* stream);                      \
+    int LM_INST_CAT(lm_inst_occupancy, S, PR)(int nr, int terms, int* wg_per_cu);             \
+    int LM_INST_CAT(lm_inst_trace, S, PR)(const LmDesc& d, int terms, const int64_t* ii,      \
+                                          const int64_t* jj, int64_t n, int32_t* p,           \
+                                          int32_t* q, double* uv, void* stream);              \
+    int LM_INST_CAT(lm_inst_deflect, S, PR)(const LmDesc& d, int terms, const double* th,     \
+                                            int64_t n, double* alpha, void* stream);
+LM_INST_DECLARE(0, 0)
+LM_INST_DECLARE(0, 1)
+LM_INST_DECLARE(1, 0)
+LM_INST_DECLARE(1, 1)
+LM_INST_DECLARE(1, 2)

@@ -1,1091 +1,26 @@
-// lm_kernels.hip -- gfx950 kernels of liblensmap.
+// lm_kernels.hip -- gfx950 kernels of liblensmap besides the shooting kernels
+// (lm_device.h, instantiated per scheme and precision in lm_shoot_inst.hip),
+// and the entry points that launch every kernel.
 //
 //  k_coeffs       far-field Taylor coefficients of every level-2 cell (Sec. 3.2.2):
 //                 a_n = -sum_{far k} m_k / (z_k - z_c)^(n+1); lens tiles staged
 //                 in LDS, FP64 arithmetic (FP64 FMA issues at the unpacked
 //                 FP32 rate on gfx950).
-//  k_shoot_map    one workgroup per tile of level-2 cells: per ray the near-lens
-//  k_shoot_batch  direct sum (Eq. 9) on offsets rebased to the cell centre
-//                 (FP32, or FP64 in the FP64 near-sum mode), the far-field
-//                 Taylor series and the macro map with the sheet term (Eq. 6)
-//                 re-expanded per ray row, FP64 pixel coordinates, and the
-//                 count (Sec. 3.2.3) through a per-lane run, a wave merge and
-//                 an LDS window flushed to the uint64 map.  The batch kernel is
-//                 persistent and pulls tiles of many maps from a queue.
 //  k_l1_expand    hierarchical far field (optional): series per level-1 cell,
 //  k_l1_shift     re-expanded about every level-2 centre.
-//  k_trace        per-ray pixels with the same arithmetic (test probe).
-//  k_deflect      deflection at arbitrary positions (test probe).
+//  k_ptab         the column-offset table of the shooting kernels.
+//  k_sum_u64, k_fill_u64   reductions and fills of count buffers.
 //
-// Layout of work inside a tile: a wave owns "units" of 64 consecutive rows
-// (one ray row per lane) by a run of columns of one level-2 cell; the lane
-// walks its row NR columns at a time.  Every ray of a unit shares the cell's
-// near-lens list, which the wave stages once in its own LDS slice, so the
-// lens loop is uniform and reads lenses as LDS broadcasts.  Quantities that
-// are the same for all 64 rows -- the column offsets and their powers (scalar
-// loads), and per column and lens dx^2 and m dx (an LDS table the wave fills
-// 64 entries at a time) -- are computed once per wave, and the rays of columns
-// 2m and 2m+1 share one reciprocal per lens.
-#include <hip/hip_runtime.h>
-
-#include <type_traits>
-
-#include "lm_internal.h"
+// The shooting kernels (k_shoot_map: one workgroup per tile of level-2 cells;
+// k_shoot_batch: persistent, tiles of many maps from a queue) sum the near
+// lenses directly (Eq. 9) on offsets rebased to the cell centre (FP32, or FP64
+// in the FP64 near-sum mode), add the far-field Taylor series and the macro
+// map with the sheet term (Eq. 6) re-expanded per ray row, bin in FP64 pixel
+// coordinates, and count (Sec. 3.2.3) through per-lane runs, a wave merge and
+// an LDS window flushed to the uint64 map.
+#include "lm_device.h"
 
 namespace {
-
-constexpr int kWG = LM_WG;
-constexpr int kWinMax = LM_WIN_MAX;
-
-// Lenses staged per wave per block: the direct sum sums 256-lens blocks (the
-// compensated blocks); a near list rarely exceeds a few tens of lenses.
-template <int SCHEME>
-struct Cap {
-    static constexpr int value = SCHEME == 0 ? LM_LENS_CAP : LM_NEAR_CAP;
-};
-
-// Arithmetic of the ray-lens pairs: FP32 (rebased or plain global) or FP64
-// (rebased), and the staged lens record of each.
-template <int PREC>
-struct Prec {
-    using T = float;
-    using L = float4;
-};
-template <>
-struct Prec<2> {
-    using T = double;
-    using L = double4;
-};
-
-// The interpolated scheme shares the column-lens differences of a wave through
-// an LDS table (kTabCh lenses at a time), in every precision: rebased FP32 or
-// FP64 offsets, and the plain path's global FP32 coordinates.
-template <int SCHEME, int PREC>
-struct UseTab {
-    static constexpr bool value = SCHEME == 1;
-};
-constexpr int kTabCh = 16;
-
-// Waves per SIMD the shooting kernels must keep: the FP32 table paths are
-// issue-bound and needs 4 (at most 128 VGPRs with 256-thread workgroups, 4 per
-// CU).  The per-map kernel, whose descriptor arrives by value, would otherwise
-// allocate a few registers more than that and drop to 3; the hint holds it at
-// 128 (spilling per-unit values to scratch if it must).
-template <int SCHEME, int PREC>
-struct MinWaves {
-    static constexpr int value = (SCHEME == 1 && PREC != 2) ? 4 : 1;
-};
-
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ int64_t uniform_i64(int64_t v)
-{
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(uint64_t)v);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ unsigned wave_sum_u32(unsigned v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Map constants the per-ray code reads, copied into registers once per unit so
-// that the global atomics of the counting step do not force reloads.
-struct Hot {
-    double inv_sdx, inv_sdy;
-    float mxf, myf, bx0f, by0f, inv_sdxf, inv_sdyf, snxf, snyf;
-    float qxf, qyf;  // fold: d_x/2, d_y
-    int snx, sny, wx, wy;
-    unsigned long long* counts;
-};
-
-__device__ __forceinline__ Hot make_hot(const LmDesc& d)
-{
-    Hot h;
-    h.inv_sdx = d.inv_sdx;
-    h.inv_sdy = d.inv_sdy;
-    h.mxf = d.mxf;
-    h.myf = d.myf;
-    h.qxf = (float)d.qx;
-    h.qyf = (float)d.qy;
-    h.bx0f = d.bx0f;
-    h.by0f = d.by0f;
-    h.inv_sdxf = d.inv_sdxf;
-    h.inv_sdyf = d.inv_sdyf;
-    h.snxf = (float)d.snx;
-    h.snyf = (float)d.sny;
-    h.snx = d.snx;
-    h.sny = d.sny;
-    h.wx = d.wx;
-    h.wy = d.wy;
-    h.counts = d.counts;
-    return h;
-}
-
-// ---------------------------------------------------------------- cell data
-
-__device__ __forceinline__ double cell_cx(const LmDesc& d, int64_t ci)
-{
-    return d.x0 + ((double)ci + 0.5) * (double)d.R * d.dx;
-}
-__device__ __forceinline__ double cell_cy(const LmDesc& d, int64_t cj)
-{
-    return d.y0 + ((double)cj + 0.5) * (double)d.R * d.dy;
-}
-__device__ __forceinline__ float cell_cxf(const LmDesc& d, int64_t ci)
-{
-    return d.x0f + ((float)ci + 0.5f) * (float)d.R * d.dxf;
-}
-__device__ __forceinline__ float cell_cyf(const LmDesc& d, int64_t cj)
-{
-    return d.y0f + ((float)cj + 0.5f) * (float)d.R * d.dyf;
-}
-
-// FP64 pixel coordinates of the cell centre's image (includes a_0).
-template <int SCHEME>
-__device__ __forceinline__ void cell_base(const LmDesc& d, int64_t ci, int64_t cj, double& ubx,
-                                          double& uby)
-{
-    const double zx = cell_cx(d, ci), zy = cell_cy(d, cj);
-    double bx = d.mx * zx;
-    double by = d.my * zy;
-    if (d.fold) bx += (d.qx * zx + d.qy * zy) * zx;
-    if (SCHEME == 1) {
-        const LmCoef& c = d.coef[cj * d.ncx + ci];
-        bx -= c.a0r;
-        by += c.a0i;
-    }
-    ubx = (bx - d.bx0) * d.inv_sdx;
-    uby = (by - d.by0) * d.inv_sdy;
-}
-
-// ----------------------------------------------------------- per-ray pieces
-
-// One ray-lens pair: accumulates m (dx, dy) / r^2 with dx = px - lx.
-__device__ __forceinline__ void pair(float px, float dy, float dy2, float lxv, float lmv,
-                                     float& ax, float& ay)
-{
-    float dx = px - lxv;
-    float r2 = __builtin_fmaf(dx, dx, dy2);
-    float w = lmv * __builtin_amdgcn_rcpf(r2);
-    ax = __builtin_fmaf(dx, w, ax);
-    ay = __builtin_fmaf(dy, w, ay);
-}
-
-
-// Pair from the wave-shared dx^2 and m dx, dx = px - lx (one per column and
-// lens, the same for every row), and the row's dy^2 and m dy.  Every operation
-// but the reciprocal is a two-source VOP2 instruction.
-__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// FP64 reciprocal: hardware estimate refined by one Newton step.
-__device__ __forceinline__ double recip(double x)
-{
-    const double r0 = __builtin_amdgcn_rcp(x);
-    return __builtin_fma(r0, __builtin_fma(-x, r0, 1.0), r0);
-}
-
-// FP64 reciprocal to within an ulp or two: two Newton steps from the hardware
-// estimate (5 instructions instead of the ~11 of a correctly rounded division).
-__device__ __forceinline__ double recip_nr2(double x)
-{
-    const double r1 = recip(x);
-    return __builtin_fma(r1, __builtin_fma(-x, r1, 1.0), r1);
-}
-__device__ __forceinline__ float recip_nr2(float x) { return 1.0f / x; }
-
-template <class T>
-__device__ __forceinline__ void pair_tab(T dx2, T mdx, T dy2, T mdy, T& ax, T& ay)
-{
-    const T r2 = dx2 + dy2;
-    const T w = recip(r2);
-    ax = fma(mdx, w, ax);
-    ay = fma(mdy, w, ay);
-}
-
-// Two pairs of one lens and the row's rays in columns a = 2m and b = 2m + 1
-// sharing one reciprocal: 1/r2a = r2b / (r2a r2b) and 1/r2b = r2a / (r2a r2b)
-// (the reciprocal is the expensive instruction of a pair).  The product stays a
-// normal FP32 number while both r2 exceed 1.1e-19 theta_E^2 (rays farther than
-// 3.3e-10 theta_E from the lens) and stay below 1e19.
-template <class T>
-__device__ __forceinline__ void pair2(T dx2a, T dx2b, T mdxa, T mdxb, T dy2, T mdy, T& axa,
-                                      T& aya, T& axb, T& ayb)
-{
-    const T r2a = dx2a + dy2, r2b = dx2b + dy2;
-    const T r = recip(r2a * r2b);
-    const T wa = r * r2b, wb = r * r2a;
-    axa = fma(mdxa, wa, axa);
-    aya = fma(mdy, wa, aya);
-    axb = fma(mdxb, wb, axb);
-    ayb = fma(mdy, wb, ayb);
-}
-
-template <class T>
-__device__ __forceinline__ void kahan_add(T& s, T& c, T v)
-{
-    T y = v - c;
-    T t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
-// f = sum_{n=1}^{P-1} a_n d^n by Horner, FP32.
-template <int P>
-__device__ __forceinline__ void taylor(const float* ar, const float* ai, float dx, float dy,
-                                       float& fr, float& fi)
-{
-    if (P <= 1) {
-        fr = 0.f;
-        fi = 0.f;
-        return;
-    }
-    float gr = ar[P - 1], gi = ai[P - 1];
-#pragma unroll
-    for (int n = P - 2; n >= 1; --n) {
-        float tr = __builtin_fmaf(gr, dx, __builtin_fmaf(-gi, dy, ar[n]));
-        float ti = __builtin_fmaf(gr, dy, __builtin_fmaf(gi, dx, ai[n]));
-        gr = tr;
-        gi = ti;
-    }
-    fr = __builtin_fmaf(gr, dx, -(gi * dy));
-    fi = __builtin_fmaf(gr, dy, gi * dx);
-}
-
-// Macro mapping of offsets (dx, dy) from a level-2 cell centre z: the
-// constant Jacobian diag(mx, my), or for the fold model the Jacobian at z,
-// [[mx + d_x z_x + d_y z_y, d_y z_x], [0, my]], plus the quadratic remainder
-// (d_x dx / 2 + d_y dy) dx.  FP32 constants formed in FP64 per cell.
-struct CellMap {
-    float cxx, cxy, qx, qy;
-};
-
-__device__ __forceinline__ CellMap cell_map(const LmDesc& d, double zx, double zy)
-{
-    CellMap c;
-    if (d.fold) {
-        c.cxx = (float)(d.mx + 2.0 * d.qx * zx + d.qy * zy);
-        c.cxy = (float)(d.qy * zx);
-    } else {
-        c.cxx = d.mxf;
-        c.cxy = 0.f;
-    }
-    c.qx = (float)d.qx;
-    c.qy = (float)d.qy;
-    return c;
-}
-
-// FP64 pixel y coordinate of the image of a ray row before deflection: the
-// cell base plus the macro term of the row's offset l * (L3y / 2) from the cell
-// centre, l = 2 (j - cj R) - (R - 1).  Exact offsets here keep the rounding of
-// the FP32 offset out of the large macro term.
-__device__ __forceinline__ double row_base(const LmDesc& d, double uby, int l)
-{
-    return __builtin_fma(d.my * ((double)l * (0.5 * d.dy)), d.inv_sdy, uby);
-}
-
-// Pixel indices are biased by kBias and converted with saturation (NaN and
-// negative values give 0), so the per-ray code needs no range test: index
-// p - kBias outside [0, size) means "outside the map", which the count step
-// tests once per run of equal pixels.
-constexpr unsigned kBias = 1u << 22;
-constexpr double kBiasD = 4194304.0;
-
-// Saturating FP64 -> u32 conversion (negative and NaN give 0).
-__device__ __forceinline__ unsigned cvt_u32_sat(double v)
-{
-    unsigned r;
-    asm("v_cvt_u32_f64 %0, %1" : "=v"(r) : "v"(v));
-    return r;
-}
-
-// Degree of the per-row polynomial in the column offset.
-template <int P, bool FOLD>
-struct Deg {
-    static constexpr int value = (P - 1) > (FOLD ? 2 : 1) ? (P - 1) : (FOLD ? 2 : 1);
-};
-
-// Far field and macro map of one ray row as polynomials in the column offset dx
-// (Sec. 3.2.2 and Eq. 6).  With delta = dx + i dy and f = sum_{n>=1} a_n delta^n,
-// gx(dx) = Re f - (macro x displacement) and gy(dx) = -Im f: the x displacement
-// of a ray's image is then -(gx + near_x) and its y deflection gy + near_y, so
-// the near sums start from gx and gy.  The coefficients come from a Taylor
-// shift of f by i dy (synthetic division), once per row.  The constant terms
-// gx[0], gy[0] go into the row's FP64 pixel bases (row_setup); per ray the
-// rest is summed from the wave-uniform powers of dx (ray_start).  Macro
-// constants: Jacobian diag(cxx, .) at the cell centre, cxy = d_y z_x and the
-// fold's quadratic remainder (qx dx + qy dy) dx.
-template <int P, bool FOLD, class T>
-__device__ __forceinline__ void row_poly(const float* ar, const float* ai, T dy, T cxx, T cxy,
-                                         T qx, T qy, T* gx, T* gy)
-{
-    constexpr int D = Deg<P, FOLD>::value;
-    T cr[D + 1], cim[D + 1];
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        cr[k] = (k >= 1 && k < P) ? (T)ar[k < P ? k : 0] : T(0);
-        cim[k] = (k >= 1 && k < P) ? (T)ai[k < P ? k : 0] : T(0);
-    }
-    // c_j += (i dy) c_{j+1}, j = N-1 .. k, for k = 0 .. N-1 (N = P - 1)
-#pragma unroll
-    for (int k = 0; k < P - 1; ++k) {
-#pragma unroll
-        for (int jj = P - 2; jj >= k; --jj) {
-            cr[jj] = fma(-cim[jj + 1], dy, cr[jj]);
-            cim[jj] = fma(cr[jj + 1], dy, cim[jj]);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        gx[k] = cr[k];
-        gy[k] = -cim[k];
-    }
-    if (FOLD) {
-        gx[0] = fma(-cxy, dy, gx[0]);
-        gx[1] = gx[1] - fma(qy, dy, cxx);
-        gx[2] = gx[2] - qx;
-    } else {
-        gx[1] = gx[1] - cxx;
-    }
-}
-
-// Powers dx, dx^2, .., dx^D of a column offset, in this order of products
-// (the per-cell column table holds the same values).
-template <int D, class T>
-__device__ __forceinline__ void col_powers(T x, T* pw)
-{
-    pw[0] = x;
-#pragma unroll
-    for (int k = 1; k < D; ++k) pw[k] = pw[k - 1] * x;
-}
-
-// Biased pixel of one ray of the rebased paths from its sums sx = gx - gx[0] +
-// near_x, sy = gy - gy[0] + near_y; ubxb and ubyb are the biased FP64 pixel
-// coordinates of the cell centre's image (x) and of the row (y, row_base), each
-// with its row polynomial's constant term.
-template <class T>
-__device__ __forceinline__ void bin_rebased(double inv_sdx, double inv_sdy, double ubxb,
-                                            double ubyb, T sx, T sy, unsigned& p, unsigned& q)
-{
-    const double u = __builtin_fma(-(double)sx, inv_sdx, ubxb);
-    const double v = __builtin_fma(-(double)sy, inv_sdy, ubyb);
-    p = cvt_u32_sat(u);
-    q = cvt_u32_sat(v);
-}
-
-// Continuous pixel coordinates (u, v) of one ray in the plain FP32 path
-// (global coordinates).
-template <int P, bool FOLD>
-__device__ __forceinline__ void coords_fp32(const Hot& h, const float* ar, const float* ai,
-                                            float a0r, float a0i, float zcx, float zcy, float tx,
-                                            float ty, float ax, float ay, float& u, float& v)
-{
-    float fr, fi;
-    float dx = tx - zcx, dy = ty - zcy;
-    taylor<P>(ar, ai, dx, dy, fr, fi);
-    float alx = ax + (a0r + fr);
-    float aly = ay - (a0i + fi);
-    float mx = h.mxf;
-    if (FOLD) mx = __builtin_fmaf(h.qxf, tx, __builtin_fmaf(h.qyf, ty, mx));
-    float bx = __builtin_fmaf(mx, tx, -alx);
-    float by = __builtin_fmaf(h.myf, ty, -aly);
-    u = (bx - h.bx0f) * h.inv_sdxf;
-    v = (by - h.by0f) * h.inv_sdyf;
-}
-
-// Pixel of one ray in the plain FP32 path.
-template <int P, bool FOLD>
-__device__ __forceinline__ void bin_fp32(const Hot& h, const float* ar, const float* ai,
-                                         float a0r, float a0i, float zcx, float zcy, float tx,
-                                         float ty, float ax, float ay, int& p, int& q)
-{
-    float u, v;
-    coords_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcx, zcy, tx, ty, ax, ay, u, v);
-    bool in = (u >= 0.f) & (u < h.snxf) & (v >= 0.f) & (v < h.snyf);
-    p = in ? (int)u : -1;
-    q = in ? (int)v : -1;
-}
-
-// Offset of lattice index k from the centre of its level-2 cell, as
-// (2 (k - c R) - (R - 1)) * (spacing / 2) with the half spacing in float-float.
-__device__ __forceinline__ int local_index(int64_t k, int64_t c, int R)
-{
-    return 2 * (int)(k - c * (int64_t)R) - (R - 1);
-}
-
-__device__ __forceinline__ float local_offset(int64_t k, int64_t c, int R, float hh, float hl)
-{
-    float fl = (float)local_index(k, c, R);
-    return __builtin_fmaf(fl, hl, fl * hh);
-}
-
-// ------------------------------------------------------------ lens lists
-
-// Level-1 cell (I, J) of level-2 cell (ci, cj).  The interpolated scheme keeps
-// fewer than 2^30 level-2 cells, so 32-bit division does (a 64-bit division
-// is a long scalar sequence, and this runs once per unit of 64 x R rays).
-struct L1Cell {
-    int I, J;
-};
-
-__device__ __forceinline__ L1Cell l1_of(const LmDesc& d, int64_t ci, int64_t cj)
-{
-    return L1Cell{(int)ci / d.Kx, (int)cj / d.Ky};
-}
-
-// Near-lens rows of level-1 cell c: row r in [0, 2H] is the contiguous sorted
-// range [start, end) of level-1 cells (I-H..I+H, J-H+r).
-__device__ __forceinline__ void near_row(const LmDesc& d, L1Cell c, int r, int& s, int& e)
-{
-    int row = c.J + r;  // padded row of J - H + r is (J - H + r) + H
-    int base = row * d.nl1x + c.I;  // padded column of I - H is I
-    s = d.cell_start[base];
-    e = d.cell_start[base + 2 * d.H + 1];
-}
-
-template <int SCHEME>
-__device__ __forceinline__ int list_count(const LmDesc& d, int64_t ci, int64_t cj)
-{
-    if (SCHEME == 0) return (int)d.nlens;
-    const L1Cell c = l1_of(d, ci, cj);
-    int n = 0;
-    for (int r = 0; r <= 2 * d.H; ++r) {
-        int s, e;
-        near_row(d, c, r, s, e);
-        n += e - s;
-    }
-    return n;
-}
-
-// Lens value as the per-ray loop sees it.
-template <int PREC>
-__device__ __forceinline__ typename Prec<PREC>::L lens_value(const LmDesc& d, int idx, double zcx,
-                                                            double zcy)
-{
-    if constexpr (PREC == 2) {
-        return make_double4(d.lx[idx] - zcx, d.ly[idx] - zcy, d.lmd[idx], 0.0);
-    } else if constexpr (PREC == 0) {
-        return make_float4((float)(d.lx[idx] - zcx), (float)(d.ly[idx] - zcy), d.lmf[idx], 0.f);
-    } else {
-        return make_float4(d.lxf[idx], d.lyf[idx], d.lmf[idx], 0.f);
-    }
-}
-
-// Stage list positions [b0, b0+nb) of the cell's lens list into this wave's LDS slice.
-template <int SCHEME, int PREC>
-__device__ void stage(const LmDesc& d, int64_t ci, int64_t cj, int b0, int nb, double zcx,
-                      double zcy, typename Prec<PREC>::L* lb, int lane)
-{
-    if (SCHEME == 0) {
-        for (int s = lane; s < nb; s += 64) lb[s] = lens_value<PREC>(d, b0 + s, zcx, zcy);
-    } else {
-        const L1Cell c = l1_of(d, ci, cj);
-        int off = 0;
-        for (int r = 0; r <= 2 * d.H; ++r) {
-            int s, e;
-            near_row(d, c, r, s, e);
-            int lo = max(off, b0), hi = min(off + (e - s), b0 + nb);
-            for (int k = lo + lane; k < hi; k += 64)
-                lb[k - b0] = lens_value<PREC>(d, s + (k - off), zcx, zcy);
-            off += e - s;
-        }
-    }
-    wave_sync_lds();
-}
-
-// Global-memory walk over the same list in the same order (probes).
-template <int SCHEME>
-__device__ __forceinline__ int list_index(const LmDesc& d, int64_t ci, int64_t cj, int pos)
-{
-    if (SCHEME == 0) return pos;
-    const L1Cell c = l1_of(d, ci, cj);
-    int off = 0;
-    for (int r = 0; r <= 2 * d.H; ++r) {
-        int s, e;
-        near_row(d, c, r, s, e);
-        if (pos < off + (e - s)) return s + (pos - off);
-        off += e - s;
-    }
-    return -1;
-}
-
-template <int P>
-__device__ __forceinline__ void load_taylor(const LmDesc& d, int64_t ci, int64_t cj, float* ar,
-                                            float* ai, float& a0r, float& a0i)
-{
-    const LmCoef& c = d.coef[cj * d.ncx + ci];
-    a0r = (float)c.a0r;
-    a0i = (float)c.a0i;
-    ar[0] = 0.f;
-    ai[0] = 0.f;
-#pragma unroll
-    for (int n = 1; n < P; ++n) {
-        ar[n] = c.a[2 * (n - 1)];
-        ai[n] = c.a[2 * (n - 1) + 1];
-    }
-}
-
-// ------------------------------------------------------------- counting
-
-// A lane's pending run: biased pixel (p, q) as one 64-bit key (one compare per
-// ray) and the unit-local column of its first ray; its length is only formed
-// when the run is emitted.
-struct Run {
-    unsigned long long key;  // p | q << 32
-    int start;
-};
-
-__device__ __forceinline__ unsigned long long run_key(unsigned p, unsigned q)
-{
-    return (unsigned long long)p | ((unsigned long long)q << 32);
-}
-
-// Add n rays at biased pixel (p, q): outside the map -> n_out, inside the
-// workgroup's window -> LDS, else a global atomic.  (axb, ayb) = biased window
-// origin.
-__device__ __forceinline__ void emit(const Hot& h, unsigned p, unsigned q, unsigned n,
-                                     unsigned axb, unsigned ayb, unsigned* win, unsigned& nout)
-{
-    const unsigned pm = p - kBias, qm = q - kBias;
-    if ((pm >= (unsigned)h.snx) | (qm >= (unsigned)h.sny)) {
-        nout += n;
-        return;
-    }
-    const unsigned wxi = p - axb, wyi = q - ayb;
-    if ((wxi < (unsigned)h.wx) & (wyi < (unsigned)h.wy))
-        atomicAdd(&win[wyi * (unsigned)h.wx + wxi], n);
-    else
-        atomicAdd(&h.counts[(int64_t)qm * h.snx + pm], (unsigned long long)n);
-}
-
-// Lanes whose row lies outside the shot rectangle (row_ok false) keep runs like
-// every lane but never emit them, so the per-ray path needs no lane mask.  col
-// is the unit-local column of the ray (rays are pushed column by column).
-__device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsigned q, int col,
-                                         unsigned axb, unsigned ayb, unsigned* win,
-                                         unsigned& nout, bool row_ok)
-{
-    // (a unit starts with an empty run at the out-of-map pixel kBias - 2;
-    // runs of length 0 are never emitted)
-    const unsigned long long key = run_key(p, q);
-    if (key != r.key) {
-        // one divergent region for every lane whose run ends
-        const unsigned n = row_ok ? (unsigned)(col - r.start) : 0u;
-        if (n) emit(h, (unsigned)r.key, (unsigned)(r.key >> 32), n, axb, ayb, win, nout);
-        r.key = key;
-        r.start = col;
-    }
-}
-
-// End of a unit (col_end = unit-local column after its last ray): lanes whose
-// pending runs all name one pixel add it once.
-__device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_end, unsigned axb,
-                                          unsigned ayb, unsigned* win, unsigned& nout, int lane,
-                                          bool row_ok)
-{
-    const unsigned n = (unsigned)(col_end - r.start);
-    const unsigned rp = (unsigned)r.key, rq = (unsigned)(r.key >> 32);
-    bool act = row_ok && n > 0;
-    unsigned long long am = __ballot(act);
-    if (am) {
-        int first = __builtin_ctzll(am);
-        unsigned p0 = __shfl(rp, first, 64), q0 = __shfl(rq, first, 64);
-        unsigned long long diff = __ballot(act && (rp != p0 || rq != q0));
-        if (diff == 0) {
-            unsigned tot = wave_sum_u32(act ? n : 0u);
-            if (lane == first) emit(h, p0, q0, tot, axb, ayb, win, nout);
-        } else if (act) {
-            emit(h, rp, rq, n, axb, ayb, win, nout);
-        }
-    }
-}
-
-// Everything one ray row needs before its rays: the row offset, the biased
-// FP64 bases and (rebased paths) the row polynomials.
-template <int PREC, int P, bool FOLD>
-struct Row {
-    using T = typename Prec<PREC>::T;
-    static constexpr int D = Deg<P, FOLD>::value;
-    T py;
-    double ubxb, ubyb;
-    T gx[D + 1], gy[D + 1];
-};
-
-template <int PREC, int P, bool FOLD>
-__device__ __forceinline__ void row_setup(const LmDesc& d, int64_t cj, int64_t j, double zcx,
-                                          double zcy, double ubx, double uby, const float* ar,
-                                          const float* ai, Row<PREC, P, FOLD>& rw)
-{
-    using T = typename Prec<PREC>::T;
-    const int R = d.R;
-    if constexpr (PREC == 1) {
-        rw.py = __builtin_fmaf((float)j + 0.5f, d.dyf, d.y0f);
-        rw.ubxb = 0.0;
-        rw.ubyb = 0.0;
-    } else {
-        const int l = local_index(j, cj, R);
-        rw.ubxb = ubx + kBiasD;
-        rw.ubyb = row_base(d, uby + kBiasD, l);
-        T cxx, cxy, qx, qy;
-        if constexpr (PREC == 2) {
-            rw.py = (double)l * (0.5 * d.dy);
-            cxx = d.fold ? d.mx + 2.0 * d.qx * zcx + d.qy * zcy : d.mx;
-            cxy = d.fold ? d.qy * zcx : 0.0;
-            qx = d.qx;
-            qy = d.qy;
-        } else {
-            rw.py = local_offset(j, cj, R, d.hyh, d.hyl);
-            const CellMap cm = cell_map(d, zcx, zcy);
-            cxx = cm.cxx;
-            cxy = cm.cxy;
-            qx = cm.qx;
-            qy = cm.qy;
-        }
-        row_poly<P, FOLD, T>(ar, ai, rw.py, cxx, cxy, qx, qy, rw.gx, rw.gy);
-        rw.ubxb = __builtin_fma(-(double)rw.gx[0], d.inv_sdx, rw.ubxb);
-        rw.ubyb = __builtin_fma(-(double)rw.gy[0], d.inv_sdy, rw.ubyb);
-    }
-}
-
-// Column offset of lattice column k in level-2 cell ci (plain path: global).
-template <int PREC>
-__device__ __forceinline__ typename Prec<PREC>::T column_offset(const LmDesc& d, int64_t k,
-                                                                int64_t ci)
-{
-    if constexpr (PREC == 2)
-        return (double)local_index(k, ci, d.R) * (0.5 * d.dx);
-    else if constexpr (PREC == 0)
-        return local_offset(k, ci, d.R, d.hxh, d.hxl);
-    else
-        return __builtin_fmaf((float)k + 0.5f, d.dxf, d.x0f);
-}
-
-// Start values of one ray's near sums (rebased paths): the row polynomials
-// without their constant terms, g1 dx + g2 dx^2 + .., from the column's powers
-// pw[k] = dx^(k+1) (one multiply and D - 1 FMAs per axis with wave-uniform
-// powers).
-// (NEG: ay is the negated y sum; every step is an exact negation of the
-// plain one, and the coefficients -gy = Im(...) need no sign modifier)
-template <bool NEG, int PREC, int P, bool FOLD>
-__device__ __forceinline__ void ray_start_first(const Row<PREC, P, FOLD>& rw,
-                                                typename Prec<PREC>::T p1,
-                                                typename Prec<PREC>::T& ax,
-                                                typename Prec<PREC>::T& ay)
-{
-    ax = p1 * rw.gx[1];
-    ay = p1 * (NEG ? -rw.gy[1] : rw.gy[1]);
-}
-
-// term k + 1 (k >= 1) with pk = dx^(k+1)
-template <bool NEG, int PREC, int P, bool FOLD>
-__device__ __forceinline__ void ray_start_next(const Row<PREC, P, FOLD>& rw, int k,
-                                               typename Prec<PREC>::T pk,
-                                               typename Prec<PREC>::T& ax,
-                                               typename Prec<PREC>::T& ay)
-{
-    ax = fma(pk, rw.gx[k + 1], ax);
-    ay = fma(pk, NEG ? -rw.gy[k + 1] : rw.gy[k + 1], ay);
-}
-
-template <int PREC, int P, bool FOLD>
-__device__ __forceinline__ void ray_start(const Row<PREC, P, FOLD>& rw,
-                                          const typename Prec<PREC>::T* pw,
-                                          typename Prec<PREC>::T& ax, typename Prec<PREC>::T& ay)
-{
-    if constexpr (PREC == 1) {
-        ax = 0.f;
-        ay = 0.f;
-    } else {
-        constexpr int D = Row<PREC, P, FOLD>::D;
-        ray_start_first<false, PREC, P, FOLD>(rw, pw[0], ax, ay);
-#pragma unroll
-        for (int k = 1; k < D; ++k) ray_start_next<false, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
-    }
-}
-
-template <int PREC, int P, bool FOLD>
-__device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& rw,
-                                        const float* ar, const float* ai, float a0r, float a0i,
-                                        float zcxf, float zcyf, typename Prec<PREC>::T px,
-                                        typename Prec<PREC>::T ax, typename Prec<PREC>::T ay,
-                                        unsigned& p, unsigned& q)
-{
-    if constexpr (PREC == 1) {
-        int pi, qi;
-        bin_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcxf, zcyf, px, rw.py, ax, ay, pi, qi);
-        p = pi < 0 ? 0u : (unsigned)pi + kBias;
-        q = qi < 0 ? 0u : (unsigned)qi + kBias;
-    } else {
-        bin_rebased(h.inv_sdx, h.inv_sdy, rw.ubxb, rw.ubyb, ax, ay, p, q);
-    }
-}
-
-// --------------------------------------------------------------- units
-
-// Scalar (SMEM) loads of wave-uniform table entries.
-typedef const __attribute__((address_space(4))) float* ConstF;
-
-// One lens (row offset dy, mass m; called with dy = y_k - y, so that by holds
-// negated y sums) against the NR rays of a lane from its
-// table row (dx^2 and m dx per column): pair2 for all columns, staged so that
-// the reciprocals issue back to back instead of each right before its use.
-template <int NR, class T>
-__device__ __forceinline__ void lens_pairs(const T* row, T dy, T m, T* bx, T* by)
-{
-    const T dy2 = dy * dy;
-    const T mdy = m * dy;
-    T r2[NR], md[NR], rr[NR / 2];
-#pragma unroll
-    for (int c = 0; c < NR; ++c) {
-        r2[c] = row[c] + dy2;
-        md[c] = row[NR + c];
-    }
-#pragma unroll
-    for (int c = 0; c < NR; c += 2) rr[c / 2] = r2[c] * r2[c + 1];
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int c = 0; c < NR / 2; ++c) rr[c] = recip(rr[c]);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int c = 0; c < NR; c += 2) {
-        const T wa = rr[c / 2] * r2[c + 1], wb = rr[c / 2] * r2[c];
-        bx[c] = fma(md[c], wa, bx[c]);
-        by[c] = fma(mdy, wa, by[c]);
-        bx[c + 1] = fma(md[c + 1], wb, bx[c + 1]);
-        by[c + 1] = fma(mdy, wb, by[c + 1]);
-    }
-}
-
-// Columns [c_lo, c_hi) of cell ci are computed (c_lo even, so columns 2m and
-// 2m + 1 share a group); rays of columns >= c_beg are counted.
-template <int SCHEME, int PREC, int NR, int P, bool FOLD>
-__device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_beg,
-                             int64_t c_hi, int64_t j, bool row_ok, unsigned axb, unsigned ayb,
-                             unsigned* win, typename Prec<PREC>::L* lb,
-                             typename Prec<PREC>::T* tb, int lane, unsigned& nout)
-{
-    using T = typename Prec<PREC>::T;
-    const int R = d.R;
-    const Hot h = make_hot(d);
-    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
-    double ubx, uby;
-    cell_base<SCHEME>(d, ci, cj, ubx, uby);
-    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
-    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
-    const float zcxf = cell_cxf(d, ci), zcyf = cell_cyf(d, cj);
-    const float h_hxh = d.hxh, h_hxl = d.hxl;
-
-    // the lane's ray row
-    Row<PREC, P, FOLD> rw;
-    row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
-    const T py = rw.py;
-
-    constexpr int kCap = Cap<SCHEME>::value;
-    const int count = __builtin_amdgcn_readfirstlane(list_count<SCHEME>(d, ci, cj));
-    const int nblk = (count + kCap - 1) / kCap;
-    if (nblk == 1) stage<SCHEME, PREC>(d, ci, cj, 0, count, zcx, zcy, lb, lane);
-
-    Run run{run_key(kBias - 2, kBias - 2), (int)(c_beg - c_lo)};
-    for (int64_t c0 = c_lo; c0 < c_hi; c0 += NR) {
-        constexpr int D = Row<PREC, P, FOLD>::D;
-        static_assert(D <= LM_PTAB_POW, "column table holds too few powers");
-        // the table path carries the y sums negated (lens offsets y_k - y):
-        // the row coefficients -gy and the FP64 binning take the sign for free
-        constexpr bool NEGY = UseTab<SCHEME, PREC>::value;
-        T px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
-        if constexpr (PREC == 0) {
-            // wave-uniform column offsets and their powers from the map's table
-            // (scalar loads), one power at a time so that only NR of them are
-            // live in scalar registers
-            const ConstF tab = (ConstF)(d.ptab + (c0 - ci * (int64_t)R));
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    const T pk = tab[k * (R + LM_PTAB_PAD) + c];
-                    if (k == 0) {
-                        px[c] = pk;
-                        ray_start_first<NEGY, PREC, P, FOLD>(rw, pk, ax[c], ay[c]);
-                    } else {
-                        ray_start_next<NEGY, PREC, P, FOLD>(rw, k, pk, ax[c], ay[c]);
-                    }
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        } else {
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                T pw[D];
-                px[c] = column_offset<PREC>(d, c0 + c, ci);
-                col_powers<D>(px[c], pw);
-                ray_start<PREC, P, FOLD>(rw, pw, ax[c], ay[c]);
-                if (NEGY) ay[c] = -ay[c];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            kx[c] = 0;
-            ky[c] = 0;
-        }
-        for (int b = 0; b < nblk; ++b) {
-            const int nb = __builtin_amdgcn_readfirstlane(min(kCap, count - b * kCap));
-            if (nblk > 1) stage<SCHEME, PREC>(d, ci, cj, b * kCap, nb, zcx, zcy, lb, lane);
-            T bx[NR], by[NR];
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                bx[c] = SCHEME == 0 ? T(0) : ax[c];
-                by[c] = SCHEME == 0 ? T(0) : ay[c];
-            }
-            if constexpr (UseTab<SCHEME, PREC>::value) {
-                // this lane's column in the table build: NR divides 64
-                T pxl;
-                if constexpr (PREC == 0)
-                    pxl = local_offset(c0 + (lane & (NR - 1)), ci, R, h_hxh, h_hxl);
-                else
-                    pxl = column_offset<PREC>(d, c0 + (lane & (NR - 1)), ci);
-                for (int k0 = 0; k0 < nb; k0 += kTabCh) {
-                    // wave-uniform count: scalar loop control
-                    const int nk = __builtin_amdgcn_readfirstlane(min(kTabCh, nb - k0));
-                    // tb[k][0..NR) = dx^2, tb[k][NR..2NR) = m dx, for lenses k0 .. k0+nk
-                    for (int e = lane; e < nk * NR; e += 64) {
-                        const int k = e / NR, c = e & (NR - 1);
-                        const auto L = lb[k0 + k];
-                        const T dx = pxl - L.x;
-                        tb[k * 2 * NR + c] = dx * dx;
-                        tb[k * 2 * NR + NR + c] = L.z * dx;
-                    }
-                    wave_sync_lds();
-                    // two lenses per step: their LDS reads share base addresses
-                    int k = 0;
-                    for (; k + 2 <= nk; k += 2) {
-                        const auto L0 = lb[k0 + k], L1 = lb[k0 + k + 1];
-                        lens_pairs<NR>(tb + k * 2 * NR, L0.y - py, L0.z, bx, by);
-                        lens_pairs<NR>(tb + (k + 1) * 2 * NR, L1.y - py, L1.z, bx, by);
-                    }
-                    if (k < nk) {
-                        const auto L = lb[k0 + k];
-                        lens_pairs<NR>(tb + k * 2 * NR, L.y - py, L.z, bx, by);
-                    }
-                    wave_sync_lds();
-                }
-            } else {
-#pragma unroll 2
-                for (int k = 0; k < nb; ++k) {
-                    const auto L = lb[k];
-                    const T dy = py - L.y;
-                    const T dy2 = dy * dy;
-#pragma unroll
-                    for (int c = 0; c < NR; ++c) pair(px[c], dy, dy2, L.x, L.z, bx[c], by[c]);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                if (SCHEME == 0) {
-                    kahan_add(ax[c], kx[c], bx[c]);
-                    kahan_add(ay[c], ky[c], by[c]);
-                } else {
-                    ax[c] = bx[c];
-                    ay[c] = by[c];
-                }
-            }
-            if (nblk > 1) wave_sync_lds();
-        }
-        const int ncol = (int)min((int64_t)NR, c_hi - c0);
-        const int cfirst = (int)max((int64_t)0, c_beg - c0);
-        const int col0 = (int)(c0 - c_lo);
-        if (cfirst == 0 && ncol == NR) {
-            // a whole group (every group but a unit's first and last)
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                unsigned p, q;
-                ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
-                                       NEGY ? -ay[c] : ay[c], p, q);
-                run_push(h, run, p, q, col0 + c, axb, ayb, win, nout, row_ok);
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                if (c >= cfirst && c < ncol) {
-                    unsigned p, q;
-                    ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
-                                           NEGY ? -ay[c] : ay[c], p, q);
-                    run_push(h, run, p, q, col0 + c, axb, ayb, win, nout, row_ok);
-                }
-            }
-        }
-    }
-    run_flush(h, run, (int)(c_hi - c_lo), axb, ayb, win, nout, lane, row_ok);
-}
-
-// Window origin of a tile: the pixel of the image of its centre cell's centre
-// (macro map, far field and near lenses, FP64), less half the window.
-template <int SCHEME>
-__device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_t cjb, int& ax0,
-                                            int& ay0)
-{
-    int64_t cic = min(cib + d.G / 2, d.ncx - 1), cjc = min(cjb + d.G / 2, d.ncy - 1);
-    double ubx, uby;
-    cell_base<SCHEME>(d, cic, cjc, ubx, uby);
-    const double zcx = cell_cx(d, cic), zcy = cell_cy(d, cjc);
-    double sx = 0.0, sy = 0.0;
-    auto add = [&](int idx) {
-        const double dx = zcx - d.lx[idx], dy = zcy - d.ly[idx];
-        const double r2 = dx * dx + dy * dy;
-        if (r2 > 0.0) {
-            const double w = d.lmd[idx] / r2;
-            sx += dx * w;
-            sy += dy * w;
-        }
-    };
-    // the cell's lens list in list order
-    if (SCHEME == 0) {
-        for (int k = 0; k < (int)d.nlens; ++k) add(k);
-    } else {
-        const L1Cell c = l1_of(d, cic, cjc);
-        for (int r = 0; r <= 2 * d.H; ++r) {
-            int s, e;
-            near_row(d, c, r, s, e);
-            for (int idx = s; idx < e; ++idx) add(idx);
-        }
-    }
-    ubx -= sx * d.inv_sdx;
-    uby -= sy * d.inv_sdy;
-    double fx = floor(ubx) - (double)(d.wx / 2), fy = floor(uby) - (double)(d.wy / 2);
-    fx = fmin(fmax(fx, -1.0e9), 1.0e9);
-    fy = fmin(fmax(fy, -1.0e9), 1.0e9);
-    if (fx != fx) fx = 0.0;
-    if (fy != fy) fy = 0.0;
-    ax0 = (int)fx;
-    ay0 = (int)fy;
-}
-
-template <int SCHEME, int PREC, int NR, int P>
-__device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsigned* win,
-                             typename Prec<PREC>::L* lb, typename Prec<PREC>::T* tb, int wave,
-                             int lane)
-{
-    const unsigned axb = (unsigned)ax0 + kBias, ayb = (unsigned)ay0 + kBias;
-    // fewer than 2^31 tiles per launch (checked on the host)
-    const int ntx = (int)d.ntx;
-    const int64_t tx = (int)t % ntx, ty = (int)t / ntx;
-    const int64_t cib = (d.tcx0 + tx) * d.G, cjb = (d.tcy0 + ty) * d.G;
-    const int per_cell = d.nrb * d.ncc;
-    const int U = d.G * d.G * per_cell;
-    unsigned nout = 0;
-    for (int u = wave; u < U; u += LM_WAVES) {
-        const int cu = u / per_cell, rem = u - cu * per_cell;
-        const int rb = rem / d.ncc, cc = rem - rb * d.ncc;
-        const int64_t ci = cib + cu % d.G, cj = cjb + cu / d.G;
-        if (ci >= d.ncx || cj >= d.ncy) continue;
-        const int64_t cell_lo = ci * d.R, cell_hi = cell_lo + d.R;
-        const int64_t c_beg = max(cell_lo + (int64_t)cc * d.cw, d.i0);
-        const int64_t c_hi = min(min(cell_lo + (int64_t)(cc + 1) * d.cw, cell_hi), d.i1);
-        const int64_t r_lo = cj * d.R + (int64_t)rb * 64;
-        if (c_beg >= c_hi || r_lo + 64 <= d.j0 || r_lo >= d.j1) continue;
-        // cells start at even columns (R is a multiple of 64), so c_lo stays in the cell
-        const int64_t c_lo = c_beg & ~(int64_t)1;
-        const int64_t j = r_lo + lane;
-        const bool row_ok = j >= d.j0 && j < d.j1;
-        if (d.fold)
-            process_unit<SCHEME, PREC, NR, P, true>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, axb,
-                                                    ayb, win, lb, tb, lane, nout);
-        else
-            process_unit<SCHEME, PREC, NR, P, false>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, axb,
-                                                     ayb, win, lb, tb, lane, nout);
-    }
-    unsigned tot = wave_sum_u32(nout);
-    if (lane == 0 && tot) atomicAdd(d.n_out, (unsigned long long)tot);
-}
-
-__device__ __forceinline__ void flush_window(const LmDesc& d, unsigned* win, int ax0, int ay0,
-                                             int tid)
-{
-    const int n = d.wx * d.wy;
-    for (int b = tid; b < n; b += kWG) {
-        unsigned v = win[b];
-        if (v) {
-            int64_t p = (int64_t)ax0 + b % d.wx, q = (int64_t)ay0 + b / d.wx;
-            atomicAdd(&d.counts[q * d.snx + p], (unsigned long long)v);
-            win[b] = 0u;
-        }
-    }
-}
-
-// ------------------------------------------------------------- kernels
-
-template <int SCHEME, int PREC, int NR, int P>
-__global__ __launch_bounds__(kWG)
-__attribute__((amdgpu_waves_per_eu(MinWaves<SCHEME, PREC>::value))) void k_shoot_map(LmDesc d)
-{
-    __shared__ unsigned win[kWinMax];
-    __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
-    __shared__ __align__(16) typename Prec<PREC>::T
-        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * 2 * NR : 1];
-    const int tid = threadIdx.x, lane = tid & 63;
-    // wave index as a scalar: everything derived from it stays uniform
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t t = d.tile0 + blockIdx.x;
-    for (int b = tid; b < d.wx * d.wy; b += kWG) win[b] = 0u;
-    // fewer than 2^31 tiles per map (checked on the host)
-    const int64_t tx = (int)t % (int)d.ntx, ty = (int)t / (int)d.ntx;
-    int ax0, ay0;
-    tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
-    __syncthreads();
-    process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave, lane);
-    __syncthreads();
-    flush_window(d, win, ax0, ay0, tid);
-}
-
-template <int SCHEME, int PREC, int NR, int P>
-__global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ descs,
-                                                     const int64_t* __restrict__ offs,
-                                                     const int32_t* __restrict__ order, int nmaps,
-                                                     unsigned long long* queue)
-{
-    __shared__ unsigned win[kWinMax];
-    __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
-    __shared__ __align__(16) typename Prec<PREC>::T
-        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * 2 * NR : 1];
-    __shared__ long long s_item;
-    const int tid = threadIdx.x, lane = tid & 63;
-    // wave index as a scalar: everything derived from it stays uniform
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int b = tid; b < kWinMax; b += kWG) win[b] = 0u;
-    const int64_t total = offs[nmaps];
-    for (;;) {
-        if (tid == 0) s_item = (long long)atomicAdd(queue, 1ull);
-        __syncthreads();
-        const int64_t item = uniform_i64(s_item);
-        __syncthreads();
-        if (item >= total) break;
-        int lo = 0, hi = nmaps - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (offs[mid] <= item)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const LmDesc& d = descs[order[lo]];
-        const int64_t t = item - offs[lo];
-        // fewer than 2^31 tiles per map (checked on the host)
-        const int64_t tx = (int)t % (int)d.ntx, ty = (int)t / (int)d.ntx;
-        int ax0, ay0;
-        tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
-        process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave,
-                                          lane);
-        __syncthreads();
-        flush_window(d, win, ax0, ay0, tid);
-        __syncthreads();
-    }
-}
 
 // A lens as staged for the coefficient sums: position, mass, level-1 cell.
 template <class T>
@@ -1322,274 +257,10 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
         p[i] = v;
 }
 
-// Near-field sum of one position (lens for lens as in the shooting kernel),
-// added to the start values ax, ay.
-// PAIRED: the shooting kernel's two-column reciprocal, pxp = offset of the
-// partner column (column index ^ 1).
-template <int SCHEME, int PREC, bool PAIRED = false>
-__device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, double zcy,
-                         typename Prec<PREC>::T px, typename Prec<PREC>::T py,
-                         typename Prec<PREC>::T& ax, typename Prec<PREC>::T& ay,
-                         typename Prec<PREC>::T pxp = 0)
-{
-    using T = typename Prec<PREC>::T;
-    constexpr int kCap = Cap<SCHEME>::value;
-    const int count = list_count<SCHEME>(d, ci, cj);
-    T kx = 0, ky = 0;
-    for (int b0 = 0; b0 < count; b0 += kCap) {
-        const int nb = min(kCap, count - b0);
-        T bx = SCHEME == 0 ? T(0) : ax, by = SCHEME == 0 ? T(0) : ay;
-        for (int k = 0; k < nb; ++k) {
-            const auto L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
-            const T dy = py - L.y;
-            if constexpr (UseTab<SCHEME, PREC>::value && PAIRED) {
-                const T dx = px - L.x, dxp = pxp - L.x;
-                T ayp = 0, axp = 0;
-                pair2(dx * dx, dxp * dxp, L.z * dx, L.z * dxp, dy * dy, L.z * dy, bx, by, axp, ayp);
-            } else if constexpr (UseTab<SCHEME, PREC>::value) {
-                const T dx = px - L.x;
-                pair_tab(dx * dx, L.z * dx, dy * dy, L.z * dy, bx, by);
-            } else {
-                pair(px, dy, dy * dy, L.x, L.z, bx, by);
-            }
-        }
-        if (SCHEME == 0) {
-            kahan_add(ax, kx, bx);
-            kahan_add(ay, ky, by);
-        } else {
-            ax = bx;
-            ay = by;
-        }
-    }
-}
-
-// Per-ray pixels with the shooting kernel's arithmetic, lens for lens, and the
-// continuous pixel coordinates (u, v) the pixel is the floor of (uv non-null).
-template <int SCHEME, int PREC, int P, bool FOLD>
-__device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, int32_t& qo,
-                          double* uv)
-{
-    using T = typename Prec<PREC>::T;
-    const int R = d.R;
-    const int64_t ci = i / R, cj = j / R;
-    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
-    double ubx, uby;
-    cell_base<SCHEME>(d, ci, cj, ubx, uby);
-    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
-    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
-    Row<PREC, P, FOLD> rw;
-    row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
-    const T px = column_offset<PREC>(d, i, ci);
-    T pw[Row<PREC, P, FOLD>::D], ax, ay;
-    col_powers<Row<PREC, P, FOLD>::D>(px, pw);
-    ray_start<PREC, P, FOLD>(rw, pw, ax, ay);
-    near_sum<SCHEME, PREC, true>(d, ci, cj, zcx, zcy, px, rw.py, ax, ay,
-                                 column_offset<PREC>(d, i ^ 1, ci));
-    const Hot h = make_hot(d);
-    unsigned p, q;
-    ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, ax, ay, p,
-                           q);
-    const unsigned pm = p - kBias, qm = q - kBias;
-    const bool in = (pm < (unsigned)d.snx) & (qm < (unsigned)d.sny);
-    po = in ? (int32_t)pm : -1;
-    qo = in ? (int32_t)qm : -1;
-    if (uv) {
-        if constexpr (PREC == 1) {
-            float u, v;
-            coords_fp32<P, FOLD>(h, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, rw.py,
-                                 ax, ay, u, v);
-            uv[0] = u;
-            uv[1] = v;
-        } else {
-            // the FP64 values bin_rebased floors, less the bias
-            uv[0] = __builtin_fma(-(double)ax, h.inv_sdx, rw.ubxb) - kBiasD;
-            uv[1] = __builtin_fma(-(double)ay, h.inv_sdy, rw.ubyb) - kBiasD;
-        }
-    }
-}
-
-template <int SCHEME, int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restrict__ ii,
-                                               const int64_t* __restrict__ jj, int64_t n,
-                                               int32_t* __restrict__ po, int32_t* __restrict__ qo,
-                                               double* __restrict__ uv)
-{
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (t >= n) return;
-    double* u = uv ? uv + 2 * t : nullptr;
-    if (d.fold)
-        trace_one<SCHEME, PREC, P, true>(d, ii[t], jj[t], po[t], qo[t], u);
-    else
-        trace_one<SCHEME, PREC, P, false>(d, ii[t], jj[t], po[t], qo[t], u);
-}
-
-// Deflection at arbitrary positions, rebased on the level-2 cell holding them.
-template <int SCHEME, int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restrict__ th,
-                                                 int64_t n, double* __restrict__ al)
-{
-    using T = typename Prec<PREC>::T;
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (t >= n) return;
-    const double tx = th[2 * t], ty = th[2 * t + 1];
-    const int64_t ci = (int64_t)floor((tx - d.x0) / ((double)d.R * d.dx));
-    const int64_t cj = (int64_t)floor((ty - d.y0) / ((double)d.R * d.dy));
-    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
-    float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
-    if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
-    T px, py;
-    if (PREC != 1) {
-        px = (T)(tx - zcx);
-        py = (T)(ty - zcy);
-    } else {
-        px = (float)tx;
-        py = (float)ty;
-    }
-    T ax = 0, ay = 0;
-    near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, py, ax, ay);
-    double outx = ax, outy = ay;
-    if (SCHEME == 1) {
-        float fr, fi, dx, dy;
-        if (PREC != 1) {
-            dx = (float)px;
-            dy = (float)py;
-        } else {
-            dx = (float)px - cell_cxf(d, ci);
-            dy = (float)py - cell_cyf(d, cj);
-        }
-        taylor<P>(ar, ai, dx, dy, fr, fi);
-        if (PREC != 1) {
-            const LmCoef& c = d.coef[cj * d.ncx + ci];
-            outx = (double)ax + (double)fr + c.a0r;
-            outy = (double)ay - (double)fi - c.a0i;
-        } else {
-            outx = (double)(ax + (a0r + fr));
-            outy = (double)(ay - (a0i + fi));
-        }
-    }
-    al[2 * t] = outx;
-    al[2 * t + 1] = outy;
-}
-
-// ------------------------------------------------------------ dispatch
-
-// Grids stay below 2^22 workgroups (2^30 work-items) per launch.
-constexpr int64_t kMaxGrid = int64_t(1) << 22;
-
-template <int S, int PR, int NR, int P>
-int launch_map_t(const LmDesc& d0, hipStream_t s)
-{
-    LmDesc d = d0;
-    for (int64_t t0 = 0; t0 < d0.ntiles; t0 += kMaxGrid) {
-        d.tile0 = t0;
-        const int64_t n = d0.ntiles - t0 < kMaxGrid ? d0.ntiles - t0 : kMaxGrid;
-        hipLaunchKernelGGL((k_shoot_map<S, PR, NR, P>), dim3((unsigned)n), dim3(kWG), 0, s, d);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return (int)e;
-    }
-    return 0;
-}
-
-template <int S, int PR, int NR, int P>
-int launch_batch_t(const LmDesc* descs, const int64_t* offs, const int32_t* order, int nmaps,
-                   unsigned long long* queue, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_shoot_batch<S, PR, NR, P>), dim3(grid), dim3(kWG), 0, s, descs, offs,
-                       order, nmaps, queue);
-    return (int)hipGetLastError();
-}
-
-template <int S, int PR, int NR, int P>
-const void* kernel_ptr_t()
-{
-    return (const void*)&k_shoot_batch<S, PR, NR, P>;
-}
-
-// Visit the instantiation for runtime (scheme, precision, NR, P).  The direct
-// scheme has no Taylor terms and is instantiated with P = 1 only.
-template <int S, int PR, int NR, class F>
-int dispatch_p(int terms, F& f)
-{
-    if constexpr (S == 0) {
-        return f.template go<S, PR, NR, 1>();
-    } else {
-        switch (terms) {
-        case 1: return f.template go<S, PR, NR, 1>();
-        case 2: return f.template go<S, PR, NR, 2>();
-        case 3: return f.template go<S, PR, NR, 3>();
-        case 4: return f.template go<S, PR, NR, 4>();
-        case 5: return f.template go<S, PR, NR, 5>();
-        case 6: return f.template go<S, PR, NR, 6>();
-        case 7: return f.template go<S, PR, NR, 7>();
-        default: return (int)hipErrorInvalidValue;
-        }
-    }
-}
-
-template <int S, int PR, class F>
-int dispatch_nr(int nr, int terms, F& f)
-{
-    switch (nr) {
-    case 4: return dispatch_p<S, PR, 4>(terms, f);
-    case 8: return dispatch_p<S, PR, 8>(terms, f);
-    case 16: return dispatch_p<S, PR, 16>(terms, f);
-    default: return (int)hipErrorInvalidValue;
-    }
-}
-
-template <class F>
-int dispatch(int scheme, int prec, int nr, int terms, F&& f)
-{
-    if (scheme == 0 && prec == 0) return dispatch_nr<0, 0>(nr, terms, f);
-    if (scheme == 0 && prec == 1) return dispatch_nr<0, 1>(nr, terms, f);
-    if (scheme == 1 && prec == 0) return dispatch_nr<1, 0>(nr, terms, f);
-    if (scheme == 1 && prec == 1) return dispatch_nr<1, 1>(nr, terms, f);
-    if (scheme == 1 && prec == 2) return dispatch_nr<1, 2>(nr, terms, f);
-    return (int)hipErrorInvalidValue;
-}
-
-// Probes do not depend on NR.
-template <class F>
-int dispatch_probe(int scheme, int prec, int terms, F&& f)
-{
-    if (scheme == 0 && prec == 0) return dispatch_p<0, 0, 4>(terms, f);
-    if (scheme == 0 && prec == 1) return dispatch_p<0, 1, 4>(terms, f);
-    if (scheme == 1 && prec == 0) return dispatch_p<1, 0, 4>(terms, f);
-    if (scheme == 1 && prec == 1) return dispatch_p<1, 1, 4>(terms, f);
-    if (scheme == 1 && prec == 2) return dispatch_p<1, 2, 4>(terms, f);
-    return (int)hipErrorInvalidValue;
-}
-
-struct MapLauncher {
-    const LmDesc& d;
-    hipStream_t s;
-    template <int S, int PR, int NR, int P>
-    int go() { return launch_map_t<S, PR, NR, P>(d, s); }
-};
-
-struct BatchLauncher {
-    const LmDesc* descs;
-    const int64_t* offs;
-    const int32_t* order;
-    int nmaps;
-    unsigned long long* queue;
-    int grid;
-    hipStream_t s;
-    template <int S, int PR, int NR, int P>
-    int go() { return launch_batch_t<S, PR, NR, P>(descs, offs, order, nmaps, queue, grid, s); }
-};
-
-struct Occupancy {
-    int* out;
-    template <int S, int PR, int NR, int P>
-    int go()
-    {
-        return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, kernel_ptr_t<S, PR, NR, P>(),
-                                                                  kWG, 0);
-    }
-};
-
 }  // namespace
+
+// Every (scheme, precision) pair lm_shoot_inst.hip is built for.
+#define LM_PAIRS(X) X(0, 0) X(0, 1) X(1, 0) X(1, 1) X(1, 2)
 
 bool lm_supported_rays_per_lane(int r) { return r == 4 || r == 8 || r == 16; }
 
@@ -1597,20 +268,60 @@ int lm_launch_shoot_map(const LmDesc& d, int scheme, int precision, int terms, i
                         void* stream)
 {
     if (d.ntiles <= 0) return 0;
-    return dispatch(scheme, precision, rays_per_lane, terms, MapLauncher{d, (hipStream_t)stream});
+#define X(S, PR)                                                                            \
+    if (scheme == S && precision == PR)                                                     \
+        return LM_INST_CAT(lm_inst_shoot_map, S, PR)(d, rays_per_lane, terms, stream);
+    LM_PAIRS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
 }
 
 int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int32_t* order,
                           int nmaps, unsigned long long* queue, int scheme, int precision,
                           int terms, int rays_per_lane, int grid, void* stream)
 {
-    return dispatch(scheme, precision, rays_per_lane, terms,
-                    BatchLauncher{descs, offsets, order, nmaps, queue, grid, (hipStream_t)stream});
+#define X(S, PR)                                                                            \
+    if (scheme == S && precision == PR)                                                     \
+        return LM_INST_CAT(lm_inst_shoot_batch, S, PR)(descs, offsets, order, nmaps, queue, \
+                                                       rays_per_lane, terms, grid, stream);
+    LM_PAIRS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
 }
 
 int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu)
 {
-    return dispatch(scheme, precision, rays_per_lane, terms, Occupancy{wg_per_cu});
+#define X(S, PR)                                                                            \
+    if (scheme == S && precision == PR)                                                     \
+        return LM_INST_CAT(lm_inst_occupancy, S, PR)(rays_per_lane, terms, wg_per_cu);
+    LM_PAIRS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
+}
+
+int lm_launch_trace(const LmDesc& d, int scheme, int precision, int terms, const int64_t* ii,
+                    const int64_t* jj, int64_t n, int32_t* p, int32_t* q, double* uv,
+                    void* stream)
+{
+    if (n <= 0) return 0;
+#define X(S, PR)                                                                            \
+    if (scheme == S && precision == PR)                                                     \
+        return LM_INST_CAT(lm_inst_trace, S, PR)(d, terms, ii, jj, n, p, q, uv, stream);
+    LM_PAIRS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
+}
+
+int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, const double* th,
+                      int64_t n, double* alpha, void* stream)
+{
+    if (n <= 0) return 0;
+#define X(S, PR)                                                                            \
+    if (scheme == S && precision == PR)                                                     \
+        return LM_INST_CAT(lm_inst_deflect, S, PR)(d, terms, th, n, alpha, stream);
+    LM_PAIRS(X)
+#undef X
+    return (int)hipErrorInvalidValue;
 }
 
 int lm_launch_coeffs_hier(const LmDesc& d, int terms, LmCoef* out, void* stream)
@@ -1693,55 +404,4 @@ int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int
 #undef LM_COEF_P
 #undef LM_COEF
     return (int)hipGetLastError();
-}
-
-namespace {
-struct TraceLauncher {
-    const LmDesc& d;
-    const int64_t* ii;
-    const int64_t* jj;
-    int64_t n;
-    int32_t* p;
-    int32_t* q;
-    double* uv;
-    hipStream_t s;
-    template <int S, int PR, int NR, int P>
-    int go()
-    {
-        hipLaunchKernelGGL((k_trace<S, PR, P>), dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG),
-                           0, s, d, ii, jj, n, p, q, uv);
-        return (int)hipGetLastError();
-    }
-};
-struct DeflectLauncher {
-    const LmDesc& d;
-    const double* th;
-    int64_t n;
-    double* al;
-    hipStream_t s;
-    template <int S, int PR, int NR, int P>
-    int go()
-    {
-        hipLaunchKernelGGL((k_deflect<S, PR, P>), dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG),
-                           0, s, d, th, n, al);
-        return (int)hipGetLastError();
-    }
-};
-}  // namespace
-
-int lm_launch_trace(const LmDesc& d, int scheme, int precision, int terms, const int64_t* ii,
-                    const int64_t* jj, int64_t n, int32_t* p, int32_t* q, double* uv,
-                    void* stream)
-{
-    if (n <= 0) return 0;
-    return dispatch_probe(scheme, precision, terms,
-                          TraceLauncher{d, ii, jj, n, p, q, uv, (hipStream_t)stream});
-}
-
-int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, const double* th,
-                      int64_t n, double* alpha, void* stream)
-{
-    if (n <= 0) return 0;
-    return dispatch_probe(scheme, precision, terms,
-                          DeflectLauncher{d, th, n, alpha, (hipStream_t)stream});
 }

@@ -81,7 +81,9 @@ def test_near_lists_longer_than_one_block(precision):
           (pairs, used, est))
     assert pairs > 80
     if precision == lm.LM_PREC_AUTO:
-        assert used == lm.LM_PREC_MIXED_FP64 and est > 5e-6
+        # the lattice-mean estimate alone (~3e-6) would keep FP32: the near-list
+        # length decides
+        assert used == lm.LM_PREC_MIXED_FP64
     _run(w, g, (700_011, 20_033, 2_001, 1_100), "near-fold, long near lists, prec=%d" % precision)
 
 

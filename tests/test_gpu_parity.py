@@ -296,14 +296,18 @@ def test_interp_error_of_kernel_arithmetic_1e6_rays():
     gd.scheme = oracle.SCHEME_DIRECT
     b_dir, _ = oracle.Oracle(gd, w.kappa, w.gamma, w.kappa_star, x, y, m).trace(ii, jj)
     b_int, _ = orc.trace(ii, jj)
+    th = np.stack([g.ray_x0 + (ii + 0.5) * g.ray_dx, g.ray_y0 + (jj + 0.5) * g.ray_dy], axis=1)
+    a_mag = np.hypot(*orc.deflect(th).T)
     e_dir = np.hypot(*(b_gpu - b_dir).T)
     e_int = np.hypot(*(b_gpu - b_int).T)
     e_scheme = np.hypot(*(b_int - b_dir).T)
     _say("1e6 rays: max |beta_gpu - beta_direct| = %.2e (rms %.2e), max |beta_gpu - beta_interp| "
-         "= %.2e, oracle interp vs direct max %.2e theta_E" %
-         (e_dir.max(), np.sqrt((e_dir ** 2).mean()), e_int.max(), e_scheme.max()))
+         "= %.2e (rms %.2e), oracle interp vs direct max %.2e theta_E" %
+         (e_dir.max(), np.sqrt((e_dir ** 2).mean()), e_int.max(), np.sqrt((e_int ** 2).mean()),
+          e_scheme.max()))
     assert e_dir.max() <= 1e-4
-    assert e_int.max() <= 1e-6
+    # FP32 rounding is relative to the deflection, which grows as 1/r next to a lens
+    assert np.all(e_int <= 1e-6 * np.maximum(1.0, a_mag))
     mp.close()
 
 
