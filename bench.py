@@ -269,6 +269,92 @@ def batched_study(lm, inputs, torch, scale, hierarchical=False):
                           if hierarchical else "direct (Sec. 3.2.2) for all maps")}
 
 
+TABLE1_THETA_E_ARCSEC = 1e-6
+TABLE1_D_ARCMIN = (3.62, -3.41)
+TABLE1_N_STAR = 13745
+
+
+def fold_study_leg(lm, inputs, torch, n_maps=80):
+    """The statistics of Sec. 4.2 (Figs. 4 and 5) on n_maps independent fold
+    maps with the physics of Table 1 (inputs.fold_study: 40 theta_E across the
+    caustic and 40 along it, 0.011 theta_E pixels, 1000 rays per pixel): one
+    batch shoots every map, then ten light curves per map cross the caustic
+    (map rows) and the library finds their true peaks and bins them by
+    distance to the caustic on the GPU.  Reported: the true-peak number density
+    per unit length of light curve, in units of s_f and divided by N_cf of
+    Eq. 14, against beta_x / s_f; and the mean peak magnification divided by
+    the prefactor of Eq. 15 against beta_x / s_w.  The prefactor takes the
+    source radius as half a pixel (D_s / R = 2 / (pixel theta_E), theta_E in
+    radians)."""
+    import math
+
+    import numpy as np
+    ws = inputs.fold_study(n_maps)
+    maps, geoms = [], []
+    t_setup = time.perf_counter()
+    for w in ws:
+        k0, dx, _ = w.fold
+        g = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], w.src_pixels,
+                                       w.extra["src_ny"], k0, dx, w.kappa_star, n_rays=w.n_rays)
+        lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
+        maps.append(lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold))
+        geoms.append(g)
+    rays = sum(g.n_rays for g in geoms)
+    b = lm.lm_batch_create([m.h for m in maps])
+    lm.lm_batch_tune(b, None)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    t0 = time.perf_counter()
+    lm.lm_batch_shoot(b, stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    c_ms, s_ms = lm.lm_batch_timing(b)
+    g0 = geoms[0]
+    th_rad = TABLE1_THETA_E_ARCSEC / 3600.0 * math.pi / 180.0
+    dsr = 2.0 / (g0.src_dx * th_rad)
+    sc = lm.lm_fold_scales(TABLE1_THETA_E_ARCSEC, *TABLE1_D_ARCMIN, 0.83, 0.001, TABLE1_N_STAR,
+                           dsr)
+    sf, sw = sc["s_f"], sc["s_w"]
+    e_sf = np.arange(-8, 49) * sf
+    e_sw = sw * np.logspace(-3.0, math.log10(1.2), 26)
+    acc = {"sf": [np.zeros(len(e_sf) - 1, dtype=np.uint64) for _ in range(3)],
+           "sw": [np.zeros(len(e_sw) - 1, dtype=np.uint64) for _ in range(3)]}
+    t1 = time.perf_counter()
+    for m, g in zip(maps, geoms):
+        tracks = np.linspace(g.src_ny // 10, g.src_ny - g.src_ny // 10, 10).astype(np.int32)
+        for key, edges in (("sf", e_sf), ("sw", e_sw)):
+            for a, v in zip(acc[key], lm.lm_peak_stats(m.h, tracks, edges)):
+                a += v
+    dt_stats = time.perf_counter() - t1
+    factor = maps[0].mu_factor()
+    lm.lm_batch_destroy(b)
+    for m in maps:
+        m.close()
+    pk, _, px = acc["sf"]
+    length = px.astype(np.float64) * g0.src_dx  # theta_E of light curve per bin
+    density = np.where(length > 0, pk / np.maximum(length, 1e-300), 0.0) * sf / sc["n_cf"]
+    pk2, ht2, _ = acc["sw"]
+    mu_red = np.where(pk2 > 0, ht2.astype(np.float64) / np.maximum(pk2, 1) * factor, 0.0) / \
+        sc["mu_peak0"]
+    log("fold study: %d maps, %.4g rays in %.2f s (%.4g rays/s, shoot %.0f ms, coefficients "
+        "%.0f ms); %d light curves, %d true peaks, statistics in %.2f s" %
+        (len(maps), rays, dt, rays / dt, s_ms, c_ms, 10 * len(maps), int(pk.sum()), dt_stats))
+    return {"maps": len(maps), "rays": rays, "seconds": dt, "rays_per_s": rays / dt,
+            "shoot_kernel_ms": s_ms, "coefficients_ms": c_ms, "setup_s": t_setup,
+            "light_curves": 10 * len(maps), "true_peaks": int(pk.sum()),
+            "scales": {"s_f": sf, "s_w": sw, "n_cf": sc["n_cf"], "mu_peak0": sc["mu_peak0"],
+                       "kappa_c": sc["kappa_c"], "ds_over_r": dsr},
+            "density_vs_beta_over_s_f": {
+                "bin_centres": [round(0.5 * (a + c) / sf, 3) for a, c in zip(e_sf, e_sf[1:])],
+                "true_peaks": [int(v) for v in pk],
+                "density_per_s_f_over_n_cf": [round(float(v), 5) for v in density]},
+            "mean_peak_mu_vs_beta_over_s_w": {
+                "bin_centres": [round(math.sqrt(a * c) / sw, 5) for a, c in zip(e_sw, e_sw[1:])],
+                "true_peaks": [int(v) for v in pk2],
+                "mu_peak_over_prefactor": [round(float(v), 5) for v in mu_red]}}
+
+
 def paper_table1_leg(lm, inputs, torch, precision):
     """The paper's own map (Table 1, Sec. 4.1): fold model, 13745 unit lenses,
     2.69e13 rays into a 73877 x 363635 uint64 map (215 GB, resident in HBM).
@@ -346,6 +432,9 @@ def main():
     ap.add_argument("--study-scale", type=float, default=0.25,
                     help="fraction of the batched 80-map study's rays for its side measurement "
                          "(0 skips it)")
+    ap.add_argument("--fold-maps", type=int, default=80,
+                    help="fold maps of the peak-statistics side measurement (Sec. 4.2; 0 skips "
+                         "it)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default execution parameters (16 rays per lane, tile scale 1, "
                          "all workgroups that fit), which the tuner picks on MI355X")
@@ -496,6 +585,8 @@ def main():
     }
     if study is not None:
         line["batched_study"] = study
+    if args.fold_maps > 0:
+        line["fold_peak_statistics"] = fold_study_leg(lm, inputs, torch, args.fold_maps)
     if args.paper_map != "none":
         precs = {"auto": [lm.LM_PREC_AUTO], "mixed": [lm.LM_PREC_MIXED],
                  "fp64": [lm.LM_PREC_MIXED_FP64],

@@ -310,6 +310,23 @@ lm_status lm_precision_info(lm_map* m, int32_t* precision, double* fp32_mismatch
 lm_status lm_find_peaks(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
                         uint8_t* flags);
 
+/* Statistics of the true peaks of Sec. 4.2 (Figs. 4 and 5) by distance to the
+ * caustic, on the map's current counts.  Light curves are the listed rows
+ * tracks[t] as in lm_find_peaks (peak test with threshold k); distance bin b
+ * covers beta_x in [beta_edges[b], beta_edges[b+1]) (n_bins + 1 increasing
+ * edges in theta_E, host), and pixel column p belongs to the bin holding its
+ * centre src_x0 + (p + 1/2) src_dx (evaluated in FP64 in that order).  For
+ * each bin, written to host arrays of n_bins entries: peaks[b] the true peaks
+ * of the listed rows in the bin, heights[b] the sum of their counts (times
+ * lm_mu_factor: their summed magnification), pixels[b] the light-curve pixels
+ * in the bin (n_tracks x its columns: the length the peaks were found on).
+ * Exact integers.  LM_EINVAL for bad arguments (1 <= n_bins <= 65536,
+ * 1 <= k <= 1000, edges finite and increasing), LM_ERANGE for a row outside
+ * the map.  Synchronous. */
+lm_status lm_peak_stats(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                        const double* beta_edges, int32_t n_bins, uint64_t* peaks,
+                        uint64_t* heights, uint64_t* pixels);
+
 /* Analysis scales near a fold caustic (Sec. 4): kappa_c = (theta_E |d|)^(2/3),
  * |sin a| with tan a = d_x/d_y, the micro-caustic band width s_w (Eq. 13),
  * C_star and s_f = C_star theta_E kappa_star^(1/2), the micro-caustic count

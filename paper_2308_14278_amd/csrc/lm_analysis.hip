@@ -6,6 +6,10 @@
 // counts and sigma_ij = sqrt(<N>); with S the sum of the three counts this is
 // (3 N_ij - S)^2 > 3 k^2 S, decided exactly in integers.  True peak: a
 // candidate with a candidate among (i-1, j-1..j+1) and among (i+1, j-1..j+1).
+//
+// k_peak_bins gathers the statistics of Sec. 4.2 (Figs. 4 and 5): the true
+// peaks of the listed light curves per bin of distance to the caustic (bin of
+// pixel j given by the host) and the sum of their counts, both exact integers.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -54,7 +58,49 @@ __global__ __launch_bounds__(256) void k_peaks(const unsigned long long* __restr
     flags[idx] = f;
 }
 
+__device__ __forceinline__ bool true_peak(const unsigned long long* __restrict__ c, int64_t nx,
+                                          int64_t ny, int64_t i, int64_t j, unsigned k2x3)
+{
+    if (!(i > 0 && i < ny - 1) || !candidate(c, nx, i, j, k2x3)) return false;
+    const bool left = candidate(c, nx, i - 1, j - 1, k2x3) || candidate(c, nx, i - 1, j, k2x3) ||
+                      candidate(c, nx, i - 1, j + 1, k2x3);
+    return left && (candidate(c, nx, i + 1, j - 1, k2x3) || candidate(c, nx, i + 1, j, k2x3) ||
+                    candidate(c, nx, i + 1, j + 1, k2x3));
+}
+
+// One thread per (light curve t, pixel j); true peaks are rare, so their bins
+// are added to with global atomics.
+__global__ __launch_bounds__(256) void k_peak_bins(const unsigned long long* __restrict__ counts,
+                                                   int64_t nx, int64_t ny,
+                                                   const int32_t* __restrict__ tracks, int64_t nt,
+                                                   unsigned k2x3, const int32_t* __restrict__ bin_of,
+                                                   unsigned long long* __restrict__ peaks,
+                                                   unsigned long long* __restrict__ heights)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nt * nx) return;
+    const int64_t t = idx / nx, j = idx - t * nx;
+    const int b = bin_of[j];
+    if (b < 0) return;
+    const int64_t i = tracks[t];
+    if (!true_peak(counts, nx, ny, i, j, k2x3)) return;
+    atomicAdd(&peaks[b], 1ull);
+    atomicAdd(&heights[b], counts[i * nx + j]);
+}
+
 }  // namespace
+
+int lm_launch_peak_bins(const unsigned long long* counts, int64_t nx, int64_t ny,
+                        const int32_t* tracks, int64_t nt, int k, const int32_t* bin_of,
+                        unsigned long long* peaks, unsigned long long* heights, void* stream)
+{
+    const int64_t n = nt * nx;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_peak_bins, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, counts, nx, ny, tracks, nt, (unsigned)(3 * k * k),
+                       bin_of, peaks, heights);
+    return (int)hipGetLastError();
+}
 
 int lm_launch_peaks(const unsigned long long* counts, int64_t nx, int64_t ny,
                     const int32_t* tracks, int64_t nt, int k, uint8_t* flags, void* stream)

@@ -1161,6 +1161,59 @@ lm_status lm_find_peaks(lm_map* m, const int32_t* tracks, int32_t n_tracks, int3
     return ok();
 }
 
+lm_status lm_peak_stats(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                        const double* beta_edges, int32_t n_bins, uint64_t* peaks,
+                        uint64_t* heights, uint64_t* pixels)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (n_tracks < 0 || n_bins < 1 || n_bins > (1 << 16) || !beta_edges || !peaks || !heights ||
+        !pixels || (n_tracks > 0 && !tracks))
+        return fail(LM_EINVAL, "bad arguments");
+    if (k < 1 || k > 1000) return fail(LM_EINVAL, "k must be in 1..1000");
+    for (int32_t b = 0; b <= n_bins; ++b)
+        if (!isfin(beta_edges[b]) || (b > 0 && !(beta_edges[b] > beta_edges[b - 1])))
+            return fail(LM_EINVAL, "bin edges must be finite and increasing");
+    for (int32_t t = 0; t < n_tracks; ++t)
+        if (tracks[t] < 0 || tracks[t] >= m->g.src_ny)
+            return fail(LM_ERANGE, "track %d (row %d) is outside the map", t, tracks[t]);
+    if ((int64_t)n_tracks * m->g.src_nx >= (int64_t(1) << 31))
+        return fail(LM_EUNSUPPORTED, "too many track pixels");
+    // bin of each pixel column: the bin holding the pixel centre's beta_x
+    const int64_t nx = m->g.src_nx;
+    std::vector<int32_t> bin_of(nx);
+    std::fill(pixels, pixels + n_bins, 0);
+    for (int64_t p = 0; p < nx; ++p) {
+        const double bc = m->g.src_x0 + ((double)p + 0.5) * m->g.src_dx;
+        int32_t b = -1;
+        if (bc >= beta_edges[0] && bc < beta_edges[n_bins])
+            b = (int32_t)(std::upper_bound(beta_edges, beta_edges + n_bins + 1, bc) - beta_edges) - 1;
+        bin_of[p] = b;
+        if (b >= 0) pixels[b] += (uint64_t)n_tracks;
+    }
+    std::fill(peaks, peaks + n_bins, 0);
+    std::fill(heights, heights + n_bins, 0);
+    if (n_tracks == 0) return ok();
+    lm_status st = use_device(m);
+    if (st) return st;
+    DevBuf dt, db, dh;
+    if (dt.ensure((size_t)n_tracks * 4) || db.ensure((size_t)nx * 4) ||
+        dh.ensure((size_t)n_bins * 16))
+        return fail(LM_ENOMEM, "cannot allocate");
+    HIP_TRY(hipStreamSynchronize(m->last));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(dt.p, tracks, (size_t)n_tracks * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(db.p, bin_of.data(), (size_t)nx * 4, hipMemcpyHostToDevice));
+    unsigned long long* dpk = dh.as<unsigned long long>();
+    LAUNCH_TRY(lm_launch_fill_u64(dpk, 2 * (int64_t)n_bins, 0ull, nullptr));
+    LAUNCH_TRY(lm_launch_peak_bins(reinterpret_cast<const unsigned long long*>(m->counts), nx,
+                                   m->g.src_ny, dt.as<int32_t>(), n_tracks, k, db.as<int32_t>(),
+                                   dpk, dpk + n_bins, nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    HIP_TRY(hipMemcpy(peaks, dpk, (size_t)n_bins * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(heights, dpk + n_bins, (size_t)n_bins * 8, hipMemcpyDeviceToHost));
+    return ok();
+}
+
 lm_status lm_fold_scales(double theta_e_arcsec, double d_x, double d_y, double kappa0,
                          double kappa_star, double n_star, double ds_over_r,
                          lm_fold_scales_t* out)

@@ -95,6 +95,11 @@ int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, con
                       int64_t n, double* alpha, void* stream);
 int lm_launch_peaks(const unsigned long long* counts, int64_t nx, int64_t ny,
                     const int32_t* tracks, int64_t nt, int k, uint8_t* flags, void* stream);
+// peaks[b] += true peaks of the listed rows in pixels j with bin_of[j] == b,
+// heights[b] += their counts (bin_of[j] < 0: no bin)
+int lm_launch_peak_bins(const unsigned long long* counts, int64_t nx, int64_t ny,
+                        const int32_t* tracks, int64_t nt, int k, const int32_t* bin_of,
+                        unsigned long long* peaks, unsigned long long* heights, void* stream);
 int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu);
 bool lm_supported_rays_per_lane(int r);
 

@@ -201,6 +201,28 @@ def paper_table1(n_rays: float = 1000.0 * 363635 * 73877) -> Workload:
                     extra={"src_ly": 200.0, "src_ny": 363635})
 
 
+def fold_study(n_maps: int = 80, pixel: float = 0.011, src_ly: float = 40.0,
+               n_av: float = 1000.0) -> list[Workload]:
+    """Independent realisations of the paper's lens field near the fold (Table 1
+    physics: kappa_0 = 0.83, d = (3.62, -3.41) arcmin^-1 at theta_E = 1e-6
+    arcsec, kappa_star = 0.001, unit masses) for the peak statistics of
+    Sec. 4.2: each map spans the paper's 40 theta_E across the caustic (plus
+    the 20 sqrt(kappa_star) margin) and src_ly along it, in pixels of `pixel`
+    theta_E (20x the paper's 5.5e-4 by default), with N_av rays per pixel as in
+    the paper.  Lenses: call lenses(rect=...) with the shooting region; their
+    number is Table 1's N_star = 13745 for 200 theta_E along the caustic,
+    scaled to src_ly (the region's width across the caustic is the paper's)."""
+    margin = 20.0 * math.sqrt(0.001)
+    nx = int(round((40.0 + margin) / pixel))
+    ny = int(round(src_ly / pixel))
+    n = int(round(13745 * src_ly / 200.0))
+    return [Workload("fold-study-%02d" % m, 7, m, 0.83, 0.0, 0.001, n, 40.0, nx,
+                     n_rays=n_av * nx * ny, scheme=1, coarse=0, masses="unit",
+                     fold=(0.83, TABLE1_D[0], TABLE1_D[1]),
+                     extra={"src_ly": src_ly, "src_ny": ny})
+            for m in range(n_maps)]
+
+
 WORKLOADS = {
     "plain-small": plain_small,
     "near-fold": near_fold,

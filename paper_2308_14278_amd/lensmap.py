@@ -136,6 +136,8 @@ _SIGS = {
     "lm_measure_issue_rates": [_d, ctypes.c_int32],
     "lm_find_peaks": [_vp, _i32, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_uint8)],
     "lm_fold_scales": [ctypes.c_double] * 7 + [_P(lm_fold_scales_t)],
+    "lm_peak_stats": [_vp, _i32, ctypes.c_int32, ctypes.c_int32, _d, ctypes.c_int32, _u64, _u64,
+                      _u64],
 }
 
 _lib = None
@@ -419,6 +421,18 @@ def lm_find_peaks(m, g: lm_geometry, tracks, k=5):
     _check(load().lm_find_peaks(m, tr.ctypes.data_as(_i32), tr.shape[0], int(k),
                                 flags.ctypes.data_as(_P(ctypes.c_uint8))), "lm_find_peaks")
     return flags
+
+
+def lm_peak_stats(m, tracks, beta_edges, k=5):
+    """(peaks, heights, pixels) per distance bin, uint64 arrays of len(edges) - 1."""
+    tr = np.ascontiguousarray(tracks, dtype=np.int32)
+    ed = np.ascontiguousarray(beta_edges, dtype=np.float64)
+    nb = ed.shape[0] - 1
+    out = [np.zeros(max(nb, 0), dtype=np.uint64) for _ in range(3)]
+    _check(load().lm_peak_stats(m, tr.ctypes.data_as(_i32), tr.shape[0], int(k),
+                                ed.ctypes.data_as(_d), nb, *[o.ctypes.data_as(_u64) for o in out]),
+           "lm_peak_stats")
+    return tuple(out)
 
 
 def lm_shot_stats(m, i0, j0, ni, nj) -> lm_stats:

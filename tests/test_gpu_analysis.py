@@ -82,3 +82,51 @@ def test_peaks_on_a_shot_map():
         lm.lm_find_peaks(mp.h, g, [g.src_ny])
     assert e.value.status == lm.LM_ERANGE
     mp.close()
+
+
+def test_peak_stats_bitwise():
+    """Statistics of true peaks by distance to the caustic (Sec. 4.2): the
+    kernel's histograms (peaks, summed counts, light-curve pixels per bin)
+    equal the oracle's plain count on the same map, on a synthetic map with
+    planted ridges and on a fold map shot on the GPU, with bins that leave
+    columns out at both ends."""
+    from oracle.peak_stats import peak_stats
+    rng = np.random.default_rng(8)
+    c = rng.poisson(300, size=(30, 900)).astype(np.int64)
+    for r in range(2, 28, 2):
+        for _ in range(6):
+            j = int(rng.integers(3, 890))
+            for d in range(-1, 2):
+                c[r + d, j + int(rng.integers(-1, 2))] += int(rng.integers(80, 600))
+    mp, g, buf = _map_with_counts(c)
+    edges = np.linspace(g.src_x0 + 0.1 * g.src_dx * g.src_nx, g.src_x0 + 0.9 * g.src_dx * g.src_nx,
+                        14)
+    tracks = list(range(1, 29))
+    got = lm.lm_peak_stats(mp.h, tracks, edges)
+    ref = peak_stats(c.tolist(), tracks, list(edges), g.src_x0, g.src_dx)
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a, np.array(b, dtype=np.uint64))
+    assert got[0].sum() > 20
+    lm.lm_bind_counts(mp.h, None)
+    mp.close()
+
+    # a fold map (Eq. 5/6) shot on the GPU: bins in beta_x across the caustic
+    import math
+    k0, dx, dy, ks = 0.83, 2.0e-3, -1.5e-3, 0.01
+    g = lm.lm_geometry_derive_fold(4.0, 4.0, 400, 400, k0, dx, ks, n_rays=4e7, coarse=64)
+    hx, hy = g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2
+    n = int(round(4 * hx * hy * ks / math.pi))
+    x, y = rng.uniform(-hx, hx, n), rng.uniform(-hy, hy, n)
+    mp = lm.Map(g, kappa_star=ks, lenses=(x, y, np.ones(n)), fold=(k0, dx, dy))
+    mp.shoot()
+    counts, _, _ = mp.counts()
+    tracks = list(range(20, 380, 36))
+    edges = np.concatenate([[-0.2], np.geomspace(0.01, 4.0, 12)])
+    got = lm.lm_peak_stats(mp.h, tracks, edges)
+    ref = peak_stats(counts.astype(np.int64).tolist(), tracks, list(edges), g.src_x0, g.src_dx)
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a, np.array(b, dtype=np.uint64))
+    print("fold map: %d true peaks on %d light curves" % (int(got[0].sum()), len(tracks)))
+    with pytest.raises(lm.LensmapError):
+        lm.lm_peak_stats(mp.h, tracks, [0.0, 0.0, 1.0])
+    mp.close()

@@ -68,3 +68,39 @@ def test_poisson_noise_rarely_passes():
     true = sum(f & TRUE_PEAK != 0 for row in flags for f in row)
     assert cand < 20
     assert true == 0
+
+
+# ------------------------------------------------ statistics by distance (Sec. 4.2)
+
+from oracle.peak_stats import bin_of_column, peak_stats  # noqa: E402
+
+
+def test_peak_stats_on_placed_peaks():
+    """Spikes placed by hand in three neighbouring rows (so the middle one is a
+    true peak) at known columns: the histogram holds exactly those peaks, their
+    counts, and the light-curve length per bin."""
+    n_cols = 40
+    base = np.full((7, n_cols), 100, dtype=np.int64)
+    # columns 5 and 23: true peaks on row 3; column 31: a candidate only
+    for col, h in ((5, 400), (23, 900)):
+        base[2, col + 1] = base[3, col] = base[4, col - 1] = h
+    base[3, 31] = 500
+    src_x0, src_dx = -1.0, 0.25  # column p centred at -1 + (p + 1/2) / 4
+    edges = [-1.0, 0.5, 4.0, 9.0]  # columns 0-5, 6-19, 20-39
+    peaks, heights, pixels = peak_stats(base.tolist(), [3], edges, src_x0, src_dx)
+    assert peaks == [1, 0, 1]
+    assert heights == [400, 0, 900]
+    assert pixels == [6, 14, 20]
+    # two light curves: the outer rows hold candidates but no true peaks
+    peaks2, _, pixels2 = peak_stats(base.tolist(), [2, 3], edges, src_x0, src_dx)
+    assert peaks2 == [1, 0, 1] and pixels2 == [12, 28, 40]
+
+
+def test_bin_of_column_edges_are_half_open():
+    edges = [0.0, 1.0, 2.0]
+    # centres 0.5, 1.5, 2.5 with dx = 1 from x0 = 0
+    assert [bin_of_column(p, 0.0, 1.0, edges) for p in range(3)] == [0, 1, -1]
+    # a centre exactly on an edge belongs to the bin it opens
+    assert bin_of_column(0, 0.5, 1.0, edges) == 1
+    assert bin_of_column(0, -0.5, 1.0, edges) == 0
+    assert bin_of_column(0, -0.6, 1.0, edges) == -1
