@@ -488,8 +488,9 @@ def main():
         log("tuned %s in %.1f s" % (lm.lm_batch_params(b), time.perf_counter() - t0))
     tune_results = lm.lm_batch_tune_results(b)
     for r in tune_results:
-        log("  candidate rays/lane %d, tile scale %d, WG/CU %d: %.4g rays/s on %.3g rays" %
-            (r["rays_per_lane"], r["tile_scale"], r["wg_per_cu"], r["rays_per_s"], r["rays"]))
+        log("  candidate rays/lane %d, tile scale %d, WG/CU %d, LDS layout %d: %.4g rays/s on "
+            "%.3g rays" % (r["rays_per_lane"], r["tile_scale"], r["wg_per_cu"], r["lds_layout"],
+                           r["rays_per_s"], r["rays"]))
 
     def step():
         lm.lm_reset_counts(mp.h, stream)
@@ -568,7 +569,7 @@ def main():
                                         "fp32_mismatch_estimate": prec_est},
                    "exec_params": list(lm.lm_batch_params(b)),
                    "tuner_candidates": [{"params": [r["rays_per_lane"], r["tile_scale"],
-                                                    r["wg_per_cu"]],
+                                                    r["wg_per_cu"], r["lds_layout"]],
                                          "rays_per_s": r["rays_per_s"], "rays": r["rays"]}
                                         for r in tune_results]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,

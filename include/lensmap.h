@@ -327,6 +327,20 @@ lm_status lm_peak_stats(lm_map* m, const int32_t* tracks, int32_t n_tracks, int3
                         const double* beta_edges, int32_t n_bins, uint64_t* peaks,
                         uint64_t* heights, uint64_t* pixels);
 
+/* lm_peak_stats without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * lm_peak_stats; its device staging (the rows, the bin of every pixel column,
+ * the bin edges and the two histograms, 4.2 MB) lives in a scratch array that
+ * the library holds on each device it runs on until the process ends, which
+ * limits a call to at most 8192 rows, maps of at most 2^20 columns and at most
+ * 4096 bins (LM_EINVAL beyond).  Every call on one device shares that array,
+ * so calls that overlap on one device (from several threads) race; the
+ * histograms are cleared at the start of each call.  Synchronous. */
+lm_status lm_peak_stats_noalloc(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                                const double* beta_edges, int32_t n_bins, uint64_t* peaks,
+                                uint64_t* heights, uint64_t* pixels);
+
 /* Analysis scales near a fold caustic (Sec. 4): kappa_c = (theta_E |d|)^(2/3),
  * |sin a| with tan a = d_x/d_y, the micro-caustic band width s_w (Eq. 13),
  * C_star and s_f = C_star theta_E kappa_star^(1/2), the micro-caustic count
@@ -373,14 +387,15 @@ lm_status lm_batch_set_rect(lm_batch* b, int32_t index, int64_t i0, int64_t j0, 
                             int64_t nj);
 
 /* Pick execution parameters (rays per lane, workgroup tile size, workgroups
- * per CU) for the study of Sec. 4.2 by timing every candidate on one fixed
+ * per CU, LDS layout) for the study of Sec. 4.2 by timing every candidate on one fixed
  * sample of the batch's rays (lm_tune_sample of each map with the fraction
  * that makes about 2e10 rays in all, or the whole batch if smaller): the
  * fastest in rays/s wins.  Results never depend on the choice.  Unless the
  * cache holds the choice, the maps must have no counts (LM_ESTATE); they are
  * zero again afterwards.  The choice is
  * cached at cache_path (NULL: no cache), a text file of lines "key
- * rays_per_lane tile_scale wg_per_cu" keyed by device and batch shape.
+ * rays_per_lane tile_scale wg_per_cu lds_layout" keyed by device and batch
+ * shape.
  * Synchronous. */
 lm_status lm_batch_tune(lm_batch* b, const char* cache_path);
 
@@ -427,14 +442,20 @@ lm_status lm_batch_timing(lm_batch* b, float* coeff_ms, float* shoot_ms);
 
 /* Execution parameters in use: rays per lane, tile scale (multiplier of the
  * default level-2 cells per workgroup tile side), workgroups per CU (0: as many
- * as fit).  Any pointer may be NULL.  (Execution shape: no passage.) */
+ * as fit), LDS layout of the maps that run with FP32 near sums (0..3: lenses
+ * per block of the wave-shared LDS table / uint32 bins of the workgroup's LDS
+ * window / near lenses staged per block = 16/7040/64, 8/8064/64, 32/5000/64,
+ * 16/7552/32; each fits 40 KiB per workgroup).  Any pointer may be NULL.
+ * (Execution shape: no passage.) */
 lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* tile_cells,
-                          int32_t* wg_per_cu);
+                          int32_t* wg_per_cu, int32_t* lds_layout);
 /* Set the execution parameters by hand instead of lm_batch_tune: rays per
  * lane 4, 8 or 16, tile scale 1..8, workgroups per CU 0..8 (0: as many as
- * fit).  Results never depend on them.  LM_EINVAL outside those ranges. */
+ * fit), LDS layout 0..3.  Results never depend on them.  LM_EINVAL outside
+ * those ranges; LM_EUNSUPPORTED for layouts 1..3 except with the interpolated
+ * scheme, 4 Taylor terms and 8 or 16 rays per lane. */
 lm_status lm_batch_set_params(lm_batch* b, int32_t rays_per_lane, int32_t tile_cells,
-                              int32_t wg_per_cu);
+                              int32_t wg_per_cu, int32_t lds_layout);
 void lm_batch_destroy(lm_batch* b);
 
 /* Device micro-benchmarks on the current device (diagnostics for the

@@ -477,9 +477,12 @@ int lmo_shoot_window(const lmo_params *p, const double *lx, const double *ly, co
     if (ni < 0 || nj < 0 || i0 < 0 || j0 < 0 || i0 + ni > p->ray_nx || j0 + nj > p->ray_ny)
         return -1;
     if (ni == 0 || nj == 0) return 0;
+    /* thread count of this call only: a num_threads clause, not
+     * omp_set_num_threads, which would stay in force for later calls */
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
+    const int nt = 1;
     (void)nthreads;
 #endif
     lmo_lenses L = {lx, ly, lm, n};
@@ -487,7 +490,7 @@ int lmo_shoot_window(const lmo_params *p, const double *lx, const double *ly, co
     int err = 0;
     if (p->scheme == 0) {
         /* direct: one row of rays per task */
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : outs)
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : outs) num_threads(nt)
         for (int64_t j = j0; j < j0 + nj; ++j) {
             double ty = p->ray_y0 + ((double)j + 0.5) * p->ray_dy;
             for (int64_t i = i0; i < i0 + ni; ++i) {
@@ -510,7 +513,7 @@ int lmo_shoot_window(const lmo_params *p, const double *lx, const double *ly, co
         int64_t R = p->coarse, P = p->terms;
         int64_t ci0 = i0 / R, ci1 = (i0 + ni - 1) / R, cj0 = j0 / R, cj1 = (j0 + nj - 1) / R;
         int64_t ncx = ci1 - ci0 + 1, ncells = ncx * (cj1 - cj0 + 1);
-#pragma omp parallel reduction(+ : outs)
+#pragma omp parallel reduction(+ : outs) num_threads(nt)
         {
             unsigned char *near = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
             int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));

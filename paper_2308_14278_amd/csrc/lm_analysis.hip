@@ -14,7 +14,20 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
+#include "lm_internal.h"
+
 namespace {
+
+// Scratch memory of the allocation-free peak statistics: the listed rows, the
+// bin of every pixel column and the two histograms, at fixed offsets.  Each
+// device holds its own copy; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) unsigned char scratch[LM_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[LM_MAX_DEVICES] = {};
 
 __device__ __forceinline__ bool candidate(const unsigned long long* __restrict__ c, int64_t nx,
                                           int64_t i, int64_t j, unsigned k2x3)
@@ -68,6 +81,31 @@ __device__ __forceinline__ bool true_peak(const unsigned long long* __restrict__
                     candidate(c, nx, i + 1, j + 1, k2x3));
 }
 
+// Distance bin of every pixel column: the bin holding the column centre
+// x0 + (p + 1/2) dx, with the multiply and the add rounded separately as the
+// host computes the same centres.
+__global__ __launch_bounds__(256) void k_column_bins(double x0, double dx, int64_t nx,
+                                                     const double* __restrict__ edges, int nb,
+                                                     int32_t* __restrict__ bin_of)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= nx) return;
+    const double c = __dadd_rn(x0, __dmul_rn((double)p + 0.5, dx));
+    int b = -1;
+    if (c >= edges[0] && c < edges[nb]) {
+        int lo = 0, hi = nb - 1;  // the largest b with edges[b] <= c
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (edges[mid] <= c)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        b = lo;
+    }
+    bin_of[p] = b;
+}
+
 // One thread per (light curve t, pixel j); true peaks are rare, so their bins
 // are added to with global atomics.
 __global__ __launch_bounds__(256) void k_peak_bins(const unsigned long long* __restrict__ counts,
@@ -90,6 +128,15 @@ __global__ __launch_bounds__(256) void k_peak_bins(const unsigned long long* __r
 
 }  // namespace
 
+int lm_launch_column_bins(double x0, double dx, int64_t nx, const double* edges, int nb,
+                          int32_t* bin_of, void* stream)
+{
+    if (nx <= 0) return 0;
+    hipLaunchKernelGGL(k_column_bins, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, x0, dx, nx, edges, nb, bin_of);
+    return (int)hipGetLastError();
+}
+
 int lm_launch_peak_bins(const unsigned long long* counts, int64_t nx, int64_t ny,
                         const int32_t* tracks, int64_t nt, int k, const int32_t* bin_of,
                         unsigned long long* peaks, unsigned long long* heights, void* stream)
@@ -111,4 +158,21 @@ int lm_launch_peaks(const unsigned long long* counts, int64_t nx, int64_t ny,
                        (hipStream_t)stream, counts, nx, ny, tracks, nt, (unsigned)(3 * k * k),
                        flags);
     return (int)hipGetLastError();
+}
+
+int lm_scratch_address(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= LM_MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
 }

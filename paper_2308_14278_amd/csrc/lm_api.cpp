@@ -222,7 +222,9 @@ void rect_cells(int R, int64_t i0, int64_t j0, int64_t ni, int64_t nj, int64_t& 
     cy = nj > 0 ? (j0 + nj - 1) / R - j0 / R + 1 : 1;
 }
 
-Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scale)
+// win_max: uint32 bins the kernel's LDS window holds (its layout's).
+Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scale,
+                 int win_max = kLayWin[0])
 {
     const lm_geometry& g = m->g;
     Exec e;
@@ -250,10 +252,10 @@ Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scal
     const double ext_y = (double)G * R * g.ray_dy * my / g.src_dy + 2.0 * std::max(8.0, 0.1 / g.src_dy);
     // use the whole LDS window in the extents' aspect ratio (sides multiples
     // of 8): more rays counted in LDS, fewer global atomics
-    const double fill = std::sqrt((double)LM_WIN_MAX / (ext_x * ext_y));
-    int wx = std::max(8, std::min(LM_WIN_MAX / 8, (int)(ext_x * fill) / 8 * 8));
-    int wy = std::max(8, std::min(LM_WIN_MAX / 8, (int)(ext_y * fill) / 8 * 8));
-    while (wx * wy > LM_WIN_MAX) {
+    const double fill = std::sqrt((double)win_max / (ext_x * ext_y));
+    int wx = std::max(8, std::min(win_max / 8, (int)(ext_x * fill) / 8 * 8));
+    int wy = std::max(8, std::min(win_max / 8, (int)(ext_y * fill) / 8 * 8));
+    while (wx * wy > win_max) {
         if (wy <= 8 || (wx > 8 && wx / ext_x > wy / ext_y))
             wx -= 8;
         else
@@ -1161,9 +1163,23 @@ lm_status lm_find_peaks(lm_map* m, const int32_t* tracks, int32_t n_tracks, int3
     return ok();
 }
 
-lm_status lm_peak_stats(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
-                        const double* beta_edges, int32_t n_bins, uint64_t* peaks,
-                        uint64_t* heights, uint64_t* pixels)
+}  // extern "C"
+
+namespace {
+
+// Device buffers of one peak-statistics call: tracks (n_tracks int32), the bin
+// of every pixel column (src_nx int32), the bin edges (n_bins + 1 doubles) and
+// the two histograms (2 n_bins uint64).
+struct PeakScratch {
+    int32_t* tracks;
+    int32_t* bin_of;
+    double* edges;
+    unsigned long long* hist;
+};
+
+lm_status peak_stats_check(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                           const double* beta_edges, int32_t n_bins, const uint64_t* peaks,
+                           const uint64_t* heights, const uint64_t* pixels)
 {
     if (!m) return fail(LM_EINVAL, "map is NULL");
     if (n_tracks < 0 || n_bins < 1 || n_bins > (1 << 16) || !beta_edges || !peaks || !heights ||
@@ -1178,40 +1194,93 @@ lm_status lm_peak_stats(lm_map* m, const int32_t* tracks, int32_t n_tracks, int3
             return fail(LM_ERANGE, "track %d (row %d) is outside the map", t, tracks[t]);
     if ((int64_t)n_tracks * m->g.src_nx >= (int64_t(1) << 31))
         return fail(LM_EUNSUPPORTED, "too many track pixels");
-    // bin of each pixel column: the bin holding the pixel centre's beta_x
+    return LM_OK;
+}
+
+// The statistics proper, on device buffers the caller provides.  Light-curve
+// pixels per bin are counted on the host with the same column centres the
+// device bins by; the device does the peak test and the histograms.
+lm_status peak_stats_run(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                         const double* beta_edges, int32_t n_bins, uint64_t* peaks,
+                         uint64_t* heights, uint64_t* pixels, const PeakScratch& d)
+{
     const int64_t nx = m->g.src_nx;
-    std::vector<int32_t> bin_of(nx);
     std::fill(pixels, pixels + n_bins, 0);
     for (int64_t p = 0; p < nx; ++p) {
         const double bc = m->g.src_x0 + ((double)p + 0.5) * m->g.src_dx;
-        int32_t b = -1;
-        if (bc >= beta_edges[0] && bc < beta_edges[n_bins])
-            b = (int32_t)(std::upper_bound(beta_edges, beta_edges + n_bins + 1, bc) - beta_edges) - 1;
-        bin_of[p] = b;
-        if (b >= 0) pixels[b] += (uint64_t)n_tracks;
+        if (bc >= beta_edges[0] && bc < beta_edges[n_bins]) {
+            const int64_t b =
+                (std::upper_bound(beta_edges, beta_edges + n_bins + 1, bc) - beta_edges) - 1;
+            pixels[b] += (uint64_t)n_tracks;
+        }
     }
     std::fill(peaks, peaks + n_bins, 0);
     std::fill(heights, heights + n_bins, 0);
     if (n_tracks == 0) return ok();
     lm_status st = use_device(m);
     if (st) return st;
-    DevBuf dt, db, dh;
-    if (dt.ensure((size_t)n_tracks * 4) || db.ensure((size_t)nx * 4) ||
-        dh.ensure((size_t)n_bins * 16))
-        return fail(LM_ENOMEM, "cannot allocate");
     HIP_TRY(hipStreamSynchronize(m->last));
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(dt.p, tracks, (size_t)n_tracks * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(db.p, bin_of.data(), (size_t)nx * 4, hipMemcpyHostToDevice));
-    unsigned long long* dpk = dh.as<unsigned long long>();
-    LAUNCH_TRY(lm_launch_fill_u64(dpk, 2 * (int64_t)n_bins, 0ull, nullptr));
+    HIP_TRY(hipMemcpy(d.tracks, tracks, (size_t)n_tracks * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.edges, beta_edges, (size_t)(n_bins + 1) * 8, hipMemcpyHostToDevice));
+    LAUNCH_TRY(lm_launch_column_bins(m->g.src_x0, m->g.src_dx, nx, d.edges, n_bins, d.bin_of,
+                                     nullptr));
+    LAUNCH_TRY(lm_launch_fill_u64(d.hist, 2 * (int64_t)n_bins, 0ull, nullptr));
     LAUNCH_TRY(lm_launch_peak_bins(reinterpret_cast<const unsigned long long*>(m->counts), nx,
-                                   m->g.src_ny, dt.as<int32_t>(), n_tracks, k, db.as<int32_t>(),
-                                   dpk, dpk + n_bins, nullptr));
+                                   m->g.src_ny, d.tracks, n_tracks, k, d.bin_of, d.hist,
+                                   d.hist + n_bins, nullptr));
     HIP_TRY(hipStreamSynchronize(nullptr));
-    HIP_TRY(hipMemcpy(peaks, dpk, (size_t)n_bins * 8, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(heights, dpk + n_bins, (size_t)n_bins * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(peaks, d.hist, (size_t)n_bins * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(heights, d.hist + n_bins, (size_t)n_bins * 8, hipMemcpyDeviceToHost));
     return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+lm_status lm_peak_stats(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                        const double* beta_edges, int32_t n_bins, uint64_t* peaks,
+                        uint64_t* heights, uint64_t* pixels)
+{
+    lm_status st = peak_stats_check(m, tracks, n_tracks, k, beta_edges, n_bins, peaks, heights,
+                                    pixels);
+    if (st) return st;
+    st = use_device(m);
+    if (st) return st;
+    DevBuf dt, db, de, dh;
+    if (dt.ensure((size_t)std::max(n_tracks, 1) * 4) || db.ensure((size_t)m->g.src_nx * 4) ||
+        de.ensure((size_t)(n_bins + 1) * 8) || dh.ensure((size_t)n_bins * 16))
+        return fail(LM_ENOMEM, "cannot allocate");
+    return peak_stats_run(m, tracks, n_tracks, k, beta_edges, n_bins, peaks, heights, pixels,
+                          PeakScratch{dt.as<int32_t>(), db.as<int32_t>(), de.as<double>(),
+                                      dh.as<unsigned long long>()});
+}
+
+lm_status lm_peak_stats_noalloc(lm_map* m, const int32_t* tracks, int32_t n_tracks, int32_t k,
+                                const double* beta_edges, int32_t n_bins, uint64_t* peaks,
+                                uint64_t* heights, uint64_t* pixels)
+{
+    lm_status st = peak_stats_check(m, tracks, n_tracks, k, beta_edges, n_bins, peaks, heights,
+                                    pixels);
+    if (st) return st;
+    if (n_tracks > LM_SCRATCH_TRACKS || m->g.src_nx > LM_SCRATCH_COLS || n_bins > LM_SCRATCH_BINS)
+        return fail(LM_EINVAL,
+                    "lm_peak_stats_noalloc takes at most %d rows, maps of at most %d columns and "
+                    "%d bins (got %d rows, %d columns, %d bins)",
+                    LM_SCRATCH_TRACKS, LM_SCRATCH_COLS, LM_SCRATCH_BINS, n_tracks, m->g.src_nx,
+                    n_bins);
+    st = use_device(m);
+    if (st) return st;
+    void* base = nullptr;
+    LAUNCH_TRY(lm_scratch_address(&base));
+    unsigned char* s = static_cast<unsigned char*>(base);
+    return peak_stats_run(m, tracks, n_tracks, k, beta_edges, n_bins, peaks, heights, pixels,
+                          PeakScratch{reinterpret_cast<int32_t*>(s),
+                                      reinterpret_cast<int32_t*>(s + LM_SCRATCH_OFF_BINOF),
+                                      reinterpret_cast<double*>(s + LM_SCRATCH_OFF_EDGES),
+                                      reinterpret_cast<unsigned long long*>(
+                                          s + LM_SCRATCH_OFF_HIST)});
 }
 
 lm_status lm_fold_scales(double theta_e_arcsec, double d_x, double d_y, double kappa0,
@@ -1300,6 +1369,7 @@ struct lm_batch {
     std::vector<uint64_t> gens; // each map's generation when the graphs were built
     int scheme = 0, terms = 4, device = 0;
     int rays_per_lane = 16, g_scale = 1, wg_per_cu = 0;
+    int layout = 0;             // LDS layout of the LM_PREC_MIXED group (others use 0)
     DevBuf descs;               // one LmDesc per map
     BatchGroup grp[3];          // indexed by precision
     DevBuf queue;               // one counter per group
@@ -1322,6 +1392,18 @@ struct lm_batch {
 };
 
 namespace {
+
+// LDS layout of the maps that run in precision `prec`: the batch's for the
+// FP32 rebased path, layout 0 for the others.
+int group_layout(const lm_batch* b, int prec) { return prec == LM_PREC_MIXED ? b->layout : 0; }
+
+// Layouts with instances for this batch's MIXED group at rays_per_lane nr.
+bool layout_built(const lm_batch* b, int nr, int layout)
+{
+    return layout == 0 ||
+           (layout > 0 && layout < LM_LAYOUTS && b->scheme == LM_SCHEME_INTERP && b->terms == 4 &&
+            (nr == 8 || nr == 16));
+}
 
 int device_cus(int dev)
 {
@@ -1349,7 +1431,7 @@ lm_status batch_build(lm_batch* b, const std::vector<int64_t>& work)
         const int64_t* own = &b->rect[4 * k];
         int64_t cx, cy;
         rect_cells(m->g.coarse, own[0], own[1], own[2], own[3], cx, cy);
-        const Exec e = choose_exec(m, cx, cy, b->g_scale);
+        const Exec e = choose_exec(m, cx, cy, b->g_scale, kLayWin[group_layout(b, m->prec)]);
         ds[k] = make_desc(m, r[0], r[1], r[0] + r[2], r[1] + r[3], e);
         if (r[2] == 0 || r[3] == 0) ds[k].ntiles = 0;
         if (ds[k].ntiles > 0x7fffffffLL)
@@ -1380,7 +1462,8 @@ lm_status batch_build(lm_batch* b, const std::vector<int64_t>& work)
         HIP_TRY(hipMemcpy(G.offs.p, offs.data(), (G.nmaps + 1) * 8, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(G.order.p, order.data(), G.nmaps * 4, hipMemcpyHostToDevice));
         int occ = 0;
-        LAUNCH_TRY(lm_shoot_occupancy(b->scheme, pr, b->terms, b->rays_per_lane, &occ));
+        LAUNCH_TRY(lm_shoot_occupancy(b->scheme, pr, b->terms, b->rays_per_lane,
+                                      group_layout(b, pr), &occ));
         if (occ <= 0) occ = 1;
         const int wg = b->wg_per_cu > 0 ? std::min(b->wg_per_cu, occ) : occ;
         G.grid = device_cus(b->device) * wg;
@@ -1409,7 +1492,8 @@ lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs, bool pre =
             LAUNCH_TRY(lm_launch_shoot_batch(b->descs.as<LmDesc>(), G.offs.as<int64_t>(),
                                              G.order.as<int32_t>(), G.nmaps,
                                              b->queue.as<unsigned long long>() + pr, b->scheme,
-                                             pr, b->terms, b->rays_per_lane, G.grid, s));
+                                             pr, b->terms, b->rays_per_lane, group_layout(b, pr),
+                                             G.grid, s));
         }
     return LM_OK;
 }
@@ -1480,8 +1564,9 @@ std::string batch_key(const lm_batch* b)
     return k.str();
 }
 
-// Tuning cache: a text file of "key rays_per_lane tile_scale wg_per_cu" lines.
-bool cache_lookup(const char* path, const std::string& key, int& nr, int& gs, int& wg)
+// Tuning cache: a text file of "key rays_per_lane tile_scale wg_per_cu
+// layout" lines.
+bool cache_lookup(const char* path, const std::string& key, int& nr, int& gs, int& wg, int& lay)
 {
     if (!path) return false;
     std::ifstream f(path);
@@ -1489,18 +1574,20 @@ bool cache_lookup(const char* path, const std::string& key, int& nr, int& gs, in
     while (std::getline(f, line)) {
         std::istringstream is(line);
         std::string k;
-        int a, c, d;
-        if (is >> k >> a >> c >> d && k == key && lm_supported_rays_per_lane(a) && c >= 1 && d >= 0) {
+        int a, c, d, e;
+        if (is >> k >> a >> c >> d >> e && k == key && lm_supported_rays_per_lane(a) && c >= 1 &&
+            d >= 0 && e >= 0 && e < LM_LAYOUTS) {
             nr = a;
             gs = c;
             wg = d;
+            lay = e;
             return true;
         }
     }
     return false;
 }
 
-void cache_store(const char* path, const std::string& key, int nr, int gs, int wg)
+void cache_store(const char* path, const std::string& key, int nr, int gs, int wg, int lay)
 {
     if (!path) return;
     std::vector<std::string> keep;
@@ -1512,7 +1599,7 @@ void cache_store(const char* path, const std::string& key, int nr, int gs, int w
     }
     std::ofstream f(path, std::ios::trunc);
     for (auto& l : keep) f << l << "\n";
-    f << key << " " << nr << " " << gs << " " << wg << "\n";
+    f << key << " " << nr << " " << gs << " " << wg << " " << lay << "\n";
 }
 
 // Rays the tuner times each candidate on: about 2e10 (25 ms at 8e11 rays/s),
@@ -1676,8 +1763,8 @@ lm_status lm_batch_tune(lm_batch* b, const char* cache_path)
         if (st) return st;
     }
     const std::string key = batch_key(b);
-    int nr = 0, gs = 0, wg = 0;
-    if (!cache_lookup(cache_path, key, nr, gs, wg)) {
+    int nr = 0, gs = 0, wg = 0, lay = 0;
+    if (!cache_lookup(cache_path, key, nr, gs, wg, lay)) {
         for (lm_map* m : b->maps)
             if (m->has_counts) return fail(LM_ESTATE, "tuning shoots: the maps must have no counts");
         // coefficients once, then every candidate on the same sample of rays
@@ -1704,35 +1791,39 @@ lm_status lm_batch_tune(lm_batch* b, const char* cache_path)
         const int nrs[] = {4, 8, 16};
         const int gss[] = {1, 2};
         lm_status st = LM_OK;
-        for (int cnr : nrs)
-            for (int cgs : gss)
-                for (int cwg : {0, 2}) {
-                    b->rays_per_lane = cnr;
-                    b->g_scale = cgs;
-                    b->wg_per_cu = cwg;
-                    st = batch_build(b, sample);
-                    if (!st) st = batch_enqueue(b, b->cap, false);  // warm-up
-                    if (st) break;
-                    HIP_TRY(hipEventRecord(e0, b->cap));
-                    st = batch_enqueue(b, b->cap, false);
-                    if (st) break;
-                    HIP_TRY(hipEventRecord(e1, b->cap));
-                    HIP_TRY(hipEventSynchronize(e1));
-                    float ms = 0;
-                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                    lm_tune_result r{cnr, cgs, cwg, 0, rays, ms * 1e-3};
-                    b->tuned.push_back(r);
-                    if (r.seconds < best) {
-                        best = r.seconds;
-                        nr = cnr;
-                        gs = cgs;
-                        wg = cwg;
+        for (int clay = 0; clay < LM_LAYOUTS && !st; ++clay)
+            for (int cnr : nrs)
+                for (int cgs : gss)
+                    for (int cwg : {0, 2}) {
+                        if (st || !layout_built(b, cnr, clay)) continue;
+                        b->rays_per_lane = cnr;
+                        b->g_scale = cgs;
+                        b->wg_per_cu = cwg;
+                        b->layout = clay;
+                        st = batch_build(b, sample);
+                        if (!st) st = batch_enqueue(b, b->cap, false);  // warm-up
+                        if (st) break;
+                        HIP_TRY(hipEventRecord(e0, b->cap));
+                        st = batch_enqueue(b, b->cap, false);
+                        if (st) break;
+                        HIP_TRY(hipEventRecord(e1, b->cap));
+                        HIP_TRY(hipEventSynchronize(e1));
+                        float ms = 0;
+                        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                        lm_tune_result r{cnr, cgs, cwg, clay, rays, ms * 1e-3};
+                        b->tuned.push_back(r);
+                        if (r.seconds < best) {
+                            best = r.seconds;
+                            nr = cnr;
+                            gs = cgs;
+                            wg = cwg;
+                            lay = clay;
+                        }
                     }
-                }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (st) return st;
-        cache_store(cache_path, key, nr, gs, wg);
+        cache_store(cache_path, key, nr, gs, wg, lay);
         for (lm_map* m : b->maps) {
             st = lm_reset_counts(m, b->cap);
             if (st) return st;
@@ -1742,6 +1833,7 @@ lm_status lm_batch_tune(lm_batch* b, const char* cache_path)
     b->rays_per_lane = nr;
     b->g_scale = gs;
     b->wg_per_cu = wg;
+    b->layout = lay;
     b->dirty = true;
     return ok();
 }
@@ -1768,26 +1860,35 @@ lm_status lm_batch_timing(lm_batch* b, float* coeff_ms, float* shoot_ms)
 }
 
 lm_status lm_batch_params(const lm_batch* b, int32_t* rays_per_lane, int32_t* tile_cells,
-                          int32_t* wg_per_cu)
+                          int32_t* wg_per_cu, int32_t* lds_layout)
 {
     if (!b) return fail(LM_EINVAL, "batch is NULL");
     if (rays_per_lane) *rays_per_lane = b->rays_per_lane;
     if (tile_cells) *tile_cells = b->g_scale;
     if (wg_per_cu) *wg_per_cu = b->wg_per_cu;
+    if (lds_layout) *lds_layout = b->layout;
     return ok();
 }
 
 lm_status lm_batch_set_params(lm_batch* b, int32_t rays_per_lane, int32_t tile_cells,
-                              int32_t wg_per_cu)
+                              int32_t wg_per_cu, int32_t lds_layout)
 {
     if (!b) return fail(LM_EINVAL, "batch is NULL");
     if (!lm_supported_rays_per_lane(rays_per_lane))
         return fail(LM_EINVAL, "rays_per_lane must be 4, 8 or 16, got %d", rays_per_lane);
     if (tile_cells < 1 || tile_cells > 8) return fail(LM_EINVAL, "tile_cells must be in 1..8");
     if (wg_per_cu < 0 || wg_per_cu > 8) return fail(LM_EINVAL, "wg_per_cu must be in 0..8");
+    if (lds_layout < 0 || lds_layout >= LM_LAYOUTS)
+        return fail(LM_EINVAL, "lds_layout must be in 0..%d", LM_LAYOUTS - 1);
+    if (!layout_built(b, rays_per_lane, lds_layout))
+        return fail(LM_EUNSUPPORTED,
+                    "LDS layout %d is built for the interpolated scheme with 4 Taylor terms and 8 "
+                    "or 16 rays per lane only",
+                    lds_layout);
     b->rays_per_lane = rays_per_lane;
     b->g_scale = tile_cells;
     b->wg_per_cu = wg_per_cu;
+    b->layout = lds_layout;
     b->dirty = true;
     return ok();
 }

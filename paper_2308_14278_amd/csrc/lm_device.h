@@ -25,13 +25,12 @@ namespace {
 
 
 constexpr int kWG = LM_WG;
-constexpr int kWinMax = LM_WIN_MAX;
 
 // Lenses staged per wave per block: the direct sum sums 256-lens blocks (the
 // compensated blocks); a near list rarely exceeds a few tens of lenses.
-template <int SCHEME>
+template <int SCHEME, int LAY>
 struct Cap {
-    static constexpr int value = SCHEME == 0 ? LM_LENS_CAP : LM_NEAR_CAP;
+    static constexpr int value = SCHEME == 0 ? LM_LENS_CAP : kLayNear[LAY];
 };
 
 // Arithmetic of the ray-lens pairs: FP32 (rebased or plain global) or FP64
@@ -48,13 +47,12 @@ struct Prec<2> {
 };
 
 // The interpolated scheme shares the column-lens differences of a wave through
-// an LDS table (kTabCh lenses at a time), in every precision: rebased FP32 or
-// FP64 offsets, and the plain path's global FP32 coordinates.
+// an LDS table (kLayTab[LAY] lenses at a time), in every precision: rebased
+// FP32 or FP64 offsets, and the plain path's global FP32 coordinates.
 template <int SCHEME, int PREC>
 struct UseTab {
     static constexpr bool value = SCHEME == 1;
 };
-constexpr int kTabCh = 16;
 
 // Waves per SIMD the shooting kernels must keep: the FP32 table paths are
 // issue-bound and needs 4 (at most 128 VGPRs with 256-thread workgroups, 4 per
@@ -753,8 +751,9 @@ __device__ __forceinline__ void lens_pairs(const T* row, T dy, T m, T* bx, T* by
 }
 
 // Columns [c_lo, c_hi) of cell ci are computed (c_lo even, so columns 2m and
-// 2m + 1 share a group); rays of columns >= c_beg are counted.
-template <int SCHEME, int PREC, int NR, int P, bool FOLD>
+// 2m + 1 share a group); rays of columns >= c_beg are counted.  LAY: the LDS
+// layout (near-list block, table block).
+template <int SCHEME, int PREC, int NR, int P, bool FOLD, int LAY>
 __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_beg,
                              int64_t c_hi, int64_t j, bool row_ok, unsigned axb, unsigned ayb,
                              unsigned* win, typename Prec<PREC>::L* lb,
@@ -776,7 +775,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
     row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
     const T py = rw.py;
 
-    constexpr int kCap = Cap<SCHEME>::value;
+    constexpr int kCap = Cap<SCHEME, LAY>::value;
+    constexpr int kTabCh = kLayTab[LAY];
     const int count = __builtin_amdgcn_readfirstlane(list_count<SCHEME>(d, ci, cj));
     const int nblk = (count + kCap - 1) / kCap;
     if (nblk == 1) stage<SCHEME, PREC>(d, ci, cj, 0, count, zcx, zcy, lb, lane);
@@ -956,7 +956,7 @@ __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_
     ay0 = (int)fy;
 }
 
-template <int SCHEME, int PREC, int NR, int P>
+template <int SCHEME, int PREC, int NR, int P, int LAY>
 __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsigned* win,
                              typename Prec<PREC>::L* lb, typename Prec<PREC>::T* tb, int wave,
                              int lane)
@@ -984,11 +984,11 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
         const int64_t j = r_lo + lane;
         const bool row_ok = j >= d.j0 && j < d.j1;
         if (d.fold)
-            process_unit<SCHEME, PREC, NR, P, true>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, axb,
-                                                    ayb, win, lb, tb, lane, nout);
+            process_unit<SCHEME, PREC, NR, P, true, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok,
+                                                         axb, ayb, win, lb, tb, lane, nout);
         else
-            process_unit<SCHEME, PREC, NR, P, false>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, axb,
-                                                     ayb, win, lb, tb, lane, nout);
+            process_unit<SCHEME, PREC, NR, P, false, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok,
+                                                          axb, ayb, win, lb, tb, lane, nout);
     }
     unsigned tot = wave_sum_u32(nout);
     if (lane == 0 && tot) atomicAdd(d.n_out, (unsigned long long)tot);
@@ -1014,10 +1014,10 @@ template <int SCHEME, int PREC, int NR, int P>
 __global__ __launch_bounds__(kWG)
 __attribute__((amdgpu_waves_per_eu(MinWaves<SCHEME, PREC>::value))) void k_shoot_map(LmDesc d)
 {
-    __shared__ unsigned win[kWinMax];
-    __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
+    __shared__ unsigned win[kLayWin[0]];
+    __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME, 0>::value];
     __shared__ __align__(16) typename Prec<PREC>::T
-        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * 2 * NR : 1];
+        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kLayTab[0] * 2 * NR : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1028,26 +1028,26 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<SCHEME, PREC>::value))) void k_shoot
     int ax0, ay0;
     tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
     __syncthreads();
-    process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave, lane);
+    process_tile<SCHEME, PREC, NR, P, 0>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave, lane);
     __syncthreads();
     flush_window(d, win, ax0, ay0, tid);
 }
 
-template <int SCHEME, int PREC, int NR, int P>
+template <int SCHEME, int PREC, int NR, int P, int LAY>
 __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ descs,
                                                      const int64_t* __restrict__ offs,
                                                      const int32_t* __restrict__ order, int nmaps,
                                                      unsigned long long* queue)
 {
-    __shared__ unsigned win[kWinMax];
-    __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME>::value];
+    __shared__ unsigned win[kLayWin[LAY]];
+    __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME, LAY>::value];
     __shared__ __align__(16) typename Prec<PREC>::T
-        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kTabCh * 2 * NR : 1];
+        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kLayTab[LAY] * 2 * NR : 1];
     __shared__ long long s_item;
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int b = tid; b < kWinMax; b += kWG) win[b] = 0u;
+    for (int b = tid; b < kLayWin[LAY]; b += kWG) win[b] = 0u;
     const int64_t total = offs[nmaps];
     for (;;) {
         if (tid == 0) s_item = (long long)atomicAdd(queue, 1ull);
@@ -1069,8 +1069,8 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
         const int64_t tx = (int)t % (int)d.ntx, ty = (int)t / (int)d.ntx;
         int ax0, ay0;
         tile_anchor<SCHEME>(d, (d.tcx0 + tx) * d.G, (d.tcy0 + ty) * d.G, ax0, ay0);
-        process_tile<SCHEME, PREC, NR, P>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave,
-                                          lane);
+        process_tile<SCHEME, PREC, NR, P, LAY>(d, t, ax0, ay0, win, lens[wave], tab[wave], wave,
+                                               lane);
         __syncthreads();
         flush_window(d, win, ax0, ay0, tid);
         __syncthreads();
@@ -1088,7 +1088,7 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
                          typename Prec<PREC>::T pxp = 0)
 {
     using T = typename Prec<PREC>::T;
-    constexpr int kCap = Cap<SCHEME>::value;
+    constexpr int kCap = Cap<SCHEME, 0>::value;
     const int count = list_count<SCHEME>(d, ci, cj);
     T kx = 0, ky = 0;
     for (int b0 = 0; b0 < count; b0 += kCap) {
@@ -1245,19 +1245,42 @@ int launch_map_t(const LmDesc& d0, hipStream_t s)
     return 0;
 }
 
-template <int S, int PR, int NR, int P>
+template <int S, int PR, int NR, int P, int LAY>
 int launch_batch_t(const LmDesc* descs, const int64_t* offs, const int32_t* order, int nmaps,
                    unsigned long long* queue, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_shoot_batch<S, PR, NR, P>), dim3(grid), dim3(kWG), 0, s, descs, offs,
-                       order, nmaps, queue);
+    hipLaunchKernelGGL((k_shoot_batch<S, PR, NR, P, LAY>), dim3(grid), dim3(kWG), 0, s, descs,
+                       offs, order, nmaps, queue);
     return (int)hipGetLastError();
 }
 
-template <int S, int PR, int NR, int P>
+template <int S, int PR, int NR, int P, int LAY>
 const void* kernel_ptr_t()
 {
-    return (const void*)&k_shoot_batch<S, PR, NR, P>;
+    return (const void*)&k_shoot_batch<S, PR, NR, P, LAY>;
+}
+
+// The LDS layouts built for (S, PR, NR, P): every one for the FP32 rebased
+// path with P = 4 and 8 or 16 rays per lane, layout 0 for the rest.
+template <int S, int PR, int NR, int P>
+struct HasLayouts {
+    static constexpr bool value = S == 1 && PR == 0 && P == 4 && (NR == 8 || NR == 16);
+};
+
+// f.template with<S, PR, NR, P, LAY>() for a runtime layout.
+template <int S, int PR, int NR, int P, class F>
+int dispatch_layout(int layout, F& f)
+{
+    if (layout == 0) return f.template with<S, PR, NR, P, 0>();
+    if constexpr (HasLayouts<S, PR, NR, P>::value) {
+        switch (layout) {
+        case 1: return f.template with<S, PR, NR, P, 1>();
+        case 2: return f.template with<S, PR, NR, P, 2>();
+        case 3: return f.template with<S, PR, NR, P, 3>();
+        default: break;
+        }
+    }
+    return (int)hipErrorInvalidValue;
 }
 
 // Visit the instantiation for runtime (scheme, precision, NR, P).  The direct
@@ -1305,20 +1328,29 @@ struct BatchLauncher {
     const int32_t* order;
     int nmaps;
     unsigned long long* queue;
+    int layout;
     int grid;
     hipStream_t s;
+    template <int S, int PR, int NR, int P, int LAY>
+    int with()
+    {
+        return launch_batch_t<S, PR, NR, P, LAY>(descs, offs, order, nmaps, queue, grid, s);
+    }
     template <int S, int PR, int NR, int P>
-    int go() { return launch_batch_t<S, PR, NR, P>(descs, offs, order, nmaps, queue, grid, s); }
+    int go() { return dispatch_layout<S, PR, NR, P>(layout, *this); }
 };
 
 struct Occupancy {
+    int layout;
     int* out;
-    template <int S, int PR, int NR, int P>
-    int go()
+    template <int S, int PR, int NR, int P, int LAY>
+    int with()
     {
-        return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, kernel_ptr_t<S, PR, NR, P>(),
-                                                                  kWG, 0);
+        return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            out, kernel_ptr_t<S, PR, NR, P, LAY>(), kWG, 0);
     }
+    template <int S, int PR, int NR, int P>
+    int go() { return dispatch_layout<S, PR, NR, P>(layout, *this); }
 };
 struct TraceLauncher {
     const LmDesc& d;

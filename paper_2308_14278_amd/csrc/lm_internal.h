@@ -6,10 +6,30 @@
 #define LM_WG 256          // threads per workgroup: 4 waves of 64
 #define LM_WAVES 4
 #define LM_LENS_CAP 256    // direct sum: lenses staged per wave per block (the summation block)
-#define LM_NEAR_CAP 64     // interpolated scheme: near lenses staged per wave per block
-#define LM_WIN_MAX 7040    // uint32 bins of a workgroup's LDS window
+// LDS layouts of the interpolated-scheme shooting kernels, the tuner's third
+// axis besides rays per lane and tile size: lenses per LDS table block (the
+// wave-shared dx^2, m dx table), uint32 bins of the workgroup's LDS window
+// (the histogram tile), near lenses staged per wave per block.  With 16 rays
+// per lane and FP32 sums each fits 40 KiB per workgroup (four per CU).  Layout
+// 0 serves every kernel; the others are built for the FP32 rebased path with
+// P = 4 and 8 or 16 rays per lane.  Results never depend on the layout.
+#define LM_LAYOUTS 4
+static constexpr int kLayTab[LM_LAYOUTS] = {16, 8, 32, 16};
+static constexpr int kLayWin[LM_LAYOUTS] = {7040, 8064, 5000, 7552};
+static constexpr int kLayNear[LM_LAYOUTS] = {64, 64, 64, 32};
 #define LM_PTAB_PAD 64     // column-offset table entries past R (last column group)
 #define LM_PTAB_POW 6      // powers dx .. dx^6 per column (row polynomials, P <= 7)
+
+// Allocation-free peak statistics: limits and layout of the per-device scratch
+// array (tracks, column bins, two histograms; each part 256-byte aligned).
+#define LM_SCRATCH_TRACKS 8192
+#define LM_SCRATCH_COLS (1 << 20)
+#define LM_SCRATCH_BINS 4096
+#define LM_SCRATCH_OFF_BINOF (4 * LM_SCRATCH_TRACKS)
+#define LM_SCRATCH_OFF_EDGES (LM_SCRATCH_OFF_BINOF + 4 * LM_SCRATCH_COLS)
+#define LM_SCRATCH_OFF_HIST (LM_SCRATCH_OFF_EDGES + (8 * (LM_SCRATCH_BINS + 1) + 255) / 256 * 256)
+#define LM_SCRATCH_BYTES (LM_SCRATCH_OFF_HIST + 16 * LM_SCRATCH_BINS)
+#define LM_MAX_DEVICES 64
 
 // Taylor coefficients of one level-2 cell: a_0 in FP64 (it carries the large
 // far-field deflection of the cell centre), a_1..a_6 in FP32 (they multiply
@@ -79,9 +99,11 @@ int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int
 int lm_launch_coeffs_hier(const LmDesc& d, int terms, LmCoef* out, void* stream);
 int lm_launch_shoot_map(const LmDesc& d, int scheme, int precision, int terms, int rays_per_lane,
                         void* stream);
+// layout: an LDS layout (above); LM_LAYOUTS pairs it is not built for give
+// hipErrorInvalidValue
 int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int32_t* order,
                           int nmaps, unsigned long long* queue, int scheme, int precision,
-                          int terms, int rays_per_lane, int grid, void* stream);
+                          int terms, int rays_per_lane, int layout, int grid, void* stream);
 int lm_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
 // *total (zeroed by the caller) += sum of p[0..n)
 int lm_launch_sum_u64(const unsigned long long* p, int64_t n, unsigned long long* total,
@@ -95,12 +117,20 @@ int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, con
                       int64_t n, double* alpha, void* stream);
 int lm_launch_peaks(const unsigned long long* counts, int64_t nx, int64_t ny,
                     const int32_t* tracks, int64_t nt, int k, uint8_t* flags, void* stream);
+// bin_of[p] = b with edges[b] <= x0 + (p + 1/2) dx < edges[b+1] (FP64, multiply
+// and add each rounded to nearest), -1 outside [edges[0], edges[nb])
+int lm_launch_column_bins(double x0, double dx, int64_t nx, const double* edges, int nb,
+                          int32_t* bin_of, void* stream);
 // peaks[b] += true peaks of the listed rows in pixels j with bin_of[j] == b,
 // heights[b] += their counts (bin_of[j] < 0: no bin)
 int lm_launch_peak_bins(const unsigned long long* counts, int64_t nx, int64_t ny,
                         const int32_t* tracks, int64_t nt, int k, const int32_t* bin_of,
                         unsigned long long* peaks, unsigned long long* heights, void* stream);
-int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu);
+int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int layout,
+                       int* wg_per_cu);
+// Device address of the current device's scratch array (resolved once per
+// device); returns a hipError_t.
+int lm_scratch_address(void** out);
 bool lm_supported_rays_per_lane(int r);
 
 // Per-pair instances of the shooting kernels, probes and their launchers
@@ -112,8 +142,8 @@ bool lm_supported_rays_per_lane(int r);
     int LM_INST_CAT(lm_inst_shoot_batch, S, PR)(const LmDesc* descs, const int64_t* offs,     \
                                                 const int32_t* order, int nmaps,              \
                                                 unsigned long long* queue, int nr, int terms, \
-                                                int grid, void* stream);                      \
-    int LM_INST_CAT(lm_inst_occupancy, S, PR)(int nr, int terms, int* wg_per_cu);             \
+                                                int layout, int grid, void* stream);          \
+    int LM_INST_CAT(lm_inst_occupancy, S, PR)(int nr, int terms, int layout, int* wg_per_cu); \
     int LM_INST_CAT(lm_inst_trace, S, PR)(const LmDesc& d, int terms, const int64_t* ii,      \
                                           const int64_t* jj, int64_t n, int32_t* p,           \
                                           int32_t* q, double* uv, void* stream);              \

@@ -278,22 +278,24 @@ int lm_launch_shoot_map(const LmDesc& d, int scheme, int precision, int terms, i
 
 int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int32_t* order,
                           int nmaps, unsigned long long* queue, int scheme, int precision,
-                          int terms, int rays_per_lane, int grid, void* stream)
+                          int terms, int rays_per_lane, int layout, int grid, void* stream)
 {
 #define X(S, PR)                                                                            \
     if (scheme == S && precision == PR)                                                     \
         return LM_INST_CAT(lm_inst_shoot_batch, S, PR)(descs, offsets, order, nmaps, queue, \
-                                                       rays_per_lane, terms, grid, stream);
+                                                       rays_per_lane, terms, layout, grid,  \
+                                                       stream);
     LM_PAIRS(X)
 #undef X
     return (int)hipErrorInvalidValue;
 }
 
-int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int* wg_per_cu)
+int lm_shoot_occupancy(int scheme, int precision, int terms, int rays_per_lane, int layout,
+                       int* wg_per_cu)
 {
 #define X(S, PR)                                                                            \
     if (scheme == S && precision == PR)                                                     \
-        return LM_INST_CAT(lm_inst_occupancy, S, PR)(rays_per_lane, terms, wg_per_cu);
+        return LM_INST_CAT(lm_inst_occupancy, S, PR)(rays_per_lane, terms, layout, wg_per_cu);
     LM_PAIRS(X)
 #undef X
     return (int)hipErrorInvalidValue;

@@ -19,15 +19,15 @@ int LM_INST_CAT(lm_inst_shoot_map, LM_S, LM_PR)(const LmDesc& d, int nr, int ter
 int LM_INST_CAT(lm_inst_shoot_batch, LM_S, LM_PR)(const LmDesc* descs, const int64_t* offs,
                                                   const int32_t* order, int nmaps,
                                                   unsigned long long* queue, int nr, int terms,
-                                                  int grid, void* stream)
+                                                  int layout, int grid, void* stream)
 {
-    BatchLauncher f{descs, offs, order, nmaps, queue, grid, (hipStream_t)stream};
+    BatchLauncher f{descs, offs, order, nmaps, queue, layout, grid, (hipStream_t)stream};
     return dispatch_nr<LM_S, LM_PR>(nr, terms, f);
 }
 
-int LM_INST_CAT(lm_inst_occupancy, LM_S, LM_PR)(int nr, int terms, int* wg_per_cu)
+int LM_INST_CAT(lm_inst_occupancy, LM_S, LM_PR)(int nr, int terms, int layout, int* wg_per_cu)
 {
-    Occupancy f{wg_per_cu};
+    Occupancy f{layout, wg_per_cu};
     return dispatch_nr<LM_S, LM_PR>(nr, terms, f);
 }
 

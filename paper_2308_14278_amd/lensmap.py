@@ -124,8 +124,9 @@ _SIGS = {
                           ctypes.c_int64],
     "lm_batch_tune": [_vp, ctypes.c_char_p],
     "lm_batch_shoot": [_vp, _vp],
-    "lm_batch_params": [_vp, _i32, _i32, _i32],
-    "lm_batch_set_params": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "lm_batch_params": [_vp, _i32, _i32, _i32, _i32],
+    "lm_batch_set_params": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_int32],
     "lm_shot_stats": [_vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                       _P(lm_stats)],
     "lm_batch_timing": [_vp, _P(ctypes.c_float), _P(ctypes.c_float)],
@@ -138,6 +139,8 @@ _SIGS = {
     "lm_fold_scales": [ctypes.c_double] * 7 + [_P(lm_fold_scales_t)],
     "lm_peak_stats": [_vp, _i32, ctypes.c_int32, ctypes.c_int32, _d, ctypes.c_int32, _u64, _u64,
                       _u64],
+    "lm_peak_stats_noalloc": [_vp, _i32, ctypes.c_int32, ctypes.c_int32, _d, ctypes.c_int32,
+                              _u64, _u64, _u64],
 }
 
 _lib = None
@@ -391,15 +394,16 @@ def lm_batch_shoot(b, stream=None):
 
 
 def lm_batch_params(b):
-    a, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(load().lm_batch_params(b, ctypes.byref(a), ctypes.byref(c), ctypes.byref(d)),
-           "lm_batch_params")
-    return int(a.value), int(c.value), int(d.value)
+    """(rays per lane, tile scale, workgroups per CU, LDS layout)."""
+    a, c, d, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lm_batch_params(b, ctypes.byref(a), ctypes.byref(c), ctypes.byref(d),
+                                  ctypes.byref(e)), "lm_batch_params")
+    return int(a.value), int(c.value), int(d.value), int(e.value)
 
 
-def lm_batch_set_params(b, rays_per_lane, tile_cells, wg_per_cu):
-    _check(load().lm_batch_set_params(b, int(rays_per_lane), int(tile_cells), int(wg_per_cu)),
-           "lm_batch_set_params")
+def lm_batch_set_params(b, rays_per_lane, tile_cells, wg_per_cu, lds_layout=0):
+    _check(load().lm_batch_set_params(b, int(rays_per_lane), int(tile_cells), int(wg_per_cu),
+                                      int(lds_layout)), "lm_batch_set_params")
 
 
 def lm_fold_scales(theta_e_arcsec, d_x, d_y, kappa0, kappa_star, n_star, ds_over_r=0.0):
@@ -423,16 +427,25 @@ def lm_find_peaks(m, g: lm_geometry, tracks, k=5):
     return flags
 
 
-def lm_peak_stats(m, tracks, beta_edges, k=5):
-    """(peaks, heights, pixels) per distance bin, uint64 arrays of len(edges) - 1."""
+def _peak_stats(name, m, tracks, beta_edges, k):
     tr = np.ascontiguousarray(tracks, dtype=np.int32)
     ed = np.ascontiguousarray(beta_edges, dtype=np.float64)
     nb = ed.shape[0] - 1
     out = [np.zeros(max(nb, 0), dtype=np.uint64) for _ in range(3)]
-    _check(load().lm_peak_stats(m, tr.ctypes.data_as(_i32), tr.shape[0], int(k),
-                                ed.ctypes.data_as(_d), nb, *[o.ctypes.data_as(_u64) for o in out]),
-           "lm_peak_stats")
+    _check(getattr(load(), name)(m, tr.ctypes.data_as(_i32), tr.shape[0], int(k),
+                                 ed.ctypes.data_as(_d), nb,
+                                 *[o.ctypes.data_as(_u64) for o in out]), name)
     return tuple(out)
+
+
+def lm_peak_stats(m, tracks, beta_edges, k=5):
+    """(peaks, heights, pixels) per distance bin, uint64 arrays of len(edges) - 1."""
+    return _peak_stats("lm_peak_stats", m, tracks, beta_edges, k)
+
+
+def lm_peak_stats_noalloc(m, tracks, beta_edges, k=5):
+    """lm_peak_stats on the library's per-device scratch memory (no allocation)."""
+    return _peak_stats("lm_peak_stats_noalloc", m, tracks, beta_edges, k)
 
 
 def lm_shot_stats(m, i0, j0, ni, nj) -> lm_stats:

@@ -144,7 +144,7 @@ def test_null_handles_are_rejected(lib):
     assert lib.lm_set_macro(None, 0.0, 0.0, 0.0) == lm.LM_EINVAL
     assert lib.lm_read_counts(None, None, None, None) == lm.LM_EINVAL
     assert lib.lm_batch_shoot(None, None) == lm.LM_EINVAL
-    assert lib.lm_batch_set_params(None, 8, 1, 0) == lm.LM_EINVAL
+    assert lib.lm_batch_set_params(None, 8, 1, 0, 0) == lm.LM_EINVAL
     assert lib.lm_read_coeffs(None, 0, 0, None) == lm.LM_EINVAL
     lib.lm_destroy(None)
     lib.lm_batch_destroy(None)

@@ -350,12 +350,13 @@ def test_batch_equals_per_map_and_tuned_equals_default(tmp_path):
     # the cache is reused
     lm.lm_batch_tune(b, cache)
     assert lm.lm_batch_params(b) == params
-    # every hand-set execution shape gives the same counts
-    for nr, gs, wg in ((4, 2, 0), (16, 1, 2), (8, 3, 1)):
+    # every hand-set execution shape gives the same counts, every LDS layout included
+    for nr, gs, wg, lay in ((4, 2, 0, 0), (16, 1, 2, 0), (8, 3, 1, 0), (16, 1, 0, 1),
+                            (8, 2, 0, 2), (16, 1, 0, 3), (8, 1, 2, 3)):
         for _, _, mp in maps:
             mp.reset()
-        lm.lm_batch_set_params(b, nr, gs, wg)
-        assert lm.lm_batch_params(b) == (nr, gs, wg)
+        lm.lm_batch_set_params(b, nr, gs, wg, lay)
+        assert lm.lm_batch_params(b) == (nr, gs, wg, lay)
         lm.lm_batch_shoot(b)
         for (w, g, mp), (c, o, s) in zip(maps, ref):
             c2, o2, s2 = mp.counts()
@@ -529,9 +530,13 @@ def test_error_paths():
         mp.trace([g.ray_nx], [0])
     assert e.value.status == lm.LM_ERANGE
     b = lm.lm_batch_create([mp.h])
-    for bad in ((5, 1, 0), (8, 0, 0), (8, 9, 0), (8, 1, -1), (8, 1, 9)):
+    for bad in ((5, 1, 0, 0), (8, 0, 0, 0), (8, 9, 0, 0), (8, 1, -1, 0), (8, 1, 9, 0),
+                (8, 1, 0, 4)):
         with pytest.raises(lm.LensmapError) as e:
             lm.lm_batch_set_params(b, *bad)
         assert e.value.status == lm.LM_EINVAL
+    with pytest.raises(lm.LensmapError) as e:
+        lm.lm_batch_set_params(b, 4, 1, 0, 2)  # layouts 1-3 need 8 or 16 rays per lane
+    assert e.value.status == lm.LM_EUNSUPPORTED
     lm.lm_batch_destroy(b)
     mp.close()
