@@ -13,14 +13,16 @@ import pytest
 import paper_2308_14278_amd.lensmap as lm
 from paper_2308_14278_amd import codeobj
 
-# <scheme 1 (interpolated), precision 0 (mixed), NR 16, P 4>; the batch kernel
-# must fit without spills, the per-map kernel (descriptor by value, held to 4
-# waves by an attribute) may spill a few per-unit values to scratch
-DEFAULT = (("_ZN12_GLOBAL__N_113k_shoot_batchILi1ELi0ELi16ELi4EEEvPK6LmDescPKlPKiiPy", 0),
-           ("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi0ELi16ELi4EEEv6LmDesc", 4),
-           # the plain FP32 comparison path (precision 1), per map and batched
-           ("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi1ELi16ELi4EEEv6LmDesc", 4),
-           ("_ZN12_GLOBAL__N_113k_shoot_batchILi1ELi1ELi16ELi4EEEvPK6LmDescPKlPKiiPy", 0))
+# <scheme 1 (interpolated), precision 0 (mixed), NR 16, P 4, LDS layout>; the
+# batch kernel must fit without spills in every LDS layout the tuner may pick,
+# the per-map kernel (descriptor by value, held to 4 waves by an attribute) may
+# spill a few per-unit values to scratch
+BATCH = "_ZN12_GLOBAL__N_113k_shoot_batchILi1ELi%dELi%dELi4ELi%dEEEvPK6LmDescPKlPKiiPy"
+DEFAULT = tuple([(BATCH % (0, nr, lay), 0) for nr in (8, 16) for lay in range(4)] +
+                [("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi0ELi16ELi4EEEv6LmDesc", 4),
+                 # the plain FP32 comparison path (precision 1), per map and batched
+                 ("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi1ELi16ELi4EEEv6LmDesc", 4),
+                 (BATCH % (1, 16, 0), 0)])
 
 
 def test_default_shooting_kernels_fit_four_waves_per_simd():
@@ -47,8 +49,8 @@ def test_kernel_code_hash_is_a_function_of_the_code():
     reads of the same library agree, and distinct kernels hash apart."""
     if not codeobj.tools_available():
         pytest.skip("ROCm LLVM tools not found")
-    a = codeobj.kernel_code_sha(DEFAULT[0][0])
+    a = codeobj.kernel_code_sha(BATCH % (0, 16, 0))
     assert a is not None and len(a) == 16
-    assert codeobj.kernel_code_sha(DEFAULT[0][0]) == a
-    assert codeobj.kernel_code_sha(DEFAULT[1][0]) not in (None, a)
+    assert codeobj.kernel_code_sha(BATCH % (0, 16, 0)) == a
+    assert codeobj.kernel_code_sha(BATCH % (0, 16, 1)) not in (None, a)
     assert codeobj.kernel_code_sha("no_such_kernel") is None
