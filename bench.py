@@ -367,7 +367,7 @@ def paper_table1_leg(lm, inputs, torch, precision):
     g.precision = precision
     lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
     mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold)
-    used, est = mp.precision()
+    used, est, est_c = mp.precision()
     flops = algorithmic_flops(lm.lm_shot_stats(mp.h, 0, 0, g.ray_nx, g.ray_ny), g.taylor_terms)
     b = lm.lm_batch_create([mp.h])
     lm.lm_batch_tune(b, None)
@@ -386,7 +386,7 @@ def paper_table1_leg(lm, inputs, torch, precision):
     lm.lm_batch_destroy(b)
     mp.close()
     name = {lm.LM_PREC_MIXED_FP64: "fp64-near", lm.LM_PREC_MIXED: "mixed",
-            lm.LM_PREC_AUTO: "auto"}[precision]
+            lm.LM_PREC_MIXED_CENTRED: "centred", lm.LM_PREC_AUTO: "auto"}[precision]
     # near pairs in FP64 are priced against the FP64 vector peak
     peak = PEAK_FP64_TFLOPS if used == lm.LM_PREC_MIXED_FP64 else PEAK_FP32_TFLOPS
     tflops = flops / (s_ms * 1e-3) / 1e12
@@ -395,6 +395,7 @@ def paper_table1_leg(lm, inputs, torch, precision):
         (name, g.ray_nx, g.ray_ny, g.n_rays, g.coarse, dt, s_ms / 1e3, tflops, tflops / peak,
          c_ms, g.n_rays / dt, total))
     return {"precision": name, "precision_used": used, "fp32_mismatch_estimate": est,
+            "centred_fp32_mismatch_estimate": est_c,
             "exec_params": params,
             "rays": g.n_rays, "seconds": dt, "rays_per_s": g.n_rays / dt,
             "shoot_algorithmic_tflops": tflops, "shoot_frac_of_peak": tflops / peak,
@@ -440,7 +441,8 @@ def main():
                          "all workgroups that fit), which the tuner picks on MI355X")
     ap.add_argument("--no-comparison", action="store_true",
                     help="skip the per-map comparison runs (profiling)")
-    ap.add_argument("--paper-map", choices=("none", "auto", "mixed", "fp64", "both"),
+    ap.add_argument("--paper-map", choices=("none", "auto", "mixed", "centred", "fp64", "both",
+                                            "all"),
                     default="none",
                     help="also shoot the paper's own Table 1 map (2.69e13 rays, 215 GB map) once "
                          "per chosen precision (auto: the library's choice; both: FP32 and FP64 "
@@ -474,8 +476,9 @@ def main():
     log("geometry: %d x %d rays (%.4g), R=%d, K=%dx%d, %d lenses" %
         (g.ray_nx, g.ray_ny, g.n_rays, g.coarse, g.l1_kx, g.l1_ky, w.n_lenses))
     mp, _ = make_map(lm, w, g, lenses, g.precision)  # the library's default (LM_PREC_AUTO)
-    prec_used, prec_est = mp.precision()
-    log("precision: %d (FP32 near-sum mismatch estimate %.2e)" % (prec_used, prec_est))
+    prec_used, prec_est, prec_est_c = mp.precision()
+    log("precision: %d (near-sum mismatch estimates: plain FP32 %.2e, centred FP32 %.2e)" %
+        (prec_used, prec_est, prec_est_c))
     stats = lm.lm_shot_stats(mp.h, 0, 0, g.ray_nx, g.ray_ny)
     flops = algorithmic_flops(stats, g.taylor_terms)
     log("near pairs per ray %.3f, FLOP per ray %.1f" % (stats.near_pairs / stats.rays,
@@ -566,7 +569,8 @@ def main():
                    "precision": "FP32 lens sums on rebased offsets, FP64 cell bases and pixel "
                                 "coordinates, FP64 Taylor coefficients",
                    "precision_choice": {"requested": "LM_PREC_AUTO", "used": prec_used,
-                                        "fp32_mismatch_estimate": prec_est},
+                                        "fp32_mismatch_estimate": prec_est,
+                                        "centred_fp32_mismatch_estimate": prec_est_c},
                    "exec_params": list(lm.lm_batch_params(b)),
                    "tuner_candidates": [{"params": [r["rays_per_lane"], r["tile_scale"],
                                                     r["wg_per_cu"], r["lds_layout"]],
@@ -590,8 +594,10 @@ def main():
         line["fold_peak_statistics"] = fold_study_leg(lm, inputs, torch, args.fold_maps)
     if args.paper_map != "none":
         precs = {"auto": [lm.LM_PREC_AUTO], "mixed": [lm.LM_PREC_MIXED],
-                 "fp64": [lm.LM_PREC_MIXED_FP64],
-                 "both": [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64]}[args.paper_map]
+                 "centred": [lm.LM_PREC_MIXED_CENTRED], "fp64": [lm.LM_PREC_MIXED_FP64],
+                 "both": [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64],
+                 "all": [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_CENTRED,
+                         lm.LM_PREC_MIXED_FP64]}[args.paper_map]
         line["paper_table1_map"] = [paper_table1_leg(lm, inputs, torch, pr) for pr in precs]
     if not args.no_cpu_baseline:
         cb, errors = cpu_baseline_leg(lm, w, g, lenses, mp, mp32, args.cpu_seconds)

@@ -40,7 +40,7 @@ def _run(cmd):
 
 # (scheme, precision) pairs the shooting kernels are instantiated for, one
 # compilation of lm_shoot_inst.hip each
-PAIRS = ((0, 0), (0, 1), (1, 0), (1, 1), (1, 2))
+PAIRS = ((0, 0), (0, 1), (1, 0), (1, 1), (1, 2), (1, 4))
 
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:

@@ -117,10 +117,13 @@ lm_status validate_geometry(const lm_geometry* g)
     if (g->scheme != LM_SCHEME_DIRECT && g->scheme != LM_SCHEME_INTERP)
         return fail(LM_EINVAL, "unknown scheme %d", g->scheme);
     if (g->precision != LM_PREC_MIXED && g->precision != LM_PREC_FP32 &&
-        g->precision != LM_PREC_MIXED_FP64 && g->precision != LM_PREC_AUTO)
+        g->precision != LM_PREC_MIXED_FP64 && g->precision != LM_PREC_AUTO &&
+        g->precision != LM_PREC_MIXED_CENTRED)
         return fail(LM_EINVAL, "unknown precision %d", g->precision);
-    if (g->precision == LM_PREC_MIXED_FP64 && g->scheme != LM_SCHEME_INTERP)
-        return fail(LM_EUNSUPPORTED, "LM_PREC_MIXED_FP64 is built for the interpolated scheme only");
+    if ((g->precision == LM_PREC_MIXED_FP64 || g->precision == LM_PREC_MIXED_CENTRED) &&
+        g->scheme != LM_SCHEME_INTERP)
+        return fail(LM_EUNSUPPORTED, "precision %d is built for the interpolated scheme only",
+                    g->precision);
     if (g->far_order != 0) {
         if (g->scheme != LM_SCHEME_INTERP)
             return fail(LM_EINVAL, "far_order needs the interpolated scheme");
@@ -186,6 +189,7 @@ struct lm_map {
     int prec = LM_PREC_MIXED;
     uint64_t prec_gen = ~0ull;
     double prec_est = -1.0;  // LM_PREC_AUTO: estimated FP32 near-sum bin mismatch
+    double prec_est_centred = -1.0;  // ... and of the centred FP32 near sums
 };
 
 namespace {
@@ -223,6 +227,10 @@ void rect_cells(int R, int64_t i0, int64_t j0, int64_t ni, int64_t nj, int64_t& 
 }
 
 // win_max: uint32 bins the kernel's LDS window holds (its layout's).
+// Rays per lane a kernel of precision prec runs when nr are asked for (the
+// centred sums run at most 8).
+int lanes_nr(int prec, int nr) { return prec == LM_PREC_MIXED_CENTRED && nr > 8 ? 8 : nr; }
+
 Exec choose_exec(const lm_map* m, int64_t ncells_x, int64_t ncells_y, int g_scale,
                  int win_max = kLayWin[0])
 {
@@ -371,13 +379,16 @@ lm_status ensure_coef(lm_map* m)
     return LM_OK;
 }
 
-// Coefficients of every level-2 cell of a map (direct, or hierarchical).
+// Coefficients of every level-2 cell of a map (direct, or hierarchical), and
+// the near-lens deflection of every cell centre (for the centred near sums).
 int launch_coefficients(const lm_map* m, const LmDesc& d, hipStream_t s)
 {
-    if (m->g.far_order > 0)
-        return lm_launch_coeffs_hier(d, m->g.taylor_terms, m->coef.as<LmCoef>(), s);
-    return lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
-                            m->coef.as<LmCoef>(), s);
+    int e = m->g.far_order > 0
+                ? lm_launch_coeffs_hier(d, m->g.taylor_terms, m->coef.as<LmCoef>(), s)
+                : lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
+                                   m->coef.as<LmCoef>(), s);
+    if (e == 0) e = lm_launch_near_centre(d, m->coef.as<LmCoef>(), s);
+    return e;
 }
 
 lm_status prepare(lm_map* m, hipStream_t s)
@@ -437,12 +448,13 @@ double mean_near(const lm_map* m)
 // LM_PREC_AUTO: the near-sum precision for the current lenses and macro model.
 // A ray changes pixel when rounding moves its image across a pixel edge; for
 // images spread evenly over their pixels that happens with probability
-// |du| + |dv|, the move in pixel units.  The FP32 near sums' bin mismatch is
-// estimated as the mean of that move, FP32 against FP64 near sums, over the
-// rays of a fixed lattice sample (all rays of small lattices) whose images lie
-// in the map.  FP32 is kept while the estimate is
-// at most kPrecFp32Max, half the 1e-5 bar, and the mean near list holds at most
-// kPrecFp32MaxNear lenses; otherwise the near pairs are summed in FP64.  The
+// |du| + |dv|, the move in pixel units.  The bin mismatch of FP32 near sums,
+// plain and centred, is estimated as the mean of that move against FP64 near
+// sums over the rays of a fixed lattice sample (all rays of small lattices)
+// whose images lie in the map.  The cheapest form whose estimate is at most
+// kPrecFp32Max, half the 1e-5 bar, is taken -- plain FP32, then centred FP32
+// (about a third more work per near pair) -- while the mean near list holds at
+// most kPrecFp32MaxNear lenses; otherwise the near pairs are summed in FP64.  The
 // second condition covers what a lattice mean misses: the rounding of an FP32
 // running sum grows with the number of its terms and, with long lists, varies
 // strongly from one region to the next (with ~110 near lenses a lattice mean of
@@ -460,6 +472,7 @@ lm_status resolve_precision(lm_map* m, hipStream_t s)
     if (m->g.scheme != LM_SCHEME_INTERP || m->nlens == 0) {
         m->prec = LM_PREC_MIXED;
         m->prec_est = 0.0;
+        m->prec_est_centred = 0.0;
         m->prec_gen = m->model_gen;
         return LM_OK;
     }
@@ -481,9 +494,9 @@ lm_status resolve_precision(lm_map* m, hipStream_t s)
             hj[t] = (int64_t)(splitmix64(2 * (uint64_t)t + 1) % (uint64_t)g.ray_ny);
         }
     }
-    DevBuf di, dj, dp, dq, u32, u64;
+    DevBuf di, dj, dp, dq, u32, uct, u64;
     if (di.ensure(n * 8) || dj.ensure(n * 8) || dp.ensure(n * 4) || dq.ensure(n * 4) ||
-        u32.ensure(n * 16) || u64.ensure(n * 16))
+        u32.ensure(n * 16) || uct.ensure(n * 16) || u64.ensure(n * 16))
         return fail(LM_ENOMEM, "cannot allocate the precision probe");
     HIP_TRY(hipMemcpyAsync(di.p, hi.data(), n * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(dj.p, hj.data(), n * 8, hipMemcpyHostToDevice, s));
@@ -491,28 +504,41 @@ lm_status resolve_precision(lm_map* m, hipStream_t s)
     LAUNCH_TRY(lm_launch_trace(d, g.scheme, LM_PREC_MIXED, g.taylor_terms, di.as<int64_t>(),
                                dj.as<int64_t>(), n, dp.as<int32_t>(), dq.as<int32_t>(),
                                u32.as<double>(), s));
+    LAUNCH_TRY(lm_launch_trace(d, g.scheme, LM_PREC_MIXED_CENTRED, g.taylor_terms,
+                               di.as<int64_t>(), dj.as<int64_t>(), n, dp.as<int32_t>(),
+                               dq.as<int32_t>(), uct.as<double>(), s));
     LAUNCH_TRY(lm_launch_trace(d, g.scheme, LM_PREC_MIXED_FP64, g.taylor_terms, di.as<int64_t>(),
                                dj.as<int64_t>(), n, dp.as<int32_t>(), dq.as<int32_t>(),
                                u64.as<double>(), s));
-    std::vector<double> a(2 * n), b(2 * n);
+    std::vector<double> a(2 * n), c(2 * n), b(2 * n);
     HIP_TRY(hipMemcpyAsync(a.data(), u32.p, n * 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(c.data(), uct.p, n * 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(b.data(), u64.p, n * 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    double acc = 0.0;
+    double acc = 0.0, acc_c = 0.0;
     int64_t n_in = 0;
+    auto move = [](double du, double dv) {
+        const double mv = std::fabs(du) + std::fabs(dv);
+        return std::isfinite(mv) ? std::min(1.0, mv) : 1.0;
+    };
     for (int64_t t = 0; t < n; ++t) {
         const double u = b[2 * t], v = b[2 * t + 1];
         if (!(u >= 0.0 && u < g.src_nx && v >= 0.0 && v < g.src_ny)) continue;
         ++n_in;
-        const double mv = std::fabs(a[2 * t] - u) + std::fabs(a[2 * t + 1] - v);
-        acc += std::isfinite(mv) ? std::min(1.0, mv) : 1.0;
+        acc += move(a[2 * t] - u, a[2 * t + 1] - v);
+        acc_c += move(c[2 * t] - u, c[2 * t + 1] - v);
     }
     // per ray imaged into the map: a shot region that lands inside the map
     // sees this rate, however few of the lattice's rays reach the map
     m->prec_est = n_in > 0 ? acc / (double)n_in : 0.0;
-    m->prec = m->prec_est <= kPrecFp32Max && mean_near(m) <= kPrecFp32MaxNear
-                  ? LM_PREC_MIXED
-                  : LM_PREC_MIXED_FP64;
+    m->prec_est_centred = n_in > 0 ? acc_c / (double)n_in : 0.0;
+    const bool short_lists = mean_near(m) <= kPrecFp32MaxNear;
+    if (short_lists && m->prec_est <= kPrecFp32Max)
+        m->prec = LM_PREC_MIXED;
+    else if (short_lists && m->prec_est_centred <= kPrecFp32Max)
+        m->prec = LM_PREC_MIXED_CENTRED;
+    else
+        m->prec = LM_PREC_MIXED_FP64;
     m->prec_gen = m->model_gen;
     m->last = s;
     return LM_OK;
@@ -881,7 +907,8 @@ lm_status lm_shoot(lm_map* m, int64_t i0, int64_t j0, int64_t ni, int64_t nj, vo
     st = resolve_precision(m, s);
     if (st) return st;
     const int64_t R = m->g.coarse;
-    const Exec e = choose_exec(m, (i0 + ni - 1) / R - i0 / R + 1, (j0 + nj - 1) / R - j0 / R + 1, 1);
+    const Exec e = choose_exec(m, (i0 + ni - 1) / R - i0 / R + 1, (j0 + nj - 1) / R - j0 / R + 1, 1,
+                               window_bins(m->prec, 0, lanes_nr(m->prec, m->rays_per_lane)));
     LmDesc d = make_desc(m, i0, j0, i0 + ni, j0 + nj, e);
     if (d.ntiles > 0x7fffffffLL) return fail(LM_EUNSUPPORTED, "too many workgroup tiles");
     LAUNCH_TRY(lm_launch_shoot_map(d, m->g.scheme, m->prec, m->g.taylor_terms,
@@ -1123,7 +1150,7 @@ lm_status lm_trace_beta(lm_map* m, const int64_t* i, const int64_t* j, int64_t n
     return trace_rays(m, i, j, n, nullptr, nullptr, beta_xy);
 }
 
-lm_status lm_precision_info(lm_map* m, int32_t* precision, double* fp32_mismatch_estimate)
+lm_status lm_precision_info(lm_map* m, int32_t* precision, double* mismatch_estimates)
 {
     if (!m) return fail(LM_EINVAL, "map is NULL");
     lm_status st = use_device(m);
@@ -1131,7 +1158,10 @@ lm_status lm_precision_info(lm_map* m, int32_t* precision, double* fp32_mismatch
     st = resolve_precision(m, nullptr);
     if (st) return st;
     if (precision) *precision = m->prec;
-    if (fp32_mismatch_estimate) *fp32_mismatch_estimate = m->prec_est;
+    if (mismatch_estimates) {
+        mismatch_estimates[0] = m->prec_est;
+        mismatch_estimates[1] = m->prec_est_centred;
+    }
     return ok();
 }
 
@@ -1354,6 +1384,10 @@ lm_status lm_shot_stats(const lm_map* m, int64_t i0, int64_t j0, int64_t ni, int
 
 // ==================================================================== batch
 
+// Precision groups of a batch: indexed by the LM_PREC_* value a map's kernels
+// run in (LM_PREC_AUTO, 3, is resolved before and never one).
+constexpr int kGroups = 5;
+
 // Maps of a batch whose kernels run in one precision (LM_PREC_*): one
 // persistent shooting launch over their tiles, fed from its own work counter.
 struct BatchGroup {
@@ -1371,7 +1405,7 @@ struct lm_batch {
     int rays_per_lane = 16, g_scale = 1, wg_per_cu = 0;
     int layout = 0;             // LDS layout of the LM_PREC_MIXED group (others use 0)
     DevBuf descs;               // one LmDesc per map
-    BatchGroup grp[3];          // indexed by precision
+    BatchGroup grp[kGroups];    // indexed by precision
     DevBuf queue;               // one counter per group
     hipStream_t cap = nullptr;
     // two graphs: every map's coefficients + queue reset, then the persistent
@@ -1431,7 +1465,9 @@ lm_status batch_build(lm_batch* b, const std::vector<int64_t>& work)
         const int64_t* own = &b->rect[4 * k];
         int64_t cx, cy;
         rect_cells(m->g.coarse, own[0], own[1], own[2], own[3], cx, cy);
-        const Exec e = choose_exec(m, cx, cy, b->g_scale, kLayWin[group_layout(b, m->prec)]);
+        const Exec e = choose_exec(
+            m, cx, cy, b->g_scale,
+            window_bins(m->prec, group_layout(b, m->prec), lanes_nr(m->prec, b->rays_per_lane)));
         ds[k] = make_desc(m, r[0], r[1], r[0] + r[2], r[1] + r[3], e);
         if (r[2] == 0 || r[3] == 0) ds[k].ntiles = 0;
         if (ds[k].ntiles > 0x7fffffffLL)
@@ -1441,10 +1477,10 @@ lm_status batch_build(lm_batch* b, const std::vector<int64_t>& work)
                                   : (double)m->nlens;
         cost[k] = (double)r[2] * (double)r[3] * (20.0 + 6.0 * lenses);
     }
-    if (b->descs.ensure(n * sizeof(LmDesc)) || b->queue.ensure(3 * 8))
+    if (b->descs.ensure(n * sizeof(LmDesc)) || b->queue.ensure(kGroups * 8))
         return fail(LM_ENOMEM, "cannot allocate batch tables");
     HIP_TRY(hipMemcpy(b->descs.p, ds.data(), n * sizeof(LmDesc), hipMemcpyHostToDevice));
-    for (int pr = 0; pr < 3; ++pr) {
+    for (int pr = 0; pr < kGroups; ++pr) {
         BatchGroup& G = b->grp[pr];
         std::vector<int32_t> order;
         for (int k = 0; k < n; ++k)
@@ -1484,9 +1520,9 @@ lm_status batch_enqueue(lm_batch* b, hipStream_t s, bool with_coeffs, bool pre =
             LmDesc d = make_desc(m, 0, 0, 0, 0, Exec{});
             LAUNCH_TRY(launch_coefficients(m, d, s));
         }
-    if (pre) LAUNCH_TRY(lm_launch_fill_u64(b->queue.as<unsigned long long>(), 3, 0ull, s));
+    if (pre) LAUNCH_TRY(lm_launch_fill_u64(b->queue.as<unsigned long long>(), kGroups, 0ull, s));
     if (shoot)
-        for (int pr = 0; pr < 3; ++pr) {
+        for (int pr = 0; pr < kGroups; ++pr) {
             const BatchGroup& G = b->grp[pr];
             if (G.total <= 0) continue;
             LAUNCH_TRY(lm_launch_shoot_batch(b->descs.as<LmDesc>(), G.offs.as<int64_t>(),

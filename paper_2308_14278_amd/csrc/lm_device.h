@@ -458,6 +458,11 @@ __device__ __forceinline__ typename Prec<PREC>::L lens_value(const LmDesc& d, in
 {
     if constexpr (PREC == 2) {
         return make_double4(d.lx[idx] - zcx, d.ly[idx] - zcy, d.lmd[idx], 0.0);
+    } else if constexpr (PREC == kPrecCentred) {
+        // offset delta_k and c_k = m / delta_k (complex) of the centred sums
+        const double ox = d.lx[idx] - zcx, oy = d.ly[idx] - zcy;
+        const double q = d.lmd[idx] / (ox * ox + oy * oy);
+        return make_float4((float)ox, (float)oy, (float)(q * ox), (float)(-(q * oy)));
     } else if constexpr (PREC == 0) {
         return make_float4((float)(d.lx[idx] - zcx), (float)(d.ly[idx] - zcy), d.lmf[idx], 0.f);
     } else {
@@ -648,7 +653,7 @@ __device__ __forceinline__ typename Prec<PREC>::T column_offset(const LmDesc& d,
 {
     if constexpr (PREC == 2)
         return (double)local_index(k, ci, d.R) * (0.5 * d.dx);
-    else if constexpr (PREC == 0)
+    else if constexpr (PREC == 0 || PREC == kPrecCentred)
         return local_offset(k, ci, d.R, d.hxh, d.hxl);
     else
         return __builtin_fmaf((float)k + 0.5f, d.dxf, d.x0f);
@@ -668,6 +673,19 @@ __device__ __forceinline__ void ray_start_first(const Row<PREC, P, FOLD>& rw,
 {
     ax = p1 * rw.gx[1];
     ay = p1 * (NEG ? -rw.gy[1] : rw.gy[1]);
+}
+
+// the same on top of a value (x0, y0): the centred sums' change of deflection
+template <bool NEG, int PREC, int P, bool FOLD>
+__device__ __forceinline__ void ray_start_first_on(const Row<PREC, P, FOLD>& rw,
+                                                   typename Prec<PREC>::T p1,
+                                                   typename Prec<PREC>::T x0,
+                                                   typename Prec<PREC>::T y0,
+                                                   typename Prec<PREC>::T& ax,
+                                                   typename Prec<PREC>::T& ay)
+{
+    ax = fma(p1, rw.gx[1], x0);
+    ay = fma(p1, NEG ? -rw.gy[1] : rw.gy[1], y0);
 }
 
 // term k + 1 (k >= 1) with pk = dx^(k+1)
@@ -750,6 +768,118 @@ __device__ __forceinline__ void lens_pairs(const T* row, T dy, T m, T* bx, T* by
     }
 }
 
+// Centred near sums.  With delta the ray's offset from the level-2 cell centre
+// and delta_k a near lens's, the lens deflects the ray by m (delta - delta_k) /
+// |delta - delta_k|^2; as complex numbers its change from the cell centre is
+//   conj(that - at the centre) = delta c_k / d_k,  c_k = m / delta_k,
+//   d_k = delta - delta_k,
+// so the near lenses change the deflection by conj(delta S), S = sum_k c_k /
+// d_k = sum_k c_k conj(d_k) / |d_k|^2, while the deflection of the centre
+// itself is summed once per cell in FP64 (k_near_centre).  Every FP32 term is
+// then small (of order m |delta| / |delta_k|^2 instead of m / |delta_k|), so
+// its rounding is too.  One lens (e = y_k - y; the row holds dx^2, c_r dx and
+// c_i dx per column) against the NR rays of a lane, two columns sharing one
+// reciprocal as in lens_pairs:
+//   S_r += (c_r dx - c_i e) w,  S_i += (c_i dx + c_r e) w,  w = 1 / |d|^2.
+template <int NR, class T>
+__device__ __forceinline__ void lens_pairs_c(const T* row, T e, T cr, T ci, T* sr, T* si)
+{
+    const T e2 = e * e;
+    const T cie = ci * e, cre = cr * e;
+    T r2[NR], rr[NR / 2];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) r2[c] = row[c] + e2;
+#pragma unroll
+    for (int c = 0; c < NR; c += 2) rr[c / 2] = r2[c] * r2[c + 1];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < NR / 2; ++c) rr[c] = recip(rr[c]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < NR; c += 2) {
+        const T wa = rr[c / 2] * r2[c + 1], wb = rr[c / 2] * r2[c];
+        sr[c] = fma(row[NR + c] - cie, wa, sr[c]);
+        si[c] = fma(row[2 * NR + c] + cre, wa, si[c]);
+        sr[c + 1] = fma(row[NR + c + 1] - cie, wb, sr[c + 1]);
+        si[c + 1] = fma(row[2 * NR + c + 1] + cre, wb, si[c + 1]);
+    }
+}
+
+// One centred pair of the probes: the ray's column a, its partner column b
+// (the kernel's shared reciprocal) or, unpaired, a reciprocal of its own.
+template <bool PAIRED, class T>
+__device__ __forceinline__ void pair_c(T dxa, T dxb, T e, T cr, T ci, T& sr, T& si)
+{
+    const T e2 = e * e;
+    const T cie = ci * e, cre = cr * e;
+    const T r2a = dxa * dxa + e2;
+    T w;
+    if constexpr (PAIRED) {
+        const T r2b = dxb * dxb + e2;
+        w = recip(r2a * r2b) * r2b;
+    } else {
+        w = recip(r2a);
+    }
+    sr = fma(cr * dxa - cie, w, sr);
+    si = fma(ci * dxa + cre, w, si);
+}
+
+// The change conj(delta S) of a ray's near deflection from S (sr, si) at
+// column offset px and row offset py: x change dx = Re(delta S), and the
+// negated y change dyn = Im(delta S) (the table path's y sums are negated).
+template <class T>
+__device__ __forceinline__ void centred_change(T px, T py, T sr, T si, T& dx, T& dyn)
+{
+    dx = fma(px, sr, -(py * si));
+    dyn = fma(px, si, py * sr);
+}
+
+// The cell centre's near-lens deflection into a row's FP64 pixel bases.
+template <int PREC, int P, bool FOLD>
+__device__ __forceinline__ void centre_bases(const LmDesc& d, const LmCoef& cf,
+                                             Row<PREC, P, FOLD>& rw)
+{
+    rw.ubxb = __builtin_fma(-cf.n0x, d.inv_sdx, rw.ubxb);
+    rw.ubyb = __builtin_fma(-cf.n0y, d.inv_sdy, rw.ubyb);
+}
+
+// Row-polynomial start values of the NR rays of a lane from the wave-uniform
+// column powers (scalar loads), one power at a time so that only NR of them
+// are live in scalar registers; px gets the column offsets (first powers).
+// CENT: ax, ay hold the centred sums S on entry, and the start is added on top
+// of their change conj(delta S) (with py the row offset).
+template <bool NEGY, int PREC, int P, bool FOLD, int NR, bool CENT = false>
+__device__ __forceinline__ void table_start(ConstF tab, int R, const Row<PREC, P, FOLD>& rw,
+                                            typename Prec<PREC>::T* px,
+                                            typename Prec<PREC>::T* ax,
+                                            typename Prec<PREC>::T* ay,
+                                            typename Prec<PREC>::T py = 0)
+{
+    using T = typename Prec<PREC>::T;
+    constexpr int D = Row<PREC, P, FOLD>::D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            const T pk = tab[k * (R + LM_PTAB_PAD) + c];
+            if (k == 0) {
+                px[c] = pk;
+                if constexpr (CENT) {
+                    T dx, dyn;
+                    centred_change(pk, py, ax[c], ay[c], dx, dyn);
+                    ray_start_first_on<NEGY, PREC, P, FOLD>(rw, pk, dx, dyn, ax[c], ay[c]);
+                } else {
+                    ray_start_first<NEGY, PREC, P, FOLD>(rw, pk, ax[c], ay[c]);
+                }
+            } else {
+                ray_start_next<NEGY, PREC, P, FOLD>(rw, k, pk, ax[c], ay[c]);
+            }
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // Columns [c_lo, c_hi) of cell ci are computed (c_lo even, so columns 2m and
 // 2m + 1 share a group); rays of columns >= c_beg are counted.  LAY: the LDS
 // layout (near-list block, table block).
@@ -760,6 +890,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                              typename Prec<PREC>::T* tb, int lane, unsigned& nout)
 {
     using T = typename Prec<PREC>::T;
+    constexpr bool CENT = PREC == kPrecCentred;
     const int R = d.R;
     const Hot h = make_hot(d);
     const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
@@ -773,6 +904,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
     // the lane's ray row
     Row<PREC, P, FOLD> rw;
     row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
+    if constexpr (CENT) centre_bases(d, d.coef[cj * d.ncx + ci], rw);
     const T py = rw.py;
 
     constexpr int kCap = Cap<SCHEME, LAY>::value;
@@ -788,27 +920,20 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
         // the table path carries the y sums negated (lens offsets y_k - y):
         // the row coefficients -gy and the FP64 binning take the sign for free
         constexpr bool NEGY = UseTab<SCHEME, PREC>::value;
+        constexpr int TW = tab_width(PREC);
         T px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
-        if constexpr (PREC == 0) {
-            // wave-uniform column offsets and their powers from the map's table
-            // (scalar loads), one power at a time so that only NR of them are
-            // live in scalar registers
-            const ConstF tab = (ConstF)(d.ptab + (c0 - ci * (int64_t)R));
+        if constexpr (CENT) {
+            // the sums S start at zero; the row-polynomial start is added after
+            // the lenses (table_start on the sums' change)
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int c = 0; c < NR; ++c) {
-                    const T pk = tab[k * (R + LM_PTAB_PAD) + c];
-                    if (k == 0) {
-                        px[c] = pk;
-                        ray_start_first<NEGY, PREC, P, FOLD>(rw, pk, ax[c], ay[c]);
-                    } else {
-                        ray_start_next<NEGY, PREC, P, FOLD>(rw, k, pk, ax[c], ay[c]);
-                    }
-                }
+            for (int c = 0; c < NR; ++c) {
+                ax[c] = 0;
+                ay[c] = 0;
             }
-            __builtin_amdgcn_sched_barrier(0);
+        } else if constexpr (PREC == 0) {
+            // wave-uniform column offsets and their powers from the map's table
+            table_start<NEGY, PREC, P, FOLD, NR>((ConstF)(d.ptab + (c0 - ci * (int64_t)R)), R, rw,
+                                                 px, ax, ay);
         } else {
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
@@ -836,32 +961,43 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
             if constexpr (UseTab<SCHEME, PREC>::value) {
                 // this lane's column in the table build: NR divides 64
                 T pxl;
-                if constexpr (PREC == 0)
+                if constexpr (PREC == 0 || CENT)
                     pxl = local_offset(c0 + (lane & (NR - 1)), ci, R, h_hxh, h_hxl);
                 else
                     pxl = column_offset<PREC>(d, c0 + (lane & (NR - 1)), ci);
                 for (int k0 = 0; k0 < nb; k0 += kTabCh) {
                     // wave-uniform count: scalar loop control
                     const int nk = __builtin_amdgcn_readfirstlane(min(kTabCh, nb - k0));
-                    // tb[k][0..NR) = dx^2, tb[k][NR..2NR) = m dx, for lenses k0 .. k0+nk
+                    // tb[k][0..NR) = dx^2, tb[k][NR..2NR) = m dx (centred: c_r dx,
+                    // and c_i dx in tb[k][2NR..3NR)), for lenses k0 .. k0+nk
                     for (int e = lane; e < nk * NR; e += 64) {
                         const int k = e / NR, c = e & (NR - 1);
                         const auto L = lb[k0 + k];
                         const T dx = pxl - L.x;
-                        tb[k * 2 * NR + c] = dx * dx;
-                        tb[k * 2 * NR + NR + c] = L.z * dx;
+                        tb[k * TW * NR + c] = dx * dx;
+                        tb[k * TW * NR + NR + c] = L.z * dx;
+                        if constexpr (CENT) tb[k * TW * NR + 2 * NR + c] = L.w * dx;
                     }
                     wave_sync_lds();
                     // two lenses per step: their LDS reads share base addresses
                     int k = 0;
                     for (; k + 2 <= nk; k += 2) {
                         const auto L0 = lb[k0 + k], L1 = lb[k0 + k + 1];
-                        lens_pairs<NR>(tb + k * 2 * NR, L0.y - py, L0.z, bx, by);
-                        lens_pairs<NR>(tb + (k + 1) * 2 * NR, L1.y - py, L1.z, bx, by);
+                        if constexpr (CENT) {
+                            lens_pairs_c<NR>(tb + k * TW * NR, L0.y - py, L0.z, L0.w, bx, by);
+                            lens_pairs_c<NR>(tb + (k + 1) * TW * NR, L1.y - py, L1.z, L1.w, bx,
+                                             by);
+                        } else {
+                            lens_pairs<NR>(tb + k * TW * NR, L0.y - py, L0.z, bx, by);
+                            lens_pairs<NR>(tb + (k + 1) * TW * NR, L1.y - py, L1.z, bx, by);
+                        }
                     }
                     if (k < nk) {
                         const auto L = lb[k0 + k];
-                        lens_pairs<NR>(tb + k * 2 * NR, L.y - py, L.z, bx, by);
+                        if constexpr (CENT)
+                            lens_pairs_c<NR>(tb + k * TW * NR, L.y - py, L.z, L.w, bx, by);
+                        else
+                            lens_pairs<NR>(tb + k * TW * NR, L.y - py, L.z, bx, by);
                     }
                     wave_sync_lds();
                 }
@@ -886,6 +1022,12 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 }
             }
             if (nblk > 1) wave_sync_lds();
+        }
+        if constexpr (CENT) {
+            // the change conj(delta S) of the near deflection, then the
+            // row-polynomial start on top of it (and the column offsets)
+            table_start<NEGY, PREC, P, FOLD, NR, true>(
+                (ConstF)(d.ptab + (c0 - ci * (int64_t)R)), R, rw, px, ax, ay, py);
         }
         const int ncol = (int)min((int64_t)NR, c_hi - c0);
         const int cfirst = (int)max((int64_t)0, c_beg - c0);
@@ -983,12 +1125,25 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
         const int64_t c_lo = c_beg & ~(int64_t)1;
         const int64_t j = r_lo + lane;
         const bool row_ok = j >= d.j0 && j < d.j1;
-        if (d.fold)
-            process_unit<SCHEME, PREC, NR, P, true, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok,
-                                                         axb, ayb, win, lb, tb, lane, nout);
-        else
-            process_unit<SCHEME, PREC, NR, P, false, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok,
-                                                          axb, ayb, win, lb, tb, lane, nout);
+        // centred sums: a cell with a near lens close to its centre (n0 NaN,
+        // wave-uniform) sums its near lenses plainly
+        constexpr int PU = PREC == kPrecCentred ? 0 : PREC;
+        if (PREC == kPrecCentred && !__builtin_isnan(d.coef[cj * d.ncx + ci].n0x)) {
+            if (d.fold)
+                process_unit<SCHEME, PREC, NR, P, true, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j,
+                                                             row_ok, axb, ayb, win, lb, tb, lane,
+                                                             nout);
+            else
+                process_unit<SCHEME, PREC, NR, P, false, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j,
+                                                              row_ok, axb, ayb, win, lb, tb, lane,
+                                                              nout);
+        } else if (d.fold) {
+            process_unit<SCHEME, PU, NR, P, true, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, axb,
+                                                       ayb, win, lb, tb, lane, nout);
+        } else {
+            process_unit<SCHEME, PU, NR, P, false, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok,
+                                                        axb, ayb, win, lb, tb, lane, nout);
+        }
     }
     unsigned tot = wave_sum_u32(nout);
     if (lane == 0 && tot) atomicAdd(d.n_out, (unsigned long long)tot);
@@ -1014,10 +1169,10 @@ template <int SCHEME, int PREC, int NR, int P>
 __global__ __launch_bounds__(kWG)
 __attribute__((amdgpu_waves_per_eu(MinWaves<SCHEME, PREC>::value))) void k_shoot_map(LmDesc d)
 {
-    __shared__ unsigned win[kLayWin[0]];
+    __shared__ unsigned win[window_bins(PREC, 0, NR)];
     __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME, 0>::value];
     __shared__ __align__(16) typename Prec<PREC>::T
-        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kLayTab[0] * 2 * NR : 1];
+        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kLayTab[0] * tab_width(PREC) * NR : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1039,15 +1194,15 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
                                                      const int32_t* __restrict__ order, int nmaps,
                                                      unsigned long long* queue)
 {
-    __shared__ unsigned win[kLayWin[LAY]];
+    __shared__ unsigned win[window_bins(PREC, LAY, NR)];
     __shared__ typename Prec<PREC>::L lens[LM_WAVES][Cap<SCHEME, LAY>::value];
     __shared__ __align__(16) typename Prec<PREC>::T
-        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kLayTab[LAY] * 2 * NR : 1];
+        tab[LM_WAVES][UseTab<SCHEME, PREC>::value ? kLayTab[LAY] * tab_width(PREC) * NR : 1];
     __shared__ long long s_item;
     const int tid = threadIdx.x, lane = tid & 63;
     // wave index as a scalar: everything derived from it stays uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int b = tid; b < kLayWin[LAY]; b += kWG) win[b] = 0u;
+    for (int b = tid; b < window_bins(PREC, LAY, NR); b += kWG) win[b] = 0u;
     const int64_t total = offs[nmaps];
     for (;;) {
         if (tid == 0) s_item = (long long)atomicAdd(queue, 1ull);
@@ -1090,6 +1245,17 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
     using T = typename Prec<PREC>::T;
     constexpr int kCap = Cap<SCHEME, 0>::value;
     const int count = list_count<SCHEME>(d, ci, cj);
+    if constexpr (PREC == kPrecCentred) {
+        // the centred sums S over the list in list order (ax, ay get S)
+        T sr = 0, si = 0;
+        for (int k = 0; k < count; ++k) {
+            const auto L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, k), zcx, zcy);
+            pair_c<PAIRED>(px - L.x, pxp - L.x, L.y - py, L.z, L.w, sr, si);
+        }
+        ax = sr;
+        ay = si;
+        return;
+    }
     T kx = 0, ky = 0;
     for (int b0 = 0; b0 < count; b0 += kCap) {
         const int nb = min(kCap, count - b0);
@@ -1127,6 +1293,12 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
     using T = typename Prec<PREC>::T;
     const int R = d.R;
     const int64_t ci = i / R, cj = j / R;
+    if constexpr (PREC == kPrecCentred) {
+        if (__builtin_isnan(d.coef[cj * d.ncx + ci].n0x)) {  // as the kernel: plain sums
+            trace_one<SCHEME, 0, P, FOLD>(d, i, j, po, qo, uv);
+            return;
+        }
+    }
     const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
     double ubx, uby;
     cell_base<SCHEME>(d, ci, cj, ubx, uby);
@@ -1134,12 +1306,26 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
     if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
     Row<PREC, P, FOLD> rw;
     row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
+    if constexpr (PREC == kPrecCentred) centre_bases(d, d.coef[cj * d.ncx + ci], rw);
     const T px = column_offset<PREC>(d, i, ci);
-    T pw[Row<PREC, P, FOLD>::D], ax, ay;
-    col_powers<Row<PREC, P, FOLD>::D>(px, pw);
-    ray_start<PREC, P, FOLD>(rw, pw, ax, ay);
-    near_sum<SCHEME, PREC, true>(d, ci, cj, zcx, zcy, px, rw.py, ax, ay,
-                                 column_offset<PREC>(d, i ^ 1, ci));
+    constexpr int D = Row<PREC, P, FOLD>::D;
+    T pw[D], ax, ay;
+    col_powers<D>(px, pw);
+    if constexpr (PREC == kPrecCentred) {
+        // as the kernel: S, its change, the start on top with the y sum negated
+        T sr, si, dx, dyn;
+        near_sum<SCHEME, PREC, true>(d, ci, cj, zcx, zcy, px, rw.py, sr, si,
+                                     column_offset<PREC>(d, i ^ 1, ci));
+        centred_change(px, rw.py, sr, si, dx, dyn);
+        ray_start_first_on<true, PREC, P, FOLD>(rw, pw[0], dx, dyn, ax, ay);
+#pragma unroll
+        for (int k = 1; k < D; ++k) ray_start_next<true, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
+        ay = -ay;
+    } else {
+        ray_start<PREC, P, FOLD>(rw, pw, ax, ay);
+        near_sum<SCHEME, PREC, true>(d, ci, cj, zcx, zcy, px, rw.py, ax, ay,
+                                     column_offset<PREC>(d, i ^ 1, ci));
+    }
     const Hot h = make_hot(d);
     unsigned p, q;
     ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, ax, ay, p,
@@ -1178,17 +1364,19 @@ __global__ __launch_bounds__(kWG) void k_trace(LmDesc d, const int64_t* __restri
         trace_one<SCHEME, PREC, P, false>(d, ii[t], jj[t], po[t], qo[t], u);
 }
 
-// Deflection at arbitrary positions, rebased on the level-2 cell holding them.
+// Deflection at an arbitrary position, rebased on the level-2 cell holding it.
 template <int SCHEME, int PREC, int P>
-__global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restrict__ th,
-                                                 int64_t n, double* __restrict__ al)
+__device__ void deflect_one(const LmDesc& d, double tx, double ty, double& outx, double& outy)
 {
     using T = typename Prec<PREC>::T;
-    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (t >= n) return;
-    const double tx = th[2 * t], ty = th[2 * t + 1];
     const int64_t ci = (int64_t)floor((tx - d.x0) / ((double)d.R * d.dx));
     const int64_t cj = (int64_t)floor((ty - d.y0) / ((double)d.R * d.dy));
+    if constexpr (PREC == kPrecCentred) {
+        if (__builtin_isnan(d.coef[cj * d.ncx + ci].n0x)) {  // plain sums for this cell
+            deflect_one<SCHEME, 0, P>(d, tx, ty, outx, outy);
+            return;
+        }
+    }
     const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
     float ar[P > 1 ? P : 1], ai[P > 1 ? P : 1], a0r = 0.f, a0i = 0.f;
     if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
@@ -1202,7 +1390,14 @@ __global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restr
     }
     T ax = 0, ay = 0;
     near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, py, ax, ay);
-    double outx = ax, outy = ay;
+    if constexpr (PREC == kPrecCentred) {
+        T dx, dyn;
+        centred_change(px, py, ax, ay, dx, dyn);
+        ax = dx;
+        ay = -dyn;
+    }
+    outx = ax;
+    outy = ay;
     if (SCHEME == 1) {
         float fr, fi, dx, dy;
         if (PREC != 1) {
@@ -1217,13 +1412,25 @@ __global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restr
             const LmCoef& c = d.coef[cj * d.ncx + ci];
             outx = (double)ax + (double)fr + c.a0r;
             outy = (double)ay - (double)fi - c.a0i;
+            if constexpr (PREC == kPrecCentred) {
+                // the centred sums hold the change from the centre's near deflection
+                outx += c.n0x;
+                outy += c.n0y;
+            }
         } else {
             outx = (double)(ax + (a0r + fr));
             outy = (double)(ay - (a0i + fi));
         }
     }
-    al[2 * t] = outx;
-    al[2 * t + 1] = outy;
+}
+
+template <int SCHEME, int PREC, int P>
+__global__ __launch_bounds__(kWG) void k_deflect(LmDesc d, const double* __restrict__ th,
+                                                 int64_t n, double* __restrict__ al)
+{
+    const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (t >= n) return;
+    deflect_one<SCHEME, PREC, P>(d, th[2 * t], th[2 * t + 1], al[2 * t], al[2 * t + 1]);
 }
 
 // ------------------------------------------------------------ dispatch
@@ -1304,13 +1511,20 @@ int dispatch_p(int terms, F& f)
     }
 }
 
+// The centred sums run at most 8 rays per lane: with 16, their wider table
+// rows and the change of deflection need more than the 128 VGPRs of four waves
+// per SIMD.
 template <int S, int PR, class F>
 int dispatch_nr(int nr, int terms, F& f)
 {
     switch (nr) {
     case 4: return dispatch_p<S, PR, 4>(terms, f);
     case 8: return dispatch_p<S, PR, 8>(terms, f);
-    case 16: return dispatch_p<S, PR, 16>(terms, f);
+    case 16:
+        if constexpr (PR == kPrecCentred)
+            return dispatch_p<S, PR, 8>(terms, f);
+        else
+            return dispatch_p<S, PR, 16>(terms, f);
     default: return (int)hipErrorInvalidValue;
     }
 }

@@ -6,6 +6,11 @@
 #define LM_WG 256          // threads per workgroup: 4 waves of 64
 #define LM_WAVES 4
 #define LM_LENS_CAP 256    // direct sum: lenses staged per wave per block (the summation block)
+// Kernel value of LM_PREC_MIXED_CENTRED: FP32 near sums of each near lens's
+// deflection change from the level-2 cell centre, whose near-lens deflection
+// is taken in FP64 (n0 below).
+constexpr int kPrecCentred = 4;
+
 // LDS layouts of the interpolated-scheme shooting kernels, the tuner's third
 // axis besides rays per lane and tile size: lenses per LDS table block (the
 // wave-shared dx^2, m dx table), uint32 bins of the workgroup's LDS window
@@ -17,6 +22,19 @@
 static constexpr int kLayTab[LM_LAYOUTS] = {16, 8, 32, 16};
 static constexpr int kLayWin[LM_LAYOUTS] = {7040, 8064, 5000, 7552};
 static constexpr int kLayNear[LM_LAYOUTS] = {64, 64, 64, 32};
+
+// Table entries per (column, lens) of a precision's wave-shared LDS table: dx^2
+// and m dx, or for the centred sums dx^2, c_r dx and c_i dx.
+constexpr int tab_width(int prec) { return prec == kPrecCentred ? 3 : 2; }
+
+// Window bins of a shooting kernel: the layout's, less what the wider table of
+// the centred sums takes (rays_per_lane columns per lens and wave), so that
+// the workgroup keeps to the layout's LDS budget.
+constexpr int window_bins(int prec, int layout, int rays_per_lane)
+{
+    return kLayWin[layout] -
+           (prec == kPrecCentred ? LM_WAVES * kLayTab[layout] * rays_per_lane : 0);
+}
 #define LM_PTAB_PAD 64     // column-offset table entries past R (last column group)
 #define LM_PTAB_POW 6      // powers dx .. dx^6 per column (row polynomials, P <= 7)
 
@@ -33,9 +51,12 @@ static constexpr int kLayNear[LM_LAYOUTS] = {64, 64, 64, 32};
 
 // Taylor coefficients of one level-2 cell: a_0 in FP64 (it carries the large
 // far-field deflection of the cell centre), a_1..a_6 in FP32 (they multiply
-// offsets of at most half a cell).  64 bytes per cell.
+// offsets of at most half a cell); and for the centred near sums the
+// deflection of the cell centre by its near lenses, FP64, NaN when a near lens
+// lies within twice the cell's half-diagonal of the centre.  80 bytes per cell.
 struct LmCoef {
     double a0r, a0i;
+    double n0x, n0y;
     float a[12];  // (re, im) of a_1 .. a_6
 };
 
@@ -97,6 +118,9 @@ int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int
 // Hierarchical far field: level-1 series (d.Q terms) into d.l1exp, then the
 // coefficients of every level-2 cell.
 int lm_launch_coeffs_hier(const LmDesc& d, int terms, LmCoef* out, void* stream);
+// Near-lens deflection of every level-2 cell centre (LmCoef::n0x, n0y) for the
+// centred near sums; the rest of each record is left as it is.
+int lm_launch_near_centre(const LmDesc& d, LmCoef* out, void* stream);
 int lm_launch_shoot_map(const LmDesc& d, int scheme, int precision, int terms, int rays_per_lane,
                         void* stream);
 // layout: an LDS layout (above); LM_LAYOUTS pairs it is not built for give
@@ -154,3 +178,4 @@ LM_INST_DECLARE(0, 1)
 LM_INST_DECLARE(1, 0)
 LM_INST_DECLARE(1, 1)
 LM_INST_DECLARE(1, 2)
+LM_INST_DECLARE(1, 4)

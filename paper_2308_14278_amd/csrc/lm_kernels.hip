@@ -257,10 +257,43 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
         p[i] = v;
 }
 
+// Near-lens deflection of each level-2 cell centre, one cell per thread: the
+// sum over the cell's near list, in list order, of m (z_c - z_k) / |z_c - z_k|^2
+// in FP64 (the centred near sums add each ray's FP32 change from it).  NaN when
+// a near lens lies within twice the cell's half-diagonal of the centre: there
+// the change is not small, and the shooting kernel sums that cell's near
+// lenses plainly.
+__global__ __launch_bounds__(kWG) void k_near_centre(LmDesc d, LmCoef* __restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (c >= d.ncx * d.ncy) return;
+    const int64_t ci = c % d.ncx, cj = c / d.ncx;
+    const double zcx = cell_cx(d, ci), zcy = cell_cy(d, cj);
+    const double rc2 = (double)d.R * d.R * (d.dx * d.dx + d.dy * d.dy);
+    const L1Cell l1 = l1_of(d, ci, cj);
+    double sx = 0.0, sy = 0.0;
+    bool close = false;
+    for (int r = 0; r <= 2 * d.H; ++r) {
+        int s, e;
+        near_row(d, l1, r, s, e);
+        for (int k = s; k < e; ++k) {
+            const double ox = d.lx[k] - zcx, oy = d.ly[k] - zcy;
+            const double r2 = ox * ox + oy * oy;
+            close |= r2 < rc2;
+            const double q = d.lmd[k] / r2;
+            sx -= q * ox;
+            sy -= q * oy;
+        }
+    }
+    LmCoef& o = out[cj * d.ncx + ci];
+    o.n0x = close ? __builtin_nan("") : sx;
+    o.n0y = close ? __builtin_nan("") : sy;
+}
+
 }  // namespace
 
 // Every (scheme, precision) pair lm_shoot_inst.hip is built for.
-#define LM_PAIRS(X) X(0, 0) X(0, 1) X(1, 0) X(1, 1) X(1, 2)
+#define LM_PAIRS(X) X(0, 0) X(0, 1) X(1, 0) X(1, 1) X(1, 2) X(1, 4)
 
 bool lm_supported_rays_per_lane(int r) { return r == 4 || r == 8 || r == 16; }
 
@@ -346,6 +379,15 @@ int lm_launch_coeffs_hier(const LmDesc& d, int terms, LmCoef* out, void* stream)
     case 7: hipLaunchKernelGGL(k_l1_shift<7>, grid, dim3(kWG), 0, s, d, out); break;
     default: return (int)hipErrorInvalidValue;
     }
+    return (int)hipGetLastError();
+}
+
+int lm_launch_near_centre(const LmDesc& d, LmCoef* out, void* stream)
+{
+    const int64_t n = d.ncx * d.ncy;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_near_centre, dim3((unsigned)((n + kWG - 1) / kWG)), dim3(kWG), 0,
+                       (hipStream_t)stream, d, out);
     return (int)hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ LM_PREC_MIXED = 0
 LM_PREC_FP32 = 1
 LM_PREC_MIXED_FP64 = 2
 LM_PREC_AUTO = 3
+LM_PREC_MIXED_CENTRED = 4
 LM_MAX_TERMS = 7
 
 _STATUS_NAMES = {0: "LM_OK", -1: "LM_EINVAL", -2: "LM_ENOMEM", -3: "LM_EDEVICE", -4: "LM_ESTATE",
@@ -340,11 +341,12 @@ def lm_trace_beta(m, i, j):
 
 
 def lm_precision_info(m):
-    """(precision the kernels run in, estimated FP32 near-sum bin mismatch or -1)."""
+    """(precision the kernels run in, estimated bin mismatch of plain FP32 near sums,
+    of centred FP32 near sums); estimates are -1 for a fixed precision."""
     p = ctypes.c_int32()
-    e = ctypes.c_double()
-    _check(load().lm_precision_info(m, ctypes.byref(p), ctypes.byref(e)), "lm_precision_info")
-    return int(p.value), float(e.value)
+    e = (ctypes.c_double * 2)()
+    _check(load().lm_precision_info(m, ctypes.byref(p), e), "lm_precision_info")
+    return int(p.value), float(e[0]), float(e[1])
 
 
 def lm_batch_tune_results(b):

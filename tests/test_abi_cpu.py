@@ -81,7 +81,7 @@ def _good():
 
 @pytest.mark.parametrize("field,value", [("coarse", 100), ("coarse", 0), ("src_nx", 0),
                                          ("ray_dx", -1.0), ("taylor_terms", 9),
-                                         ("scheme", 5), ("precision", 4), ("l1_kx", 0),
+                                         ("scheme", 5), ("precision", 5), ("l1_kx", 0),
                                          ("ray_x0", float("inf"))])
 def test_create_rejects_invalid_geometry(field, value):
     g = _good()

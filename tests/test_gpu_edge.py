@@ -74,7 +74,7 @@ def test_near_lists_longer_than_one_block(precision):
     g.l1_ky *= 5
     lm_map = lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses())
     st = lm.lm_shot_stats(lm_map.h, 700_000, 20_000, 3_000, 1_500)
-    used, est = lm_map.precision()
+    used, est, _ = lm_map.precision()
     lm_map.close()
     pairs = st.near_pairs / st.rays
     print("near lenses per ray: %.1f; precision %d (FP32 mismatch estimate %.2e)" %

@@ -112,7 +112,8 @@ def paper_window():
     return (i0, j0, ni, nj), (p0, q0, np_, nq), ref
 
 
-@pytest.mark.parametrize("precision", [lm.LM_PREC_MIXED_FP64, lm.LM_PREC_AUTO])
+@pytest.mark.parametrize("precision", [lm.LM_PREC_MIXED_FP64, lm.LM_PREC_MIXED_CENTRED,
+                                       lm.LM_PREC_AUTO])
 def test_paper_table1_map(precision, paper_window):
     """The paper's own map (Sec. 4.1, Table 1): 13745 unit lenses, 2.69e13-ray
     lattice, 73877 x 363635 pixels of 5.5e-4 theta_E.  Pixels of 3000 sampled
@@ -120,13 +121,15 @@ def test_paper_table1_map(precision, paper_window):
     the window counts of a shot sub-rectangle against the oracle's, at the
     1e-5 bar.  At this resolution FP32 near sums (rms error ~1e-8 theta_E,
     2e-5 of a pixel) would move 1.2-2.2e-5 of the rays, so the library's
-    default choice must be FP64 near sums."""
+    default choice must be the centred FP32 sums or FP64 sums."""
     g, mp, orc = _paper_map(precision)
-    name = "fp64-near" if precision == lm.LM_PREC_MIXED_FP64 else "auto"
-    used, est = mp.precision()
-    print("paper map %s: runs in precision %d, FP32 mismatch estimate %.2e" % (name, used, est))
+    name = {lm.LM_PREC_MIXED_FP64: "fp64-near", lm.LM_PREC_MIXED_CENTRED: "centred"}.get(
+        precision, "auto")
+    used, est, est_c = mp.precision()
+    print("paper map %s: runs in precision %d, mismatch estimates: plain FP32 %.2e, centred "
+          "FP32 %.2e" % (name, used, est, est_c))
     if precision == lm.LM_PREC_AUTO:
-        assert used == lm.LM_PREC_MIXED_FP64 and est > 5e-6
+        assert est > 5e-6 and used in (lm.LM_PREC_MIXED_CENTRED, lm.LM_PREC_MIXED_FP64)
     rng = np.random.default_rng(13)
     ii = rng.integers(0, g.ray_nx, 3000)
     jj = rng.integers(0, g.ray_ny, 3000)

@@ -124,7 +124,8 @@ def test_near_fold_subrect_vs_oracle():
     mp.close()
 
 
-@pytest.mark.parametrize("precision", [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64])
+@pytest.mark.parametrize("precision", [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64,
+                                       lm.LM_PREC_MIXED_CENTRED])
 def test_trace_probe_rebuilds_shot_map(precision):
     """lm_trace (one ray per thread) reproduces the shooting kernel bit for bit."""
     w = inputs.near_fold()
@@ -141,6 +142,38 @@ def test_trace_probe_rebuilds_shot_map(precision):
     np.add.at(rebuilt, q[inside].astype(np.int64) * g.src_nx + p[inside], 1)
     np.testing.assert_array_equal(rebuilt.reshape(counts.shape), counts.astype(np.int64))
     assert (~inside).sum() == n_out
+    mp.close()
+
+
+def test_centred_sums_with_lenses_at_cell_centres():
+    """Centred near sums where near lenses sit at (and next to) level-2 cell
+    centres: those cells sum plainly (their centre's near deflection is not
+    small), every other cell centred; the shot map against the oracle, and the
+    trace probe rebuilds it bit for bit."""
+    w = inputs.near_fold()
+    g = _geom(w, precision=lm.LM_PREC_MIXED_CENTRED)
+    x, y, m = w.lenses()
+    i0, j0, ni, nj = 1_000_000, 30_000, 1_920, 640
+    # move the first lenses onto cell centres (and within a tenth of a cell)
+    # of the shot rectangle
+    R = g.coarse
+    x, y = x.copy(), y.copy()
+    for t, (ci, cj, f) in enumerate(((i0 // R + 3, j0 // R + 2, 0.0), (i0 // R + 10, j0 // R + 5, 0.1),
+                                     (i0 // R + 20, j0 // R + 1, 0.6))):
+        x[t] = g.ray_x0 + (ci + 0.5 + f) * R * g.ray_dx
+        y[t] = g.ray_y0 + (cj + 0.5) * R * g.ray_dy
+    mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, (x, y, m))
+    orc = oracle.Oracle(oracle_geom(g), w.kappa, w.gamma, w.kappa_star, x, y, m)
+    mp.shoot(i0, j0, ni, nj)
+    counts, n_out, _ = mp.counts()
+    ref, ref_out = orc.shoot(i0, j0, ni, nj, nthreads=NTHREADS)
+    _compare(g, counts, n_out, ref, ref_out, ni * nj, "centred sums, lenses at cell centres")
+    ii, jj = np.meshgrid(np.arange(i0, i0 + ni), np.arange(j0, j0 + nj))
+    p, q = mp.trace(ii.ravel(), jj.ravel())
+    inside = p >= 0
+    rebuilt = np.zeros(g.src_nx * g.src_ny, dtype=np.int64)
+    np.add.at(rebuilt, q[inside].astype(np.int64) * g.src_nx + p[inside], 1)
+    np.testing.assert_array_equal(rebuilt.reshape(counts.shape), counts.astype(np.int64))
     mp.close()
 
 
@@ -205,7 +238,8 @@ def test_paper_scale_band_conservation_and_probe():
     mp.close()
 
 
-@pytest.mark.parametrize("precision", [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64])
+@pytest.mark.parametrize("precision", [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64,
+                                       lm.LM_PREC_MIXED_CENTRED])
 def test_paper_scale_subrect_map_vs_oracle(precision):
     """Paper-scale geometry (13000 lenses, ~1856-ray cells): a 2.2e7-ray map
     region against the oracle."""
@@ -253,8 +287,9 @@ def test_precision_stress_region_vs_oracle():
     nj = 8 * g.coarse
     ni = int(1e9 // nj)
     i0, j0 = g.ray_nx // 2 - ni // 2, g.ray_ny // 2 - nj // 2
-    used, est = mp.precision()
-    _say("precision stress: runs in precision %d (FP32 mismatch estimate %.2e)" % (used, est))
+    used, est, est_c = mp.precision()
+    _say("precision stress: runs in precision %d (mismatch estimates %.2e plain, %.2e centred)" %
+         (used, est, est_c))
     mp.shoot(i0, j0, ni, nj)
     counts, n_out, _ = mp.counts()
     ref, ref_out = orc.shoot(i0, j0, ni, nj, nthreads=NTHREADS)
@@ -270,8 +305,9 @@ def test_default_precision_choice_on_the_workloads():
         w = inputs.WORKLOADS[kind]()
         g, mp, _ = _pair(w)
         assert g.precision == lm.LM_PREC_AUTO
-        used, est = mp.precision()
-        _say("%s: precision %d, FP32 mismatch estimate %.2e" % (kind, used, est))
+        used, est, est_c = mp.precision()
+        _say("%s: precision %d, mismatch estimates %.2e plain, %.2e centred" %
+             (kind, used, est, est_c))
         assert used == lm.LM_PREC_MIXED and 0.0 <= est <= 5e-6
         mp.close()
 
