@@ -203,23 +203,58 @@ static void far_coeffs(const lmo_params *p, const lmo_lenses *L, const unsigned 
     free(im);
 }
 
+/* Centre Z of the hierarchical expansion that serves level-2 cell (ci,cj).
+ * Normally the centre of its level-1 cell (I,J).  A level-1 cell whose sides
+ * L1x = Kx R L3x and L1y = Ky R L3y differ is cut along its longer side into
+ * n = round(long / short) boxes of b = ceil(K / n) level-2 cells (the last one
+ * may be narrower), and Z is the centre of the box holding the level-2 cell:
+ * a single series about the centre of an elongated cell would not converge
+ * at the cell's far ends, while a near-square box keeps the convergence ratio
+ * of a square cell.  The far set stays that of the level-1 cell. */
+static void far_centre(const lmo_params *p, int64_t ci, int64_t cj, double *Zx, double *Zy)
+{
+    int64_t Kx = p->l1_kx, Ky = p->l1_ky;
+    int64_t I = floor_div_i64(ci, Kx), J = floor_div_i64(cj, Ky);
+    double l1x = (double)(Kx * p->coarse) * p->ray_dx, l1y = (double)(Ky * p->coarse) * p->ray_dy;
+    int64_t nx = 1, ny = 1;
+    if (l1x > l1y) nx = (int64_t)floor(l1x / l1y + 0.5);
+    if (l1y > l1x) ny = (int64_t)floor(l1y / l1x + 0.5);
+    if (nx < 1) nx = 1;
+    if (ny < 1) ny = 1;
+    if (nx == 1) {
+        *Zx = p->ray_x0 + ((double)I + 0.5) * (double)(Kx * p->coarse) * p->ray_dx;
+    } else {
+        int64_t b = (Kx + nx - 1) / nx;
+        int64_t c0 = I * Kx + ((ci - I * Kx) / b) * b;
+        int64_t c1 = c0 + b < (I + 1) * Kx ? c0 + b : (I + 1) * Kx;
+        *Zx = p->ray_x0 + 0.5 * (double)(c0 + c1) * (double)p->coarse * p->ray_dx;
+    }
+    if (ny == 1) {
+        *Zy = p->ray_y0 + ((double)J + 0.5) * (double)(Ky * p->coarse) * p->ray_dy;
+    } else {
+        int64_t b = (Ky + ny - 1) / ny;
+        int64_t r0 = J * Ky + ((cj - J * Ky) / b) * b;
+        int64_t r1 = r0 + b < (J + 1) * Ky ? r0 + b : (J + 1) * Ky;
+        *Zy = p->ray_y0 + 0.5 * (double)(r0 + r1) * (double)p->coarse * p->ray_dy;
+    }
+}
+
 /* Hierarchical far field: the far set of level-2 cell (ci,cj) is the far set
  * of its level-1 cell (I,J) (Sec. 3.2.1), so its Taylor series about the
- * level-2 centre z_c (Sec. 3.2.2) can be obtained from one series about the
- * level-1 centre Z, truncated after Q terms:
+ * level-2 centre z_c (Sec. 3.2.2) can be obtained from one series about a
+ * centre Z of the level-1 cell (far_centre), truncated after Q terms:
  *   A_n = - sum_{k far} m_k / (z_k - Z)^{n+1},                n < Q,
  *   a_p = sum_{n=p}^{Q-1} C(n,p) A_n (z_c - Z)^{n-p},           p < P,
  * which is the re-expansion of sum_n A_n (z - Z)^n about z_c.  Far lenses lie
  * outside the (2H+1)^2 block of level-1 cells, so |z_c - Z| / |z_k - Z| stays
- * below about 0.47 for square level-1 cells and the truncation error falls
- * geometrically with Q. */
+ * below about 0.47 for square level-1 cells and square boxes of elongated ones,
+ * and the truncation error falls geometrically with Q. */
 static void far_coeffs_hier(const lmo_params *p, const lmo_lenses *L, const unsigned char *near,
                             int64_t ci, int64_t cj, double *a)
 {
     int64_t Q = p->far_order, P = p->terms;
-    int64_t I = floor_div_i64(ci, p->l1_kx), J = floor_div_i64(cj, p->l1_ky);
-    double Zx = p->ray_x0 + ((double)I + 0.5) * (double)(p->l1_kx * p->coarse) * p->ray_dx;
-    double Zy = p->ray_y0 + ((double)J + 0.5) * (double)(p->l1_ky * p->coarse) * p->ray_dy;
+    double Zx, Zy;
+    far_centre(p, ci, cj, &Zx, &Zy);
     double zx, zy;
     cell_centre(p, ci, cj, &zx, &zy);
     /* level-1 expansion */

@@ -33,10 +33,14 @@ MUTATIONS = {
                               "binom = 1.0;"),
     "hier_shift_reversed": ("double sx = zx - Zx, sy = zy - Zy;",
                             "double sx = Zx - zx, sy = Zy - zy;"),
-    "hier_level1_centre_offset": ("double Zx = p->ray_x0 + ((double)I + 0.5)",
-                                  "double Zx = p->ray_x0 + ((double)I + 0.0)"),
+    "hier_level1_centre_offset": ("*Zx = p->ray_x0 + ((double)I + 0.5)",
+                                  "*Zx = p->ray_x0 + ((double)I + 0.0)"),
     "hier_series_truncated_early": ("for (int64_t n = q; n < Q; ++n) {",
                                     "for (int64_t n = q; n < Q - 1; ++n) {"),
+    "hier_box_width_floor": ("int64_t b = (Kx + nx - 1) / nx;", "int64_t b = Kx / nx;"),
+    "hier_box_centre_at_start": ("0.5 * (double)(c0 + c1)", "((double)c0 + 0.5)"),
+    "hier_elongated_not_split": ("if (l1x > l1y) nx = (int64_t)floor(l1x / l1y + 0.5);",
+                                 "if (l1x > l1y) nx = 1;"),
 }
 
 # slips in the analysis scales (Eq. 13-15 and the s_f definition)
