@@ -156,12 +156,15 @@ lm_status lm_geometry_derive_fold(lm_geometry* g, double src_lx, double src_ly, 
 
 /*
  * Opt a geometry into the hierarchical far field (an extension of the level-2
- * Taylor coefficients of Sec. 3.2.2): set g->far_order to the
- * smallest Q in [taylor_terms, 64] for which the level-1 series meets its
- * truncation bound on this geometry (rho^Q / (1 - rho) <= 1e-9, rho the
- * largest ratio of a level-2 centre's and a far lens's distances from their
- * level-1 centre).  LM_EUNSUPPORTED, far_order left at 0, when no Q does
- * (level-1 cells too elongated) or for the direct scheme or LM_PREC_FP32.
+ * Taylor coefficients of Sec. 3.2.2): set g->far_order to the smallest Q in
+ * [taylor_terms, 64] for which the series meets its truncation bound on this
+ * geometry (rho^Q / (1 - rho) <= 1e-9, rho the largest ratio of a level-2
+ * centre's and a far lens's distances from the series centre).  The series of
+ * a level-1 cell is taken about the centre of the cell, or, when its sides
+ * differ, about the centres of near-square boxes that cut it along its longer
+ * side (round(long / short) boxes of ceil(K / boxes) level-2 cells), so that
+ * elongated cells converge too.  LM_EUNSUPPORTED, far_order left at 0, when no
+ * Q does, or for the direct scheme or LM_PREC_FP32.
  */
 lm_status lm_geometry_far_order(lm_geometry* g);
 

@@ -88,15 +88,48 @@ struct DevBuf {
     T* as() const { return static_cast<T*>(p); }
 };
 
+// Boxes of the hierarchical far field: a level-1 cell whose sides differ is
+// cut along its longer side into n = round(long / short) near-square boxes of
+// b = ceil(K / n) level-2 cells (the last one may be narrower), each with its
+// own series about its centre; a square-ish cell is one box.
+struct FarBoxes {
+    int nx = 1, ny = 1, bx = 1, by = 1;
+};
+
+FarBoxes far_boxes(const lm_geometry& g)
+{
+    FarBoxes f;
+    const double l1x = (double)((int64_t)g.l1_kx * g.coarse) * g.ray_dx;
+    const double l1y = (double)((int64_t)g.l1_ky * g.coarse) * g.ray_dy;
+    if (l1x > l1y) f.nx = (int)std::max<int64_t>(1, round_half_away(l1x / l1y));
+    if (l1y > l1x) f.ny = (int)std::max<int64_t>(1, round_half_away(l1y / l1x));
+    f.nx = std::min(f.nx, g.l1_kx);
+    f.ny = std::min(f.ny, g.l1_ky);
+    f.bx = (int)ceil_div(g.l1_kx, f.nx);
+    f.by = (int)ceil_div(g.l1_ky, f.ny);
+    return f;
+}
+
 // Largest ratio |z_c - Z| / |z_k - Z| of the hierarchical far field: level-2
-// centres lie within ((Kx-1)/2 L2x, (Ky-1)/2 L2y) of their level-1 centre Z,
-// far lenses at least (H + 1/2) min(L1x, L1y) from it.
+// centres lie within ((b-1)/2 L2x, (b'-1)/2 L2y) of their box centre Z, far
+// lenses outside the (2H+1)^2 block of level-1 cells, at least H L1 + b L2 / 2
+// from Z along each axis; the largest over full and narrower last boxes.
 double far_ratio(const lm_geometry& g)
 {
     const double l2x = (double)g.coarse * g.ray_dx, l2y = (double)g.coarse * g.ray_dy;
-    const double wx = 0.5 * (g.l1_kx - 1) * l2x, wy = 0.5 * (g.l1_ky - 1) * l2y;
-    const double umin = (g.near_halo + 0.5) * std::min(g.l1_kx * l2x, g.l1_ky * l2y);
-    return std::sqrt(wx * wx + wy * wy) / umin;
+    const double l1x = g.l1_kx * l2x, l1y = g.l1_ky * l2y;
+    const FarBoxes f = far_boxes(g);
+    const int lastx = g.l1_kx - (f.nx - 1) * f.bx, lasty = g.l1_ky - (f.ny - 1) * f.by;
+    double rho = 0.0;
+    for (int wx : {f.bx, lastx})
+        for (int wy : {f.by, lasty}) {
+            if (wx < 1 || wy < 1) continue;
+            const double hx = 0.5 * (wx - 1) * l2x, hy = 0.5 * (wy - 1) * l2y;
+            const double umin = std::min(g.near_halo * l1x + 0.5 * wx * l2x,
+                                         g.near_halo * l1y + 0.5 * wy * l2y);
+            rho = std::max(rho, std::sqrt(hx * hx + hy * hy) / umin);
+        }
+    return rho;
 }
 
 lm_status validate_geometry(const lm_geometry* g)
@@ -360,6 +393,13 @@ LmDesc make_desc(const lm_map* m, int64_t i0, int64_t j0, int64_t i1, int64_t j1
     d.ptab = m->ptab.as<float>();
     d.Q = g.scheme == LM_SCHEME_INTERP ? g.far_order : 0;
     d.n1x = m->n1x;
+    {
+        const FarBoxes f = far_boxes(g);
+        d.nbx = f.nx;
+        d.nby = f.ny;
+        d.bx = f.bx;
+        d.by = f.by;
+    }
     d.n1y = m->n1y;
     d.l1exp = m->l1exp.as<double>();
     d.counts = reinterpret_cast<unsigned long long*>(m->counts);
@@ -374,7 +414,8 @@ lm_status ensure_coef(lm_map* m)
         return fail(LM_ENOMEM, "cannot allocate %lld level-2 coefficient records",
                     (long long)(m->ncx * m->ncy));
     if (m->g.far_order > 0 &&
-        m->l1exp.ensure((size_t)(m->n1x * m->n1y) * m->g.far_order * 16) != hipSuccess)
+        m->l1exp.ensure((size_t)(m->n1x * m->n1y) * far_boxes(m->g).nx * far_boxes(m->g).ny *
+                        m->g.far_order * 16) != hipSuccess)
         return fail(LM_ENOMEM, "cannot allocate the level-1 series");
     return LM_OK;
 }

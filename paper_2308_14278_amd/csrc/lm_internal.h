@@ -77,6 +77,8 @@ struct LmDesc {
     int32_t snx, sny;
     int32_t fold;                  // 1: fold macro model
     int32_t Q;                     // terms of the level-1 series (0: direct coefficients)
+    int32_t nbx, nby;              // boxes of the level-1 series per level-1 cell side
+    int32_t bx, by;                // level-2 cells per box side (the last box may be narrower)
     // scheme and work decomposition
     int32_t R, Kx, Ky, H;
     int32_t G;                     // level-2 cells per workgroup-tile side
@@ -106,7 +108,7 @@ struct LmDesc {
     const LmCoef* coef;            // [ncy][ncx]
     const float* ptab;             // [LM_PTAB_POW][R + LM_PTAB_PAD] column offsets of a
                                    // level-2 cell and their powers
-    double* l1exp;                 // [n1y][n1x][Q] level-1 series, complex (re, im)
+    double* l1exp;                 // [n1y nby][n1x nbx][Q] level-1 series per box, complex
     unsigned long long* counts;    // [sny][snx]
     unsigned long long* n_out;
 };

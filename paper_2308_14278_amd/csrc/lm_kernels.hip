@@ -130,19 +130,44 @@ __global__ void k_ptab(LmDesc d, float* __restrict__ out, int n)
     }
 }
 
+// Centre of box (sx, sy) of level-1 cell (I, J) of the hierarchical far
+// field: the level-1 cell's centre when it is one box along that axis, else
+// the centre of the box's level-2 cells (boxes of d.bx x d.by cells, the last
+// one narrower).
+__device__ __forceinline__ void box_centre(const LmDesc& d, int64_t I, int64_t J, int sx, int sy,
+                                           double& Zx, double& Zy)
+{
+    if (d.nbx == 1) {
+        Zx = d.x0 + ((double)I + 0.5) * (double)((int64_t)d.Kx * d.R) * d.dx;
+    } else {
+        const int64_t c0 = I * d.Kx + (int64_t)sx * d.bx;
+        const int64_t c1 = min(c0 + d.bx, (I + 1) * d.Kx);
+        Zx = d.x0 + 0.5 * (double)(c0 + c1) * (double)d.R * d.dx;
+    }
+    if (d.nby == 1) {
+        Zy = d.y0 + ((double)J + 0.5) * (double)((int64_t)d.Ky * d.R) * d.dy;
+    } else {
+        const int64_t r0 = J * d.Ky + (int64_t)sy * d.by;
+        const int64_t r1 = min(r0 + d.by, (J + 1) * d.Ky);
+        Zy = d.y0 + 0.5 * (double)(r0 + r1) * (double)d.R * d.dy;
+    }
+}
+
 // Hierarchical far field, step 1: the series of the far lenses of level-1 cell
-// (I, J) about its centre Z, A_n = -sum_far m_k / (z_k - Z)^(n+1), n < Q <= 64
-// (the level-2 series of Sec. 3.2.2 taken one level up).  One workgroup per
-// level-1 cell; thread t sums terms 8 s .. 8 s + 7 (s = t mod 8) over every
-// 32nd far lens, then threads n < Q add the 32 partial sums in a fixed order.
+// (I, J) about the centre Z of one of its boxes, A_n = -sum_far m_k / (z_k -
+// Z)^(n+1), n < Q <= 64 (the level-2 series of Sec. 3.2.2 taken one level up).
+// One workgroup per box; thread t sums terms 8 s .. 8 s + 7 (s = t mod 8) over
+// every 32nd far lens, then threads n < Q add the 32 partial sums in a fixed
+// order.
 __global__ __launch_bounds__(kWG) void k_l1_expand(LmDesc d)
 {
     __shared__ double2 part[32][64];
     const int tid = threadIdx.x, s = tid & 7, grp = tid >> 3;
-    const int64_t cell = blockIdx.x;
-    const int64_t I = cell % d.n1x, J = cell / d.n1x;
-    const double Zx = d.x0 + ((double)I + 0.5) * (double)((int64_t)d.Kx * d.R) * d.dx;
-    const double Zy = d.y0 + ((double)J + 0.5) * (double)((int64_t)d.Ky * d.R) * d.dy;
+    const int64_t cell = blockIdx.x;  // the box: row-major over [n1y nby][n1x nbx]
+    const int64_t bi = cell % (d.n1x * d.nbx), bj = cell / (d.n1x * d.nbx);
+    const int64_t I = bi / d.nbx, J = bj / d.nby;
+    double Zx, Zy;
+    box_centre(d, I, J, (int)(bi % d.nbx), (int)(bj % d.nby), Zx, Zy);
     double ar[8], ai[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -193,9 +218,10 @@ __global__ __launch_bounds__(kWG) void k_l1_expand(LmDesc d)
     }
 }
 
-// Hierarchical far field, step 2: the series of step 1 re-expanded about the
-// centre z_c of each level-2 cell, a_p = sum_{n>=p} C(n,p) A_n (z_c - Z)^(n-p),
-// with T_n[p] = C(n,p) w^(n-p) advanced by T_{n+1}[p] = w T_n[p] + T_n[p-1].
+// Hierarchical far field, step 2: the series of step 1 of the box holding each
+// level-2 cell re-expanded about the cell's centre z_c, a_p = sum_{n>=p}
+// C(n,p) A_n (z_c - Z)^(n-p), with T_n[p] = C(n,p) w^(n-p) advanced by
+// T_{n+1}[p] = w T_n[p] + T_n[p-1].
 template <int P>
 __global__ __launch_bounds__(kWG) void k_l1_shift(LmDesc d, LmCoef* __restrict__ out)
 {
@@ -203,8 +229,10 @@ __global__ __launch_bounds__(kWG) void k_l1_shift(LmDesc d, LmCoef* __restrict__
     if (c >= d.ncx * d.ncy) return;
     const int64_t ci = c % d.ncx, cj = c / d.ncx;
     const int64_t I = ci / d.Kx, J = cj / d.Ky;
-    const double Zx = d.x0 + ((double)I + 0.5) * (double)((int64_t)d.Kx * d.R) * d.dx;
-    const double Zy = d.y0 + ((double)J + 0.5) * (double)((int64_t)d.Ky * d.R) * d.dy;
+    const int sx = (int)((ci - I * d.Kx) / d.bx), sy = (int)((cj - J * d.Ky) / d.by);
+    double Zx, Zy;
+    box_centre(d, I, J, sx, sy, Zx, Zy);
+    const int64_t box = (J * d.nby + sy) * (d.n1x * d.nbx) + (I * d.nbx + sx);
     const double wx = cell_cx(d, ci) - Zx, wy = cell_cy(d, cj) - Zy;
     double tr[P], ti[P], ar[P], ai[P];
 #pragma unroll
@@ -214,7 +242,7 @@ __global__ __launch_bounds__(kWG) void k_l1_shift(LmDesc d, LmCoef* __restrict__
         ar[p] = 0.0;
         ai[p] = 0.0;
     }
-    const double* A = d.l1exp + 2 * ((J * d.n1x + I) * d.Q);
+    const double* A = d.l1exp + 2 * (box * d.Q);
     for (int n = 0; n < d.Q; ++n) {
         const double Ar = A[2 * n], Ai = A[2 * n + 1];
 #pragma unroll
@@ -361,7 +389,7 @@ int lm_launch_deflect(const LmDesc& d, int scheme, int precision, int terms, con
 
 int lm_launch_coeffs_hier(const LmDesc& d, int terms, LmCoef* out, void* stream)
 {
-    const int64_t n1 = d.n1x * d.n1y, n2 = d.ncx * d.ncy;
+    const int64_t n1 = d.n1x * d.nbx * d.n1y * d.nby, n2 = d.ncx * d.ncy;
     if (n1 <= 0 || n2 <= 0) return 0;
     if (d.Q < terms || d.Q > 64) return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;

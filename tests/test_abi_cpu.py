@@ -134,9 +134,24 @@ def test_far_order_choice():
         (g.near_halo + 0.5) * min(g.l1_kx * l2x, g.l1_ky * l2y))
     assert 0.4 < rho < 0.5 and q == g.far_order
     assert rho ** q / (1 - rho) <= 1e-9 < rho ** (q - 1) / (1 - rho)
-    # elongated level-1 cells: no order converges
+    # elongated level-1 cells: about the cell centre no order converges; cut
+    # into round(long / short) boxes of ceil(K / boxes) level-2 cells (the last
+    # narrower), the ratio is that of the worst box
     g2 = lm.lm_geometry_derive(20, 20, 200, 200, 0.45, 0.5, 0.01, n_rays=1e9, scheme=1)
-    assert lm.lm_geometry_far_order(g2) == 0 and g2.far_order == 0
+    l2x, l2y = g2.coarse * g2.ray_dx, g2.coarse * g2.ray_dy
+    l1x, l1y = g2.l1_kx * l2x, g2.l1_ky * l2y
+    H = g2.near_halo
+    assert math.hypot(0.5 * (g2.l1_kx - 1) * l2x, 0.5 * (g2.l1_ky - 1) * l2y) / (
+        (H + 0.5) * min(l1x, l1y)) > 1.0
+    assert l1x > 1.5 * l1y
+    nb = min(g2.l1_kx, max(1, math.floor(l1x / l1y + 0.5)))
+    b = -(-g2.l1_kx // nb)
+    widths = {b, g2.l1_kx - (nb - 1) * b}
+    rho2 = max(math.hypot(0.5 * (wx - 1) * l2x, 0.5 * (g2.l1_ky - 1) * l2y) /
+               min(H * l1x + 0.5 * wx * l2x, H * l1y + 0.5 * g2.l1_ky * l2y) for wx in widths)
+    q2 = lm.lm_geometry_far_order(g2)
+    assert rho2 < 0.5 and q2 == g2.far_order > 0
+    assert rho2 ** q2 / (1 - rho2) <= 1e-9 < rho2 ** (q2 - 1) / (1 - rho2)
 
 
 def test_null_handles_are_rejected(lib):

@@ -137,3 +137,39 @@ def test_hierarchical_batch_equals_per_map():
     lm.lm_batch_destroy(b)
     for mp in maps:
         mp.close()
+
+
+def test_elongated_level1_cells_use_boxes():
+    """Near-fold map with level-1 cells made 6x longer than wide: a single
+    series per cell would not converge (lm_geometry_far_order refuses that
+    for the cell centre), the library cuts each cell into near-square boxes;
+    coefficients against the oracle's box expansion, and a map region against
+    the oracle."""
+    w = inputs.near_fold()
+    g = _geom(w)
+    g.l1_kx = max(1, round(6 * g.l1_ky * g.ray_dy / g.ray_dx))
+    assert lm.lm_geometry_far_order(g) > 0
+    print("level-1 cells %d x %d level-2 cells, far_order %d" % (g.l1_kx, g.l1_ky, g.far_order))
+    x, y, m = w.lenses()
+    mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, (x, y, m))
+    orc = oracle.Oracle(oracle_geom(g), w.kappa, w.gamma, w.kappa_star, x, y, m)
+    rng = np.random.default_rng(41)
+    ncx, ncy = -(-g.ray_nx // g.coarse), -(-g.ray_ny // g.coarse)
+    worst0 = 0.0
+    for _ in range(12):
+        ci, cj = int(rng.integers(ncx)), int(rng.integers(ncy))
+        got = lm.lm_read_coeffs(mp.h, ci, cj, g.taylor_terms)
+        ref = orc.coeffs(ci, cj)
+        worst0 = max(worst0, abs(got[0] - ref[0]) / abs(ref[0]))
+        rel = np.abs(got[1:] - ref[1:]) / np.maximum(np.abs(ref[1:]), 1e-30)
+        assert rel.max() <= 2e-7
+    assert worst0 <= 1e-12
+    i0, j0, ni, nj = 700_011, 20_033, 3_001, 1_500
+    mp.shoot(i0, j0, ni, nj)
+    counts, n_out, _ = mp.counts()
+    ref, ref_out = orc.shoot(i0, j0, ni, nj, nthreads=NTHREADS)
+    mis = mismatch_fraction(counts, ref, ni * nj)
+    print("elongated level-1 cells: a_0 rel err %.2e, map mismatch %.2e" % (worst0, mis))
+    assert int(counts.sum()) + n_out == ni * nj
+    assert mis <= 1e-5 and max_pixel_rel(counts, ref) <= 1e-3
+    mp.close()
