@@ -205,6 +205,59 @@ def precision_stress_leg(lm, inputs):
     return out
 
 
+def table1_window_leg(lm, inputs, precisions):
+    """The paper's Table 1 map against the FP64 oracle on an 8e8-ray window of
+    its lattice near the critical line (400000 x 2000 rays): the bin mismatch
+    of every near-sum precision the Table 1 leg shot, the library's default
+    (LM_PREC_AUTO) included."""
+    import numpy as np
+
+    import oracle
+    from oracle.geometry import OracleGeometry
+    w = inputs.paper_table1()
+    k0, dx, _ = w.fold
+    out = {}
+    win = None
+    for prec in precisions:
+        g = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], w.src_pixels,
+                                       w.extra["src_ny"], k0, dx, w.kappa_star, n_rays=w.n_rays)
+        g.precision = prec
+        lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
+        ni, nj = 400_000, 2000
+        i0, j0 = g.ray_nx // 2 + 1000, g.ray_ny // 2
+        if win is None:
+            og = OracleGeometry(**{k: getattr(g, k) for k in
+                                   ("src_x0", "src_y0", "src_dx", "src_dy", "src_nx", "src_ny",
+                                    "ray_x0", "ray_y0", "ray_dx", "ray_dy", "ray_nx", "ray_ny",
+                                    "scheme", "coarse", "l1_kx", "l1_ky")},
+                                halo=g.near_halo, terms=g.taylor_terms, far_order=g.far_order)
+            orc = oracle.Oracle(og, 0.0, 0.0, w.kappa_star, *lenses, fold=w.fold)
+            _, pix = orc.trace(np.array([i0, i0 + ni - 1, i0, i0 + ni - 1]),
+                               np.array([j0, j0, j0 + nj - 1, j0 + nj - 1]))
+            ps = [int(v % g.src_nx) for v in pix if v >= 0]
+            qs = [int(v // g.src_nx) for v in pix if v >= 0]
+            p0, q0 = max(0, min(ps) - 400), max(0, min(qs) - 400)
+            np_ = min(g.src_nx - p0, max(ps) - p0 + 400)
+            nq = min(g.src_ny - q0, max(qs) - q0 + 400)
+            t0 = time.perf_counter()
+            ref, _ = orc.shoot_window(i0, j0, ni, nj, p0, q0, np_, nq)
+            log("Table 1 window: oracle %d rays in %.1f s" % (ni * nj, time.perf_counter() - t0))
+            win = (p0, q0, np_, nq)
+        mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold)
+        used, est, est_c = mp.precision()
+        mp.shoot(i0, j0, ni, nj)
+        got = lm.lm_read_counts_region(mp.h, *win)
+        mp.close()
+        mis = 0.5 * float(np.abs(got.astype(np.int64) - ref.astype(np.int64)).sum()) / (ni * nj)
+        name = {lm.LM_PREC_MIXED_FP64: "fp64-near", lm.LM_PREC_MIXED: "mixed",
+                lm.LM_PREC_MIXED_CENTRED: "centred", lm.LM_PREC_AUTO: "auto"}[prec]
+        out[name] = {"precision_used": used, "bin_mismatch": mis,
+                     "fp32_mismatch_estimate": est, "centred_fp32_mismatch_estimate": est_c}
+        log("Table 1 window %s (precision %d): mismatch %.3g" % (name, used, mis))
+    out["sample"] = "%d x %d rays of the 2.69e13-ray lattice beside the critical line" % (ni, nj)
+    return out
+
+
 def batched_study(lm, inputs, torch, scale, hierarchical=False):
     """The 80-map study at a fraction of its rays: one batch (coefficients of
     every map, one persistent shooting kernel over all maps' tiles), then ten
@@ -446,7 +499,9 @@ def main():
                     default="none",
                     help="also shoot the paper's own Table 1 map (2.69e13 rays, 215 GB map) once "
                          "per chosen precision (auto: the library's choice; both: FP32 and FP64 "
-                         "near sums; side measurement, about a minute each)")
+                         "near sums; all: the library's choice and the three forms; side "
+                         "measurement, about a minute each), and with the CPU baseline compare "
+                         "an 8e8-ray window of it with the oracle")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM "
                          "byte counters) and exit")
@@ -592,17 +647,20 @@ def main():
         line["batched_study"] = study
     if args.fold_maps > 0:
         line["fold_peak_statistics"] = fold_study_leg(lm, inputs, torch, args.fold_maps)
+    precs = []
     if args.paper_map != "none":
         precs = {"auto": [lm.LM_PREC_AUTO], "mixed": [lm.LM_PREC_MIXED],
                  "centred": [lm.LM_PREC_MIXED_CENTRED], "fp64": [lm.LM_PREC_MIXED_FP64],
                  "both": [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64],
-                 "all": [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_CENTRED,
+                 "all": [lm.LM_PREC_AUTO, lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_CENTRED,
                          lm.LM_PREC_MIXED_FP64]}[args.paper_map]
         line["paper_table1_map"] = [paper_table1_leg(lm, inputs, torch, pr) for pr in precs]
     if not args.no_cpu_baseline:
         cb, errors = cpu_baseline_leg(lm, w, g, lenses, mp, mp32, args.cpu_seconds)
         line["cpu_baseline"] = cb
         errors["precision_stress"] = precision_stress_leg(lm, inputs)
+        if precs:
+            errors["paper_table1_window"] = table1_window_leg(lm, inputs, precs)
         line["map_error_vs_fp64"] = errors
     lm.lm_batch_destroy(b)
     mp.close()

@@ -60,6 +60,27 @@ ANALYSIS_MUTATIONS = {
 }
 
 
+# slips in the peak finder and the statistics by distance (Sec. 4.2)
+PEAK_MUTATIONS = {
+    "peaks.py": {
+        "threshold_k_not_squared": ("t * t > 3 * k * k * s", "t * t > 3 * k * s"),
+        "neighbour_ge": ("if not (n > a and n > b):", "if not (n >= a and n >= b):"),
+        "one_sided_cross_validation": ("if left and right:", "if left or right:"),
+        "cross_validation_window_narrow": ("for d in (-1, 0, 1))\n                    right",
+                                           "for d in (0,))\n                    right"),
+    },
+    "peak_stats.py": {
+        "column_centre_offset_dropped": ("centre = src_x0 + (float(p) + 0.5) * src_dx",
+                                         "centre = src_x0 + float(p) * src_dx"),
+        "bin_upper_edge_closed": ("edges[b] <= centre < edges[b + 1]",
+                                  "edges[b] <= centre <= edges[b + 1]"),
+        "candidates_counted_as_peaks": ("if flags[t][p] & TRUE_PEAK:", "if flags[t][p]:"),
+        "height_of_wrong_row": ("heights[b] += int(counts[i][p])",
+                                "heights[b] += int(counts[t][p])"),
+    },
+}
+
+
 def _copy_tree(tmp_path):
     d = tmp_path / "copy"
     shutil.copytree(os.path.join(ROOT, "oracle"), d / "oracle",
@@ -100,4 +121,14 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     _plant(d, "lensoracle.c", *MUTATIONS[name])
     failed, out = _pins_fail(d, ["tests/test_oracle_pins.py", "tests/test_oracle_fold.py",
                                  "tests/test_oracle_hier.py"])
+    assert failed, "planted mistake %r was not caught:\n%s" % (name, out)
+
+
+@pytest.mark.parametrize("name", sorted("%s:%s" % (f, n) for f in PEAK_MUTATIONS
+                                        for n in PEAK_MUTATIONS[f]))
+def test_peak_pins_catch_planted_mistake(name, tmp_path):
+    rel, key = name.split(":")
+    d = _copy_tree(tmp_path)
+    _plant(d, rel, *PEAK_MUTATIONS[rel][key])
+    failed, out = _pins_fail(d, ["tests/test_oracle_peaks.py"])
     assert failed, "planted mistake %r was not caught:\n%s" % (name, out)
