@@ -292,6 +292,10 @@ def batched_study(lm, inputs, torch, scale, hierarchical=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     c_ms, s_ms = lm.lm_batch_timing(b)
+    precisions = {}
+    for m in maps:
+        used = m.precision()[0]
+        precisions[str(used)] = precisions.get(str(used), 0) + 1
     t1 = time.perf_counter()
     n_cand = n_true = 0
     for m, g in zip(maps, geoms):
@@ -316,7 +320,8 @@ def batched_study(lm, inputs, torch, scale, hierarchical=False):
             "coefficients_ms": c_ms, "shoot_kernel_ms": s_ms,
             "shoot_algorithmic_tflops": shoot_tflops,
             "shoot_frac_of_fp32_peak": shoot_tflops / PEAK_FP32_TFLOPS,
-            "rays_scale": scale, "light_curves": 800, "candidate_peaks": n_cand,
+            "rays_scale": scale, "maps_per_precision": precisions,
+            "light_curves": 800, "candidate_peaks": n_cand,
             "true_peaks": n_true, "peak_finding_s": dt_peaks,
             "far_field": ("hierarchical for %d maps, direct for %d" % (n_hier, 80 - n_hier)
                           if hierarchical else "direct (Sec. 3.2.2) for all maps")}
@@ -331,7 +336,9 @@ def fold_study_leg(lm, inputs, torch, n_maps=80):
     """The statistics of Sec. 4.2 (Figs. 4 and 5) on n_maps independent fold
     maps with the physics of Table 1 (inputs.fold_study: 40 theta_E across the
     caustic and 40 along it, 0.011 theta_E pixels, 1000 rays per pixel): one
-    batch shoots every map, then ten light curves per map cross the caustic
+    batch shoots every map (far field from the hierarchical series, which
+    converges for these elongated level-1 cells through their near-square
+    boxes), then ten light curves per map cross the caustic
     (map rows) and the library finds their true peaks and bins them by
     distance to the caustic on the GPU.  Reported: the true-peak number density
     per unit length of light curve, in units of s_f and divided by N_cf of
@@ -349,6 +356,7 @@ def fold_study_leg(lm, inputs, torch, n_maps=80):
         k0, dx, _ = w.fold
         g = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], w.src_pixels,
                                        w.extra["src_ny"], k0, dx, w.kappa_star, n_rays=w.n_rays)
+        lm.lm_geometry_far_order(g)  # hierarchical far field where it converges
         lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
         maps.append(lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold))
         geoms.append(g)
@@ -396,6 +404,7 @@ def fold_study_leg(lm, inputs, torch, n_maps=80):
     return {"maps": len(maps), "rays": rays, "seconds": dt, "rays_per_s": rays / dt,
             "shoot_kernel_ms": s_ms, "coefficients_ms": c_ms, "setup_s": t_setup,
             "light_curves": 10 * len(maps), "true_peaks": int(pk.sum()),
+            "far_field_orders": sorted({int(g.far_order) for g in geoms}),
             "scales": {"s_f": sf, "s_w": sw, "n_cf": sc["n_cf"], "mu_peak0": sc["mu_peak0"],
                        "kappa_c": sc["kappa_c"], "ds_over_r": dsr},
             "density_vs_beta_over_s_f": {

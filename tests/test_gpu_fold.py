@@ -23,10 +23,13 @@ def _gpu():
     oracle.build()
 
 
-def _small_fold(n_rays=4e7, precision=lm.LM_PREC_MIXED):
+def _small_fold(n_rays=4e7, precision=lm.LM_PREC_MIXED, hierarchical=False):
     k0, dx, dy, ks = 0.83, 2.0e-3, -1.5e-3, 0.01
     g = lm.lm_geometry_derive_fold(4.0, 4.0, 400, 400, k0, dx, ks, n_rays=n_rays, coarse=64)
     g.precision = precision
+    if hierarchical:
+        # level-1 cells of 36 x 3 level-2 cells: twelve boxes each
+        assert lm.lm_geometry_far_order(g) > 0 and g.l1_kx >= 4 * g.l1_ky
     hx, hy = g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2
     n = int(round(4 * hx * hy * ks / math.pi))
     rng = np.random.default_rng(31)
@@ -37,9 +40,14 @@ def _small_fold(n_rays=4e7, precision=lm.LM_PREC_MIXED):
     return g, mp, orc
 
 
-@pytest.mark.parametrize("precision", [lm.LM_PREC_MIXED, lm.LM_PREC_MIXED_FP64])
-def test_fold_map_vs_oracle(precision):
-    g, mp, orc = _small_fold(precision=precision)
+@pytest.mark.parametrize("precision,hierarchical", [(lm.LM_PREC_MIXED, False),
+                                                    (lm.LM_PREC_MIXED_FP64, False),
+                                                    (lm.LM_PREC_AUTO, True)])
+def test_fold_map_vs_oracle(precision, hierarchical):
+    """A small fold map against the oracle; the last case takes its far field
+    from the near-square boxes of strongly elongated level-1 cells, on both
+    sides."""
+    g, mp, orc = _small_fold(precision=precision, hierarchical=hierarchical)
     mp.shoot()
     counts, n_out, n_shot = mp.counts()
     ref, ref_out = orc.shoot(nthreads=NTHREADS)
