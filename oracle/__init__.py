@@ -55,6 +55,8 @@ class _Params(ctypes.Structure):
         ("halo", ctypes.c_int64), ("terms", ctypes.c_int64),
         ("macro", ctypes.c_int64), ("d_x", ctypes.c_double), ("d_y", ctypes.c_double),
         ("far_order", ctypes.c_int64),
+        ("sheet", ctypes.c_int64), ("sx0", ctypes.c_double), ("sx1", ctypes.c_double),
+        ("sy0", ctypes.c_double), ("sy1", ctypes.c_double),
     ]
 
 
@@ -89,6 +91,8 @@ def _load():
         lib.lmo_mu_factor.argtypes = [pp]
         lib.lmo_mu_factor.restype = ctypes.c_double
         lib.lmo_num_threads.restype = ctypes.c_int
+        lib.lmo_sheet.argtypes = [pp, _d, ctypes.c_int64, _d]
+        lib.lmo_sheet.restype = ctypes.c_int
         for f in (lib.lmo_deflect_direct, lib.lmo_coeffs, lib.lmo_near_mask, lib.lmo_deflect,
                   lib.lmo_trace, lib.lmo_shoot):
             f.restype = ctypes.c_int
@@ -111,9 +115,11 @@ class Oracle:
     Lenses are copied to contiguous float64 arrays.
     """
 
-    def __init__(self, geom, kappa, gamma, kappa_star, lx, ly, lm, fold=None):
+    def __init__(self, geom, kappa, gamma, kappa_star, lx, ly, lm, fold=None, sheet=None):
         """fold=(kappa_0, d_x, d_y) selects the fold macro model of Eq. 5/6
-        (d in 1/theta_E); kappa and gamma are then ignored."""
+        (d in 1/theta_E); kappa and gamma are then ignored.  sheet=(x0, x1, y0,
+        y1): the -kappa_star sheet covers that rectangle (the region of the
+        lenses); None: an infinite sheet about the origin."""
         self.geom = geom
         self.kappa, self.gamma, self.kappa_star = float(kappa), float(gamma), float(kappa_star)
         macro, dx, dy = 0, 0.0, 0.0
@@ -130,7 +136,8 @@ class Oracle:
             g.ray_x0, g.ray_y0, g.ray_dx, g.ray_dy, g.ray_nx, g.ray_ny,
             self.kappa, self.gamma, self.kappa_star,
             g.scheme, g.coarse, g.l1_kx, g.l1_ky, g.halo, g.terms, macro, dx, dy,
-            getattr(g, "far_order", 0))
+            getattr(g, "far_order", 0), 0 if sheet is None else 1,
+            *(float(v) for v in (sheet if sheet is not None else (0.0, 0.0, 0.0, 0.0))))
 
     @property
     def n(self):
@@ -147,6 +154,15 @@ class Oracle:
                                  _dp(out))
         if rc:
             raise RuntimeError("lmo_deflect failed (%d)" % rc)
+        return out
+
+    def sheet(self, theta):
+        """The sheet term s(theta) of the lens equation at positions theta[n,2]."""
+        th = _f64(theta).reshape(-1, 2)
+        out = np.empty_like(th)
+        rc = _load().lmo_sheet(ctypes.byref(self._p), _dp(th), th.shape[0], _dp(out))
+        if rc:
+            raise RuntimeError("lmo_sheet failed (%d)" % rc)
         return out
 
     def deflect_direct(self, theta):

@@ -12,14 +12,22 @@
  *  Lens equation with point-mass microlenses and a compensating negative mass
  *  sheet (Sec. 2, Eq. 6), with either macro model:
  *   linear (Eq. 1): beta = diag(1-kappa-gamma, 1-kappa+gamma) theta
- *                          + kappa_star theta - alpha(theta);
+ *                          + s(theta) - alpha(theta);
  *   fold (Eq. 5, 6): beta_x = (d_x theta_x / 2 + d_y theta_y) theta_x
- *                            + kappa_star theta_x - alpha_x,
- *                    beta_y = 2 (1 - kappa_0) theta_y + kappa_star theta_y - alpha_y,
+ *                            + s_x(theta) - alpha_x,
+ *                    beta_y = 2 (1 - kappa_0) theta_y + s_y(theta) - alpha_y,
  *  alpha(theta) = sum_k m_k (theta - theta_k) / |theta - theta_k|^2.
- *  The sheet of density -kappa_star is read as infinite and uniform about the
- *  coordinate origin, so its term is +kappa_star * theta.  In fold mode the
- *  kappa field holds kappa_0 and d = (d_x, d_y) is in units of 1/theta_E.
+ *  The sheet of density -kappa_star subtracts the microlenses' mean density
+ *  where they are (Sec. 2: the total density stays that of the smooth model),
+ *  so it covers the region of the microlenses.  Its term (sheet = 1) is the
+ *  deflection of a uniform density kappa_star on the rectangle
+ *  [sx0, sx1] x [sy0, sy1] that holds them,
+ *    s(theta) = (kappa_star / pi) int int (theta - t) / |theta - t|^2 d^2 t,
+ *  in closed form (rect_sheet below); for a region that is large and round
+ *  about theta this tends to kappa_star * theta, which is the term of an
+ *  infinite sheet about the coordinate origin (sheet = 0, also exact inside a
+ *  disk of lenses centred there).  In fold mode the kappa field holds kappa_0
+ *  and d = (d_x, d_y) is in units of 1/theta_E.
  *
  *  Ray lattice (Sec. 3.2, level-3 grid, Eq. 11): ray (i,j) sits at the centre
  *  of level-3 pixel (i,j): theta = (X0 + (i+1/2) L3x, Y0 + (j+1/2) L3y).
@@ -59,6 +67,8 @@
 #include <omp.h>
 #endif
 
+#define LMO_PI 3.14159265358979323846
+
 typedef struct {
     /* source map */
     double src_x0, src_y0, src_dx, src_dy;
@@ -76,6 +86,10 @@ typedef struct {
     /* far field: 0 direct per level-2 cell; Q > 0 through a Q-term expansion
      * per level-1 cell (hierarchical far field) */
     int64_t far_order;
+    /* the -kappa_star sheet: 0 infinite about the origin, 1 the rectangle
+     * [sx0, sx1] x [sy0, sy1] */
+    int64_t sheet;
+    double sx0, sx1, sy0, sy1;
 } lmo_params;
 
 typedef struct {
@@ -299,6 +313,8 @@ static void far_coeffs_hier(const lmo_params *p, const lmo_lenses *L, const unsi
 }
 
 /* Coefficients of level-2 cell (ci,cj) by the configured far-field method. */
+static void sheet_coeffs(const lmo_params *p, int64_t ci, int64_t cj, double *c);
+
 static void cell_coeffs(const lmo_params *p, const lmo_lenses *L, const unsigned char *near,
                         int64_t ci, int64_t cj, double *a)
 {
@@ -308,6 +324,14 @@ static void cell_coeffs(const lmo_params *p, const lmo_lenses *L, const unsigned
         double zx, zy;
         cell_centre(p, ci, cj, &zx, &zy);
         far_coeffs(p, L, near, zx, zy, a);
+    }
+    if (p->sheet == 1) {
+        /* the rectangle sheet's holomorphic part rides with the far field:
+         * the far term is subtracted in the lens equation and the sheet's is
+         * added */
+        double c[32];
+        sheet_coeffs(p, ci, cj, c);
+        for (int64_t n = 0; n < 2 * p->terms; ++n) a[n] -= c[n];
     }
 }
 
@@ -325,19 +349,127 @@ static void far_eval(int64_t P, const double *a, double dx, double dy, double *a
     *ay = -fy;
 }
 
+/* F(u, v) = u atan(v / u) + (v / 2) ln(u^2 + v^2), whose mixed derivative
+ * d2F / du dv is u / (u^2 + v^2); F -> 0 as u -> 0 in its first term and as
+ * (u, v) -> 0 in its second. */
+static double rect_prim(double u, double v)
+{
+    double r2 = u * u + v * v;
+    double a = (u != 0.0) ? u * atan(v / u) : 0.0;
+    double b = (r2 > 0.0) ? 0.5 * v * log(r2) : 0.0;
+    return a + b;
+}
+
+/* Deflection of a uniform density kappa on the rectangle [x0, x1] x [y0, y1]
+ * at theta = (tx, ty):
+ *   s_x = (kappa / pi) int_{x0}^{x1} int_{y0}^{y1} (tx - x) / ((tx - x)^2 + (ty - y)^2) dy dx,
+ * with u = tx - x, v = ty - y the double integral of u / (u^2 + v^2) over
+ * u in [tx - x1, tx - x0], v in [ty - y1, ty - y0], i.e. the double difference
+ * of F over the corners; s_y likewise with the roles of u and v exchanged. */
+static void rect_sheet(double kappa, double x0, double x1, double y0, double y1, double tx,
+                       double ty, double *sx, double *sy)
+{
+    double ua = tx - x1, ub = tx - x0, va = ty - y1, vb = ty - y0;
+    double fx = rect_prim(ub, vb) - rect_prim(ua, vb) - rect_prim(ub, va) + rect_prim(ua, va);
+    double fy = rect_prim(vb, ub) - rect_prim(va, ub) - rect_prim(vb, ua) + rect_prim(va, ua);
+    *sx = kappa / LMO_PI * fx;
+    *sy = kappa / LMO_PI * fy;
+}
+
+/* the sheet term s(theta) of the lens equation */
+static void sheet_term(const lmo_params *p, double tx, double ty, double *sx, double *sy)
+{
+    if (p->sheet == 1) {
+        rect_sheet(p->kappa_star, p->sx0, p->sx1, p->sy0, p->sy1, tx, ty, sx, sy);
+    } else {
+        *sx = p->kappa_star * tx;
+        *sy = p->kappa_star * ty;
+    }
+}
+
+/* Interpolated scheme with the rectangle sheet.  Inside the rectangle,
+ * s(theta) = kappa_star theta + h(theta) where conj(h) is holomorphic (the
+ * density is uniform, so s - kappa_star theta has no divergence and no curl);
+ * that part is carried by P Taylor coefficients per level-2 cell, like the far
+ * lenses.  The expansion point z_e is the centre of the part of the cell that
+ * lies in the ray lattice (the cell centre itself except in a partial last
+ * column or row).  About z_e the coefficients are
+ *   e_n = (1 / 2 pi i) oint conj(h)(z_e + w) w^-(n+1) dw
+ * on the circle |w| = r, r half the distance from z_e to the nearest edge of
+ * the rectangle (so the circle stays where the closed form is conj(h)); the
+ * trapezoid rule over M equally spaced points,
+ *   e_n = (1/M) sum_j conj(h)(z_e + w_j) w_j^-n,
+ * is exact to rounding for a function analytic on a larger disk.  The
+ * polynomial is then written about the cell centre z_c: with t = z_c - z_e,
+ * c_k = sum_{n>=k} C(n,k) e_n t^(n-k).  c holds (re, im) of c_0 .. c_{P-1}. */
+static void sheet_coeffs(const lmo_params *p, int64_t ci, int64_t cj, double *c)
+{
+    const int64_t P = p->terms;
+    const int M = 64;
+    double zx, zy;
+    cell_centre(p, ci, cj, &zx, &zy);
+    int64_t i1 = (ci + 1) * p->coarse, j1 = (cj + 1) * p->coarse;
+    if (i1 > p->ray_nx) i1 = p->ray_nx;
+    if (j1 > p->ray_ny) j1 = p->ray_ny;
+    double ex = p->ray_x0 + 0.5 * ((double)(ci * p->coarse) + (double)i1) * p->ray_dx;
+    double ey = p->ray_y0 + 0.5 * ((double)(cj * p->coarse) + (double)j1) * p->ray_dy;
+    double dist = fmin(fmin(ex - p->sx0, p->sx1 - ex), fmin(ey - p->sy0, p->sy1 - ey));
+    double r = 0.5 * dist;
+    double e[32];
+    for (int64_t n = 0; n < 2 * P; ++n) e[n] = 0.0;
+    for (int j = 0; j < M; ++j) {
+        double phi = 2.0 * LMO_PI * (double)j / (double)M;
+        double tx = ex + r * cos(phi), ty = ey + r * sin(phi);
+        double sx, sy;
+        rect_sheet(p->kappa_star, p->sx0, p->sx1, p->sy0, p->sy1, tx, ty, &sx, &sy);
+        /* conj(h) = conj(s) - kappa_star conj(theta) */
+        double hr = sx - p->kappa_star * tx, hi = -(sy - p->kappa_star * ty);
+        for (int64_t n = 0; n < P; ++n) {
+            /* w^-n = r^-n e^(-i n phi) */
+            double rn = pow(r, -(double)n), cn = cos((double)n * phi), sn = sin((double)n * phi);
+            e[2 * n] += (hr * cn + hi * sn) * rn / (double)M;
+            e[2 * n + 1] += (hi * cn - hr * sn) * rn / (double)M;
+        }
+    }
+    double t_x = zx - ex, t_y = zy - ey;
+    for (int64_t k = 0; k < P; ++k) {
+        double sr = 0.0, si = 0.0;
+        double pr = 1.0, pi = 0.0;  /* t^(n-k) */
+        double binom = 1.0;         /* C(n, k) */
+        for (int64_t n = k; n < P; ++n) {
+            sr += binom * (e[2 * n] * pr - e[2 * n + 1] * pi);
+            si += binom * (e[2 * n] * pi + e[2 * n + 1] * pr);
+            double npr = pr * t_x - pi * t_y, npi = pr * t_y + pi * t_x;
+            pr = npr;
+            pi = npi;
+            binom = binom * (double)(n + 1) / (double)(n + 1 - k);
+        }
+        c[2 * k] = sr;
+        c[2 * k + 1] = si;
+    }
+}
+
 /* source-plane position (Eq. 6 with the constant Jacobian of Eq. 1, or the
  * fold mapping of Eq. 5) */
 static void lens_map(const lmo_params *p, double tx, double ty, double ax, double ay,
                      double *bx, double *by)
 {
+    double sx, sy;
+    if (p->scheme == 1) {
+        /* interpolated: the rectangle's holomorphic part is in alpha (far) */
+        sx = p->kappa_star * tx;
+        sy = p->kappa_star * ty;
+    } else {
+        sheet_term(p, tx, ty, &sx, &sy);
+    }
     if (p->macro == 1) {
-        *bx = (0.5 * p->d_x * tx + p->d_y * ty) * tx + p->kappa_star * tx - ax;
-        *by = 2.0 * (1.0 - p->kappa) * ty + p->kappa_star * ty - ay;
+        *bx = (0.5 * p->d_x * tx + p->d_y * ty) * tx + sx - ax;
+        *by = 2.0 * (1.0 - p->kappa) * ty + sy - ay;
         return;
     }
     double lt = 1.0 - p->kappa - p->gamma, lr = 1.0 - p->kappa + p->gamma;
-    *bx = (lt + p->kappa_star) * tx - ax;
-    *by = (lr + p->kappa_star) * ty - ay;
+    *bx = lt * tx + sx - ax;
+    *by = lr * ty + sy - ay;
 }
 
 /* pixel index q*nx + p of a source position, or -1 outside the map */
@@ -352,6 +484,18 @@ static int64_t bin_of(const lmo_params *p, double bx, double by)
 static int check_params(const lmo_params *p)
 {
     if (p->macro != 0 && p->macro != 1) return -1;
+    if (p->sheet != 0 && p->sheet != 1) return -1;
+    if (p->sheet == 1) {
+        /* the rectangle holds the ray lattice (up to rounding of its ends) */
+        double lx1 = p->ray_x0 + (double)p->ray_nx * p->ray_dx;
+        double ly1 = p->ray_y0 + (double)p->ray_ny * p->ray_dy;
+        double tol = 1e-9 * (fabs(p->ray_x0) + fabs(lx1) + fabs(p->ray_y0) + fabs(ly1));
+        if (!(p->sx1 > p->sx0 && p->sy1 > p->sy0)) return -1;
+        if (p->scheme == 1 && p->terms > 16) return -1;
+        if (p->scheme == 1 && (p->ray_x0 < p->sx0 - tol || lx1 > p->sx1 + tol ||
+                               p->ray_y0 < p->sy0 - tol || ly1 > p->sy1 + tol))
+            return -1;
+    }
     if (!(p->src_dx > 0 && p->src_dy > 0 && p->ray_dx > 0 && p->ray_dy > 0)) return -1;
     if (p->src_nx <= 0 || p->src_ny <= 0 || p->ray_nx < 0 || p->ray_ny < 0) return -1;
     if (p->scheme == 1) {
@@ -365,6 +509,15 @@ static int check_params(const lmo_params *p)
 }
 
 /* ---- exported entry points ---------------------------------------------- */
+
+/* The sheet term s(theta) of the configured map at arbitrary positions. */
+int lmo_sheet(const lmo_params *p, const double *theta, int64_t nth, double *s)
+{
+    if (check_params(p)) return -1;
+    for (int64_t t = 0; t < nth; ++t)
+        sheet_term(p, theta[2 * t], theta[2 * t + 1], &s[2 * t], &s[2 * t + 1]);
+    return 0;
+}
 
 /* Direct deflection at arbitrary positions (Sec. 3.2, direct sum). */
 int lmo_deflect_direct(const double *lx, const double *ly, const double *lm, int64_t n,

@@ -12,8 +12,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 MUTATIONS = {
-    "sheet_sign": ("*bx = (lt + p->kappa_star) * tx - ax;", "*bx = (lt - p->kappa_star) * tx - ax;"),
-    "deflection_sign": ("*by = (lr + p->kappa_star) * ty - ay;", "*by = (lr + p->kappa_star) * ty + ay;"),
+    "sheet_sign": ("*sx = p->kappa_star * tx;", "*sx = -p->kappa_star * tx;"),
+    "deflection_sign": ("*by = lr * ty + sy - ay;", "*by = lr * ty + sy + ay;"),
     "missing_conjugate": ("    *ay = -fy;", "    *ay = fy;"),
     "dropped_taylor_term": ("for (int64_t n = P - 2; n >= 0; --n) {", "for (int64_t n = P - 2; n >= 1; --n) {"),
     "x_y_swap": ("double lt = 1.0 - p->kappa - p->gamma, lr = 1.0 - p->kappa + p->gamma;",
@@ -27,8 +27,26 @@ MUTATIONS = {
     "fold_missing_half": ("*bx = (0.5 * p->d_x * tx + p->d_y * ty) * tx",
                           "*bx = (p->d_x * tx + p->d_y * ty) * tx"),
     "fold_missing_two": ("*by = 2.0 * (1.0 - p->kappa) * ty", "*by = (1.0 - p->kappa) * ty"),
-    "fold_sheet_dropped": ("+ p->kappa_star * tx - ax;\n        *by = 2.0",
-                           "- ax;\n        *by = 2.0"),
+    "fold_sheet_dropped": ("* tx + sx - ax;\n        *by = 2.0",
+                           "* tx - ax;\n        *by = 2.0"),
+    "rect_sheet_log_half_dropped": ("double b = (r2 > 0.0) ? 0.5 * v * log(r2) : 0.0;",
+                                    "double b = (r2 > 0.0) ? v * log(r2) : 0.0;"),
+    "rect_sheet_corner_sign": ("- rect_prim(ub, va) + rect_prim(ua, va);",
+                               "+ rect_prim(ub, va) + rect_prim(ua, va);"),
+    "rect_sheet_y_roles_kept": ("double fy = rect_prim(vb, ub) - rect_prim(va, ub)",
+                                "double fy = rect_prim(ub, vb) - rect_prim(ua, vb)"),
+    "rect_sheet_over_two_pi": ("*sx = kappa / LMO_PI * fx;", "*sx = kappa / (2.0 * LMO_PI) * fx;"),
+    "rect_sheet_edges_swapped": ("double ua = tx - x1, ub = tx - x0",
+                                 "double ua = tx - x0, ub = tx - x1"),
+    "sheet_series_shift_dropped": ("double t_x = zx - ex, t_y = zy - ey;",
+                                   "double t_x = 0.0, t_y = 0.0;"),
+    "sheet_series_conj_sign": ("hi = -(sy - p->kappa_star * ty);", "hi = (sy - p->kappa_star * ty);"),
+    "sheet_series_added": ("for (int64_t n = 0; n < 2 * p->terms; ++n) a[n] -= c[n];",
+                           "for (int64_t n = 0; n < 2 * p->terms; ++n) a[n] += c[n];"),
+    "sheet_series_binomial_dropped": ("binom = binom * (double)(n + 1) / (double)(n + 1 - k);",
+                                      "binom = 1.0;"),
+    "sheet_exact_and_series": ("    if (p->scheme == 1) {\n        /* interpolated",
+                               "    if (0) {\n        /* interpolated"),
     "hier_binomial_dropped": ("binom = binom * (double)(n + 1) / (double)(n + 1 - q);",
                               "binom = 1.0;"),
     "hier_shift_reversed": ("double sx = zx - Zx, sy = zy - Zy;",
@@ -120,7 +138,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     d = _copy_tree(tmp_path)
     _plant(d, "lensoracle.c", *MUTATIONS[name])
     failed, out = _pins_fail(d, ["tests/test_oracle_pins.py", "tests/test_oracle_fold.py",
-                                 "tests/test_oracle_hier.py"])
+                                 "tests/test_oracle_hier.py", "tests/test_oracle_sheet.py"])
     assert failed, "planted mistake %r was not caught:\n%s" % (name, out)
 
 
