@@ -62,7 +62,7 @@ def make_map(lm, w, g, lenses, precision):
     for k, _ in g._fields_:
         setattr(g2, k, getattr(g, k))
     g2.precision = precision
-    return lm.Map(g2, w.kappa, w.gamma, w.kappa_star, lenses), g2
+    return lm.Map(g2, w.kappa, w.gamma, w.kappa_star, lenses, sheet=w.sheet()), g2
 
 
 def cpu_model():
@@ -95,7 +95,7 @@ def cpu_baseline_leg(lm, w, g, lenses, mp_mixed, mp_fp32, budget_s):
                            ("src_x0", "src_y0", "src_dx", "src_dy", "src_nx", "src_ny", "ray_x0",
                             "ray_y0", "ray_dx", "ray_dy", "ray_nx", "ray_ny", "scheme", "coarse",
                             "l1_kx", "l1_ky")}, halo=g.near_halo, terms=g.taylor_terms)
-    orc = oracle.Oracle(og, w.kappa, w.gamma, w.kappa_star, *lenses)
+    orc = oracle.Oracle(og, w.kappa, w.gamma, w.kappa_star, *lenses, sheet=w.sheet())
     cores = oracle.num_threads()
     # calibrate on growing blocks until one takes a second, then size the
     # all-thread sample so that three runs fit the time budget
@@ -180,7 +180,7 @@ def precision_stress_leg(lm, inputs):
         nj = 8 * g.coarse
         ni = int(1e9 // nj)
         i0, j0 = g.ray_nx // 2 - ni // 2, g.ray_ny // 2 - nj // 2
-        mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, lenses)
+        mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, lenses, sheet=w.sheet())
         mp.shoot(i0, j0, ni, nj)
         c, o, _ = mp.counts()
         mp.close()
@@ -191,7 +191,8 @@ def precision_stress_leg(lm, inputs):
                                     "scheme", "coarse", "l1_kx", "l1_ky")},
                                 halo=g.near_halo, terms=g.taylor_terms)
             t0 = time.perf_counter()
-            ref, ref_out = oracle.Oracle(og, w.kappa, w.gamma, w.kappa_star, *lenses).shoot(
+            ref, ref_out = oracle.Oracle(og, w.kappa, w.gamma, w.kappa_star, *lenses,
+                                         sheet=w.sheet()).shoot(
                 i0, j0, ni, nj)
             log("precision stress: oracle %d rays in %.1f s" % (ni * nj, time.perf_counter() - t0))
         d = np.abs(c.astype(np.int64) - ref.astype(np.int64))
@@ -222,7 +223,8 @@ def table1_window_leg(lm, inputs, precisions):
         g = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], w.src_pixels,
                                        w.extra["src_ny"], k0, dx, w.kappa_star, n_rays=w.n_rays)
         g.precision = prec
-        lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
+        half = (g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2)
+        lenses, rect = w.lenses(rect=half), w.sheet(rect=half)
         ni, nj = 400_000, 2000
         i0, j0 = g.ray_nx // 2 + 1000, g.ray_ny // 2
         if win is None:
@@ -231,7 +233,7 @@ def table1_window_leg(lm, inputs, precisions):
                                     "ray_x0", "ray_y0", "ray_dx", "ray_dy", "ray_nx", "ray_ny",
                                     "scheme", "coarse", "l1_kx", "l1_ky")},
                                 halo=g.near_halo, terms=g.taylor_terms, far_order=g.far_order)
-            orc = oracle.Oracle(og, 0.0, 0.0, w.kappa_star, *lenses, fold=w.fold)
+            orc = oracle.Oracle(og, 0.0, 0.0, w.kappa_star, *lenses, fold=w.fold, sheet=rect)
             _, pix = orc.trace(np.array([i0, i0 + ni - 1, i0, i0 + ni - 1]),
                                np.array([j0, j0, j0 + nj - 1, j0 + nj - 1]))
             ps = [int(v % g.src_nx) for v in pix if v >= 0]
@@ -243,7 +245,7 @@ def table1_window_leg(lm, inputs, precisions):
             ref, _ = orc.shoot_window(i0, j0, ni, nj, p0, q0, np_, nq)
             log("Table 1 window: oracle %d rays in %.1f s" % (ni * nj, time.perf_counter() - t0))
             win = (p0, q0, np_, nq)
-        mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold)
+        mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold, sheet=rect)
         used, est, est_c = mp.precision()
         mp.shoot(i0, j0, ni, nj)
         got = lm.lm_read_counts_region(mp.h, *win)
@@ -274,7 +276,7 @@ def batched_study(lm, inputs, torch, scale, hierarchical=False):
                                   coarse=w.coarse, mean_mass=w.mean_mass)
         if hierarchical and lm.lm_geometry_far_order(g) > 0:
             n_hier += 1
-        maps.append(lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses()))
+        maps.append(lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses(), sheet=w.sheet()))
         geoms.append(g)
     rays = sum(g.n_rays for g in geoms)
     flops = sum(algorithmic_flops(lm.lm_shot_stats(m.h, 0, 0, g.ray_nx, g.ray_ny),
@@ -357,8 +359,9 @@ def fold_study_leg(lm, inputs, torch, n_maps=80):
         g = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], w.src_pixels,
                                        w.extra["src_ny"], k0, dx, w.kappa_star, n_rays=w.n_rays)
         lm.lm_geometry_far_order(g)  # hierarchical far field where it converges
-        lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
-        maps.append(lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold))
+        half = (g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2)
+        maps.append(lm.Map(g, kappa_star=w.kappa_star, lenses=w.lenses(rect=half), fold=w.fold,
+                           sheet=w.sheet(rect=half)))
         geoms.append(g)
     rays = sum(g.n_rays for g in geoms)
     b = lm.lm_batch_create([m.h for m in maps])
@@ -427,8 +430,9 @@ def paper_table1_leg(lm, inputs, torch, precision):
     g = lm.lm_geometry_derive_fold(w.src_side, w.extra["src_ly"], w.src_pixels, w.extra["src_ny"],
                                    k0, dx, w.kappa_star, n_rays=w.n_rays)
     g.precision = precision
-    lenses = w.lenses(rect=(g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2))
-    mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold)
+    half = (g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2)
+    mp = lm.Map(g, kappa_star=w.kappa_star, lenses=w.lenses(rect=half), fold=w.fold,
+                sheet=w.sheet(rect=half))
     used, est, est_c = mp.precision()
     flops = algorithmic_flops(lm.lm_shot_stats(mp.h, 0, 0, g.ray_nx, g.ray_ny), g.taylor_terms)
     b = lm.lm_batch_create([mp.h])
@@ -627,7 +631,8 @@ def main():
         "config": {"workload": "paper-scale: 13000 Salpeter lenses (0.08-1.5), lambda_t=0.005, "
                                "lambda_r=0.3, kappa_star=0.01, %.4g rays, 5000x5000 uint64 map "
                                "over 24x24 theta_E, interpolated scheme (P=4, R=%d, K=%dx%d), "
-                               "batched mixed-precision path" %
+                               "compensating sheet on the lenses' rectangle, batched "
+                               "mixed-precision path" %
                                (g.n_rays, g.coarse, g.l1_kx, g.l1_ky),
                    "rays": g.n_rays, "lenses": w.n_lenses, "map_pixels": [g.src_nx, g.src_ny],
                    "precision": "FP32 lens sums on rebased offsets, FP64 cell bases and pixel "

@@ -196,6 +196,25 @@ lm_status lm_set_macro(lm_map* m, double kappa, double gamma, double kappa_star)
  * arcmin^-1: multiply by theta_E in arcmin).  LM_ESTATE if the map has counts. */
 lm_status lm_set_fold(lm_map* m, double kappa0, double d_x, double d_y, double kappa_star);
 
+/* Where the compensating sheet of density -kappa_star lies (Sec. 2, Eq. 6).
+ * Sec. 2 subtracts the microlenses' mean density so that the total density
+ * stays the smooth model's; the sheet therefore belongs where the microlenses
+ * are.  By default (and after a call with x0 = x1 = y0 = y1 = 0) it is infinite
+ * about the origin, with the term kappa_star theta written in the macro
+ * models above, which is exact inside a disk of lenses centred there.  For
+ * lenses spread over a rectangle, pass it as [x0, x1] x [y0, y1] (theta_E):
+ * the term becomes that rectangle's deflection, kappa_star theta plus a part
+ * that is holomorphic inside the rectangle, which enters every level-2 cell's
+ * Taylor coefficients with the far field (lm_read_coeffs includes it).  Its
+ * series about a cell converges within the distance to the rectangle's
+ * nearest corner, so cells next to a corner carry a truncation error of order
+ * (kappa_star / pi) d rho^P, d that distance and rho the cell's half-diagonal
+ * over d.  The rectangle must hold the ray lattice; interpolated scheme only
+ * (LM_EUNSUPPORTED for the direct scheme).  LM_EINVAL for a non-finite or
+ * empty rectangle or one that does not hold the lattice, LM_ESTATE if the map
+ * has counts. */
+lm_status lm_set_sheet(lm_map* m, double x0, double x1, double y0, double y1);
+
 /* Copy n point-mass microlenses (Sec. 2, Eq. 6): positions (x[k], y[k]) in
  * theta_E and masses mass[k] > 0 in units of the unit mass of theta_E.  n may
  * be 0.  Sorts them by level-1 cell (Sec. 3.2.1) on the host and uploads them;
@@ -258,7 +277,8 @@ lm_status lm_read_mu(lm_map* m, double* host_mu);
 lm_status lm_reset_counts(lm_map* m, void* stream);
 
 /* Far-field coefficients a_0..a_{P-1} of level-2 cell (ci, cj) as the shooting
- * kernel reads them (Sec. 3.2.2): a[2n] = Re a_n, a[2n+1] = Im a_n, a_0 in FP64,
+ * kernel reads them (Sec. 3.2.2; with a sheet rectangle, less the Taylor
+ * coefficients of its holomorphic part): a[2n] = Re a_n, a[2n+1] = Im a_n, a_0 in FP64,
  * a_1.. stored in FP32 and widened.  Computes the coefficients first if the
  * lenses or the macro model changed.  Synchronous.  LM_ERANGE outside the
  * lattice's level-2 cells; LM_EUNSUPPORTED for the direct scheme. */

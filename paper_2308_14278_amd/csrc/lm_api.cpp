@@ -199,6 +199,9 @@ struct lm_map {
     double kappa = 0, gamma = 0, kappa_star = 0;
     bool fold = false;
     double fold_dx = 0, fold_dy = 0;  // 1/theta_E
+    // the -kappa_star sheet: infinite about the origin, or on a rectangle
+    bool sheet = false;
+    double sheet_x0 = 0, sheet_x1 = 0, sheet_y0 = 0, sheet_y1 = 0;
     int64_t nlens = 0;
     // derived
     int64_t ncx = 0, ncy = 0, n1x = 0, n1y = 0;
@@ -322,6 +325,12 @@ LmDesc make_desc(const lm_map* m, int64_t i0, int64_t j0, int64_t i1, int64_t j1
     d.y0 = g.ray_y0;
     d.dx = g.ray_dx;
     d.dy = g.ray_dy;
+    d.sheet = m->sheet ? 1 : 0;
+    d.sx0 = m->sheet_x0;
+    d.sx1 = m->sheet_x1;
+    d.sy0 = m->sheet_y0;
+    d.sy1 = m->sheet_y1;
+    d.kappa_star = m->kappa_star;
     if (m->fold) {
         d.fold = 1;
         d.mx = m->kappa_star;
@@ -428,6 +437,7 @@ int launch_coefficients(const lm_map* m, const LmDesc& d, hipStream_t s)
                 ? lm_launch_coeffs_hier(d, m->g.taylor_terms, m->coef.as<LmCoef>(), s)
                 : lm_launch_coeffs(d, m->g.precision, m->g.taylor_terms, 0, 0, m->ncx, m->ncy,
                                    m->coef.as<LmCoef>(), s);
+    if (e == 0 && m->sheet) e = lm_launch_sheet(d, m->g.taylor_terms, m->coef.as<LmCoef>(), s);
     if (e == 0) e = lm_launch_near_centre(d, m->coef.as<LmCoef>(), s);
     return e;
 }
@@ -798,6 +808,7 @@ lm_status lm_set_macro(lm_map* m, double kappa, double gamma, double kappa_star)
     m->fold_dx = m->fold_dy = 0.0;
     ++m->gen;
     ++m->model_gen;
+    if (m->sheet) m->coef_valid = false;  // the sheet's coefficients scale with kappa_star
     return ok();
 }
 
@@ -813,6 +824,37 @@ lm_status lm_set_fold(lm_map* m, double kappa0, double d_x, double d_y, double k
     m->fold = true;
     m->fold_dx = d_x;
     m->fold_dy = d_y;
+    ++m->gen;
+    ++m->model_gen;
+    if (m->sheet) m->coef_valid = false;  // the sheet's coefficients scale with kappa_star
+    return ok();
+}
+
+lm_status lm_set_sheet(lm_map* m, double x0, double x1, double y0, double y1)
+{
+    if (!m) return fail(LM_EINVAL, "map is NULL");
+    if (!(isfin(x0) && isfin(x1) && isfin(y0) && isfin(y1)))
+        return fail(LM_EINVAL, "non-finite sheet rectangle");
+    if (m->has_counts) return fail(LM_ESTATE, "map has counts; call lm_reset_counts first");
+    const bool on = !(x0 == 0.0 && x1 == 0.0 && y0 == 0.0 && y1 == 0.0);
+    if (on) {
+        const lm_geometry& g = m->g;
+        if (g.scheme != LM_SCHEME_INTERP)
+            return fail(LM_EUNSUPPORTED, "a sheet rectangle needs the interpolated scheme");
+        if (!(x1 > x0 && y1 > y0)) return fail(LM_EINVAL, "empty sheet rectangle");
+        const double lx1 = g.ray_x0 + (double)g.ray_nx * g.ray_dx;
+        const double ly1 = g.ray_y0 + (double)g.ray_ny * g.ray_dy;
+        const double tol =
+            1e-9 * (std::fabs(g.ray_x0) + std::fabs(lx1) + std::fabs(g.ray_y0) + std::fabs(ly1));
+        if (g.ray_x0 < x0 - tol || lx1 > x1 + tol || g.ray_y0 < y0 - tol || ly1 > y1 + tol)
+            return fail(LM_EINVAL, "the sheet rectangle must hold the ray lattice");
+    }
+    m->sheet = on;
+    m->sheet_x0 = on ? x0 : 0.0;
+    m->sheet_x1 = on ? x1 : 0.0;
+    m->sheet_y0 = on ? y0 : 0.0;
+    m->sheet_y1 = on ? y1 : 0.0;
+    m->coef_valid = false;
     ++m->gen;
     ++m->model_gen;
     return ok();

@@ -68,6 +68,8 @@ struct LmDesc {
                                    // fold: kappa_star, 2(1-kappa0)+kappa_star
     double qx, qy;                 // fold: d_x/2, d_y (beta_x gains (qx theta_x + qy theta_y) theta_x)
     double bx0, by0, inv_sdx, inv_sdy;
+    double sx0, sx1, sy0, sy1;     // rectangle of the -kappa_star sheet (sheet = 1)
+    double kappa_star;
     // FP32 copies: half ray spacing as float-float (rebased arithmetic) and
     // plain values (the global-FP32 comparison path)
     float hxh, hxl, hyh, hyl;
@@ -76,6 +78,7 @@ struct LmDesc {
     float inv_sdxf, inv_sdyf;
     int32_t snx, sny;
     int32_t fold;                  // 1: fold macro model
+    int32_t sheet;                 // 1: the sheet covers [sx0, sx1] x [sy0, sy1]
     int32_t Q;                     // terms of the level-1 series (0: direct coefficients)
     int32_t nbx, nby;              // boxes of the level-1 series per level-1 cell side
     int32_t bx, by;                // level-2 cells per box side (the last box may be narrower)
@@ -114,6 +117,9 @@ struct LmDesc {
 };
 
 // Launchers implemented in lm_kernels.hip (return hipError_t as int).
+// The rectangle sheet's holomorphic part added to every level-2 cell's
+// coefficients (after the far-field kernels).
+int lm_launch_sheet(const LmDesc& d, int terms, LmCoef* coef, void* stream);
 int lm_launch_ptab(const LmDesc& d, float* out, int n, void* stream);
 int lm_launch_coeffs(const LmDesc& d, int precision, int terms, int64_t ci0, int64_t cj0,
                      int64_t nci, int64_t ncj, LmCoef* out, void* stream);

@@ -285,6 +285,116 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
         p[i] = v;
 }
 
+// ------------------------------------------------ the rectangle sheet
+
+struct Cd {
+    double r, i;
+};
+__device__ __forceinline__ Cd cd(double r, double i) { return Cd{r, i}; }
+__device__ __forceinline__ Cd operator+(Cd a, Cd b) { return cd(a.r + b.r, a.i + b.i); }
+__device__ __forceinline__ Cd operator-(Cd a, Cd b) { return cd(a.r - b.r, a.i - b.i); }
+__device__ __forceinline__ Cd operator*(Cd a, Cd b)
+{
+    return cd(a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r);
+}
+__device__ __forceinline__ Cd operator*(double s, Cd a) { return cd(s * a.r, s * a.i); }
+__device__ __forceinline__ Cd cinv(Cd a)
+{
+    const double n = a.r * a.r + a.i * a.i;
+    return cd(a.r / n, -a.i / n);
+}
+// principal logarithm of wq / wp
+__device__ __forceinline__ Cd clog_ratio(Cd wq, Cd wp)
+{
+    const double qr = wq.r * wp.r + wq.i * wp.i, qi = wq.i * wp.r - wq.r * wp.i;
+    const double nq = wq.r * wq.r + wq.i * wq.i, np = wp.r * wp.r + wp.i * wp.i;
+    return cd(0.5 * log(nq / np), atan2(qi, qr));
+}
+
+// The sheet of density -kappa_star on the lenses' rectangle (Sec. 2, Eq. 6):
+// inside the rectangle its term in the lens equation is kappa_star theta +
+// h(theta), and by Green's theorem on the rectangle
+//   conj(h)(z) = (kappa_star / 2 pi i) oint z'* / (z - z') dz'
+// over its edges, counter-clockwise.  About an expansion point z_e inside,
+// conj(h) = sum_n H_n (z - z_e)^n with H_n = -(kappa_star / 2 pi i) J_n,
+//   J_n = oint z'* w^-(n+1) dz',  w = z' - z_e.
+// On an edge z'* is linear in z' (y = y_e: z'* = z' - 2 i y_e; x = x_e:
+// z'* = 2 x_e - z'), so z'* = s w + c there and each edge from wP to wQ gives
+//   n = 0:  s (wQ - wP) + c Log(wQ / wP)
+//   n = 1:  s Log(wQ / wP) + c (1/wP - 1/wQ)
+//   n >= 2: s (wQ^(1-n) - wP^(1-n)) / (1 - n) + c (wP^-n - wQ^-n) / n
+// (a straight edge that misses z_e turns by less than pi about it, so the
+// principal logarithm of the ratio is the integral).  The far field enters the
+// lens equation as -alpha_far with conj(alpha_far) = sum a_n delta^n and the
+// sheet as +h, so a_n gains -H_n = (kappa_star / 2 pi i) J_n.  z_e is the
+// centre of the part of the cell inside the lattice (the cell centre except
+// in a partial last column or row), and the polynomial is re-expanded about
+// the cell centre: b'_k = sum_{n>=k} C(n,k) b_n t^(n-k), t = z_c - z_e.
+template <int P>
+__global__ __launch_bounds__(kWG) void k_sheet(LmDesc d, LmCoef* __restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (c >= d.ncx * d.ncy) return;
+    const int64_t ci = c % d.ncx, cj = c / d.ncx;
+    const int64_t i1 = min((ci + 1) * (int64_t)d.R, d.nx), j1 = min((cj + 1) * (int64_t)d.R, d.ny);
+    const Cd ze = cd(d.x0 + 0.5 * ((double)(ci * d.R) + (double)i1) * d.dx,
+                     d.y0 + 0.5 * ((double)(cj * d.R) + (double)j1) * d.dy);
+    const Cd corner[4] = {cd(d.sx0, d.sy0), cd(d.sx1, d.sy0), cd(d.sx1, d.sy1),
+                          cd(d.sx0, d.sy1)};
+    // z'* = s w + c on the four edges, counter-clockwise from (sx0, sy0)
+    const double es[4] = {1.0, -1.0, 1.0, -1.0};
+    const Cd ec[4] = {ze - cd(0.0, 2.0 * d.sy0), cd(2.0 * d.sx1, 0.0) - ze,
+                      ze - cd(0.0, 2.0 * d.sy1), cd(2.0 * d.sx0, 0.0) - ze};
+    Cd J[P];
+#pragma unroll
+    for (int n = 0; n < P; ++n) J[n] = cd(0.0, 0.0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const Cd wp = corner[e] - ze, wq = corner[(e + 1) & 3] - ze;
+        const double s = es[e];
+        const Cd cc = ec[e];
+        const Cd L = clog_ratio(wq, wp);
+        const Cd ip = cinv(wp), iq = cinv(wq);
+        J[0] = J[0] + s * (wq - wp) + cc * L;
+        if constexpr (P > 1) J[1] = J[1] + s * L + cc * (ip - iq);
+        // wP^-(n-1), wQ^-(n-1) and wP^-n, wQ^-n, advanced by one power per n
+        Cd pp = ip, pq = iq, p2 = ip * ip, q2 = iq * iq;
+#pragma unroll
+        for (int n = 2; n < P; ++n) {
+            J[n] = J[n] + (s / (1.0 - n)) * (pq - pp) + (1.0 / n) * (cc * (p2 - q2));
+            pp = p2;
+            pq = q2;
+            p2 = p2 * ip;
+            q2 = q2 * iq;
+        }
+    }
+    // b_n = (kappa_star / 2 pi i) J_n = (kappa_star / 2 pi) (Im J_n, -Re J_n)
+    const double f = d.kappa_star / (2.0 * 3.14159265358979323846);
+    Cd b[P];
+#pragma unroll
+    for (int n = 0; n < P; ++n) b[n] = cd(f * J[n].i, -f * J[n].r);
+    const Cd t = cd(cell_cx(d, ci), cell_cy(d, cj)) - ze;
+    LmCoef& o = out[cj * d.ncx + ci];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        Cd acc = cd(0.0, 0.0), tp = cd(1.0, 0.0);
+        double binom = 1.0;
+#pragma unroll
+        for (int n = k; n < P; ++n) {
+            acc = acc + binom * (b[n] * tp);
+            tp = tp * t;
+            binom = binom * (double)(n + 1) / (double)(n + 1 - k);
+        }
+        if (k == 0) {
+            o.a0r += acc.r;
+            o.a0i += acc.i;
+        } else {
+            o.a[2 * k - 2] = (float)((double)o.a[2 * k - 2] + acc.r);
+            o.a[2 * k - 1] = (float)((double)o.a[2 * k - 1] + acc.i);
+        }
+    }
+}
+
 // Near-lens deflection of each level-2 cell centre, one cell per thread: the
 // sum over the cell's near list, in list order, of m (z_c - z_k) / |z_c - z_k|^2
 // in FP64 (the centred near sums add each ray's FP32 change from it).  NaN when
@@ -405,6 +515,25 @@ int lm_launch_coeffs_hier(const LmDesc& d, int terms, LmCoef* out, void* stream)
     case 5: hipLaunchKernelGGL(k_l1_shift<5>, grid, dim3(kWG), 0, s, d, out); break;
     case 6: hipLaunchKernelGGL(k_l1_shift<6>, grid, dim3(kWG), 0, s, d, out); break;
     case 7: hipLaunchKernelGGL(k_l1_shift<7>, grid, dim3(kWG), 0, s, d, out); break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int lm_launch_sheet(const LmDesc& d, int terms, LmCoef* coef, void* stream)
+{
+    const int64_t n = d.ncx * d.ncy;
+    if (n <= 0 || !d.sheet) return 0;
+    const dim3 grid((unsigned)((n + kWG - 1) / kWG));
+    hipStream_t s = (hipStream_t)stream;
+    switch (terms) {
+    case 1: hipLaunchKernelGGL(k_sheet<1>, grid, dim3(kWG), 0, s, d, coef); break;
+    case 2: hipLaunchKernelGGL(k_sheet<2>, grid, dim3(kWG), 0, s, d, coef); break;
+    case 3: hipLaunchKernelGGL(k_sheet<3>, grid, dim3(kWG), 0, s, d, coef); break;
+    case 4: hipLaunchKernelGGL(k_sheet<4>, grid, dim3(kWG), 0, s, d, coef); break;
+    case 5: hipLaunchKernelGGL(k_sheet<5>, grid, dim3(kWG), 0, s, d, coef); break;
+    case 6: hipLaunchKernelGGL(k_sheet<6>, grid, dim3(kWG), 0, s, d, coef); break;
+    case 7: hipLaunchKernelGGL(k_sheet<7>, grid, dim3(kWG), 0, s, d, coef); break;
     default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();

@@ -16,7 +16,8 @@ Recipe (all lengths in Einstein radii of a unit mass):
   * rectangle fields cover an area pi * N * <m> / kappa_star, so the stars'
     mean convergence equals kappa_star, with aspect ratio
     (1-kappa+gamma)/(1-kappa-gamma), i.e. elongated along the critical line
-    like the shooting region.
+    like the shooting region;
+  * the compensating sheet covers the lenses' rectangle (Workload.sheet).
 """
 from __future__ import annotations
 
@@ -104,6 +105,19 @@ class Workload:
     @property
     def mean_mass(self):
         return 1.0 if self.masses == "unit" else salpeter_mean()
+
+    def sheet(self, rect=None):
+        """The rectangle (x0, x1, y0, y1) the compensating sheet covers: that of
+        the lenses (rect as for lenses()); None for a disk field, whose sheet is
+        the infinite one (exact inside the disk)."""
+        if self.disk_radius is not None:
+            return None
+        if rect is not None:
+            hx, hy = rect
+        else:
+            hx, hy = field_rect(self.n_lenses, self.mean_mass, self.kappa_star, self.lam_t,
+                                self.lam_r)
+        return (-hx, hx, -hy, hy)
 
     def lenses(self, rect=None):
         """Draw the lens field.  rect = (half_x, half_y) places the lenses in that

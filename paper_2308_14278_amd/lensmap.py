@@ -100,6 +100,7 @@ _SIGS = {
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                 ctypes.c_int32, ctypes.c_double],
     "lm_set_fold": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "lm_set_sheet": [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
     "lm_read_counts_region": [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                               _u64],
     "lm_create": [_P(lm_geometry), _P(_vp)],
@@ -235,6 +236,10 @@ def lm_geometry_derive_fold(src_lx, src_ly, src_nx, src_ny, kappa0, d_x, kappa_s
 
 def lm_set_fold(m, kappa0, d_x, d_y, kappa_star):
     _check(load().lm_set_fold(m, kappa0, d_x, d_y, kappa_star), "lm_set_fold")
+
+
+def lm_set_sheet(m, x0, x1, y0, y1):
+    _check(load().lm_set_sheet(m, float(x0), float(x1), float(y0), float(y1)), "lm_set_sheet")
 
 
 def lm_read_counts_region(m, p0, q0, np_, nq):
@@ -519,14 +524,18 @@ class Map:
     """Owning wrapper: geometry + macro + lenses, with the ABI's calls as methods."""
 
     def __init__(self, g: lm_geometry, kappa=0.0, gamma=0.0, kappa_star=0.0, lenses=None,
-                 fold=None):
-        """fold=(kappa0, d_x, d_y) selects the fold macro model (kappa, gamma ignored)."""
+                 fold=None, sheet=None):
+        """fold=(kappa0, d_x, d_y) selects the fold macro model (kappa, gamma
+        ignored); sheet=(x0, x1, y0, y1) puts the -kappa_star sheet on that
+        rectangle (None: an infinite sheet)."""
         self.g = g
         self.h = lm_create(g)
         if fold is None:
             lm_set_macro(self.h, kappa, gamma, kappa_star)
         else:
             lm_set_fold(self.h, fold[0], fold[1], fold[2], kappa_star)
+        if sheet is not None:
+            lm_set_sheet(self.h, *sheet)
         if lenses is not None:
             lm_set_lenses(self.h, *lenses)
 
