@@ -203,3 +203,41 @@ def test_sheet_error_paths():
     with pytest.raises(lm.LensmapError):  # direct scheme
         lm.lm_set_sheet(md.h, -100.0, 100.0, -100.0, 100.0)
     md.close()
+
+
+def test_sheet_batch_equals_per_map_and_follows_the_sheet():
+    """The batch's coefficient graph carries the sheet: a batch of a map with
+    the sheet on its lens rectangle and the same map with the infinite sheet
+    reproduces each one's per-map counts bit for bit; moving a map's sheet
+    after the graphs are built makes the batch rebuild them and follow."""
+    w = inputs.near_fold()
+    g = _geom(w)
+    lenses = w.lenses()
+    ni, nj = 65536, 1024
+    i0, j0 = (g.ray_nx - ni) // 2, (g.ray_ny - nj) // 2
+    maps = [lm.Map(g, w.kappa, w.gamma, w.kappa_star, lenses, sheet=w.sheet()),
+            lm.Map(g, w.kappa, w.gamma, w.kappa_star, lenses)]
+    ref = []
+    for mp in maps:
+        mp.shoot(i0, j0, ni, nj)
+        ref.append(mp.counts())
+        mp.reset()
+    assert mismatch_fraction(ref[0][0], ref[1][0], ni * nj) > 1e-3
+    b = lm.lm_batch_create([mp.h for mp in maps])
+    for k in range(2):
+        lm.lm_batch_set_rect(b, k, i0, j0, ni, nj)
+    lm.lm_batch_shoot(b)
+    for mp, (c, o, s) in zip(maps, ref):
+        c2, o2, s2 = mp.counts()
+        np.testing.assert_array_equal(c, c2)
+        assert (o, s) == (o2, s2)
+        mp.reset()
+    # swap the sheets: the rebuilt graphs give each map the other's counts
+    lm.lm_set_sheet(maps[0].h, 0.0, 0.0, 0.0, 0.0)
+    lm.lm_set_sheet(maps[1].h, *w.sheet())
+    lm.lm_batch_shoot(b)
+    np.testing.assert_array_equal(maps[0].counts()[0], ref[1][0])
+    np.testing.assert_array_equal(maps[1].counts()[0], ref[0][0])
+    lm.lm_batch_destroy(b)
+    for mp in maps:
+        mp.close()
