@@ -47,13 +47,17 @@ def _pair(w, sheet=True, **over):
     return g, mp, orc
 
 
-def _small_fold(precision=lm.LM_PREC_AUTO, n_rays=4e7):
+def _small_fold(precision=lm.LM_PREC_AUTO, n_rays=4e7, hierarchical=False):
     """A fold map whose lenses fill the shooting region exactly, so the sheet's
     rectangle is the ray lattice itself; 22951 x 1743 rays in cells of 64
-    leave a partial last column and row of level-2 cells."""
+    leave a partial last column and row of level-2 cells.  hierarchical: the
+    far field from the series of the near-square boxes of its 36 x 3 level-1
+    cells."""
     k0, dx, dy, ks = 0.83, 2.0e-3, -1.5e-3, 0.01
     g = lm.lm_geometry_derive_fold(4.0, 4.0, 400, 400, k0, dx, ks, n_rays=n_rays, coarse=64)
     g.precision = precision
+    if hierarchical:
+        assert lm.lm_geometry_far_order(g) > 0
     hx, hy = g.ray_nx * g.ray_dx / 2, g.ray_ny * g.ray_dy / 2
     n = int(round(4 * hx * hy * ks / math.pi))
     rng = np.random.default_rng(31)
@@ -132,11 +136,15 @@ def test_sheet_near_fold_subrect_vs_oracle():
     mp2.close()
 
 
-@pytest.mark.parametrize("precision", [lm.LM_PREC_AUTO, lm.LM_PREC_MIXED_FP64])
-def test_sheet_fold_lattice_map_vs_oracle(precision):
+@pytest.mark.parametrize("precision,hierarchical", [(lm.LM_PREC_AUTO, False),
+                                                    (lm.LM_PREC_MIXED_FP64, False),
+                                                    (lm.LM_PREC_MIXED_CENTRED, True)])
+def test_sheet_fold_lattice_map_vs_oracle(precision, hierarchical):
     """Small fold map whose sheet rectangle is the lattice (partial last cells,
-    corner cells included) against the oracle's map of the same scheme."""
-    g, mp, orc = _small_fold(precision)
+    corner cells included) against the oracle's map of the same scheme; the
+    last case adds the hierarchical far field and the centred near sums, as
+    the fold study of the bench combines them."""
+    g, mp, orc = _small_fold(precision, hierarchical=hierarchical)
     mp.shoot()
     counts, n_out, n_shot = mp.counts()
     ref, ref_out = orc.shoot(nthreads=NTHREADS)
