@@ -155,15 +155,17 @@ __device__ __forceinline__ void cell_base(const LmDesc& d, int64_t ci, int64_t c
 
 // ----------------------------------------------------------- per-ray pieces
 
-// One ray-lens pair: accumulates m (dx, dy) / r^2 with dx = px - lx.
-__device__ __forceinline__ void pair(float px, float dy, float dy2, float lxv, float lmv,
+// One ray-lens pair: accumulates (mx dx, my dy) / r^2 with dx = px - lx, from
+// the row's dy^2 and my dy (the weights mx, my differ where the sums are kept
+// in pixel units).
+__device__ __forceinline__ void pair(float px, float dy2, float mdy, float lxv, float lmx,
                                      float& ax, float& ay)
 {
     float dx = px - lxv;
     float r2 = __builtin_fmaf(dx, dx, dy2);
-    float w = lmv * __builtin_amdgcn_rcpf(r2);
-    ax = __builtin_fmaf(dx, w, ax);
-    ay = __builtin_fmaf(dy, w, ay);
+    float w = __builtin_amdgcn_rcpf(r2);
+    ax = __builtin_fmaf(dx, lmx * w, ax);
+    ay = __builtin_fmaf(mdy, w, ay);
 }
 
 
@@ -290,6 +292,14 @@ __device__ __forceinline__ unsigned cvt_u32_sat(double v)
 {
     unsigned r;
     asm("v_cvt_u32_f64 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// Saturating FP32 -> u32 conversion (negative and NaN give 0).
+__device__ __forceinline__ unsigned cvt_u32_sat(float v)
+{
+    unsigned r;
+    asm("v_cvt_u32_f32 %0, %1" : "=v"(r) : "v"(v));
     return r;
 }
 
@@ -451,22 +461,29 @@ __device__ __forceinline__ int list_count(const LmDesc& d, int64_t ci, int64_t c
     return n;
 }
 
-// Lens value as the per-ray loop sees it.
-template <int PREC>
+// Lens value as the per-ray loop sees it: position (x, y) and the weights of
+// the x sums (z) and the y sums (w) -- the mass, or with PIX the mass in pixels
+// per theta_E of each axis (the rebased FP32 sums then come out in pixels).
+template <int PREC, bool PIX = PREC == 0>
 __device__ __forceinline__ typename Prec<PREC>::L lens_value(const LmDesc& d, int idx, double zcx,
                                                             double zcy)
 {
     if constexpr (PREC == 2) {
-        return make_double4(d.lx[idx] - zcx, d.ly[idx] - zcy, d.lmd[idx], 0.0);
+        return make_double4(d.lx[idx] - zcx, d.ly[idx] - zcy, d.lmd[idx], d.lmd[idx]);
     } else if constexpr (PREC == kPrecCentred) {
         // offset delta_k and c_k = m / delta_k (complex) of the centred sums
         const double ox = d.lx[idx] - zcx, oy = d.ly[idx] - zcy;
         const double q = d.lmd[idx] / (ox * ox + oy * oy);
         return make_float4((float)ox, (float)oy, (float)(q * ox), (float)(-(q * oy)));
     } else if constexpr (PREC == 0) {
-        return make_float4((float)(d.lx[idx] - zcx), (float)(d.ly[idx] - zcy), d.lmf[idx], 0.f);
+        const float ox = (float)(d.lx[idx] - zcx), oy = (float)(d.ly[idx] - zcy);
+        if constexpr (PIX)
+            return make_float4(ox, oy, (float)(d.lmd[idx] * d.inv_sdx),
+                               (float)(d.lmd[idx] * d.inv_sdy));
+        else
+            return make_float4(ox, oy, d.lmf[idx], d.lmf[idx]);
     } else {
-        return make_float4(d.lxf[idx], d.lyf[idx], d.lmf[idx], 0.f);
+        return make_float4(d.lxf[idx], d.lyf[idx], d.lmf[idx], d.lmf[idx]);
     }
 }
 
@@ -600,7 +617,11 @@ __device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_en
 }
 
 // Everything one ray row needs before its rays: the row offset, the biased
-// FP64 bases and (rebased paths) the row polynomials.
+// FP64 bases and (rebased paths) the row polynomials.  The rebased FP32 path
+// (PREC 0) keeps its sums in pixel units: the polynomials are scaled to
+// pixels, and each base is split into an integer part (bxf, byf, exact in
+// FP32) and the fraction below it (fx, fy), which the sums start from; a
+// ray's pixel is then the integer part plus the floor of its FP32 sum.
 template <int PREC, int P, bool FOLD>
 struct Row {
     using T = typename Prec<PREC>::T;
@@ -608,6 +629,7 @@ struct Row {
     T py;
     double ubxb, ubyb;
     T gx[D + 1], gy[D + 1];
+    float bxf, byf, fx, fy;
 };
 
 template <int PREC, int P, bool FOLD>
@@ -643,6 +665,20 @@ __device__ __forceinline__ void row_setup(const LmDesc& d, int64_t cj, int64_t j
         row_poly<P, FOLD, T>(ar, ai, rw.py, cxx, cxy, qx, qy, rw.gx, rw.gy);
         rw.ubxb = __builtin_fma(-(double)rw.gx[0], d.inv_sdx, rw.ubxb);
         rw.ubyb = __builtin_fma(-(double)rw.gy[0], d.inv_sdy, rw.ubyb);
+        if constexpr (PREC == 0) {
+            constexpr int D = Row<PREC, P, FOLD>::D;
+#pragma unroll
+            for (int k = 1; k <= D; ++k) {
+                rw.gx[k] = rw.gx[k] * d.inv_sdxf;
+                rw.gy[k] = rw.gy[k] * d.inv_sdyf;
+            }
+            // integer parts as FP32 values (integers at any magnitude) and the
+            // remainders against them, so that bxf + fx = ubxb to FP32 rounding
+            rw.bxf = (float)floor(rw.ubxb);
+            rw.byf = (float)floor(rw.ubyb);
+            rw.fx = (float)(rw.ubxb - (double)rw.bxf);
+            rw.fy = (float)(rw.ubyb - (double)rw.byf);
+        }
     }
 }
 
@@ -661,8 +697,8 @@ __device__ __forceinline__ typename Prec<PREC>::T column_offset(const LmDesc& d,
 
 // Start values of one ray's near sums (rebased paths): the row polynomials
 // without their constant terms, g1 dx + g2 dx^2 + .., from the column's powers
-// pw[k] = dx^(k+1) (one multiply and D - 1 FMAs per axis with wave-uniform
-// powers).
+// pw[k] = dx^(k+1) (one multiply or FMA and D - 1 FMAs per axis with
+// wave-uniform powers); in pixel units (PREC 0) less the bases' fractions.
 // (NEG: ay is the negated y sum; every step is an exact negation of the
 // plain one, and the coefficients -gy = Im(...) need no sign modifier)
 template <bool NEG, int PREC, int P, bool FOLD>
@@ -671,8 +707,13 @@ __device__ __forceinline__ void ray_start_first(const Row<PREC, P, FOLD>& rw,
                                                 typename Prec<PREC>::T& ax,
                                                 typename Prec<PREC>::T& ay)
 {
-    ax = p1 * rw.gx[1];
-    ay = p1 * (NEG ? -rw.gy[1] : rw.gy[1]);
+    if constexpr (PREC == 0) {
+        ax = fma(p1, rw.gx[1], -rw.fx);
+        ay = fma(p1, NEG ? -rw.gy[1] : rw.gy[1], NEG ? rw.fy : -rw.fy);
+    } else {
+        ax = p1 * rw.gx[1];
+        ay = p1 * (NEG ? -rw.gy[1] : rw.gy[1]);
+    }
 }
 
 // the same on top of a value (x0, y0): the centred sums' change of deflection
@@ -727,6 +768,12 @@ __device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& 
         bin_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcxf, zcyf, px, rw.py, ax, ay, pi, qi);
         p = pi < 0 ? 0u : (unsigned)pi + kBias;
         q = qi < 0 ? 0u : (unsigned)qi + kBias;
+    } else if constexpr (PREC == 0) {
+        // pixel sums (ax, ay) = (image offset less base fraction): the pixel is
+        // the base's integer part plus floor(-sum), a sum of two integers that
+        // FP32 holds exactly wherever it lands in the map
+        p = cvt_u32_sat(__builtin_floorf(-ax) + rw.bxf);
+        q = cvt_u32_sat(__builtin_floorf(-ay) + rw.byf);
     } else {
         bin_rebased(h.inv_sdx, h.inv_sdy, rw.ubxb, rw.ubyb, ax, ay, p, q);
     }
@@ -988,8 +1035,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                             lens_pairs_c<NR>(tb + (k + 1) * TW * NR, L1.y - py, L1.z, L1.w, bx,
                                              by);
                         } else {
-                            lens_pairs<NR>(tb + k * TW * NR, L0.y - py, L0.z, bx, by);
-                            lens_pairs<NR>(tb + (k + 1) * TW * NR, L1.y - py, L1.z, bx, by);
+                            lens_pairs<NR>(tb + k * TW * NR, L0.y - py, L0.w, bx, by);
+                            lens_pairs<NR>(tb + (k + 1) * TW * NR, L1.y - py, L1.w, bx, by);
                         }
                     }
                     if (k < nk) {
@@ -997,7 +1044,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                         if constexpr (CENT)
                             lens_pairs_c<NR>(tb + k * TW * NR, L.y - py, L.z, L.w, bx, by);
                         else
-                            lens_pairs<NR>(tb + k * TW * NR, L.y - py, L.z, bx, by);
+                            lens_pairs<NR>(tb + k * TW * NR, L.y - py, L.w, bx, by);
                     }
                     wave_sync_lds();
                 }
@@ -1006,9 +1053,9 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 for (int k = 0; k < nb; ++k) {
                     const auto L = lb[k];
                     const T dy = py - L.y;
-                    const T dy2 = dy * dy;
+                    const T dy2 = dy * dy, mdy = L.w * dy;
 #pragma unroll
-                    for (int c = 0; c < NR; ++c) pair(px[c], dy, dy2, L.x, L.z, bx[c], by[c]);
+                    for (int c = 0; c < NR; ++c) pair(px[c], dy2, mdy, L.x, L.z, bx[c], by[c]);
                 }
             }
 #pragma unroll
@@ -1235,8 +1282,9 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
 // Near-field sum of one position (lens for lens as in the shooting kernel),
 // added to the start values ax, ay.
 // PAIRED: the shooting kernel's two-column reciprocal, pxp = offset of the
-// partner column (column index ^ 1).
-template <int SCHEME, int PREC, bool PAIRED = false>
+// partner column (column index ^ 1).  PIX: weights in pixel units, as the
+// rebased FP32 shooting path sums (else in theta_E).
+template <int SCHEME, int PREC, bool PAIRED = false, bool PIX = PREC == 0>
 __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, double zcy,
                          typename Prec<PREC>::T px, typename Prec<PREC>::T py,
                          typename Prec<PREC>::T& ax, typename Prec<PREC>::T& ay,
@@ -1261,17 +1309,18 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
         const int nb = min(kCap, count - b0);
         T bx = SCHEME == 0 ? T(0) : ax, by = SCHEME == 0 ? T(0) : ay;
         for (int k = 0; k < nb; ++k) {
-            const auto L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
+            const auto L =
+                lens_value<PREC, PIX>(d, list_index<SCHEME>(d, ci, cj, b0 + k), zcx, zcy);
             const T dy = py - L.y;
             if constexpr (UseTab<SCHEME, PREC>::value && PAIRED) {
                 const T dx = px - L.x, dxp = pxp - L.x;
                 T ayp = 0, axp = 0;
-                pair2(dx * dx, dxp * dxp, L.z * dx, L.z * dxp, dy * dy, L.z * dy, bx, by, axp, ayp);
+                pair2(dx * dx, dxp * dxp, L.z * dx, L.z * dxp, dy * dy, L.w * dy, bx, by, axp, ayp);
             } else if constexpr (UseTab<SCHEME, PREC>::value) {
                 const T dx = px - L.x;
-                pair_tab(dx * dx, L.z * dx, dy * dy, L.z * dy, bx, by);
+                pair_tab(dx * dx, L.z * dx, dy * dy, L.w * dy, bx, by);
             } else {
-                pair(px, dy, dy * dy, L.x, L.z, bx, by);
+                pair(px, dy * dy, L.w * dy, L.x, L.z, bx, by);
             }
         }
         if (SCHEME == 0) {
@@ -1341,6 +1390,10 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
                                  ax, ay, u, v);
             uv[0] = u;
             uv[1] = v;
+        } else if constexpr (PREC == 0) {
+            // the values whose floors ray_bin forms, less the bias
+            uv[0] = ((double)rw.bxf - kBiasD) - (double)ax;
+            uv[1] = ((double)rw.byf - kBiasD) - (double)ay;
         } else {
             // the FP64 values bin_rebased floors, less the bias
             uv[0] = __builtin_fma(-(double)ax, h.inv_sdx, rw.ubxb) - kBiasD;
@@ -1389,7 +1442,7 @@ __device__ void deflect_one(const LmDesc& d, double tx, double ty, double& outx,
         py = (float)ty;
     }
     T ax = 0, ay = 0;
-    near_sum<SCHEME, PREC>(d, ci, cj, zcx, zcy, px, py, ax, ay);
+    near_sum<SCHEME, PREC, false, false>(d, ci, cj, zcx, zcy, px, py, ax, ay);
     if constexpr (PREC == kPrecCentred) {
         T dx, dyn;
         centred_change(px, py, ax, ay, dx, dyn);
