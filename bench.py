@@ -248,11 +248,18 @@ def table1_window_leg(lm, inputs, precisions):
         mp = lm.Map(g, kappa_star=w.kappa_star, lenses=lenses, fold=w.fold, sheet=rect)
         used, est, est_c = mp.precision()
         mp.shoot(i0, j0, ni, nj)
+        total = lm.lm_sum_counts(mp.h)
         got = lm.lm_read_counts_region(mp.h, *win)
         mp.close()
-        mis = 0.5 * float(np.abs(got.astype(np.int64) - ref.astype(np.int64)).sum()) / (ni * nj)
         name = {lm.LM_PREC_MIXED_FP64: "fp64-near", lm.LM_PREC_MIXED: "mixed",
                 lm.LM_PREC_MIXED_CENTRED: "centred", lm.LM_PREC_AUTO: "auto"}[prec]
+        # the window holds at most the rays counted in the whole map
+        if int(got.sum(dtype=np.uint64)) > total or int(got.max()) > total:
+            out[name] = {"precision_used": used, "error": "window read-back exceeds the map's "
+                         "%d counted rays" % total}
+            log("Table 1 window %s: inconsistent read-back" % name)
+            continue
+        mis = 0.5 * float(np.abs(got.astype(np.int64) - ref.astype(np.int64)).sum()) / (ni * nj)
         out[name] = {"precision_used": used, "bin_mismatch": mis,
                      "fp32_mismatch_estimate": est, "centred_fp32_mismatch_estimate": est_c}
         log("Table 1 window %s (precision %d): mismatch %.3g" % (name, used, mis))

@@ -260,8 +260,9 @@ lm_status lm_sum_counts(lm_map* m, uint64_t* total);
 
 /* Copy the counts of the pixel window [p0, p0+np) x [q0, q0+nq) to host
  * memory (nq rows of np uint64, caller-owned; Sec. 3.2.3, and Sec. 4.1 shows
- * such a window of the paper's map).  LM_ERANGE if the window leaves the map.
- * Synchronous. */
+ * such a window of the paper's map).  LM_ERANGE if the window leaves the map,
+ * LM_ENOMEM if the device cannot hold a packed copy of the window (np * nq * 8
+ * bytes, allocated and freed per call).  Synchronous. */
 lm_status lm_read_counts_region(lm_map* m, int32_t p0, int32_t q0, int32_t np, int32_t nq,
                                 uint64_t* host_counts);
 

@@ -1053,11 +1053,16 @@ lm_status lm_read_counts_region(lm_map* m, int32_t p0, int32_t q0, int32_t np, i
     if (np == 0 || nq == 0) return ok();
     lm_status st = use_device(m);
     if (st) return st;
+    // packed on the device, then one contiguous copy
+    DevBuf tmp;
+    if (tmp.ensure((size_t)np * nq * 8)) return fail(LM_ENOMEM, "cannot allocate the window");
     HIP_TRY(hipStreamSynchronize(m->last));
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy2D(host_counts, (size_t)np * 8,
-                        m->counts + (size_t)q0 * m->g.src_nx + p0, (size_t)m->g.src_nx * 8,
-                        (size_t)np * 8, (size_t)nq, hipMemcpyDeviceToHost));
+    LAUNCH_TRY(lm_launch_copy_region_u64(reinterpret_cast<const unsigned long long*>(m->counts),
+                                         m->g.src_nx, p0, q0, np, nq,
+                                         tmp.as<unsigned long long>(), nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    HIP_TRY(hipMemcpy(host_counts, tmp.p, (size_t)np * nq * 8, hipMemcpyDeviceToHost));
     return ok();
 }
 

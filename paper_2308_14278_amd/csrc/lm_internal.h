@@ -137,6 +137,8 @@ int lm_launch_shoot_batch(const LmDesc* descs, const int64_t* offsets, const int
                           int nmaps, unsigned long long* queue, int scheme, int precision,
                           int terms, int rays_per_lane, int layout, int grid, void* stream);
 int lm_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, void* stream);
+int lm_launch_copy_region_u64(const unsigned long long* map, int64_t snx, int64_t p0, int64_t q0,
+                              int64_t np, int64_t nq, unsigned long long* out, void* stream);
 // *total (zeroed by the caller) += sum of p[0..n)
 int lm_launch_sum_u64(const unsigned long long* p, int64_t n, unsigned long long* total,
                       void* stream);

@@ -285,6 +285,19 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
         p[i] = v;
 }
 
+// Rows [q0, q0 + nq) x columns [p0, p0 + np) of a row-major map of width snx,
+// packed row after row into out (np * nq values).
+__global__ void k_copy_region_u64(const unsigned long long* __restrict__ map, int64_t snx,
+                                  int64_t p0, int64_t q0, int64_t np, int64_t n,
+                                  unsigned long long* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / np, c = i - r * np;
+        out[i] = map[(q0 + r) * snx + p0 + c];
+    }
+}
+
 // ------------------------------------------------ the rectangle sheet
 
 struct Cd {
@@ -574,6 +587,18 @@ int lm_launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, v
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(kWG), 0, (hipStream_t)stream, p, n,
                        v);
+    return (int)hipGetLastError();
+}
+
+int lm_launch_copy_region_u64(const unsigned long long* map, int64_t snx, int64_t p0, int64_t q0,
+                              int64_t np, int64_t nq, unsigned long long* out, void* stream)
+{
+    const int64_t n = np * nq;
+    if (n <= 0) return 0;
+    int64_t blocks = (n + kWG - 1) / kWG;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_copy_region_u64, dim3((unsigned)blocks), dim3(kWG), 0,
+                       (hipStream_t)stream, map, snx, p0, q0, np, n, out);
     return (int)hipGetLastError();
 }
 

@@ -76,6 +76,15 @@ def test_fold_trace_rebuilds_shot_map_and_region_readback():
     np.testing.assert_array_equal(rebuilt.reshape(counts.shape), counts.astype(np.int64))
     region = lm.lm_read_counts_region(mp.h, 17, 40, 123, 77)
     np.testing.assert_array_equal(region, counts[40:117, 17:140])
+    # windows at the map's far corner, one pixel, one row, and an empty one
+    nx, ny = g.src_nx, g.src_ny
+    np.testing.assert_array_equal(lm.lm_read_counts_region(mp.h, nx - 31, ny - 9, 31, 9),
+                                  counts[ny - 9:, nx - 31:])
+    np.testing.assert_array_equal(lm.lm_read_counts_region(mp.h, nx - 1, 0, 1, 1),
+                                  counts[:1, nx - 1:])
+    np.testing.assert_array_equal(lm.lm_read_counts_region(mp.h, 0, ny // 2, nx, 1),
+                                  counts[ny // 2:ny // 2 + 1, :])
+    assert lm.lm_read_counts_region(mp.h, 5, 5, 0, 3).shape == (3, 0)
     mp.close()
 
 
