@@ -289,7 +289,8 @@ lm_status lm_read_coeffs(lm_map* m, int64_t ci, int64_t cj, double* a);
  * summed directly, far lenses through the Taylor coefficients) at n arbitrary
  * positions theta_xy[2t], theta_xy[2t+1] (FP64, host), written to alpha_xy
  * (host).  theta is rebased on the level-2 cell that contains it and the near
- * lenses are summed in the shooting kernel's order and precision, but one
+ * lenses are summed in the shooting kernel's order and precision (with
+ * weights in theta_E where the kernel keeps its FP32 sums in pixels), but one
  * reciprocal per lens (the kernel shares one between two lattice columns) and
  * the Taylor series by Horner (the kernel re-expands it per ray row), so its
  * rounding differs slightly from the kernel's; lm_trace_beta gives the

@@ -155,6 +155,20 @@ __device__ __forceinline__ void cell_base(const LmDesc& d, int64_t ci, int64_t c
 
 // ----------------------------------------------------------- per-ray pieces
 
+// Every r^2 of the near sums is at least 2^-62 theta_E^2 (added to the row's
+// dy^2 once per lens): with it the product of two r^2 that two columns share
+// stays a normal FP32 number and every FP32 near sum stays finite, whatever
+// the lens positions; it changes r^2 only for rays within ~1e-6 theta_E of a
+// lens's row, by at most a few ulps, and only rays within ~5e-10 theta_E of a
+// lens, deflected far out of any map, materially.
+constexpr float kR2Floor = 0x1p-62f;
+
+template <class T>
+__device__ __forceinline__ T row_dy2(T dy)
+{
+    return fma(dy, dy, T(kR2Floor));
+}
+
 // One ray-lens pair: accumulates (mx dx, my dy) / r^2 with dx = px - lx, from
 // the row's dy^2 and my dy (the weights mx, my differ where the sums are kept
 // in pixel units).
@@ -202,8 +216,8 @@ __device__ __forceinline__ void pair_tab(T dx2, T mdx, T dy2, T mdy, T& ax, T& a
 // Two pairs of one lens and the row's rays in columns a = 2m and b = 2m + 1
 // sharing one reciprocal: 1/r2a = r2b / (r2a r2b) and 1/r2b = r2a / (r2a r2b)
 // (the reciprocal is the expensive instruction of a pair).  The product stays a
-// normal FP32 number while both r2 exceed 1.1e-19 theta_E^2 (rays farther than
-// 3.3e-10 theta_E from the lens) and stay below 1e19.
+// normal FP32 number while both r2 exceed 1.1e-19 theta_E^2, which the floor
+// kR2Floor on every r2 guarantees, and stay below 1e19.
 template <class T>
 __device__ __forceinline__ void pair2(T dx2a, T dx2b, T mdxa, T mdxb, T dy2, T mdy, T& axa,
                                       T& aya, T& axb, T& ayb)
@@ -295,11 +309,12 @@ __device__ __forceinline__ unsigned cvt_u32_sat(double v)
     return r;
 }
 
-// Saturating FP32 -> u32 conversion (negative and NaN give 0).
-__device__ __forceinline__ unsigned cvt_u32_sat(float v)
+// floor(v) as a 32-bit integer, saturated at the ends of the int32 range (the
+// pixel step of the FP32 rebased path, whose sums are finite: see kR2Floor).
+__device__ __forceinline__ int cvt_floor_i32_sat(float v)
 {
-    unsigned r;
-    asm("v_cvt_u32_f32 %0, %1" : "=v"(r) : "v"(v));
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
     return r;
 }
 
@@ -619,9 +634,10 @@ __device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_en
 // Everything one ray row needs before its rays: the row offset, the biased
 // FP64 bases and (rebased paths) the row polynomials.  The rebased FP32 path
 // (PREC 0) keeps its sums in pixel units: the polynomials are scaled to
-// pixels, and each base is split into an integer part (bxf, byf, exact in
-// FP32) and the fraction below it (fx, fy), which the sums start from; a
-// ray's pixel is then the integer part plus the floor of its FP32 sum.
+// pixels, and each base is split into an integer part (bxi, byi: biased
+// pixel indices, as 32-bit integers) and the fraction below it (fx, fy),
+// which the sums start from; a ray's pixel is then the integer part plus the
+// floor of its FP32 sum, added as integers.
 template <int PREC, int P, bool FOLD>
 struct Row {
     using T = typename Prec<PREC>::T;
@@ -629,8 +645,20 @@ struct Row {
     T py;
     double ubxb, ubyb;
     T gx[D + 1], gy[D + 1];
-    float bxf, byf, fx, fy;
+    unsigned bxi, byi;
+    float fx, fy;
 };
+
+// Integer part of a biased FP64 pixel coordinate for the integer pixel step,
+// held within +-2^30 (a row whose base lies farther out sends every ray
+// outside the map: FP32 sums cannot reach back) so that base plus a
+// saturated floor never wraps into the map; and the remainder against it.
+__device__ __forceinline__ void split_base(double ub, unsigned& bi, float& f)
+{
+    const double b = fmin(fmax(floor(ub), -1073741824.0), 1073741824.0);
+    bi = (unsigned)(int)b;
+    f = (float)(ub - b);
+}
 
 template <int PREC, int P, bool FOLD>
 __device__ __forceinline__ void row_setup(const LmDesc& d, int64_t cj, int64_t j, double zcx,
@@ -672,12 +700,8 @@ __device__ __forceinline__ void row_setup(const LmDesc& d, int64_t cj, int64_t j
                 rw.gx[k] = rw.gx[k] * d.inv_sdxf;
                 rw.gy[k] = rw.gy[k] * d.inv_sdyf;
             }
-            // integer parts as FP32 values (integers at any magnitude) and the
-            // remainders against them, so that bxf + fx = ubxb to FP32 rounding
-            rw.bxf = (float)floor(rw.ubxb);
-            rw.byf = (float)floor(rw.ubyb);
-            rw.fx = (float)(rw.ubxb - (double)rw.bxf);
-            rw.fy = (float)(rw.ubyb - (double)rw.byf);
+            split_base(rw.ubxb, rw.bxi, rw.fx);
+            split_base(rw.ubyb, rw.byi, rw.fy);
         }
     }
 }
@@ -699,20 +723,20 @@ __device__ __forceinline__ typename Prec<PREC>::T column_offset(const LmDesc& d,
 // without their constant terms, g1 dx + g2 dx^2 + .., from the column's powers
 // pw[k] = dx^(k+1) (one multiply or FMA and D - 1 FMAs per axis with
 // wave-uniform powers); in pixel units (PREC 0) less the bases' fractions.
-// (NEG: ay is the negated y sum; every step is an exact negation of the
-// plain one, and the coefficients -gy = Im(...) need no sign modifier)
-template <bool NEG, int PREC, int P, bool FOLD>
+// (NEGX, NEGY: ax, ay are the negated sums; every step is an exact negation
+// of the plain one, and the negated coefficients need no sign modifier)
+template <bool NEGX, bool NEGY, int PREC, int P, bool FOLD>
 __device__ __forceinline__ void ray_start_first(const Row<PREC, P, FOLD>& rw,
                                                 typename Prec<PREC>::T p1,
                                                 typename Prec<PREC>::T& ax,
                                                 typename Prec<PREC>::T& ay)
 {
     if constexpr (PREC == 0) {
-        ax = fma(p1, rw.gx[1], -rw.fx);
-        ay = fma(p1, NEG ? -rw.gy[1] : rw.gy[1], NEG ? rw.fy : -rw.fy);
+        ax = fma(p1, NEGX ? -rw.gx[1] : rw.gx[1], NEGX ? rw.fx : -rw.fx);
+        ay = fma(p1, NEGY ? -rw.gy[1] : rw.gy[1], NEGY ? rw.fy : -rw.fy);
     } else {
-        ax = p1 * rw.gx[1];
-        ay = p1 * (NEG ? -rw.gy[1] : rw.gy[1]);
+        ax = p1 * (NEGX ? -rw.gx[1] : rw.gx[1]);
+        ay = p1 * (NEGY ? -rw.gy[1] : rw.gy[1]);
     }
 }
 
@@ -730,14 +754,14 @@ __device__ __forceinline__ void ray_start_first_on(const Row<PREC, P, FOLD>& rw,
 }
 
 // term k + 1 (k >= 1) with pk = dx^(k+1)
-template <bool NEG, int PREC, int P, bool FOLD>
+template <bool NEGX, bool NEGY, int PREC, int P, bool FOLD>
 __device__ __forceinline__ void ray_start_next(const Row<PREC, P, FOLD>& rw, int k,
                                                typename Prec<PREC>::T pk,
                                                typename Prec<PREC>::T& ax,
                                                typename Prec<PREC>::T& ay)
 {
-    ax = fma(pk, rw.gx[k + 1], ax);
-    ay = fma(pk, NEG ? -rw.gy[k + 1] : rw.gy[k + 1], ay);
+    ax = fma(pk, NEGX ? -rw.gx[k + 1] : rw.gx[k + 1], ax);
+    ay = fma(pk, NEGY ? -rw.gy[k + 1] : rw.gy[k + 1], ay);
 }
 
 template <int PREC, int P, bool FOLD>
@@ -750,9 +774,10 @@ __device__ __forceinline__ void ray_start(const Row<PREC, P, FOLD>& rw,
         ay = 0.f;
     } else {
         constexpr int D = Row<PREC, P, FOLD>::D;
-        ray_start_first<false, PREC, P, FOLD>(rw, pw[0], ax, ay);
+        ray_start_first<false, false, PREC, P, FOLD>(rw, pw[0], ax, ay);
 #pragma unroll
-        for (int k = 1; k < D; ++k) ray_start_next<false, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
+        for (int k = 1; k < D; ++k)
+            ray_start_next<false, false, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
     }
 }
 
@@ -770,10 +795,11 @@ __device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& 
         q = qi < 0 ? 0u : (unsigned)qi + kBias;
     } else if constexpr (PREC == 0) {
         // pixel sums (ax, ay) = (image offset less base fraction): the pixel is
-        // the base's integer part plus floor(-sum), a sum of two integers that
-        // FP32 holds exactly wherever it lands in the map
-        p = cvt_u32_sat(__builtin_floorf(-ax) + rw.bxf);
-        q = cvt_u32_sat(__builtin_floorf(-ay) + rw.byf);
+        // the base's integer part plus floor(-sum), added modulo 2^32 (the
+        // base within +-2^30 and the saturated floor keep every result that
+        // is not truly in the map out of it)
+        p = rw.bxi + (unsigned)cvt_floor_i32_sat(-ax);
+        q = rw.byi + (unsigned)cvt_floor_i32_sat(-ay);
     } else {
         bin_rebased(h.inv_sdx, h.inv_sdy, rw.ubxb, rw.ubyb, ax, ay, p, q);
     }
@@ -791,7 +817,7 @@ typedef const __attribute__((address_space(4))) float* ConstF;
 template <int NR, class T>
 __device__ __forceinline__ void lens_pairs(const T* row, T dy, T m, T* bx, T* by)
 {
-    const T dy2 = dy * dy;
+    const T dy2 = row_dy2(dy);
     const T mdy = m * dy;
     T r2[NR], md[NR], rr[NR / 2];
 #pragma unroll
@@ -831,7 +857,7 @@ __device__ __forceinline__ void lens_pairs(const T* row, T dy, T m, T* bx, T* by
 template <int NR, class T>
 __device__ __forceinline__ void lens_pairs_c(const T* row, T e, T cr, T ci, T* sr, T* si)
 {
-    const T e2 = e * e;
+    const T e2 = row_dy2(e);
     const T cie = ci * e, cre = cr * e;
     T r2[NR], rr[NR / 2];
 #pragma unroll
@@ -857,7 +883,7 @@ __device__ __forceinline__ void lens_pairs_c(const T* row, T e, T cr, T ci, T* s
 template <bool PAIRED, class T>
 __device__ __forceinline__ void pair_c(T dxa, T dxb, T e, T cr, T ci, T& sr, T& si)
 {
-    const T e2 = e * e;
+    const T e2 = row_dy2(e);
     const T cie = ci * e, cre = cr * e;
     const T r2a = dxa * dxa + e2;
     T w;
@@ -895,7 +921,7 @@ __device__ __forceinline__ void centre_bases(const LmDesc& d, const LmCoef& cf,
 // are live in scalar registers; px gets the column offsets (first powers).
 // CENT: ax, ay hold the centred sums S on entry, and the start is added on top
 // of their change conj(delta S) (with py the row offset).
-template <bool NEGY, int PREC, int P, bool FOLD, int NR, bool CENT = false>
+template <bool NEGX, bool NEGY, int PREC, int P, bool FOLD, int NR, bool CENT = false>
 __device__ __forceinline__ void table_start(ConstF tab, int R, const Row<PREC, P, FOLD>& rw,
                                             typename Prec<PREC>::T* px,
                                             typename Prec<PREC>::T* ax,
@@ -917,10 +943,10 @@ __device__ __forceinline__ void table_start(ConstF tab, int R, const Row<PREC, P
                     centred_change(pk, py, ax[c], ay[c], dx, dyn);
                     ray_start_first_on<NEGY, PREC, P, FOLD>(rw, pk, dx, dyn, ax[c], ay[c]);
                 } else {
-                    ray_start_first<NEGY, PREC, P, FOLD>(rw, pk, ax[c], ay[c]);
+                    ray_start_first<NEGX, NEGY, PREC, P, FOLD>(rw, pk, ax[c], ay[c]);
                 }
             } else {
-                ray_start_next<NEGY, PREC, P, FOLD>(rw, k, pk, ax[c], ay[c]);
+                ray_start_next<NEGX, NEGY, PREC, P, FOLD>(rw, k, pk, ax[c], ay[c]);
             }
         }
     }
@@ -967,6 +993,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
         // the table path carries the y sums negated (lens offsets y_k - y):
         // the row coefficients -gy and the FP64 binning take the sign for free
         constexpr bool NEGY = UseTab<SCHEME, PREC>::value;
+        // and the x sums too, but for the centred sums (their table holds c dx)
+        constexpr bool NEGX = NEGY && !CENT;
         constexpr int TW = tab_width(PREC);
         T px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
         if constexpr (CENT) {
@@ -979,8 +1007,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
             }
         } else if constexpr (PREC == 0) {
             // wave-uniform column offsets and their powers from the map's table
-            table_start<NEGY, PREC, P, FOLD, NR>((ConstF)(d.ptab + (c0 - ci * (int64_t)R)), R, rw,
-                                                 px, ax, ay);
+            table_start<NEGX, NEGY, PREC, P, FOLD, NR>((ConstF)(d.ptab + (c0 - ci * (int64_t)R)),
+                                                       R, rw, px, ax, ay);
         } else {
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
@@ -988,6 +1016,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 px[c] = column_offset<PREC>(d, c0 + c, ci);
                 col_powers<D>(px[c], pw);
                 ray_start<PREC, P, FOLD>(rw, pw, ax[c], ay[c]);
+                if (NEGX) ax[c] = -ax[c];
                 if (NEGY) ay[c] = -ay[c];
             }
         }
@@ -1020,7 +1049,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                     for (int e = lane; e < nk * NR; e += 64) {
                         const int k = e / NR, c = e & (NR - 1);
                         const auto L = lb[k0 + k];
-                        const T dx = pxl - L.x;
+                        const T dx = NEGX ? L.x - pxl : pxl - L.x;
                         tb[k * TW * NR + c] = dx * dx;
                         tb[k * TW * NR + NR + c] = L.z * dx;
                         if constexpr (CENT) tb[k * TW * NR + 2 * NR + c] = L.w * dx;
@@ -1053,7 +1082,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 for (int k = 0; k < nb; ++k) {
                     const auto L = lb[k];
                     const T dy = py - L.y;
-                    const T dy2 = dy * dy, mdy = L.w * dy;
+                    const T dy2 = row_dy2(dy), mdy = L.w * dy;
 #pragma unroll
                     for (int c = 0; c < NR; ++c) pair(px[c], dy2, mdy, L.x, L.z, bx[c], by[c]);
                 }
@@ -1073,7 +1102,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
         if constexpr (CENT) {
             // the change conj(delta S) of the near deflection, then the
             // row-polynomial start on top of it (and the column offsets)
-            table_start<NEGY, PREC, P, FOLD, NR, true>(
+            table_start<false, NEGY, PREC, P, FOLD, NR, true>(
                 (ConstF)(d.ptab + (c0 - ci * (int64_t)R)), R, rw, px, ax, ay, py);
         }
         const int ncol = (int)min((int64_t)NR, c_hi - c0);
@@ -1084,8 +1113,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
                 unsigned p, q;
-                ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
-                                       NEGY ? -ay[c] : ay[c], p, q);
+                ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c],
+                                       NEGX ? -ax[c] : ax[c], NEGY ? -ay[c] : ay[c], p, q);
                 run_push(h, run, p, q, col0 + c, axb, ayb, win, nout, row_ok);
             }
         } else {
@@ -1093,8 +1122,9 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
             for (int c = 0; c < NR; ++c) {
                 if (c >= cfirst && c < ncol) {
                     unsigned p, q;
-                    ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c], ax[c],
-                                           NEGY ? -ay[c] : ay[c], p, q);
+                    ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c],
+                                           NEGX ? -ax[c] : ax[c], NEGY ? -ay[c] : ay[c], p,
+                                           q);
                     run_push(h, run, p, q, col0 + c, axb, ayb, win, nout, row_ok);
                 }
             }
@@ -1315,12 +1345,13 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
             if constexpr (UseTab<SCHEME, PREC>::value && PAIRED) {
                 const T dx = px - L.x, dxp = pxp - L.x;
                 T ayp = 0, axp = 0;
-                pair2(dx * dx, dxp * dxp, L.z * dx, L.z * dxp, dy * dy, L.w * dy, bx, by, axp, ayp);
+                pair2(dx * dx, dxp * dxp, L.z * dx, L.z * dxp, row_dy2(dy), L.w * dy, bx, by, axp,
+                      ayp);
             } else if constexpr (UseTab<SCHEME, PREC>::value) {
                 const T dx = px - L.x;
-                pair_tab(dx * dx, L.z * dx, dy * dy, L.w * dy, bx, by);
+                pair_tab(dx * dx, L.z * dx, row_dy2(dy), L.w * dy, bx, by);
             } else {
-                pair(px, dy * dy, L.w * dy, L.x, L.z, bx, by);
+                pair(px, row_dy2(dy), L.w * dy, L.x, L.z, bx, by);
             }
         }
         if (SCHEME == 0) {
@@ -1368,7 +1399,8 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
         centred_change(px, rw.py, sr, si, dx, dyn);
         ray_start_first_on<true, PREC, P, FOLD>(rw, pw[0], dx, dyn, ax, ay);
 #pragma unroll
-        for (int k = 1; k < D; ++k) ray_start_next<true, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
+        for (int k = 1; k < D; ++k)
+            ray_start_next<false, true, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
         ay = -ay;
     } else {
         ray_start<PREC, P, FOLD>(rw, pw, ax, ay);
@@ -1392,8 +1424,8 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
             uv[1] = v;
         } else if constexpr (PREC == 0) {
             // the values whose floors ray_bin forms, less the bias
-            uv[0] = ((double)rw.bxf - kBiasD) - (double)ax;
-            uv[1] = ((double)rw.byf - kBiasD) - (double)ay;
+            uv[0] = ((double)(int)rw.bxi - kBiasD) - (double)ax;
+            uv[1] = ((double)(int)rw.byi - kBiasD) - (double)ay;
         } else {
             // the FP64 values bin_rebased floors, less the bias
             uv[0] = __builtin_fma(-(double)ax, h.inv_sdx, rw.ubxb) - kBiasD;
