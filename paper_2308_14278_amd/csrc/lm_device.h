@@ -571,20 +571,25 @@ __device__ __forceinline__ unsigned long long run_key(unsigned p, unsigned q)
     return (unsigned long long)p | ((unsigned long long)q << 32);
 }
 
-// Add n rays at biased pixel (p, q): outside the map -> n_out, inside the
-// workgroup's window -> LDS, else a global atomic.  (axb, ayb) = biased window
-// origin.
+// A workgroup's LDS window on the map: biased origin (axb, ayb) and the
+// extent (wxe, wye) of its part inside the map (the origin lies in the map).
+struct Win {
+    unsigned axb, ayb, wxe, wye;
+};
+
+// Add n rays at biased pixel (p, q): inside the window's part of the map ->
+// LDS, outside the map -> n_out, else a global atomic.
 __device__ __forceinline__ void emit(const Hot& h, unsigned p, unsigned q, unsigned n,
-                                     unsigned axb, unsigned ayb, unsigned* win, unsigned& nout)
+                                     const Win& w, unsigned* win, unsigned& nout)
 {
-    const unsigned pm = p - kBias, qm = q - kBias;
-    if ((pm >= (unsigned)h.snx) | (qm >= (unsigned)h.sny)) {
-        nout += n;
+    const unsigned wxi = p - w.axb, wyi = q - w.ayb;
+    if ((wxi < w.wxe) & (wyi < w.wye)) {
+        atomicAdd(&win[__umul24(wyi, (unsigned)h.wx) + wxi], n);
         return;
     }
-    const unsigned wxi = p - axb, wyi = q - ayb;
-    if ((wxi < (unsigned)h.wx) & (wyi < (unsigned)h.wy))
-        atomicAdd(&win[wyi * (unsigned)h.wx + wxi], n);
+    const unsigned pm = p - kBias, qm = q - kBias;
+    if ((pm >= (unsigned)h.snx) | (qm >= (unsigned)h.sny))
+        nout += n;
     else
         atomicAdd(&h.counts[(int64_t)qm * h.snx + pm], (unsigned long long)n);
 }
@@ -593,8 +598,7 @@ __device__ __forceinline__ void emit(const Hot& h, unsigned p, unsigned q, unsig
 // every lane but never emit them, so the per-ray path needs no lane mask.  col
 // is the unit-local column of the ray (rays are pushed column by column).
 __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsigned q, int col,
-                                         unsigned axb, unsigned ayb, unsigned* win,
-                                         unsigned& nout, bool row_ok)
+                                         const Win& w, unsigned* win, unsigned& nout, bool row_ok)
 {
     // (a unit starts with an empty run at the out-of-map pixel kBias - 2;
     // runs of length 0 are never emitted)
@@ -602,7 +606,7 @@ __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsig
     if (key != r.key) {
         // one divergent region for every lane whose run ends
         const unsigned n = row_ok ? (unsigned)(col - r.start) : 0u;
-        if (n) emit(h, (unsigned)r.key, (unsigned)(r.key >> 32), n, axb, ayb, win, nout);
+        if (n) emit(h, (unsigned)r.key, (unsigned)(r.key >> 32), n, w, win, nout);
         r.key = key;
         r.start = col;
     }
@@ -610,9 +614,8 @@ __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsig
 
 // End of a unit (col_end = unit-local column after its last ray): lanes whose
 // pending runs all name one pixel add it once.
-__device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_end, unsigned axb,
-                                          unsigned ayb, unsigned* win, unsigned& nout, int lane,
-                                          bool row_ok)
+__device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_end, const Win& w,
+                                          unsigned* win, unsigned& nout, int lane, bool row_ok)
 {
     const unsigned n = (unsigned)(col_end - r.start);
     const unsigned rp = (unsigned)r.key, rq = (unsigned)(r.key >> 32);
@@ -624,9 +627,9 @@ __device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_en
         unsigned long long diff = __ballot(act && (rp != p0 || rq != q0));
         if (diff == 0) {
             unsigned tot = wave_sum_u32(act ? n : 0u);
-            if (lane == first) emit(h, p0, q0, tot, axb, ayb, win, nout);
+            if (lane == first) emit(h, p0, q0, tot, w, win, nout);
         } else if (act) {
-            emit(h, rp, rq, n, axb, ayb, win, nout);
+            emit(h, rp, rq, n, w, win, nout);
         }
     }
 }
@@ -958,7 +961,7 @@ __device__ __forceinline__ void table_start(ConstF tab, int R, const Row<PREC, P
 // layout (near-list block, table block).
 template <int SCHEME, int PREC, int NR, int P, bool FOLD, int LAY>
 __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_lo, int64_t c_beg,
-                             int64_t c_hi, int64_t j, bool row_ok, unsigned axb, unsigned ayb,
+                             int64_t c_hi, int64_t j, bool row_ok, const Win& w,
                              unsigned* win, typename Prec<PREC>::L* lb,
                              typename Prec<PREC>::T* tb, int lane, unsigned& nout)
 {
@@ -1115,7 +1118,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 unsigned p, q;
                 ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c],
                                        NEGX ? -ax[c] : ax[c], NEGY ? -ay[c] : ay[c], p, q);
-                run_push(h, run, p, q, col0 + c, axb, ayb, win, nout, row_ok);
+                run_push(h, run, p, q, col0 + c, w, win, nout, row_ok);
             }
         } else {
 #pragma unroll
@@ -1125,16 +1128,19 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                     ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c],
                                            NEGX ? -ax[c] : ax[c], NEGY ? -ay[c] : ay[c], p,
                                            q);
-                    run_push(h, run, p, q, col0 + c, axb, ayb, win, nout, row_ok);
+                    run_push(h, run, p, q, col0 + c, w, win, nout, row_ok);
                 }
             }
         }
     }
-    run_flush(h, run, (int)(c_hi - c_lo), axb, ayb, win, nout, lane, row_ok);
+    run_flush(h, run, (int)(c_hi - c_lo), w, win, nout, lane, row_ok);
 }
 
 // Window origin of a tile: the pixel of the image of its centre cell's centre
-// (macro map, far field and near lenses, FP64), less half the window.
+// (macro map, far field and near lenses, FP64), less half the window, moved
+// into the map as far as the window allows (no window bin outside the map is
+// ever written, and none of its area is spent outside the map where the
+// map allows).
 template <int SCHEME>
 __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_t cjb, int& ax0,
                                             int& ay0)
@@ -1167,10 +1173,10 @@ __device__ __forceinline__ void tile_anchor(const LmDesc& d, int64_t cib, int64_
     ubx -= sx * d.inv_sdx;
     uby -= sy * d.inv_sdy;
     double fx = floor(ubx) - (double)(d.wx / 2), fy = floor(uby) - (double)(d.wy / 2);
-    fx = fmin(fmax(fx, -1.0e9), 1.0e9);
-    fy = fmin(fmax(fy, -1.0e9), 1.0e9);
     if (fx != fx) fx = 0.0;
     if (fy != fy) fy = 0.0;
+    fx = fmin(fmax(fx, 0.0), (double)max(d.snx - d.wx, 0));
+    fy = fmin(fmax(fy, 0.0), (double)max(d.sny - d.wy, 0));
     ax0 = (int)fx;
     ay0 = (int)fy;
 }
@@ -1180,7 +1186,8 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
                              typename Prec<PREC>::L* lb, typename Prec<PREC>::T* tb, int wave,
                              int lane)
 {
-    const unsigned axb = (unsigned)ax0 + kBias, ayb = (unsigned)ay0 + kBias;
+    const Win w{(unsigned)ax0 + kBias, (unsigned)ay0 + kBias,
+                (unsigned)min(d.wx, d.snx - ax0), (unsigned)min(d.wy, d.sny - ay0)};
     // fewer than 2^31 tiles per launch (checked on the host)
     const int ntx = (int)d.ntx;
     const int64_t tx = (int)t % ntx, ty = (int)t / ntx;
@@ -1208,18 +1215,16 @@ __device__ void process_tile(const LmDesc& d, int64_t t, int ax0, int ay0, unsig
         if (PREC == kPrecCentred && !__builtin_isnan(d.coef[cj * d.ncx + ci].n0x)) {
             if (d.fold)
                 process_unit<SCHEME, PREC, NR, P, true, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j,
-                                                             row_ok, axb, ayb, win, lb, tb, lane,
-                                                             nout);
+                                                             row_ok, w, win, lb, tb, lane, nout);
             else
                 process_unit<SCHEME, PREC, NR, P, false, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j,
-                                                              row_ok, axb, ayb, win, lb, tb, lane,
-                                                              nout);
+                                                              row_ok, w, win, lb, tb, lane, nout);
         } else if (d.fold) {
-            process_unit<SCHEME, PU, NR, P, true, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, axb,
-                                                       ayb, win, lb, tb, lane, nout);
+            process_unit<SCHEME, PU, NR, P, true, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, w,
+                                                       win, lb, tb, lane, nout);
         } else {
-            process_unit<SCHEME, PU, NR, P, false, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok,
-                                                        axb, ayb, win, lb, tb, lane, nout);
+            process_unit<SCHEME, PU, NR, P, false, LAY>(d, ci, cj, c_lo, c_beg, c_hi, j, row_ok, w,
+                                                        win, lb, tb, lane, nout);
         }
     }
     unsigned tot = wave_sum_u32(nout);
