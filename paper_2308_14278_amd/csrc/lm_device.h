@@ -155,18 +155,19 @@ __device__ __forceinline__ void cell_base(const LmDesc& d, int64_t ci, int64_t c
 
 // ----------------------------------------------------------- per-ray pieces
 
-// Every r^2 of the near sums is at least 2^-62 theta_E^2 (added to the row's
-// dy^2 once per lens): with it the product of two r^2 that two columns share
-// stays a normal FP32 number and every FP32 near sum stays finite, whatever
-// the lens positions; it changes r^2 only for rays within ~1e-6 theta_E of a
-// lens's row, by at most a few ulps, and only rays within ~5e-10 theta_E of a
-// lens, deflected far out of any map, materially.
+// Every r^2 of the near sums is at least 2^-62 theta_E^2, added to its dx^2
+// (in the wave-shared table, once per lens and column) or, without the table,
+// to its dy^2: with it the product of two r^2 that two columns share stays a
+// normal FP32 number and every FP32 near sum stays finite, whatever the lens
+// positions.  It changes r^2 only for rays within ~1e-6 theta_E of a lens's
+// column or row, by at most a few ulps, and only rays within ~5e-10 theta_E of
+// a lens, deflected far out of any map, materially.
 constexpr float kR2Floor = 0x1p-62f;
 
 template <class T>
-__device__ __forceinline__ T row_dy2(T dy)
+__device__ __forceinline__ T sq_floor(T v)
 {
-    return fma(dy, dy, T(kR2Floor));
+    return fma(v, v, T(kR2Floor));
 }
 
 // One ray-lens pair: accumulates (mx dx, my dy) / r^2 with dx = px - lx, from
@@ -820,7 +821,7 @@ typedef const __attribute__((address_space(4))) float* ConstF;
 template <int NR, class T>
 __device__ __forceinline__ void lens_pairs(const T* row, T dy, T m, T* bx, T* by)
 {
-    const T dy2 = row_dy2(dy);
+    const T dy2 = dy * dy;
     const T mdy = m * dy;
     T r2[NR], md[NR], rr[NR / 2];
 #pragma unroll
@@ -860,7 +861,7 @@ __device__ __forceinline__ void lens_pairs(const T* row, T dy, T m, T* bx, T* by
 template <int NR, class T>
 __device__ __forceinline__ void lens_pairs_c(const T* row, T e, T cr, T ci, T* sr, T* si)
 {
-    const T e2 = row_dy2(e);
+    const T e2 = e * e;
     const T cie = ci * e, cre = cr * e;
     T r2[NR], rr[NR / 2];
 #pragma unroll
@@ -886,12 +887,12 @@ __device__ __forceinline__ void lens_pairs_c(const T* row, T e, T cr, T ci, T* s
 template <bool PAIRED, class T>
 __device__ __forceinline__ void pair_c(T dxa, T dxb, T e, T cr, T ci, T& sr, T& si)
 {
-    const T e2 = row_dy2(e);
+    const T e2 = e * e;
     const T cie = ci * e, cre = cr * e;
-    const T r2a = dxa * dxa + e2;
+    const T r2a = sq_floor(dxa) + e2;
     T w;
     if constexpr (PAIRED) {
-        const T r2b = dxb * dxb + e2;
+        const T r2b = sq_floor(dxb) + e2;
         w = recip(r2a * r2b) * r2b;
     } else {
         w = recip(r2a);
@@ -1053,7 +1054,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                         const int k = e / NR, c = e & (NR - 1);
                         const auto L = lb[k0 + k];
                         const T dx = NEGX ? L.x - pxl : pxl - L.x;
-                        tb[k * TW * NR + c] = dx * dx;
+                        tb[k * TW * NR + c] = sq_floor(dx);
                         tb[k * TW * NR + NR + c] = L.z * dx;
                         if constexpr (CENT) tb[k * TW * NR + 2 * NR + c] = L.w * dx;
                     }
@@ -1085,7 +1086,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 for (int k = 0; k < nb; ++k) {
                     const auto L = lb[k];
                     const T dy = py - L.y;
-                    const T dy2 = row_dy2(dy), mdy = L.w * dy;
+                    const T dy2 = sq_floor(dy), mdy = L.w * dy;
 #pragma unroll
                     for (int c = 0; c < NR; ++c) pair(px[c], dy2, mdy, L.x, L.z, bx[c], by[c]);
                 }
@@ -1350,13 +1351,13 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
             if constexpr (UseTab<SCHEME, PREC>::value && PAIRED) {
                 const T dx = px - L.x, dxp = pxp - L.x;
                 T ayp = 0, axp = 0;
-                pair2(dx * dx, dxp * dxp, L.z * dx, L.z * dxp, row_dy2(dy), L.w * dy, bx, by, axp,
-                      ayp);
+                pair2(sq_floor(dx), sq_floor(dxp), L.z * dx, L.z * dxp, dy * dy, L.w * dy, bx, by,
+                      axp, ayp);
             } else if constexpr (UseTab<SCHEME, PREC>::value) {
                 const T dx = px - L.x;
-                pair_tab(dx * dx, L.z * dx, row_dy2(dy), L.w * dy, bx, by);
+                pair_tab(sq_floor(dx), L.z * dx, dy * dy, L.w * dy, bx, by);
             } else {
-                pair(px, row_dy2(dy), L.w * dy, L.x, L.z, bx, by);
+                pair(px, sq_floor(dy), L.w * dy, L.x, L.z, bx, by);
             }
         }
         if (SCHEME == 0) {
