@@ -774,7 +774,7 @@ lm_status lm_create(const lm_geometry* g, lm_map** out)
     LAUNCH_TRY(lm_launch_fill_u64(m->n_out.as<unsigned long long>(), 1, 0ull, nullptr));
     // column offsets of a level-2 cell and their powers, read by the shooting kernels
     const int nptab = g->coarse + LM_PTAB_PAD;
-    if (m->ptab.ensure((size_t)LM_PTAB_POW * nptab * sizeof(float)) != hipSuccess)
+    if (m->ptab.ensure((size_t)LM_PTAB_ROWS * nptab * sizeof(float)) != hipSuccess)
         return fail(LM_ENOMEM, "cannot allocate the column-offset table");
     LAUNCH_TRY(lm_launch_ptab(make_desc(m.get(), 0, 0, 0, 0, Exec{}), m->ptab.as<float>(), nptab,
                               nullptr));

@@ -480,7 +480,8 @@ __device__ __forceinline__ int list_count(const LmDesc& d, int64_t ci, int64_t c
 // Lens value as the per-ray loop sees it: position (x, y) and the weights of
 // the x sums (z) and the y sums (w) -- the mass, or with PIX the mass in pixels
 // per theta_E of each axis (the rebased FP32 sums then come out in pixels).
-template <int PREC, bool PIX = PREC == 0>
+// Centred sums: (z, w) = c_k = m_k / delta_k, with PIX in x pixels per theta_E.
+template <int PREC, bool PIX = PREC == 0 || PREC == kPrecCentred>
 __device__ __forceinline__ typename Prec<PREC>::L lens_value(const LmDesc& d, int idx, double zcx,
                                                             double zcy)
 {
@@ -489,7 +490,7 @@ __device__ __forceinline__ typename Prec<PREC>::L lens_value(const LmDesc& d, in
     } else if constexpr (PREC == kPrecCentred) {
         // offset delta_k and c_k = m / delta_k (complex) of the centred sums
         const double ox = d.lx[idx] - zcx, oy = d.ly[idx] - zcy;
-        const double q = d.lmd[idx] / (ox * ox + oy * oy);
+        const double q = d.lmd[idx] / (ox * ox + oy * oy) * (PIX ? d.inv_sdx : 1.0);
         return make_float4((float)ox, (float)oy, (float)(q * ox), (float)(-(q * oy)));
     } else if constexpr (PREC == 0) {
         const float ox = (float)(d.lx[idx] - zcx), oy = (float)(d.ly[idx] - zcy);
@@ -651,7 +652,16 @@ struct Row {
     T gx[D + 1], gy[D + 1];
     unsigned bxi, byi;
     float fx, fy;
+    T pyr;  // centred sums: the row offset times sdx / sdy
 };
+
+// sdx / sdy in FP32: converts the centred sums' y change from x pixels (the
+// unit of their lens weights) to y pixels; one value for the kernels, the
+// column table and the probes.
+__device__ __forceinline__ float pix_ratio(const LmDesc& d)
+{
+    return (float)(d.inv_sdy / d.inv_sdx);
+}
 
 // Integer part of a biased FP64 pixel coordinate for the integer pixel step,
 // held within +-2^30 (a row whose base lies farther out sends every ray
@@ -662,6 +672,23 @@ __device__ __forceinline__ void split_base(double ub, unsigned& bi, float& f)
     const double b = fmin(fmax(floor(ub), -1073741824.0), 1073741824.0);
     bi = (unsigned)(int)b;
     f = (float)(ub - b);
+}
+
+// Row polynomials to pixel units and the bases split (rebased FP32 paths;
+// the centred sums call it after the centre's near deflection is in the
+// bases).
+template <int PREC, int P, bool FOLD>
+__device__ __forceinline__ void row_pixels(const LmDesc& d, Row<PREC, P, FOLD>& rw)
+{
+    constexpr int D = Row<PREC, P, FOLD>::D;
+#pragma unroll
+    for (int k = 1; k <= D; ++k) {
+        rw.gx[k] = rw.gx[k] * d.inv_sdxf;
+        rw.gy[k] = rw.gy[k] * d.inv_sdyf;
+    }
+    split_base(rw.ubxb, rw.bxi, rw.fx);
+    split_base(rw.ubyb, rw.byi, rw.fy);
+    if constexpr (PREC == kPrecCentred) rw.pyr = pix_ratio(d) * rw.py;
 }
 
 template <int PREC, int P, bool FOLD>
@@ -697,16 +724,7 @@ __device__ __forceinline__ void row_setup(const LmDesc& d, int64_t cj, int64_t j
         row_poly<P, FOLD, T>(ar, ai, rw.py, cxx, cxy, qx, qy, rw.gx, rw.gy);
         rw.ubxb = __builtin_fma(-(double)rw.gx[0], d.inv_sdx, rw.ubxb);
         rw.ubyb = __builtin_fma(-(double)rw.gy[0], d.inv_sdy, rw.ubyb);
-        if constexpr (PREC == 0) {
-            constexpr int D = Row<PREC, P, FOLD>::D;
-#pragma unroll
-            for (int k = 1; k <= D; ++k) {
-                rw.gx[k] = rw.gx[k] * d.inv_sdxf;
-                rw.gy[k] = rw.gy[k] * d.inv_sdyf;
-            }
-            split_base(rw.ubxb, rw.bxi, rw.fx);
-            split_base(rw.ubyb, rw.byi, rw.fy);
-        }
+        if constexpr (PREC == 0) row_pixels(d, rw);
     }
 }
 
@@ -742,19 +760,6 @@ __device__ __forceinline__ void ray_start_first(const Row<PREC, P, FOLD>& rw,
         ax = p1 * (NEGX ? -rw.gx[1] : rw.gx[1]);
         ay = p1 * (NEGY ? -rw.gy[1] : rw.gy[1]);
     }
-}
-
-// the same on top of a value (x0, y0): the centred sums' change of deflection
-template <bool NEG, int PREC, int P, bool FOLD>
-__device__ __forceinline__ void ray_start_first_on(const Row<PREC, P, FOLD>& rw,
-                                                   typename Prec<PREC>::T p1,
-                                                   typename Prec<PREC>::T x0,
-                                                   typename Prec<PREC>::T y0,
-                                                   typename Prec<PREC>::T& ax,
-                                                   typename Prec<PREC>::T& ay)
-{
-    ax = fma(p1, rw.gx[1], x0);
-    ay = fma(p1, NEG ? -rw.gy[1] : rw.gy[1], y0);
 }
 
 // term k + 1 (k >= 1) with pk = dx^(k+1)
@@ -797,7 +802,7 @@ __device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& 
         bin_fp32<P, FOLD>(h, ar, ai, a0r, a0i, zcxf, zcyf, px, rw.py, ax, ay, pi, qi);
         p = pi < 0 ? 0u : (unsigned)pi + kBias;
         q = qi < 0 ? 0u : (unsigned)qi + kBias;
-    } else if constexpr (PREC == 0) {
+    } else if constexpr (PREC == 0 || PREC == kPrecCentred) {
         // pixel sums (ax, ay) = (image offset less base fraction): the pixel is
         // the base's integer part plus floor(-sum), added modulo 2^32 (the
         // base within +-2^30 and the saturated floor keep every result that
@@ -911,6 +916,22 @@ __device__ __forceinline__ void centred_change(T px, T py, T sr, T si, T& dx, T&
     dyn = fma(px, si, py * sr);
 }
 
+// First start values of a ray of the centred sums, both negated and in pixel
+// units: the change conj(delta S) of the near deflection (S in x pixels; the y
+// change converted with px_r = px sdx/sdy and the row's pyr), less the bases'
+// fractions, plus the first row-polynomial term.  x: -(Re(delta S) - fx +
+// g1 px); y: Im(delta S) sdx/sdy + fy - h1 px.
+template <int P, bool FOLD>
+__device__ __forceinline__ void centred_first(const Row<kPrecCentred, P, FOLD>& rw, float px,
+                                              float pxr, float sr, float si, float& axn,
+                                              float& ayn)
+{
+    const float ndx = fma(-px, sr, fma(rw.py, si, rw.fx));
+    const float dyn = fma(pxr, si, fma(rw.pyr, sr, rw.fy));
+    axn = fma(px, -rw.gx[1], ndx);
+    ayn = fma(px, -rw.gy[1], dyn);
+}
+
 // The cell centre's near-lens deflection into a row's FP64 pixel bases.
 template <int PREC, int P, bool FOLD>
 __device__ __forceinline__ void centre_bases(const LmDesc& d, const LmCoef& cf,
@@ -924,13 +945,13 @@ __device__ __forceinline__ void centre_bases(const LmDesc& d, const LmCoef& cf,
 // column powers (scalar loads), one power at a time so that only NR of them
 // are live in scalar registers; px gets the column offsets (first powers).
 // CENT: ax, ay hold the centred sums S on entry, and the start is added on top
-// of their change conj(delta S) (with py the row offset).
+// of their change conj(delta S) (centred_first; the table's row LM_PTAB_POW
+// holds the column offsets times sdx / sdy).
 template <bool NEGX, bool NEGY, int PREC, int P, bool FOLD, int NR, bool CENT = false>
 __device__ __forceinline__ void table_start(ConstF tab, int R, const Row<PREC, P, FOLD>& rw,
                                             typename Prec<PREC>::T* px,
                                             typename Prec<PREC>::T* ax,
-                                            typename Prec<PREC>::T* ay,
-                                            typename Prec<PREC>::T py = 0)
+                                            typename Prec<PREC>::T* ay)
 {
     using T = typename Prec<PREC>::T;
     constexpr int D = Row<PREC, P, FOLD>::D;
@@ -943,9 +964,9 @@ __device__ __forceinline__ void table_start(ConstF tab, int R, const Row<PREC, P
             if (k == 0) {
                 px[c] = pk;
                 if constexpr (CENT) {
-                    T dx, dyn;
-                    centred_change(pk, py, ax[c], ay[c], dx, dyn);
-                    ray_start_first_on<NEGY, PREC, P, FOLD>(rw, pk, dx, dyn, ax[c], ay[c]);
+                    // the centred sums S on entry (ax = S_r, ay = S_i)
+                    const T pkr = tab[LM_PTAB_POW * (R + LM_PTAB_PAD) + c];
+                    centred_first<P, FOLD>(rw, pk, pkr, ax[c], ay[c], ax[c], ay[c]);
                 } else {
                     ray_start_first<NEGX, NEGY, PREC, P, FOLD>(rw, pk, ax[c], ay[c]);
                 }
@@ -981,7 +1002,10 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
     // the lane's ray row
     Row<PREC, P, FOLD> rw;
     row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
-    if constexpr (CENT) centre_bases(d, d.coef[cj * d.ncx + ci], rw);
+    if constexpr (CENT) {
+        centre_bases(d, d.coef[cj * d.ncx + ci], rw);
+        row_pixels(d, rw);
+    }
     const T py = rw.py;
 
     constexpr int kCap = Cap<SCHEME, LAY>::value;
@@ -997,8 +1021,9 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
         // the table path carries the y sums negated (lens offsets y_k - y):
         // the row coefficients -gy and the FP64 binning take the sign for free
         constexpr bool NEGY = UseTab<SCHEME, PREC>::value;
-        // and the x sums too, but for the centred sums (their table holds c dx)
-        constexpr bool NEGX = NEGY && !CENT;
+        // and the x sums too; the table of the plain sums holds -m dx for it
+        // (the centred sums negate theirs when the start is added)
+        constexpr bool NEGX = NEGY;
         constexpr int TW = tab_width(PREC);
         T px[NR], ax[NR], ay[NR], kx[NR], ky[NR];
         if constexpr (CENT) {
@@ -1053,7 +1078,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                     for (int e = lane; e < nk * NR; e += 64) {
                         const int k = e / NR, c = e & (NR - 1);
                         const auto L = lb[k0 + k];
-                        const T dx = NEGX ? L.x - pxl : pxl - L.x;
+                        const T dx = (NEGX && !CENT) ? L.x - pxl : pxl - L.x;
                         tb[k * TW * NR + c] = sq_floor(dx);
                         tb[k * TW * NR + NR + c] = L.z * dx;
                         if constexpr (CENT) tb[k * TW * NR + 2 * NR + c] = L.w * dx;
@@ -1106,8 +1131,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
         if constexpr (CENT) {
             // the change conj(delta S) of the near deflection, then the
             // row-polynomial start on top of it (and the column offsets)
-            table_start<false, NEGY, PREC, P, FOLD, NR, true>(
-                (ConstF)(d.ptab + (c0 - ci * (int64_t)R)), R, rw, px, ax, ay, py);
+            table_start<NEGX, NEGY, PREC, P, FOLD, NR, true>(
+                (ConstF)(d.ptab + (c0 - ci * (int64_t)R)), R, rw, px, ax, ay);
         }
         const int ncol = (int)min((int64_t)NR, c_hi - c0);
         const int cfirst = (int)max((int64_t)0, c_beg - c0);
@@ -1320,7 +1345,8 @@ __global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ 
 // PAIRED: the shooting kernel's two-column reciprocal, pxp = offset of the
 // partner column (column index ^ 1).  PIX: weights in pixel units, as the
 // rebased FP32 shooting path sums (else in theta_E).
-template <int SCHEME, int PREC, bool PAIRED = false, bool PIX = PREC == 0>
+template <int SCHEME, int PREC, bool PAIRED = false,
+          bool PIX = PREC == 0 || PREC == kPrecCentred>
 __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, double zcy,
                          typename Prec<PREC>::T px, typename Prec<PREC>::T py,
                          typename Prec<PREC>::T& ax, typename Prec<PREC>::T& ay,
@@ -1333,7 +1359,7 @@ __device__ void near_sum(const LmDesc& d, int64_t ci, int64_t cj, double zcx, do
         // the centred sums S over the list in list order (ax, ay get S)
         T sr = 0, si = 0;
         for (int k = 0; k < count; ++k) {
-            const auto L = lens_value<PREC>(d, list_index<SCHEME>(d, ci, cj, k), zcx, zcy);
+            const auto L = lens_value<PREC, PIX>(d, list_index<SCHEME>(d, ci, cj, k), zcx, zcy);
             pair_c<PAIRED>(px - L.x, pxp - L.x, L.y - py, L.z, L.w, sr, si);
         }
         ax = sr;
@@ -1392,21 +1418,24 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
     if (SCHEME == 1) load_taylor<P>(d, ci, cj, ar, ai, a0r, a0i);
     Row<PREC, P, FOLD> rw;
     row_setup<PREC, P, FOLD>(d, cj, j, zcx, zcy, ubx, uby, ar, ai, rw);
-    if constexpr (PREC == kPrecCentred) centre_bases(d, d.coef[cj * d.ncx + ci], rw);
+    if constexpr (PREC == kPrecCentred) {
+        centre_bases(d, d.coef[cj * d.ncx + ci], rw);
+        row_pixels(d, rw);
+    }
     const T px = column_offset<PREC>(d, i, ci);
     constexpr int D = Row<PREC, P, FOLD>::D;
     T pw[D], ax, ay;
     col_powers<D>(px, pw);
     if constexpr (PREC == kPrecCentred) {
-        // as the kernel: S, its change, the start on top with the y sum negated
-        T sr, si, dx, dyn;
+        // as the kernel: S, then the start on its change, both sums negated
+        T sr, si;
         near_sum<SCHEME, PREC, true>(d, ci, cj, zcx, zcy, px, rw.py, sr, si,
                                      column_offset<PREC>(d, i ^ 1, ci));
-        centred_change(px, rw.py, sr, si, dx, dyn);
-        ray_start_first_on<true, PREC, P, FOLD>(rw, pw[0], dx, dyn, ax, ay);
+        centred_first<P, FOLD>(rw, px, pix_ratio(d) * px, sr, si, ax, ay);
 #pragma unroll
         for (int k = 1; k < D; ++k)
-            ray_start_next<false, true, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
+            ray_start_next<true, true, PREC, P, FOLD>(rw, k, pw[k], ax, ay);
+        ax = -ax;
         ay = -ay;
     } else {
         ray_start<PREC, P, FOLD>(rw, pw, ax, ay);
@@ -1428,7 +1457,7 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
                                  ax, ay, u, v);
             uv[0] = u;
             uv[1] = v;
-        } else if constexpr (PREC == 0) {
+        } else if constexpr (PREC == 0 || PREC == kPrecCentred) {
             // the values whose floors ray_bin forms, less the bias
             uv[0] = ((double)(int)rw.bxi - kBiasD) - (double)ax;
             uv[1] = ((double)(int)rw.byi - kBiasD) - (double)ay;

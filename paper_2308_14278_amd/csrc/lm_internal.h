@@ -37,6 +37,7 @@ constexpr int window_bins(int prec, int layout, int rays_per_lane)
 }
 #define LM_PTAB_PAD 64     // column-offset table entries past R (last column group)
 #define LM_PTAB_POW 6      // powers dx .. dx^6 per column (row polynomials, P <= 7)
+#define LM_PTAB_ROWS 7     // and a row of dx sdx / sdy (the centred sums' y change)
 
 // Allocation-free peak statistics: limits and layout of the per-device scratch
 // array (tracks, column bins, two histograms; each part 256-byte aligned).
@@ -109,7 +110,7 @@ struct LmDesc {
     const int32_t* lJ;
     const int32_t* cell_start;     // CSR over the padded level-1 grid
     const LmCoef* coef;            // [ncy][ncx]
-    const float* ptab;             // [LM_PTAB_POW][R + LM_PTAB_PAD] column offsets of a
+    const float* ptab;             // [LM_PTAB_ROWS][R + LM_PTAB_PAD] column offsets of a
                                    // level-2 cell and their powers
     double* l1exp;                 // [n1y nby][n1x nbx][Q] level-1 series per box, complex
     unsigned long long* counts;    // [sny][snx]

@@ -117,7 +117,8 @@ __global__ __launch_bounds__(kWG) void k_coeffs(LmDesc d, int64_t ci0, int64_t c
 }
 
 // Column offsets dx = local_offset(l) of a level-2 cell and their powers:
-// out[k n + l] = dx^(k+1), k < LM_PTAB_POW, l = 0 .. n-1 (entries past R belong
+// out[k n + l] = dx^(k+1), k < LM_PTAB_POW, and out[LM_PTAB_POW n + l] =
+// dx sdx / sdy, l = 0 .. n-1 (entries past R belong
 // to masked columns of the last group).
 __global__ void k_ptab(LmDesc d, float* __restrict__ out, int n)
 {
@@ -127,6 +128,7 @@ __global__ void k_ptab(LmDesc d, float* __restrict__ out, int n)
         col_powers<LM_PTAB_POW>(local_offset(l, 0, d.R, d.hxh, d.hxl), pw);
 #pragma unroll
         for (int k = 0; k < LM_PTAB_POW; ++k) out[(int64_t)k * n + l] = pw[k];
+        out[(int64_t)LM_PTAB_POW * n + l] = pix_ratio(d) * pw[0];
     }
 }
 
