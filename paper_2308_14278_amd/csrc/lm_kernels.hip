@@ -158,13 +158,16 @@ __device__ __forceinline__ void box_centre(const LmDesc& d, int64_t I, int64_t J
 // Hierarchical far field, step 1: the series of the far lenses of level-1 cell
 // (I, J) about the centre Z of one of its boxes, A_n = -sum_far m_k / (z_k -
 // Z)^(n+1), n < Q <= 64 (the level-2 series of Sec. 3.2.2 taken one level up).
-// One workgroup per box; thread t sums terms 8 s .. 8 s + 7 (s = t mod 8) over
-// every 32nd far lens, then threads n < Q add the 32 partial sums in a fixed
-// order.
+// One workgroup per box; the Q terms are cut into ns = ceil(Q / 8) slices of
+// eight, and the workgroup's threads into 256 / ns lens groups of ns threads
+// (thread s of a group sums terms 8 s .. 8 s + 7 over every (256 / ns)-th far
+// lens, so no thread idles on terms past Q); then threads n < Q add the
+// groups' partial sums in a fixed order.
 __global__ __launch_bounds__(kWG) void k_l1_expand(LmDesc d)
 {
-    __shared__ double2 part[32][64];
-    const int tid = threadIdx.x, s = tid & 7, grp = tid >> 3;
+    __shared__ double2 part[8 * kWG];  // [groups][8 ns]
+    const int ns = (d.Q + 7) >> 3, ng = kWG / ns;
+    const int tid = threadIdx.x, grp = tid / ns, s = tid - grp * ns;
     const int64_t cell = blockIdx.x;  // the box: row-major over [n1y nby][n1x nbx]
     const int64_t bi = cell % (d.n1x * d.nbx), bj = cell / (d.n1x * d.nbx);
     const int64_t I = bi / d.nbx, J = bj / d.nby;
@@ -176,12 +179,12 @@ __global__ __launch_bounds__(kWG) void k_l1_expand(LmDesc d)
         ar[j] = 0.0;
         ai[j] = 0.0;
     }
-    if (8 * s < d.Q) {
-        for (int64_t k = grp; k < d.nlens; k += 32) {
+    if (grp < ng) {
+        for (int64_t k = grp; k < d.nlens; k += ng) {
             if (abs(d.lI[k] - (int)I) <= d.H && abs(d.lJ[k] - (int)J) <= d.H) continue;
             const double wx = d.lx[k] - Zx, wy = d.ly[k] - Zy;
-            const double w2 = wx * wx + wy * wy;
-            const double ux = wx / w2, uy = -wy / w2;  // 1 / (z_k - Z)
+            const double iw2 = 1.0 / (wx * wx + wy * wy);
+            const double ux = wx * iw2, uy = -wy * iw2;  // 1 / (z_k - Z)
             // t = m u^(8 s + 1)
             double px = ux, py = uy;  // u^8 by three squarings
 #pragma unroll
@@ -205,15 +208,16 @@ __global__ __launch_bounds__(kWG) void k_l1_expand(LmDesc d)
                 ty = ny;
             }
         }
-    }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) part[grp][8 * s + j] = make_double2(ar[j], ai[j]);
+        for (int j = 0; j < 8; ++j) part[8 * tid + j] = make_double2(ar[j], ai[j]);
+    }
     __syncthreads();
     if (tid < d.Q) {
+        // term n of group g sits at 8 (g ns + n / 8) + n % 8 = 8 g ns + n
         double sr = 0.0, si = 0.0;
-        for (int g = 0; g < 32; ++g) {
-            sr += part[g][tid].x;
-            si += part[g][tid].y;
+        for (int g = 0; g < ng; ++g) {
+            sr += part[8 * ns * g + tid].x;
+            si += part[8 * ns * g + tid].y;
         }
         d.l1exp[2 * (cell * d.Q + tid)] = sr;
         d.l1exp[2 * (cell * d.Q + tid) + 1] = si;
