@@ -642,8 +642,8 @@ def main():
                                "mixed-precision path" %
                                (g.n_rays, g.coarse, g.l1_kx, g.l1_ky),
                    "rays": g.n_rays, "lenses": w.n_lenses, "map_pixels": [g.src_nx, g.src_ny],
-                   "precision": "FP32 lens sums on rebased offsets, FP64 cell bases and pixel "
-                                "coordinates, FP64 Taylor coefficients",
+                   "precision": "FP32 lens sums on rebased offsets in pixel units, FP64 cell "
+                                "and row pixel bases, FP64 Taylor coefficients",
                    "precision_choice": {"requested": "LM_PREC_AUTO", "used": prec_used,
                                         "fp32_mismatch_estimate": prec_est,
                                         "centred_fp32_mismatch_estimate": prec_est_c},
