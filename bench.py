@@ -336,6 +336,63 @@ def batched_study(lm, inputs, torch, scale, hierarchical=False):
                           if hierarchical else "direct (Sec. 3.2.2) for all maps")}
 
 
+def other_workloads_leg(lm, inputs, torch):
+    """The other single-map workloads (plain-small: direct sum; near-fold: 1e11
+    rays at R = 64; precision stress: 4e12 rays, lambda_t = 0.001), each shot
+    whole through the batched path (tuned, graphs built by one shot, then one
+    timed shot: the shooting launch event-timed, the whole batch from the host),
+    with direct far-field coefficients and, where its series converges, the
+    hierarchical far field."""
+    out = {}
+    for name, make in (("plain_small", inputs.plain_small), ("near_fold", inputs.near_fold),
+                       ("precision_stress", inputs.precision_stress)):
+        w = make()
+        res = {}
+        for hier in (False, True):
+            g = lm.lm_geometry_derive(w.src_side, w.src_side, w.src_pixels, w.src_pixels, w.kappa,
+                                      w.gamma, w.kappa_star, protect=w.protect,
+                                      n_rays=w.n_rays or 0.0, ray_nx=w.ray_nx or 0,
+                                      ray_ny=w.ray_ny or 0, scheme=w.scheme, coarse=w.coarse,
+                                      mean_mass=w.mean_mass)
+            if hier and (w.scheme != lm.LM_SCHEME_INTERP or lm.lm_geometry_far_order(g) <= 0):
+                continue
+            mp = lm.Map(g, w.kappa, w.gamma, w.kappa_star, w.lenses(), sheet=w.sheet())
+            stats = lm.lm_shot_stats(mp.h, 0, 0, g.ray_nx, g.ray_ny)
+            flops = algorithmic_flops(stats, g.taylor_terms)
+            b = lm.lm_batch_create([mp.h])
+            lm.lm_batch_tune(b, None)
+            stream = torch.cuda.current_stream()
+            lm.lm_batch_shoot(b, stream)
+            torch.cuda.synchronize()
+            mp.reset(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lm.lm_batch_shoot(b, stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c_ms, s_ms = lm.lm_batch_timing(b)
+            counts, n_out, n_shot = mp.counts()
+            assert n_shot == g.n_rays and int(counts.sum()) + n_out == n_shot
+            used = mp.precision()[0]
+            lm.lm_batch_destroy(b)
+            mp.close()
+            r = {"rays": g.n_rays, "near_pairs_per_ray": stats.near_pairs / stats.rays,
+                 "precision_used": used, "shoot_kernel_ms": s_ms,
+                 "shoot_rays_per_s": g.n_rays / (s_ms * 1e-3),
+                 "shoot_algorithmic_tflops": flops / (s_ms * 1e-3) / 1e12,
+                 "coefficients_ms": c_ms, "batch_seconds": dt}
+            if hier:
+                r["far_order"] = g.far_order
+            res["hierarchical" if hier else "direct"] = r
+            log("%s%s: %.3g rays, %.2f near pairs per ray, shoot %.1f ms (%.3g rays/s, %.1f TFLOP/s "
+                "algorithmic), coefficients %.1f ms, whole batch %.1f ms" %
+                (name, " (hierarchical, Q = %d)" % g.far_order if hier else "", g.n_rays,
+                 stats.near_pairs / stats.rays, s_ms, g.n_rays / (s_ms * 1e-3),
+                 flops / (s_ms * 1e-3) / 1e12, c_ms, dt * 1e3))
+        out[name] = res
+    return out
+
+
 TABLE1_THETA_E_ARCSEC = 1e-6
 TABLE1_D_ARCMIN = (3.62, -3.41)
 TABLE1_N_STAR = 13745
@@ -522,6 +579,8 @@ def main():
                          "near sums; all: the library's choice and the three forms; side "
                          "measurement, about a minute each), and with the CPU baseline compare "
                          "an 8e8-ray window of it with the oracle")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the plain-small, near-fold and precision-stress workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM "
                          "byte counters) and exit")
@@ -668,6 +727,8 @@ def main():
         line["batched_study"] = study
     if args.fold_maps > 0:
         line["fold_peak_statistics"] = fold_study_leg(lm, inputs, torch, args.fold_maps)
+    if not args.no_workloads:
+        line["other_workloads"] = other_workloads_leg(lm, inputs, torch)
     precs = []
     if args.paper_map != "none":
         precs = {"auto": [lm.LM_PREC_AUTO], "mixed": [lm.LM_PREC_MIXED],
