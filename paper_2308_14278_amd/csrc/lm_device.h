@@ -58,7 +58,9 @@ struct UseTab {
 // issue-bound and needs 4 (at most 128 VGPRs with 256-thread workgroups, 4 per
 // CU).  The per-map kernel, whose descriptor arrives by value, would otherwise
 // allocate a few registers more than that and drop to 3; the hint holds it at
-// 128 (spilling per-unit values to scratch if it must).
+// 128 (spilling per-unit values to scratch if it must).  The batch kernel
+// carries the same hint, with which the register allocator also schedules
+// the plain FP32 form a little tighter.
 template <int SCHEME, int PREC>
 struct MinWaves {
     static constexpr int value = (SCHEME == 1 && PREC != 2) ? 4 : 1;
@@ -1297,7 +1299,8 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<SCHEME, PREC>::value))) void k_shoot
 }
 
 template <int SCHEME, int PREC, int NR, int P, int LAY>
-__global__ __launch_bounds__(kWG) void k_shoot_batch(const LmDesc* __restrict__ descs,
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(MinWaves<SCHEME, PREC>::value))) void k_shoot_batch(const LmDesc* __restrict__ descs,
                                                      const int64_t* __restrict__ offs,
                                                      const int32_t* __restrict__ order, int nmaps,
                                                      unsigned long long* queue)
@@ -1641,6 +1644,8 @@ int dispatch_nr(int nr, int terms, F& f)
     case 4: return dispatch_p<S, PR, 4>(terms, f);
     case 8: return dispatch_p<S, PR, 8>(terms, f);
     case 16:
+        // the centred sums need more registers per ray: 16 rays per lane would
+        // spill at 4 waves per SIMD, so they run 8
         if constexpr (PR == kPrecCentred)
             return dispatch_p<S, PR, 8>(terms, f);
         else
