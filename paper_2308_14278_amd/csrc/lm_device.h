@@ -666,13 +666,18 @@ __device__ __forceinline__ float pix_ratio(const LmDesc& d)
 }
 
 // Integer part of a biased FP64 pixel coordinate for the integer pixel step,
-// held within +-2^30 (a row whose base lies farther out sends every ray
-// outside the map: FP32 sums cannot reach back) so that base plus a
-// saturated floor never wraps into the map; and the remainder against it.
+// and the remainder against it.  The integer part is held within 2^26 pixels
+// of any map (maps hold at most 2^30 pixels a side): a row whose base lies
+// farther out sends every ray outside the map, since an FP32 sum of more than
+// 2^26 pixels has no pixel resolution left.  Within those bounds the base
+// plus a floor saturated at the int32 limits stays below 2^32 or, when
+// negative, wraps to at least 2^31 - 2^26 + kBias, beyond every map, so no
+// result that is not truly in the map lands in it.
 __device__ __forceinline__ void split_base(double ub, unsigned& bi, float& f)
 {
-    const double b = fmin(fmax(floor(ub), -1073741824.0), 1073741824.0);
-    bi = (unsigned)(int)b;
+    constexpr double lo = kBiasD - 67108864.0, hi = kBiasD + 1073741824.0 + 67108864.0;
+    const double b = fmin(fmax(floor(ub), lo), hi);
+    bi = (unsigned)(int64_t)b;
     f = (float)(ub - b);
 }
 
@@ -807,8 +812,8 @@ __device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& 
     } else if constexpr (PREC == 0 || PREC == kPrecCentred) {
         // pixel sums (ax, ay) = (image offset less base fraction): the pixel is
         // the base's integer part plus floor(-sum), added modulo 2^32 (the
-        // base within +-2^30 and the saturated floor keep every result that
-        // is not truly in the map out of it)
+        // clamped base and the saturated floor keep every result that is not
+        // truly in the map out of it: split_base)
         p = rw.bxi + (unsigned)cvt_floor_i32_sat(-ax);
         q = rw.byi + (unsigned)cvt_floor_i32_sat(-ay);
     } else {
