@@ -639,12 +639,12 @@ __device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_en
 }
 
 // Everything one ray row needs before its rays: the row offset, the biased
-// FP64 bases and (rebased paths) the row polynomials.  The rebased FP32 path
-// (PREC 0) keeps its sums in pixel units: the polynomials are scaled to
-// pixels, and each base is split into an integer part (bxi, byi: biased
-// pixel indices, as 32-bit integers) and the fraction below it (fx, fy),
-// which the sums start from; a ray's pixel is then the integer part plus the
-// floor of its FP32 sum, added as integers.
+// FP64 bases and (rebased paths) the row polynomials.  The rebased FP32 paths
+// (plain and centred sums) keep their sums in pixel units: the polynomials
+// are scaled to pixels, and each base is split into an integer part (bxi,
+// byi: biased pixel indices, as 32-bit integers) and the fraction below it
+// (fx, fy), which the sums start from; a ray's pixel is then the integer part
+// plus the floor of its FP32 sum, added as integers.
 template <int PREC, int P, bool FOLD>
 struct Row {
     using T = typename Prec<PREC>::T;
@@ -751,7 +751,8 @@ __device__ __forceinline__ typename Prec<PREC>::T column_offset(const LmDesc& d,
 // Start values of one ray's near sums (rebased paths): the row polynomials
 // without their constant terms, g1 dx + g2 dx^2 + .., from the column's powers
 // pw[k] = dx^(k+1) (one multiply or FMA and D - 1 FMAs per axis with
-// wave-uniform powers); in pixel units (PREC 0) less the bases' fractions.
+// wave-uniform powers); in pixel units (PREC 0) less the bases' fractions
+// (the centred sums start with centred_first instead).
 // (NEGX, NEGY: ax, ay are the negated sums; every step is an exact negation
 // of the plain one, and the negated coefficients need no sign modifier)
 template <bool NEGX, bool NEGY, int PREC, int P, bool FOLD>
@@ -927,7 +928,8 @@ __device__ __forceinline__ void centred_change(T px, T py, T sr, T si, T& dx, T&
 // units: the change conj(delta S) of the near deflection (S in x pixels; the y
 // change converted with px_r = px sdx/sdy and the row's pyr), less the bases'
 // fractions, plus the first row-polynomial term.  x: -(Re(delta S) - fx +
-// g1 px); y: Im(delta S) sdx/sdy + fy - h1 px.
+// gx1 px); y: Im(delta S) sdx/sdy + fy - gy1 px (the negated y change is
+// Im(delta S)).
 template <int P, bool FOLD>
 __device__ __forceinline__ void centred_first(const Row<kPrecCentred, P, FOLD>& rw, float px,
                                               float pxr, float sr, float si, float& axn,
