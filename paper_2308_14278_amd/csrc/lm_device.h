@@ -601,16 +601,20 @@ __device__ __forceinline__ void emit(const Hot& h, unsigned p, unsigned q, unsig
 // Lanes whose row lies outside the shot rectangle (row_ok false) keep runs like
 // every lane but never emit them, so the per-ray path needs no lane mask.  col
 // is the unit-local column of the ray (rays are pushed column by column).
+// (p, q) is the pixel less the lane's row base (bx, by), which is the same for
+// all of the lane's rays, so runs compare the offsets and a run adds the base
+// only when it is emitted.
 __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsigned q, int col,
-                                         const Win& w, unsigned* win, unsigned& nout, bool row_ok)
+                                         unsigned bx, unsigned by, const Win& w, unsigned* win,
+                                         unsigned& nout, bool row_ok)
 {
-    // (a unit starts with an empty run at the out-of-map pixel kBias - 2;
-    // runs of length 0 are never emitted)
+    // (a unit starts with an empty run at an arbitrary key; a run of length 0
+    // is never emitted, and one whose rays match that key names their pixel)
     const unsigned long long key = run_key(p, q);
     if (key != r.key) {
         // one divergent region for every lane whose run ends
         const unsigned n = row_ok ? (unsigned)(col - r.start) : 0u;
-        if (n) emit(h, (unsigned)r.key, (unsigned)(r.key >> 32), n, w, win, nout);
+        if (n) emit(h, (unsigned)r.key + bx, (unsigned)(r.key >> 32) + by, n, w, win, nout);
         r.key = key;
         r.start = col;
     }
@@ -618,11 +622,12 @@ __device__ __forceinline__ void run_push(const Hot& h, Run& r, unsigned p, unsig
 
 // End of a unit (col_end = unit-local column after its last ray): lanes whose
 // pending runs all name one pixel add it once.
-__device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_end, const Win& w,
-                                          unsigned* win, unsigned& nout, int lane, bool row_ok)
+__device__ __forceinline__ void run_flush(const Hot& h, const Run& r, int col_end, unsigned bx,
+                                          unsigned by, const Win& w, unsigned* win,
+                                          unsigned& nout, int lane, bool row_ok)
 {
     const unsigned n = (unsigned)(col_end - r.start);
-    const unsigned rp = (unsigned)r.key, rq = (unsigned)(r.key >> 32);
+    const unsigned rp = (unsigned)r.key + bx, rq = (unsigned)(r.key >> 32) + by;
     bool act = row_ok && n > 0;
     unsigned long long am = __ballot(act);
     if (am) {
@@ -812,13 +817,29 @@ __device__ __forceinline__ void ray_bin(const Hot& h, const Row<PREC, P, FOLD>& 
         q = qi < 0 ? 0u : (unsigned)qi + kBias;
     } else if constexpr (PREC == 0 || PREC == kPrecCentred) {
         // pixel sums (ax, ay) = (image offset less base fraction): the pixel is
-        // the base's integer part plus floor(-sum), added modulo 2^32 (the
-        // clamped base and the saturated floor keep every result that is not
-        // truly in the map out of it: split_base)
-        p = rw.bxi + (unsigned)cvt_floor_i32_sat(-ax);
-        q = rw.byi + (unsigned)cvt_floor_i32_sat(-ay);
+        // the base's integer part (row_base_px) plus floor(-sum), added modulo
+        // 2^32 (the clamped base and the saturated floor keep every result
+        // that is not truly in the map out of it: split_base); here only the
+        // floor, the offset from the base
+        p = (unsigned)cvt_floor_i32_sat(-ax);
+        q = (unsigned)cvt_floor_i32_sat(-ay);
     } else {
         bin_rebased(h.inv_sdx, h.inv_sdy, rw.ubxb, rw.ubyb, ax, ay, p, q);
+    }
+}
+
+// The row's pixel base that ray_bin's results are offsets from (zero where
+// they are the pixels themselves).
+template <int PREC, int P, bool FOLD>
+__device__ __forceinline__ void row_base_px(const Row<PREC, P, FOLD>& rw, unsigned& bx,
+                                            unsigned& by)
+{
+    if constexpr (PREC == 0 || PREC == kPrecCentred) {
+        bx = rw.bxi;
+        by = rw.byi;
+    } else {
+        bx = 0u;
+        by = 0u;
     }
 }
 
@@ -1024,6 +1045,8 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
     if (nblk == 1) stage<SCHEME, PREC>(d, ci, cj, 0, count, zcx, zcy, lb, lane);
 
     Run run{run_key(kBias - 2, kBias - 2), (int)(c_beg - c_lo)};
+    unsigned bxr, byr;
+    row_base_px(rw, bxr, byr);
     for (int64_t c0 = c_lo; c0 < c_hi; c0 += NR) {
         constexpr int D = Row<PREC, P, FOLD>::D;
         static_assert(D <= LM_PTAB_POW, "column table holds too few powers");
@@ -1153,7 +1176,7 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                 unsigned p, q;
                 ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c],
                                        NEGX ? -ax[c] : ax[c], NEGY ? -ay[c] : ay[c], p, q);
-                run_push(h, run, p, q, col0 + c, w, win, nout, row_ok);
+                run_push(h, run, p, q, col0 + c, bxr, byr, w, win, nout, row_ok);
             }
         } else {
 #pragma unroll
@@ -1163,12 +1186,12 @@ __device__ void process_unit(const LmDesc& d, int64_t ci, int64_t cj, int64_t c_
                     ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, zcxf, zcyf, px[c],
                                            NEGX ? -ax[c] : ax[c], NEGY ? -ay[c] : ay[c], p,
                                            q);
-                    run_push(h, run, p, q, col0 + c, w, win, nout, row_ok);
+                    run_push(h, run, p, q, col0 + c, bxr, byr, w, win, nout, row_ok);
                 }
             }
         }
     }
-    run_flush(h, run, (int)(c_hi - c_lo), w, win, nout, lane, row_ok);
+    run_flush(h, run, (int)(c_hi - c_lo), bxr, byr, w, win, nout, lane, row_ok);
 }
 
 // Window origin of a tile: the pixel of the image of its centre cell's centre
@@ -1456,6 +1479,10 @@ __device__ void trace_one(const LmDesc& d, int64_t i, int64_t j, int32_t& po, in
     unsigned p, q;
     ray_bin<PREC, P, FOLD>(h, rw, ar, ai, a0r, a0i, cell_cxf(d, ci), cell_cyf(d, cj), px, ax, ay, p,
                            q);
+    unsigned bxr, byr;
+    row_base_px(rw, bxr, byr);
+    p += bxr;
+    q += byr;
     const unsigned pm = p - kBias, qm = q - kBias;
     const bool in = (pm < (unsigned)d.snx) & (qm < (unsigned)d.sny);
     po = in ? (int32_t)pm : -1;
