@@ -556,8 +556,9 @@ def test_batch_follows_changes_to_its_maps():
 def test_batched_study_map_at_full_geometry_vs_oracle():
     """A map of the 80-map study at its full geometry (the map with the fewest
     rays, ~1e11), shot by the persistent batch kernel on a centred rectangle of
-    1e-2 of its rays, against the oracle; the other maps of the batch shoot
-    small rectangles in the same launch."""
+    1e-2 of its rays, against the oracle; the other two maps of the batch shoot
+    8e6-ray rectangles at the centres of their lattices in the same launch,
+    each against the oracle too."""
     ws = inputs.batched_study(80, 1.0)
     k = int(np.argmin([w.n_rays for w in ws]))
     picks = [k, (k + 1) % 80, (k + 2) % 80]
@@ -573,9 +574,12 @@ def test_batched_study_map_at_full_geometry_vs_oracle():
     rect = ((g.ray_nx - ni) // 2, (g.ray_ny - nj) // 2, ni, nj)
     assert ni * nj >= 1e-2 * g.n_rays
     lm.lm_batch_set_rect(b, 0, *rect)
+    rects = {}
     for t in (1, 2):
         gt = maps[t][1]
-        lm.lm_batch_set_rect(b, t, 0, 0, min(4096, gt.ray_nx), min(512, gt.ray_ny))
+        rni, rnj = min(8192, gt.ray_nx), min(1024, gt.ray_ny)
+        rects[t] = ((gt.ray_nx - rni) // 2, (gt.ray_ny - rnj) // 2, rni, rnj)
+        lm.lm_batch_set_rect(b, t, *rects[t])
     lm.lm_batch_shoot(b)
     counts, n_out, _ = mp.counts()
     x, y, m = w.lenses()
@@ -583,6 +587,15 @@ def test_batched_study_map_at_full_geometry_vs_oracle():
         *rect, nthreads=NTHREADS)
     _compare(g, counts, n_out, ref, ref_out, ni * nj,
              "study map %d (%.3g rays) through the batch kernel" % (k, g.n_rays))
+    for t in (1, 2):
+        wt, gt, mpt = maps[t]
+        rt = rects[t]
+        ct, ot, _ = mpt.counts()
+        xt, yt, mt = wt.lenses()
+        rf, ro = oracle.Oracle(oracle_geom(gt), wt.kappa, wt.gamma, wt.kappa_star, xt, yt,
+                               mt).shoot(*rt, nthreads=NTHREADS)
+        _compare(gt, ct, ot, rf, ro, rt[2] * rt[3],
+                 "study map %d centre through the same launch" % picks[t])
     lm.lm_batch_destroy(b)
     for _, _, mp2 in maps:
         mp2.close()
