@@ -13,12 +13,15 @@ import pytest
 import paper_2308_14278_amd.lensmap as lm
 from paper_2308_14278_amd import codeobj
 
-# <scheme 1 (interpolated), precision 0 (mixed), NR 16, P 4, LDS layout>; the
+# <scheme 1 (interpolated), precision 0 (mixed) or 4 (centred), NR, P 4, LDS layout>; the
 # batch kernel must fit without spills in every LDS layout the tuner may pick,
 # the per-map kernel (descriptor by value, held to 4 waves by an attribute) may
 # spill a few per-unit values to scratch
 BATCH = "_ZN12_GLOBAL__N_113k_shoot_batchILi1ELi%dELi%dELi4ELi%dEEEvPK6LmDescPKlPKiiPy"
 DEFAULT = tuple([(BATCH % (0, nr, lay), 0) for nr in (8, 16) for lay in range(4)] +
+                # the centred sums (the default on the paper's own map) at 8 rays per
+                # lane, in the one LDS layout they are built for
+                [(BATCH % (4, 8, 0), 0)] +
                 [("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi0ELi16ELi4EEEv6LmDesc", 4),
                  # the plain FP32 comparison path (precision 1), per map and batched
                  ("_ZN12_GLOBAL__N_111k_shoot_mapILi1ELi1ELi16ELi4EEEv6LmDesc", 4),
